@@ -1,0 +1,249 @@
+"""Pins of the oracle's coarse representation, projection and lifting.
+
+Checks use closed forms (block sums, Parseval, least squares by a library
+routine, exact free streaming), invariants stated by the paper (charge
+conservation of the projection, Sec. 3.3 remark) and statistical properties
+of the quiet start (App. C).
+"""
+import numpy as np
+import pytest
+from scipy.special import ndtr
+
+from oracle import efpi, pic, metrics
+from oracle.pic import Grid, PERIODIC, WALLS, NOFIELD
+import synth
+
+
+# ------------------------------------------------------------------ Haar ----
+
+def test_haar_block_sum_closed_form_and_parseval():
+    g = np.random.default_rng(0)
+    f = g.standard_normal(256)
+    s, d = efpi.haar_analysis(f, 4)
+    assert np.allclose(s, f.reshape(16, 16).sum(axis=1) / 4.0, atol=1e-13)
+    energy = np.sum(s ** 2) + sum(np.sum(x ** 2) for x in d)
+    assert energy == pytest.approx(np.sum(f ** 2), rel=1e-13)
+    assert np.allclose(efpi.haar_synthesis(s, d), f, atol=1e-13)
+
+
+def test_haar_constant():
+    s, d = efpi.haar_analysis(np.full(64, 3.0), 3)
+    assert np.allclose(s, 3.0 * 2 ** 1.5) and all(np.allclose(x, 0.0) for x in d)
+
+
+def test_restriction_total_charge():
+    g = Grid(128, 128.0)
+    cell, frac, v, w = synth.random_particles(3000, 128, seed=4)
+    x = efpi.particles_to_x(cell, frac.astype(float), g)
+    c = efpi.restrict_snapshot(x, v.astype(float), np.zeros(x.size), w.astype(float), 0.0, g, 3, False)
+    assert c[0].sum() * 2 ** 1.5 * g.h == pytest.approx(w.astype(float).sum(), rel=1e-13)
+    assert c[1].sum() * 2 ** 1.5 * g.h == pytest.approx(np.sum(w.astype(float) * v), rel=1e-12)
+
+
+def test_restriction_walls_fold_and_exclusion():
+    g = Grid(16, 16.0, WALLS)
+    # A particle at 15.5 shares half to node 16, which joins the last block.
+    c = efpi.restrict_snapshot(np.array([15.5]), np.array([0.0]), np.zeros(1), np.array([1.0]),
+                               0.0, g, 2, False)
+    assert c[0][-1] * 2.0 == pytest.approx(1.0) and np.allclose(c[0][:-1], 0.0)
+    # moved beyond the wall by the characteristic: excluded from the snapshot
+    c = efpi.restrict_snapshot(np.array([15.5]), np.array([1.0]), np.zeros(1), np.array([1.0]),
+                               1.0, g, 2, True)
+    assert np.allclose(c, 0.0)
+
+
+# ------------------------------------------------------- least squares ------
+
+@pytest.mark.parametrize("ne", [1, 2, 6, 10, 20])
+def test_ls_slope_equals_polyfit(ne):
+    g = np.random.default_rng(ne)
+    dt = 0.1
+    snaps = g.standard_normal((ne + 1, 2, 8))
+    slope = efpi.ls_slope(snaps, dt)
+    t = np.arange(ne + 1) * dt
+    ref = np.polyfit(t, snaps.reshape(ne + 1, -1), 1)[0].reshape(2, 8)
+    assert np.allclose(slope, ref, atol=1e-10)
+
+
+def test_ls_exact_on_linear_data_and_shift_invariant():
+    dt = 0.1
+    base = np.random.default_rng(1).standard_normal((2, 8))
+    rate = np.random.default_rng(2).standard_normal((2, 8))
+    snaps = np.array([base + rate * p * dt for p in range(21)])
+    assert np.allclose(efpi.ls_slope(snaps, dt), rate, atol=1e-12)
+    assert np.allclose(efpi.ls_slope(snaps + 5.0, dt), rate, atol=1e-11)
+    # projection of exactly linear data is exact
+    nxt = efpi.project(snaps, dt, 20.0)
+    assert np.allclose(nxt, base + rate * 20.0, atol=1e-10)
+
+
+def test_projection_conserves_charge():
+    # Remark of Sec. 3.3: equal totals in every snapshot -> the slope sums to zero.
+    g = np.random.default_rng(3)
+    snaps = g.standard_normal((21, 2, 16))
+    snaps -= snaps.sum(axis=2, keepdims=True) / 16
+    snaps += 1.0
+    slope = efpi.ls_slope(snaps, 0.1)
+    assert abs(slope[0].sum()) < 1e-12
+    assert efpi.project(snaps, 0.1, 20.0)[0].sum() == pytest.approx(16.0, rel=1e-13)
+
+
+# ------------------------------------------------------ co-evolving frame ---
+
+def test_coevolving_frame_exact_in_free_streaming():
+    # E = 0: X~ = X^0 + Delta t V for every p (App. B, eq. B.4), so all snapshots
+    # agree, the slope vanishes and the projection equals the restriction of the
+    # exactly free-streamed state at t + Delta t.
+    g = Grid(64, 64.0, closure=NOFIELD)
+    sch = efpi.Scheme(levels=2, burst_steps=6, macro_dt=3.0, ppc=32)
+    nn, uu = synth.iaw_profile(64, 64.0)
+    cell, frac, v, w = efpi.load_particles(nn, uu, g, sch, synth.lift_shift(5))
+    x = efpi.particles_to_x(cell, frac, g)
+    snaps, *_ = efpi.pic_burst(x, v, w, g, sch)
+    assert np.max(np.abs(snaps - snaps[0])) < 1e-10
+    assert np.max(np.abs(efpi.ls_slope(snaps, g.dt))) < 1e-8
+    xf = np.mod(x + sch.macro_dt * v, g.length)
+    ref = efpi.restrict_snapshot(xf, v, np.zeros_like(v), w, 0.0, g, 2, False)
+    nxt = efpi.project(snaps, g.dt, sch.macro_dt)
+    assert np.max(np.abs(nxt - ref)) < 1e-8
+
+
+def test_plain_restriction_changes_under_streaming():
+    g = Grid(64, 64.0, closure=NOFIELD)
+    sch = efpi.Scheme(levels=2, burst_steps=6, macro_dt=3.0, ppc=32, coevolving=False)
+    nn, uu = synth.iaw_profile(64, 64.0)
+    cell, frac, v, w = efpi.load_particles(nn, uu, g, sch, synth.lift_shift(5))
+    snaps, *_ = efpi.pic_burst(efpi.particles_to_x(cell, frac, g), v, w, g, sch)
+    assert np.max(np.abs(snaps - snaps[0])) > 1e-4
+
+
+# ------------------------------------------------------------------ lift ----
+
+def test_hammersley_radical_inverse_definition():
+    idx = np.array([0, 1, 2, 3, 6, 12345, 2 ** 31 + 7], dtype=np.uint64)
+    # van der Corput by its digit expansion: sum of bit_b 2^{-(b+1)}
+    vdc = np.array([sum(((int(i) >> b) & 1) * 2.0 ** -(b + 1) for b in range(32)) for i in idx])
+    b = efpi.hammersley_b(idx, 0)
+    assert np.allclose(b, vdc + 2.0 ** -33, atol=0, rtol=1e-15)
+    b2 = efpi.hammersley_b(idx, 2 ** 31)
+    assert np.allclose(b2, np.mod(vdc + 0.5, 1.0) + 2.0 ** -33, atol=1e-15)
+
+
+def test_inverse_normal_routine():
+    from scipy.special import ndtri
+    b = np.array([1e-9, 0.025, 0.3, 0.5, 0.975, 1 - 1e-7])
+    assert np.allclose(ndtr(ndtri(b)), b, rtol=1e-12)
+    assert ndtri(0.975) == pytest.approx(1.959963984540054, rel=1e-14)
+
+
+def test_quiet_start_moments():
+    n, ppc = 256, 400
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(ppc=ppc, vth=0.3)
+    nn, uu = synth.iaw_profile(n, float(n))
+    cell, frac, v, w = efpi.load_particles(nn, uu, g, sch, synth.lift_shift(7))
+    assert cell.size == n * ppc and np.all(np.diff(cell) >= 0)
+    # weights reproduce the density: sum w = integral of the linear interpolant = L
+    assert w.sum() == pytest.approx(float(n), rel=1e-12)
+    # per-cell mean velocity ~ u and global thermal spread ~ vth (low-discrepancy error)
+    x = efpi.particles_to_x(cell, frac, g)
+    u_at = np.interp(x, np.arange(n + 1), np.append(uu, uu[0]))
+    dv = v - u_at
+    assert abs(np.mean(dv)) < 2e-3
+    assert np.sqrt(np.mean(dv ** 2)) == pytest.approx(0.3, rel=5e-3)
+
+
+def test_lift_block_correction_exact():
+    n, lv = 128, 3
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(levels=lv, ppc=50)
+    coarse = synth.random_coarse(n >> lv, seed=9, levels=lv)
+    cell, frac, v, w = efpi.lift(coarse, g, sch, synth.lift_shift(9))
+    blk = cell >> lv
+    scale = g.h * 2 ** (lv / 2)
+    assert np.allclose(np.bincount(blk, weights=w), coarse[0] * scale, rtol=1e-12)
+    assert np.allclose(np.bincount(blk, weights=w * v), coarse[1] * scale, rtol=1e-10, atol=1e-12)
+
+
+def test_lift_then_restrict_close_to_identity():
+    n, lv = 256, 4
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(levels=lv, ppc=200)
+    coarse = synth.random_coarse(n >> lv, seed=11, levels=lv)
+    cell, frac, v, w = efpi.lift(coarse, g, sch, synth.lift_shift(11))
+    x = efpi.particles_to_x(cell, frac, g)
+    back = efpi.restrict_state(x, v, w, np.ones(x.size, bool), g, sch)
+    assert metrics.rel_l2(back[0], coarse[0]) < 1e-3
+    assert metrics.rel_l2(back[1], coarse[1]) < 1e-2
+
+
+def test_piecewise_constant_lift_profile_inverts_restriction():
+    n, lv = 64, 3
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(levels=lv, lift_linear=False)
+    coarse = synth.random_coarse(n >> lv, seed=12, levels=lv)
+    nf, jf = efpi.lift_profile(coarse, g, sch)
+    s, _ = efpi.haar_analysis(nf, lv)
+    assert np.allclose(s, coarse[0], atol=1e-13)
+
+
+def test_lift_deterministic_and_shift_sensitive():
+    g = Grid(64, 64.0)
+    sch = efpi.Scheme(levels=2, ppc=20)
+    coarse = synth.random_coarse(16, seed=13, levels=2)
+    a = efpi.lift(coarse, g, sch, 12345)
+    b = efpi.lift(coarse, g, sch, 12345)
+    c = efpi.lift(coarse, g, sch, 999)
+    assert all(np.array_equal(p, q) for p, q in zip(a, b))
+    assert not np.array_equal(a[2], c[2])
+
+
+# ------------------------------------------------------------ end to end ----
+
+def test_leap_zero_equals_pic():
+    # Delta t = N_e dt: the projection adds nothing, and the last snapshot is the
+    # plain restriction of the PIC state after N_e steps (tau_{N_e} = 0).
+    n = 64
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(levels=2, burst_steps=5, macro_dt=0.5, ppc=40)
+    nn, uu = synth.iaw_profile(n, float(n))
+    cell, frac, v, w = efpi.load_particles(nn, uu, g, sch, synth.lift_shift(14))
+    x = efpi.particles_to_x(cell, frac, g)
+    snaps, *_ = efpi.pic_burst(x, v, w, g, sch)
+    nxt = efpi.project(snaps, g.dt, sch.macro_dt)
+    xp, vh, al, phi = pic.pic_run(x, v, w, g, 5)
+    vi = vh + 0.5 * g.dt * pic.gather(pic.field(phi, g), xp, g)
+    ref = efpi.restrict_state(xp, vi, w, al, g, sch)
+    assert np.allclose(nxt, ref, atol=1e-11)
+
+
+@pytest.mark.slow
+def test_efpi_error_grows_with_macro_step():
+    # Parity unpinned beyond this trend: the projective error against full PIC
+    # shrinks as Delta t approaches N_e dt (convergence claim of Sec. 4.1).
+    n = 128
+    g = Grid(n, float(n))
+    nn, uu = synth.iaw_profile(n, float(n))
+    errs = []
+    for mdt in (2.0, 6.0, 12.0):
+        sch = efpi.Scheme(levels=3, burst_steps=10, macro_dt=mdt, ppc=100)
+        cell, frac, v, w = efpi.load_particles(nn, uu, g, sch, synth.lift_shift(15))
+        x = efpi.particles_to_x(cell, frac, g)
+        c0 = efpi.restrict_state(x, v, w, np.ones(x.size, bool), g, sch)
+        nxt, _, _ = efpi.macro_step(c0, g, sch, synth.lift_shift(16))
+        steps = int(round(mdt / g.dt))
+        xp, vh, al, phi = pic.pic_run(x, v, w, g, steps)
+        ref = efpi.restrict_state(xp, vh, w, al, g, sch)
+        errs.append(metrics.rel_l2(nxt[0], ref[0]))
+    assert errs[0] < errs[2]
+
+
+def test_ensemble_mean():
+    a, b, c = (np.full((2, 4), v) for v in (1.0, 2.0, 6.0))
+    assert np.allclose(efpi.ensemble_mean([a, b, c]), 3.0)
+
+
+def test_rel_l2_metric():
+    assert metrics.rel_l2([1, 2], [1, 2]) == 0.0
+    assert metrics.rel_l2([1, 0], [0, 1]) == pytest.approx(1.0)
+    assert metrics.rel_l2([2.0], [1.0]) == pytest.approx(np.sqrt(1 / 5))

@@ -1,0 +1,276 @@
+"""Pins of the oracle's fine-scale solver against closed forms, invariants and brute force.
+
+Nothing here compares the oracle with itself: each check uses a result fixed by
+the mathematics (exact rational arithmetic, closed forms of the discrete
+operators, exact leapfrog solutions, dispersion relations of the model).
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import pic
+from oracle.pic import Grid, PERIODIC, WALLS, BOLTZMANN, LINEAR, NOFIELD
+import synth
+
+
+# ---------------------------------------------------------------- deposit ---
+
+def test_fx_single_particle_hand_computed():
+    # w = 1, theta = 1/4: q = 2^40, right share 2^38, left share 3 * 2^38.
+    g = Grid(8, 8.0)
+    q = pic.deposit_fx(np.array([3], np.int16), np.array([0.25], np.float32),
+                       np.array([1.0], np.float32), g)
+    expect = np.zeros(8, np.int64)
+    expect[3] = 3 * 2 ** 38
+    expect[4] = 2 ** 38
+    assert np.array_equal(q, expect)
+
+
+def test_fx_periodic_wrap_and_wall_node():
+    gp = Grid(8, 8.0, PERIODIC)
+    q = pic.deposit_fx(np.array([7], np.int16), np.array([0.5], np.float32),
+                       np.array([0.5], np.float32), gp)
+    assert q[7] == 2 ** 38 and q[0] == 2 ** 38 and q.sum() == 2 ** 39
+    gw = Grid(8, 8.0, WALLS)
+    q = pic.deposit_fx(np.array([7], np.int16), np.array([0.5], np.float32),
+                       np.array([0.5], np.float32), gw)
+    assert q.size == 9 and q[7] == 2 ** 38 and q[8] == 2 ** 38
+
+
+@pytest.mark.parametrize("bc", [PERIODIC, WALLS])
+def test_fx_charge_conservation_exact(bc):
+    g = Grid(64, 64.0, bc)
+    cell, frac, v, w = synth.random_particles(5000, 64, seed=1, dead_fraction=0.1)
+    q = pic.deposit_fx(cell, frac, w, g)
+    alive = cell >= 0
+    per_particle = np.rint(w[alive].astype(np.float64) * 2.0 ** 40).astype(np.int64)
+    assert int(q.sum()) == int(per_particle.sum())
+
+
+def test_fx_brute_force_rational():
+    # Exact rational CIC shares with ties-to-even rounding (Python round on Fraction);
+    # weights below 2^-11 keep q < 2^29, where the binary64 product is exact.
+    g = Grid(16, 16.0)
+    cell, frac, _, w = synth.random_particles(40, 16, seed=2, w_mean=2.0 ** -13)
+    fx = pic.deposit_fx(cell, frac, w, g)
+    brute = [0] * 16
+    for c, f, ww in zip(cell.tolist(), frac.tolist(), w.tolist()):
+        q = round(Fraction(ww) * 2 ** 40)
+        qr = round(Fraction(f) * q)
+        brute[c] += q - qr
+        brute[(c + 1) % 16] += qr
+    assert fx.tolist() == brute
+
+
+def test_fx_quiet_lattice_is_uniform():
+    # Equal weights at offsets (m + 1/2)/ppc in every cell: every node gets exactly ppc * q.
+    n, ppc = 32, 37
+    g = Grid(n, float(n))
+    cell = np.repeat(np.arange(n), ppc).astype(np.int16)
+    frac = np.tile(((np.arange(ppc) + 0.5) / ppc).astype(np.float32), n)
+    w = np.full(cell.size, 1.0 / ppc, np.float32)
+    q = pic.deposit_fx(cell, frac, w, g)
+    qp = int(np.rint(np.float64(np.float32(1.0 / ppc)) * 2.0 ** 40))
+    assert np.all(q == ppc * qp)
+
+
+def test_density_deposit_matches_hat_function():
+    # rho_k = sum_j w_j max(0, 1 - |x_j/h - k|) / V_k, evaluated with exact rationals.
+    g = Grid(8, 4.0, WALLS)  # h = 1/2
+    x = np.array([0.1, 1.3, 2.49, 3.99, 0.0])
+    w = np.array([0.3, 0.7, 1.1, 0.2, 0.5])
+    rho = pic.deposit_density(x, w, g)
+    for k in range(9):
+        s = Fraction(0)
+        for xj, wj in zip(x.tolist(), w.tolist()):
+            d = abs(Fraction(xj) / Fraction(1, 2) - k)
+            s += Fraction(wj) * max(Fraction(0), 1 - d)
+        vol = Fraction(1, 4) if k in (0, 8) else Fraction(1, 2)
+        assert rho[k] == pytest.approx(float(s / vol), rel=1e-14, abs=1e-15)
+
+
+# ----------------------------------------------------------------- field ----
+
+def _kd2(k, h):
+    return 4.0 / h ** 2 * np.sin(k * h / 2.0) ** 2
+
+
+@pytest.mark.parametrize("n,L", [(64, 64.0), (128, 64.0)])
+def test_newton_manufactured_periodic(n, L):
+    # -D2 cos(k x) = K_d^2 cos(k x) with K_d^2 = (4/h^2) sin^2(k h / 2).
+    g = Grid(n, L)
+    h = g.h
+    xk = np.arange(n) * h
+    k = 2 * np.pi * 3 / L
+    phi_star = 0.4 * np.cos(k * xk) - 0.1
+    rho = 0.4 * _kd2(k, h) * np.cos(k * xk) + np.exp(phi_star)
+    phi, it, ok = pic.newton_poisson(rho, g, phi0=np.zeros(n))
+    assert ok and it < 30
+    assert np.max(np.abs(phi - phi_star)) < 1e-12
+
+
+def test_newton_manufactured_walls():
+    # cos(pi m k / N) is even about both walls, so the mirrored-ghost Neumann rows
+    # act on it exactly like the interior stencil.
+    n = 64
+    g = Grid(n, 64.0, WALLS)
+    kk = np.arange(n + 1)
+    kw = np.pi * 5 / n
+    phi_star = 0.3 * np.cos(kw * kk) + 0.2
+    rho = 0.3 * _kd2(kw, 1.0) * np.cos(kw * kk) + np.exp(phi_star)
+    phi, _, ok = pic.newton_poisson(rho, g)
+    assert ok and np.max(np.abs(phi - phi_star)) < 1e-12
+
+
+@pytest.mark.parametrize("c", [0.05, 1.0, 3.7])
+def test_newton_uniform_density_gives_log(c):
+    g = Grid(32, 32.0)
+    phi, _, ok = pic.newton_poisson(np.full(32, c), g, phi0=np.zeros(32))
+    assert ok and np.allclose(phi, np.log(c), atol=1e-13, rtol=0)
+
+
+def test_newton_linear_response():
+    # Small perturbation: phi ~ delta cos(kx) / (1 + K_d^2) to first order.
+    n = 128
+    g = Grid(n, 128.0)
+    xk = np.arange(n, dtype=float)
+    k = 2 * np.pi * 2 / 128.0
+    d = 1e-6
+    phi, _, ok = pic.newton_poisson(1.0 + d * np.cos(k * xk), g)
+    lin = d * np.cos(k * xk) / (1.0 + _kd2(k, 1.0))
+    assert ok and np.max(np.abs(phi - lin)) < 1e-11
+
+
+def test_linear_closure_closed_form():
+    n = 64
+    g = Grid(n, 32.0, closure=LINEAR)
+    xk = np.arange(n) * g.h
+    k = 2 * np.pi * 2 / 32.0
+    phi = pic.linear_poisson(1.0 + 0.3 * np.cos(k * xk), g)
+    assert np.max(np.abs(phi - 0.3 * np.cos(k * xk) / _kd2(k, g.h))) < 1e-12
+
+
+def test_field_closed_form():
+    # -(cos(k(x+h)) - cos(k(x-h))) / 2h = sin(k h) sin(k x) / h.
+    n = 64
+    g = Grid(n, 16.0)
+    xk = np.arange(n) * g.h
+    k = 2 * np.pi * 3 / 16.0
+    e = pic.field(np.cos(k * xk), g)
+    assert np.allclose(e, np.sin(k * g.h) * np.sin(k * xk) / g.h, atol=1e-13)
+    gw = Grid(n, 16.0, WALLS)
+    ew = pic.field(np.cos(np.pi * np.arange(n + 1) / n), gw)
+    assert ew[0] == 0.0 and ew[-1] == 0.0
+
+
+def test_gather_reproduces_linear_field():
+    g = Grid(16, 16.0, WALLS)
+    e_nodes = 0.5 + 0.25 * np.arange(17)
+    x = np.array([0.0, 0.3, 7.75, 15.999])
+    assert np.allclose(pic.gather(e_nodes, x, g), 0.5 + 0.25 * x, atol=1e-14)
+
+
+# ------------------------------------------------------------------ push ----
+
+def test_free_streaming_exact():
+    g = Grid(32, 32.0, closure=NOFIELD)
+    x0 = np.array([1.0, 5.5, 31.0])
+    v0 = np.array([0.3, -0.7, 0.9])
+    w = np.ones(3)
+    x, vh, alive, _ = pic.pic_run(x0, v0, w, g, steps=50)
+    assert np.allclose(x, np.mod(x0 + 50 * g.dt * v0, 32.0), atol=1e-12)
+    assert np.allclose(vh, v0)
+
+
+def test_leapfrog_exact_for_constant_force():
+    g = Grid(64, 1000.0, WALLS)
+    a = 0.013
+    e = np.full(65, a)
+    x = np.array([100.0, 400.0])
+    v0 = np.array([0.5, -1.0])
+    vh = v0 - 0.5 * g.dt * a
+    alive = np.ones(2, bool)
+    w = np.ones(2)
+    n = 37
+    for _ in range(n):
+        x, vh, alive = pic.leapfrog_step(x, vh, w, alive, e, g)
+    t = n * g.dt
+    assert np.allclose(x, np.array([100.0, 400.0]) + v0 * t + 0.5 * a * t * t, atol=1e-10)
+
+
+def test_wall_absorbs():
+    g = Grid(16, 16.0, WALLS, closure=NOFIELD)
+    x, vh, alive, _ = pic.pic_run(np.array([0.05, 8.0, 15.95]), np.array([-1.0, 0.0, 1.0]),
+                                  np.ones(3), g, steps=1)
+    assert alive.tolist() == [False, True, False]
+
+
+# ----------------------------------------------------- plasma oscillations --
+
+def _cold_mode_frequency(closure, mode=4, n=128, ppc=16, steps=420, amp=0.01):
+    g = Grid(n, float(n), closure=closure)
+    # Cold ions displaced so that the density is 1 + amp cos(kx): x = x0 + (amp/k) sin(k x0).
+    x0 = (np.arange(n * ppc) + 0.5) / ppc
+    k = 2 * np.pi * mode / n
+    x = np.mod(x0 - (amp / k) * np.sin(k * x0), n)
+    w = np.full(x.size, 1.0 / ppc)
+    v = np.zeros_like(x)
+    alive = np.ones(x.size, bool)
+    _, phi, e = pic.field_from_particles(x, w, alive, g)
+    vh = v - 0.5 * g.dt * pic.gather(e, x, g)
+    xk = np.arange(n)
+    amps = []
+    for s in range(steps):
+        rho = pic.deposit_density(x, w, g)
+        amps.append(np.sum(rho * np.cos(k * xk)) * 2 / n)
+        x, vh, alive = pic.leapfrog_step(x, vh, w, alive, e, g)
+        _, phi, e = pic.field_from_particles(x, w, alive, g, phi)
+    a = np.array(amps)
+    # first upward zero crossing after the first downward one -> half period
+    t = np.arange(steps) * g.dt
+    zc = [i for i in range(1, steps) if np.sign(a[i]) != np.sign(a[i - 1])]
+    t0 = t[zc[0] - 1] + (t[zc[0]] - t[zc[0] - 1]) * a[zc[0] - 1] / (a[zc[0] - 1] - a[zc[0]])
+    t1 = t[zc[1] - 1] + (t[zc[1]] - t[zc[1] - 1]) * a[zc[1] - 1] / (a[zc[1] - 1] - a[zc[1]])
+    return np.pi / (t1 - t0), k, g
+
+
+def test_cold_ion_acoustic_frequency_boltzmann():
+    # Linearised Boltzmann-electron model: omega^2 = K^2 / (1 + K^2) (ion-acoustic branch);
+    # leapfrog: sin(omega dt / 2) = (dt / 2) omega_model.
+    w_num, k, g = _cold_mode_frequency(BOLTZMANN)
+    kd2 = _kd2(k, 1.0)
+    w_model = np.sqrt(kd2 / (1.0 + kd2))
+    w_leap = 2.0 / g.dt * np.arcsin(0.5 * g.dt * w_model)
+    assert abs(w_num / w_leap - 1.0) < 0.02
+
+
+def test_cold_ion_plasma_frequency_linear_closure():
+    # Fixed background: ions oscillate at the ion plasma frequency, 1 in these units.
+    w_num, _, g = _cold_mode_frequency(LINEAR, steps=120)
+    w_leap = 2.0 / g.dt * np.arcsin(0.5 * g.dt)
+    assert abs(w_num / w_leap - 1.0) < 0.02
+
+
+# ---------------------------------------------------------------- energy ----
+
+@pytest.mark.slow
+def test_energy_drift_bounded_iaw():
+    # Parity unpinned as a law: the centred-field CIC scheme conserves W only
+    # approximately; the bound is set from the oracle and must hold over 400 steps.
+    from oracle import efpi
+    n = 64
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(ppc=200)
+    nn, uu = synth.iaw_profile(n, float(n))
+    cell, frac, v, w = efpi.load_particles(nn, uu, g, sch, synth.lift_shift(3))
+    x = efpi.particles_to_x(cell, frac, g)
+    alive = np.ones(x.size, bool)
+    _, phi, _ = pic.field_from_particles(x, w, alive, g)
+    w0 = pic.energy(x, v, w, alive, phi, g)
+    kin0 = 0.5 * np.sum(w * v * v)
+    xs, vh, al, phi1 = pic.pic_run(x, v, w, g, 400)
+    e1 = pic.field(phi1, g)
+    v_int = vh + 0.5 * g.dt * pic.gather(e1, xs, g)
+    w1 = pic.energy(xs, v_int, w, al, phi1, g)
+    assert abs(w1 - w0) / kin0 < 5e-3
