@@ -1,0 +1,226 @@
+/*
+ * efpi.h - C ABI of the MI355X EFPI / PIC-burst library (libefpi.so).
+ *
+ * The library advances electrostatic 1D1V particle-in-cell ions with Boltzmann
+ * electrons and couples them to coarse Haar coefficients of the density and
+ * momentum moments through the equation-free projective integration cycle of
+ * Cazeaux & Hesthaven (arXiv:1610.01071), Sec. 3.1 and 3.3:
+ *
+ *   lift (App. C)  ->  N_e fine PIC steps, restricting after each (Sec. 2.2,
+ *   App. B)  ->  least-squares slope (eq. 3.18)  ->  projection (eq. 3.17).
+ *
+ * Units: length in Debye lengths, time in inverse ion plasma frequencies,
+ * potential in T_e/e, density in n_0; the ion charge-to-mass ratio is 1 and the
+ * field equation is -phi'' + exp(phi) = n_i (eq. 3.15).
+ *
+ * Conventions that hold for every entry point:
+ *  - Pointers named d_* are device pointers, h_* are host pointers.
+ *  - Device memory is owned by the caller.  efpi_init binds one caller-owned
+ *    workspace; the library never allocates or frees device memory.
+ *  - Every call that touches the device only enqueues work on the context's
+ *    HIP stream and returns; results are visible after the stream synchronises.
+ *    Calls documented as synchronous say so.
+ *  - Argument checks happen before anything is enqueued; a rejected call
+ *    returns a negative efpi_status, enqueues nothing and leaves the context
+ *    unchanged.  efpi_last_error() then describes the failure.
+ *  - Device-side conditions (Newton not converged, non-finite values,
+ *    particle capacity exceeded, negative projected mass) set bits of a device
+ *    status word; efpi_sync returns them.
+ *  - A context is used from one host thread at a time.
+ *
+ * Particle store (structure of arrays, cell order after a lift): per ion an
+ * int16 cell index c (-1 marks an absorbed ion), an FP32 offset frac in [0,1)
+ * inside the cell (position x = (c + frac) h), an FP32 velocity and an FP32
+ * weight.  Grid charge is accumulated as int64 fixed point in units of 2^-40,
+ * so it is independent of summation order.
+ */
+#ifndef EFPI_H
+#define EFPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EFPI_ABI_VERSION 1u
+
+typedef enum {
+  EFPI_OK = 0,
+  EFPI_EINVAL = -1,    /* invalid argument or configuration                     */
+  EFPI_ENOMEM = -2,    /* workspace smaller than efpi_workspace_size            */
+  EFPI_EHIP = -3,      /* a HIP runtime call failed                             */
+  EFPI_ENEWTON = -4,   /* Newton iteration did not reach its tolerance          */
+  EFPI_ENUMERIC = -5,  /* non-finite value in potential or coarse state         */
+  EFPI_ESTATE = -6,    /* call not valid in the current state                   */
+  EFPI_EOVERFLOW = -7  /* particle capacity exceeded at load or lift            */
+} efpi_status;
+
+/* Device status bits returned by efpi_sync. */
+#define EFPI_DEV_NEWTON 1u   /* max |Newton update| above newton_tol             */
+#define EFPI_DEV_NAN 2u      /* non-finite potential or coarse value             */
+#define EFPI_DEV_OVERFLOW 4u /* lift wanted more particles than capacity         */
+#define EFPI_DEV_NEGMASS 8u  /* projected block mass below zero (clipped at lift) */
+
+/* Boundary conditions and closures. */
+#define EFPI_BC_PERIODIC 0
+#define EFPI_BC_WALLS 1      /* absorbing walls, Neumann potential (phi' = 0)    */
+#define EFPI_CLOSURE_BOLTZMANN 0 /* Newton solve of eq. 3.15                      */
+#define EFPI_CLOSURE_NOFIELD 2   /* E = 0 (free streaming; test closure)          */
+
+/* One replica (an independent plasma).  Ensembles pass several. */
+typedef struct {
+  int32_t n_cells;      /* N: power of two in [8, 16384]                          */
+  int32_t bc;           /* EFPI_BC_*                                              */
+  int32_t closure;      /* EFPI_CLOSURE_*                                         */
+  int32_t ppc;          /* ions per occupied cell at load and lift, >= 1          */
+  int32_t haar_levels;  /* l: coarse blocks of 2^l cells; N_c = N >> l, l <= log2 N */
+  int32_t burst_steps;  /* N_e: fine steps per burst (Sec. 3.1), >= 1            */
+  int32_t coevolving;   /* 1: restriction along approximate characteristics (App. B) */
+  int32_t lift_linear;  /* 1: linear interpolation of block means at lift        */
+  double length;        /* L, with h = L / N                                      */
+  double vth;           /* thermal speed sqrt(T_i/T_e) of the lifted Maxwellian   */
+  double dt;            /* fine step delta t > 0                                  */
+  double macro_dt;      /* projective step Delta t >= N_e dt (eq. 3.17)           */
+  double n_floor;       /* density below which a cell is empty at lift (> 0)     */
+  int64_t capacity;     /* particle slots reserved for this replica               */
+} efpi_replica;
+
+typedef struct {
+  uint32_t abi_version;              /* EFPI_ABI_VERSION                          */
+  uint32_t n_replicas;               /* R >= 1                                    */
+  const efpi_replica* replicas;      /* host array of R replicas, copied at init  */
+  int32_t newton_iters;              /* Newton iterations per fine step, >= 1     */
+  int32_t newton_iters_start;        /* iterations after a load, lift or set      */
+  double newton_tol;                 /* status threshold on max |last Newton update|;
+                                        convergence is quadratic, so the remaining
+                                        error is about its square                 */
+  int32_t tile;                      /* particles per work item: 0 (default) or a
+                                        multiple of 1024 up to 65536              */
+  int32_t grid_blocks;               /* persistent grid size, 0 = default         */
+  uint32_t flags;                    /* EFPI_FLAG_*                               */
+} efpi_config;
+
+/* Reserve a second particle store so that efpi_sort can reorder out of place. */
+#define EFPI_FLAG_SORT_BUFFER 1u
+
+typedef struct efpi_ctx efpi_ctx; /* opaque host object owned by the library */
+
+/* ---------------------------------------------------------------- set-up -- */
+
+/* Bytes of device workspace the configuration needs (synchronous, host only). */
+efpi_status efpi_workspace_size(const efpi_config* cfg, size_t* h_bytes);
+
+/* Validate cfg, bind the caller's workspace (>= efpi_workspace_size bytes,
+ * 256-byte aligned) and the caller's HIP stream (hipStream_t, may be NULL for
+ * the null stream), clear the workspace on that stream and return a context in
+ * *out.  The workspace must stay allocated until efpi_destroy. */
+efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes,
+                      void* hip_stream, efpi_ctx** out);
+
+/* Release the host context (the workspace stays the caller's). */
+void efpi_destroy(efpi_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+efpi_status efpi_set_stream(efpi_ctx* ctx, void* hip_stream);
+
+/* Number of Haar coarse coefficients per moment of replica r (host only). */
+efpi_status efpi_n_coarse(efpi_ctx* ctx, int32_t replica, int32_t* h_nc);
+
+/* ------------------------------------------------------- particle state -- */
+
+/* Copy n particles (int16 cell, FP32 frac, v, w) into replica r.  v is at an
+ * integer time level; the next burst starts the leapfrog from it.  Cells must
+ * lie in [0, N) or be -1; frac in [0, 1).  n <= capacity. */
+efpi_status efpi_set_particles(efpi_ctx* ctx, int32_t replica, const int16_t* d_cell,
+                               const float* d_frac, const float* d_v, const float* d_w,
+                               int64_t n);
+
+/* Copy replica r's particles out (any pointer may be NULL).  Synchronous: waits
+ * for the stream, then writes the particle count to *h_n.  Velocities are at
+ * the half step after a burst and at the integer step after a load or lift. */
+efpi_status efpi_get_particles(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, float* d_frac,
+                               float* d_v, float* d_w, int64_t* h_n);
+
+/* Copy replica r's last deposited fixed-point charge (int64, N or N+1 nodes,
+ * units 2^-40), potential (FP64) and node field (FP32).  Any pointer may be NULL. */
+efpi_status efpi_get_grid(efpi_ctx* ctx, int32_t replica, int64_t* d_q, double* d_phi,
+                          float* d_e);
+
+/* Set replica r's potential (warm start of the next Newton solve). */
+efpi_status efpi_set_potential(efpi_ctx* ctx, int32_t replica, const double* d_phi);
+
+/* ------------------------------------------------------------- hot path -- */
+
+/* Quiet-start load of replica r from fine node profiles of density d_n and mean
+ * velocity d_u (FP64, N or N+1 nodes): App. C particle loading with uniform
+ * in-cell offsets (m+1/2)/ppc, Maxwellian velocities by the inverse normal CDF at
+ * the Hammersley coordinate b_i = ((bitrev32(c ppc + m) + shift) mod 2^32 + 1/2)/2^32,
+ * and weights n(X) h / ppc.  Cells whose nodes are all below n_floor stay empty. */
+efpi_status efpi_load_profile(efpi_ctx* ctx, int32_t replica, const double* d_n,
+                              const double* d_u, uint32_t shift);
+
+/* Lifting operator (Sec. 3.3 "Lifting", App. C): for every replica, coarse
+ * coefficients d_coarse[r][2][N_c] (density, momentum; FP64) -> fine profile by
+ * inverse Haar (and linear interpolation of block means when lift_linear) ->
+ * quiet-start ions as in efpi_load_profile with rotation h_shifts[r] -> per
+ * coarse block, weights rescaled to the block mass and velocities shifted to
+ * the block momentum.  d_coarse must stay valid until the work has run. */
+efpi_status efpi_lift(efpi_ctx* ctx, const double* d_coarse, const uint32_t* h_shifts);
+
+/* Deposit the fixed-point CIC charge of the current particles (Sec. 2.2). */
+efpi_status efpi_deposit(efpi_ctx* ctx);
+
+/* Solve -phi'' + exp(phi) = rho (eq. 3.15) by `iters` Newton iterations from the
+ * current potential (cold != 0: from ln max(rho, 1e-8)), then set the node field
+ * E_k = -(phi_{k+1} - phi_{k-1}) / 2h.  Requires a deposit since the last state change. */
+efpi_status efpi_solve_field(efpi_ctx* ctx, int32_t iters, int32_t cold);
+
+/* Fine burst on every replica: `steps` leapfrog steps (gather, push, boundary,
+ * fixed-point deposit, Newton solve).  With restrict != 0 the burst starts by
+ * storing the field E_n and restricts after every step: snapshots p = 0..steps
+ * of the coarse (density, momentum) coefficients of the ions moved along the
+ * approximate characteristics over Delta t - p dt (App. B, eq. B.4; plain
+ * deposition when coevolving = 0).  steps <= burst_steps when restricting. */
+efpi_status efpi_pic_burst(efpi_ctx* ctx, int32_t steps, int32_t restrict_);
+
+/* Coarse snapshots of the last restricting burst: d_snap[r][p][2][N_c] (FP64)
+ * for p = 0..steps, c_B = 2^{-l/2} (block mass) / h. */
+efpi_status efpi_restrict(efpi_ctx* ctx, double* d_snap);
+
+/* Least-squares slope of eq. 3.18 over the snapshots d_snap[r][0..N_e][2][N_c]
+ * and forward-Euler projection over Delta t - N_e dt from the last snapshot
+ * (eq. 3.17) -> d_coarse_next[r][2][N_c].  d_snap may be the output of
+ * efpi_restrict; snapshots of every replica must hold burst_steps + 1 entries. */
+efpi_status efpi_project(efpi_ctx* ctx, const double* d_snap, double* d_coarse_next);
+
+/* One whole macro step for every replica: lift(d_coarse_in) -> restricting burst
+ * of burst_steps -> restrict -> project -> d_coarse_out.  d_coarse_in and
+ * d_coarse_out may alias. */
+efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_coarse_out,
+                            const uint32_t* h_shifts);
+
+/* Replace every replica's coarse state in d_coarse[r][2][N_c] by the mean over
+ * the replicas with the same n_cells and length (replica-index order). */
+efpi_status efpi_ensemble_mean(efpi_ctx* ctx, double* d_coarse);
+
+/* Stable per-tile counting sort of every replica's particles by cell; absorbed
+ * ions (cell -1) are dropped.  Needs EFPI_FLAG_SORT_BUFFER. */
+efpi_status efpi_sort(efpi_ctx* ctx);
+
+/* ---------------------------------------------------------------- status -- */
+
+/* Wait for the stream, return the device status bits in *h_bits (may be NULL)
+ * and clear them.  Returns EFPI_ENUMERIC / EFPI_ENEWTON / EFPI_EOVERFLOW when the
+ * matching bit was set (first in that order), else EFPI_OK. */
+efpi_status efpi_sync(efpi_ctx* ctx, uint32_t* h_bits);
+
+/* Message for the last failed call on this thread ("" when none). */
+const char* efpi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EFPI_H */

@@ -200,7 +200,7 @@ def linear_poisson(rho, grid: Grid):
 def solve_field(rho, grid: Grid, phi0=None):
     """Potential for the grid's closure."""
     if grid.closure == BOLTZMANN:
-        phi, _, ok = newton_poisson(rho, grid, phi0)
+        phi, _, ok = newton_poisson(rho, grid, phi0, max_iter=200)
         if not ok:
             raise RuntimeError("oracle Newton did not converge")
         return phi

@@ -1,0 +1,637 @@
+// Host side of libefpi: configuration checks, workspace layout and the
+// extern "C" entry points declared in include/efpi.h.  Every entry point only
+// enqueues kernels on the context's stream (except those documented as
+// synchronous); the library never allocates device memory.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/efpi.h"
+#include "efpi_internal.h"
+
+using namespace efpi;
+
+namespace {
+
+thread_local std::string g_err;
+
+efpi_status fail(efpi_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << (l + 1)) <= x) ++l;
+  return l;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kDefaultTile = 4096;
+constexpr int kDefaultGrid = 2048;
+
+struct NewtonGroup {
+  int M = 1;
+  int threads = 64;
+  int first = 0;  // offset into the list array
+  int count = 0;
+};
+
+}  // namespace
+
+struct efpi_ctx {
+  efpi_config cfg{};
+  std::vector<efpi_replica> reps;
+  hipStream_t stream = nullptr;
+  uint8_t* ws = nullptr;
+  size_t ws_bytes = 0;
+  int R = 0;
+  int tile = kDefaultTile;
+  int grid_blocks = kDefaultGrid;
+  std::vector<RepDev> h_reps;
+  RepDev* d_reps = nullptr;
+  uint32_t* d_status = nullptr;
+  int64_t* d_item_prefix = nullptr;
+  int64_t* d_block_prefix = nullptr;
+  int64_t* d_snap_off = nullptr;
+  int64_t* d_coarse_off = nullptr;
+  int32_t* d_group = nullptr;
+  int32_t* d_newton_list = nullptr;
+  double* d_snap = nullptr;
+  double* d_coarse = nullptr;
+  int32_t* d_sort_hist = nullptr;
+  std::vector<int64_t> h_item_prefix, h_block_prefix, h_snap_off, h_coarse_off;
+  std::vector<int32_t> h_group, h_newton_list;
+  std::vector<NewtonGroup> ngroups;
+  int64_t total_items = 0, total_blocks = 0, snap_total = 0, coarse_total = 0;
+  // state
+  int cur = 0;             // q buffer holding the latest deposit
+  bool other_zero = true;  // q[cur ^ 1] is known to be zero
+  bool deposited = false;  // charge matches the current particles
+  bool field_valid = false;
+  bool fresh = true;       // velocities at an integer time level
+  int last_burst_steps = -1;
+};
+
+namespace {
+
+efpi_status check_config(const efpi_config* cfg) {
+  if (!cfg) return fail(EFPI_EINVAL, "config is NULL");
+  if (cfg->abi_version != EFPI_ABI_VERSION) return fail(EFPI_EINVAL, "abi_version mismatch");
+  if (cfg->n_replicas < 1 || cfg->n_replicas > (uint32_t)kMaxShiftReplicas)
+    return fail(EFPI_EINVAL, "n_replicas must be in [1, 256]");
+  if (!cfg->replicas) return fail(EFPI_EINVAL, "replicas is NULL");
+  if (cfg->newton_iters < 1 || cfg->newton_iters_start < 1)
+    return fail(EFPI_EINVAL, "newton iteration counts must be >= 1");
+  if (!(cfg->newton_tol > 0.0)) return fail(EFPI_EINVAL, "newton_tol must be > 0");
+  if (cfg->tile != 0 && (cfg->tile % 1024 != 0 || cfg->tile < 1024 || cfg->tile > 65536))
+    return fail(EFPI_EINVAL, "tile must be 0 or a multiple of 1024 in [1024, 65536]");
+  if (cfg->grid_blocks < 0) return fail(EFPI_EINVAL, "grid_blocks must be >= 0");
+  for (uint32_t r = 0; r < cfg->n_replicas; ++r) {
+    const efpi_replica& p = cfg->replicas[r];
+    char buf[160];
+    auto bad = [&](const char* what) {
+      std::snprintf(buf, sizeof buf, "replica %u: %s", r, what);
+      return fail(EFPI_EINVAL, buf);
+    };
+    if (!is_pow2(p.n_cells) || p.n_cells < 8 || p.n_cells > 16384)
+      return bad("n_cells must be a power of two in [8, 16384]");
+    if (p.bc != EFPI_BC_PERIODIC && p.bc != EFPI_BC_WALLS) return bad("unknown bc");
+    if (p.closure != EFPI_CLOSURE_BOLTZMANN && p.closure != EFPI_CLOSURE_NOFIELD)
+      return bad("unsupported closure");
+    if (p.ppc < 1) return bad("ppc must be >= 1");
+    if ((int64_t)p.n_cells * p.ppc > (int64_t(1) << 32))
+      return bad("n_cells * ppc must fit in 32 bits (Hammersley index)");
+    if (p.haar_levels < 0 || p.haar_levels > ilog2(p.n_cells)) return bad("haar_levels out of range");
+    if (p.burst_steps < 1) return bad("burst_steps must be >= 1");
+    if (!(p.length > 0.0) || !std::isfinite(p.length)) return bad("length must be > 0");
+    if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return bad("dt must be > 0");
+    if (!(p.macro_dt >= p.burst_steps * p.dt * (1.0 - 1e-12)) || !std::isfinite(p.macro_dt))
+      return bad("macro_dt must be >= burst_steps * dt");
+    if (!(p.vth >= 0.0) || !std::isfinite(p.vth)) return bad("vth must be >= 0");
+    if (!(p.n_floor > 0.0)) return bad("n_floor must be > 0");
+    if (p.capacity < 1 || p.capacity > (int64_t(1) << 31)) return bad("capacity must be in [1, 2^31]");
+  }
+  return EFPI_OK;
+}
+
+// Lay the workspace out; with ctx != nullptr also fill the descriptors.
+size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return base ? base + o : nullptr;
+  };
+  const int R = (int)cfg->n_replicas;
+  uint8_t* p_status = take(sizeof(uint32_t));
+  uint8_t* p_reps = take(sizeof(RepDev) * R);
+  uint8_t* p_items = take(sizeof(int64_t) * (R + 1));
+  uint8_t* p_blocks = take(sizeof(int64_t) * (R + 1));
+  uint8_t* p_soff = take(sizeof(int64_t) * R);
+  uint8_t* p_coff = take(sizeof(int64_t) * R);
+  uint8_t* p_group = take(sizeof(int32_t) * R);
+  uint8_t* p_nlist = take(sizeof(int32_t) * R);
+  int64_t snap_total = 0, coarse_total = 0;
+  for (int r = 0; r < R; ++r) {
+    const efpi_replica& p = cfg->replicas[r];
+    const int nc = p.n_cells >> p.haar_levels;
+    snap_total += (int64_t)(p.burst_steps + 1) * 2 * nc;
+    coarse_total += 2 * nc;
+  }
+  uint8_t* p_snap = take(sizeof(double) * snap_total);
+  uint8_t* p_coarse = take(sizeof(double) * coarse_total);
+  uint8_t* p_hist = nullptr;
+  if (cfg->flags & EFPI_FLAG_SORT_BUFFER) {
+    const int tile = cfg->tile > 0 ? cfg->tile : kDefaultTile;
+    int64_t items = 0;
+    for (int r = 0; r < R; ++r) items += (cfg->replicas[r].capacity + tile - 1) / tile;
+    p_hist = take(sizeof(int32_t) * 256 * items);
+  }
+  if (ctx) {
+    ctx->d_status = reinterpret_cast<uint32_t*>(p_status);
+    ctx->d_reps = reinterpret_cast<RepDev*>(p_reps);
+    ctx->d_item_prefix = reinterpret_cast<int64_t*>(p_items);
+    ctx->d_block_prefix = reinterpret_cast<int64_t*>(p_blocks);
+    ctx->d_snap_off = reinterpret_cast<int64_t*>(p_soff);
+    ctx->d_coarse_off = reinterpret_cast<int64_t*>(p_coff);
+    ctx->d_group = reinterpret_cast<int32_t*>(p_group);
+    ctx->d_newton_list = reinterpret_cast<int32_t*>(p_nlist);
+    ctx->d_snap = reinterpret_cast<double*>(p_snap);
+    ctx->d_coarse = reinterpret_cast<double*>(p_coarse);
+    ctx->d_sort_hist = reinterpret_cast<int32_t*>(p_hist);
+    ctx->snap_total = snap_total;
+    ctx->coarse_total = coarse_total;
+    ctx->h_reps.assign(R, RepDev{});
+  }
+  int64_t soff = 0, coff = 0;
+  const bool sortbuf = (cfg->flags & EFPI_FLAG_SORT_BUFFER) != 0;
+  for (int r = 0; r < R; ++r) {
+    const efpi_replica& p = cfg->replicas[r];
+    const int n = p.n_cells;
+    const int nn = p.bc == EFPI_BC_PERIODIC ? n : n + 1;
+    const int nc = n >> p.haar_levels;
+    const int64_t cap = p.capacity;
+    uint8_t* cell = take(sizeof(int16_t) * cap);
+    uint8_t* frac = take(sizeof(float) * cap);
+    uint8_t* v = take(sizeof(float) * cap);
+    uint8_t* w = take(sizeof(float) * cap);
+    uint8_t *cell2 = nullptr, *frac2 = nullptr, *v2 = nullptr, *w2 = nullptr;
+    if (sortbuf) {
+      cell2 = take(sizeof(int16_t) * cap);
+      frac2 = take(sizeof(float) * cap);
+      v2 = take(sizeof(float) * cap);
+      w2 = take(sizeof(float) * cap);
+    }
+    uint8_t* np = take(sizeof(int64_t));
+    uint8_t* q0 = take(sizeof(int64_t) * (nn + 1));
+    uint8_t* q1 = take(sizeof(int64_t) * (nn + 1));
+    uint8_t* phi = take(sizeof(double) * (nn + 1));
+    uint8_t* e = take(sizeof(float) * (nn + 1));
+    uint8_t* en = take(sizeof(float) * (nn + 1));
+    uint8_t* rb = take(sizeof(int64_t) * (int64_t)(p.burst_steps + 1) * 2 * nc);
+    uint8_t* pn = take(sizeof(double) * (nn + 1));
+    uint8_t* pu = take(sizeof(double) * (nn + 1));
+    uint8_t* cor = take(sizeof(int32_t) * n);
+    uint8_t* br = take(sizeof(int32_t) * (nc + 1));
+    uint8_t* aux = take(sizeof(int64_t) * 4);
+    if (ctx) {
+      RepDev& d = ctx->h_reps[r];
+      d.n_cells = n;
+      d.n_nodes = nn;
+      d.bc = p.bc;
+      d.closure = p.closure;
+      d.ppc = p.ppc;
+      d.levels = p.haar_levels;
+      d.n_coarse = nc;
+      d.burst_steps = p.burst_steps;
+      d.coevolving = p.coevolving;
+      d.lift_linear = p.lift_linear;
+      d.log2n = ilog2(n);
+      d.h = p.length / n;
+      d.inv_h = n / p.length;
+      d.length = p.length;
+      d.vth = p.vth;
+      d.dt = p.dt;
+      d.macro_dt = p.macro_dt;
+      d.n_floor = p.n_floor;
+      d.capacity = cap;
+      d.cell = reinterpret_cast<int16_t*>(cell);
+      d.frac = reinterpret_cast<float*>(frac);
+      d.v = reinterpret_cast<float*>(v);
+      d.w = reinterpret_cast<float*>(w);
+      d.cell2 = reinterpret_cast<int16_t*>(cell2);
+      d.frac2 = reinterpret_cast<float*>(frac2);
+      d.v2 = reinterpret_cast<float*>(v2);
+      d.w2 = reinterpret_cast<float*>(w2);
+      d.np = reinterpret_cast<int64_t*>(np);
+      d.q[0] = reinterpret_cast<int64_t*>(q0);
+      d.q[1] = reinterpret_cast<int64_t*>(q1);
+      d.phi = reinterpret_cast<double*>(phi);
+      d.e = reinterpret_cast<float*>(e);
+      d.en = reinterpret_cast<float*>(en);
+      d.rbins = reinterpret_cast<int64_t*>(rb);
+      d.snap = ctx->d_snap + soff;
+      d.coarse_tmp = ctx->d_coarse + coff;
+      d.prof_n = reinterpret_cast<double*>(pn);
+      d.prof_u = reinterpret_cast<double*>(pu);
+      d.cell_of_rank = reinterpret_cast<int32_t*>(cor);
+      d.block_rank = reinterpret_cast<int32_t*>(br);
+      d.aux = reinterpret_cast<int64_t*>(aux);
+    }
+    soff += (int64_t)(p.burst_steps + 1) * 2 * nc;
+    coff += 2 * nc;
+  }
+  return off;
+}
+
+efpi_status hip_check(const char* where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(EFPI_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+  return EFPI_OK;
+}
+
+efpi_status check_ctx(efpi_ctx* ctx) {
+  if (!ctx) return fail(EFPI_EINVAL, "context is NULL");
+  return EFPI_OK;
+}
+
+efpi_status check_rep(efpi_ctx* ctx, int32_t r) {
+  if (!ctx) return fail(EFPI_EINVAL, "context is NULL");
+  if (r < 0 || r >= ctx->R) return fail(EFPI_EINVAL, "replica index out of range");
+  return EFPI_OK;
+}
+
+void deposit_into_next(efpi_ctx* c) {
+  const int nxt = c->cur ^ 1;
+  if (!c->other_zero) {
+    for (int r = 0; r < c->R; ++r)
+      launch_fill_u8(c->h_reps[r].q[nxt], sizeof(int64_t) * c->h_reps[r].n_nodes, c->stream);
+  }
+}
+
+void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
+  for (const NewtonGroup& g : c->ngroups)
+    launch_newton(c->d_reps, c->d_newton_list + g.first, g.count, g.M, g.threads, iters, cold,
+                  c->cur, save_en, zero_bins, c->cfg.newton_tol, c->d_status, c->stream);
+  c->other_zero = true;
+  c->field_valid = true;
+}
+
+void mark_new_particles(efpi_ctx* c) {
+  c->fresh = true;
+  c->field_valid = false;
+  c->deposited = false;
+}
+
+ShiftArg shifts_of(const efpi_ctx* c, const uint32_t* h_shifts) {
+  ShiftArg s;
+  std::memset(&s, 0, sizeof s);
+  for (int r = 0; r < c->R; ++r) s.s[r] = h_shifts ? h_shifts[r] : 0u;
+  return s;
+}
+
+efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shifts) {
+  launch_profile(c->d_reps, c->R, d_coarse, c->d_coarse_off, c->stream);
+  launch_occupancy(c->d_reps, c->R, -1, c->d_status, c->stream);
+  launch_lift_particles(c->d_reps, c->d_block_prefix, c->R, c->total_blocks, -1, d_coarse,
+                        c->d_coarse_off, shifts_of(c, h_shifts), c->grid_blocks, c->stream);
+  mark_new_particles(c);
+  return hip_check("lift");
+}
+
+efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
+  if (!c->field_valid) {
+    if (!c->deposited) {
+      deposit_into_next(c);
+      launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks,
+                       0, kDepositOnly, c->cur ^ 1, c->stream);
+      c->cur ^= 1;
+      c->other_zero = false;
+      c->deposited = true;
+    }
+    run_newton(c, c->cfg.newton_iters_start, 0, restrict_ ? 1 : 0, restrict_ ? 1 : 0);
+  } else if (restrict_) {
+    launch_prep_burst(c->d_reps, c->R, c->stream);
+  }
+  const int passes = restrict_ ? steps + 1 : steps;
+  for (int p = 0; p < passes; ++p) {
+    const bool push = p < steps;
+    int flags = 0;
+    if (p == 0 && c->fresh) flags |= kFresh;
+    if (restrict_) flags |= kRestrict;
+    if (push) {
+      flags |= kPush;
+      deposit_into_next(c);
+    }
+    launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, p,
+                     flags, c->cur ^ 1, c->stream);
+    if (push) {
+      c->cur ^= 1;
+      c->other_zero = false;
+      c->fresh = false;
+      run_newton(c, c->cfg.newton_iters, 0, 0, 0);
+    }
+  }
+  if (steps > 0) c->fresh = false;
+  if (restrict_) c->last_burst_steps = steps;
+  return hip_check("pic_burst");
+}
+
+}  // namespace
+
+extern "C" {
+
+efpi_status efpi_workspace_size(const efpi_config* cfg, size_t* h_bytes) {
+  const efpi_status st = check_config(cfg);
+  if (st != EFPI_OK) return st;
+  if (!h_bytes) return fail(EFPI_EINVAL, "h_bytes is NULL");
+  *h_bytes = layout(cfg, nullptr, nullptr);
+  return EFPI_OK;
+}
+
+efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                      efpi_ctx** out) {
+  efpi_status st = check_config(cfg);
+  if (st != EFPI_OK) return st;
+  if (!out) return fail(EFPI_EINVAL, "out is NULL");
+  if (!d_workspace) return fail(EFPI_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(EFPI_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = layout(cfg, nullptr, nullptr);
+  if (bytes < need) return fail(EFPI_ENOMEM, "workspace smaller than efpi_workspace_size");
+  efpi_ctx* c = new efpi_ctx();
+  c->cfg = *cfg;
+  c->R = (int)cfg->n_replicas;
+  c->reps.assign(cfg->replicas, cfg->replicas + c->R);
+  c->cfg.replicas = c->reps.data();
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<uint8_t*>(d_workspace);
+  c->ws_bytes = bytes;
+  c->tile = cfg->tile > 0 ? cfg->tile : kDefaultTile;
+  layout(&c->cfg, c, c->ws);
+  // work items
+  c->h_item_prefix.assign(c->R + 1, 0);
+  c->h_block_prefix.assign(c->R + 1, 0);
+  c->h_snap_off.assign(c->R, 0);
+  c->h_coarse_off.assign(c->R, 0);
+  int64_t so = 0, co = 0;
+  for (int r = 0; r < c->R; ++r) {
+    RepDev& d = c->h_reps[r];
+    d.item_begin = c->h_item_prefix[r];
+    d.block_begin = c->h_block_prefix[r];
+    c->h_item_prefix[r + 1] = c->h_item_prefix[r] + (d.capacity + c->tile - 1) / c->tile;
+    c->h_block_prefix[r + 1] = c->h_block_prefix[r] + d.n_coarse;
+    c->h_snap_off[r] = so;
+    c->h_coarse_off[r] = co;
+    so += (int64_t)(d.burst_steps + 1) * 2 * d.n_coarse;
+    co += 2 * d.n_coarse;
+  }
+  c->total_items = c->h_item_prefix[c->R];
+  c->total_blocks = c->h_block_prefix[c->R];
+  c->grid_blocks = cfg->grid_blocks > 0 ? cfg->grid_blocks : kDefaultGrid;
+  // ensemble groups: replicas with equal (n_cells, length) share the first one's index
+  c->h_group.assign(c->R, 0);
+  for (int r = 0; r < c->R; ++r) {
+    c->h_group[r] = r;
+    for (int q = 0; q < r; ++q)
+      if (c->reps[q].n_cells == c->reps[r].n_cells && c->reps[q].length == c->reps[r].length) {
+        c->h_group[r] = c->h_group[q];
+        break;
+      }
+  }
+  // Newton launch groups by rows per thread M (N <= 1024: M = 1; else N / 1024)
+  std::vector<int> ms = {1, 2, 4, 8, 16};
+  c->h_newton_list.clear();
+  for (int M : ms) {
+    NewtonGroup g;
+    g.M = M;
+    g.first = (int)c->h_newton_list.size();
+    int maxT = 0;
+    for (int r = 0; r < c->R; ++r) {
+      const int n = c->reps[r].n_cells;
+      const int m = n <= 1024 ? 1 : n / 1024;
+      if (m == M) {
+        c->h_newton_list.push_back(r);
+        maxT = std::max(maxT, n / m);
+      }
+    }
+    g.count = (int)c->h_newton_list.size() - g.first;
+    g.threads = std::max(64, (maxT + 63) / 64 * 64);
+    if (g.count > 0) c->ngroups.push_back(g);
+  }
+  // clear the workspace, then upload descriptors and tables
+  launch_fill_u8(c->ws, need, c->stream);
+  hipMemcpyAsync(c->d_reps, c->h_reps.data(), sizeof(RepDev) * c->R, hipMemcpyHostToDevice, c->stream);
+  hipMemcpyAsync(c->d_item_prefix, c->h_item_prefix.data(), sizeof(int64_t) * (c->R + 1),
+                 hipMemcpyHostToDevice, c->stream);
+  hipMemcpyAsync(c->d_block_prefix, c->h_block_prefix.data(), sizeof(int64_t) * (c->R + 1),
+                 hipMemcpyHostToDevice, c->stream);
+  hipMemcpyAsync(c->d_snap_off, c->h_snap_off.data(), sizeof(int64_t) * c->R, hipMemcpyHostToDevice,
+                 c->stream);
+  hipMemcpyAsync(c->d_coarse_off, c->h_coarse_off.data(), sizeof(int64_t) * c->R,
+                 hipMemcpyHostToDevice, c->stream);
+  hipMemcpyAsync(c->d_group, c->h_group.data(), sizeof(int32_t) * c->R, hipMemcpyHostToDevice,
+                 c->stream);
+  hipMemcpyAsync(c->d_newton_list, c->h_newton_list.data(), sizeof(int32_t) * c->R,
+                 hipMemcpyHostToDevice, c->stream);
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(EFPI_EHIP, std::string("init: ") + hipGetErrorString(e));
+  }
+  st = hip_check("init");
+  if (st != EFPI_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return EFPI_OK;
+}
+
+void efpi_destroy(efpi_ctx* ctx) { delete ctx; }
+
+efpi_status efpi_set_stream(efpi_ctx* ctx, void* hip_stream) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return EFPI_OK;
+}
+
+efpi_status efpi_n_coarse(efpi_ctx* ctx, int32_t replica, int32_t* h_nc) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (!h_nc) return fail(EFPI_EINVAL, "h_nc is NULL");
+  *h_nc = ctx->h_reps[replica].n_coarse;
+  return EFPI_OK;
+}
+
+efpi_status efpi_set_particles(efpi_ctx* ctx, int32_t replica, const int16_t* d_cell,
+                               const float* d_frac, const float* d_v, const float* d_w, int64_t n) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (n < 0 || n > ctx->h_reps[replica].capacity) return fail(EFPI_EINVAL, "n out of [0, capacity]");
+  if (n > 0 && (!d_cell || !d_frac || !d_v || !d_w)) return fail(EFPI_EINVAL, "NULL particle array");
+  launch_copy_particles(ctx->d_reps, replica, d_cell, d_frac, d_v, d_w, n, 1, nullptr, nullptr,
+                        nullptr, nullptr, ctx->stream);
+  mark_new_particles(ctx);
+  return hip_check("set_particles");
+}
+
+efpi_status efpi_get_particles(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, float* d_frac,
+                               float* d_v, float* d_w, int64_t* h_n) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  const RepDev& d = ctx->h_reps[replica];
+  launch_copy_particles(ctx->d_reps, replica, nullptr, nullptr, nullptr, nullptr, d.capacity, 0,
+                        d_cell, d_frac, d_v, d_w, ctx->stream);
+  int64_t n = 0;
+  hipMemcpyAsync(&n, d.np, sizeof n, hipMemcpyDeviceToHost, ctx->stream);
+  const hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(EFPI_EHIP, std::string("get_particles: ") + hipGetErrorString(e));
+  if (h_n) *h_n = n;
+  return hip_check("get_particles");
+}
+
+efpi_status efpi_get_grid(efpi_ctx* ctx, int32_t replica, int64_t* d_q, double* d_phi, float* d_e) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  const RepDev& d = ctx->h_reps[replica];
+  if (d_q) hipMemcpyAsync(d_q, d.q[ctx->cur], sizeof(int64_t) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (d_phi) hipMemcpyAsync(d_phi, d.phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (d_e) hipMemcpyAsync(d_e, d.e, sizeof(float) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
+  return hip_check("get_grid");
+}
+
+efpi_status efpi_set_potential(efpi_ctx* ctx, int32_t replica, const double* d_phi) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_phi) return fail(EFPI_EINVAL, "d_phi is NULL");
+  const RepDev& d = ctx->h_reps[replica];
+  hipMemcpyAsync(d.phi, d_phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
+  ctx->field_valid = false;
+  return hip_check("set_potential");
+}
+
+efpi_status efpi_load_profile(efpi_ctx* ctx, int32_t replica, const double* d_n, const double* d_u,
+                              uint32_t shift) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_n || !d_u) return fail(EFPI_EINVAL, "NULL profile");
+  launch_set_profile(ctx->d_reps, replica, d_n, d_u, ctx->stream);
+  launch_occupancy(ctx->d_reps, ctx->R, replica, ctx->d_status, ctx->stream);
+  ShiftArg s;
+  std::memset(&s, 0, sizeof s);
+  s.s[replica] = shift;
+  launch_lift_particles(ctx->d_reps, ctx->d_block_prefix, ctx->R, ctx->h_reps[replica].n_coarse,
+                        replica, nullptr, ctx->d_coarse_off, s, ctx->grid_blocks, ctx->stream);
+  mark_new_particles(ctx);
+  return hip_check("load_profile");
+}
+
+efpi_status efpi_lift(efpi_ctx* ctx, const double* d_coarse, const uint32_t* h_shifts) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_coarse) return fail(EFPI_EINVAL, "d_coarse is NULL");
+  if (!h_shifts) return fail(EFPI_EINVAL, "h_shifts is NULL");
+  return do_lift(ctx, d_coarse, h_shifts);
+}
+
+efpi_status efpi_deposit(efpi_ctx* ctx) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  deposit_into_next(ctx);
+  launch_particles(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
+                   ctx->grid_blocks, 0, kDepositOnly, ctx->cur ^ 1, ctx->stream);
+  ctx->cur ^= 1;
+  ctx->other_zero = false;
+  ctx->deposited = true;
+  return hip_check("deposit");
+}
+
+efpi_status efpi_solve_field(efpi_ctx* ctx, int32_t iters, int32_t cold) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (iters < 1 || iters > 1000) return fail(EFPI_EINVAL, "iters must be in [1, 1000]");
+  if (!ctx->deposited) return fail(EFPI_ESTATE, "solve_field needs a deposit of the current particles");
+  run_newton(ctx, iters, cold ? 1 : 0, 0, 0);
+  return hip_check("solve_field");
+}
+
+efpi_status efpi_pic_burst(efpi_ctx* ctx, int32_t steps, int32_t restrict_) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (steps < 0) return fail(EFPI_EINVAL, "steps must be >= 0");
+  if (restrict_) {
+    for (int r = 0; r < ctx->R; ++r)
+      if (steps > ctx->h_reps[r].burst_steps)
+        return fail(EFPI_EINVAL, "restricting burst longer than burst_steps");
+  }
+  return do_burst(ctx, steps, restrict_ != 0);
+}
+
+efpi_status efpi_restrict(efpi_ctx* ctx, double* d_snap) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_snap) return fail(EFPI_EINVAL, "d_snap is NULL");
+  if (ctx->last_burst_steps < 0) return fail(EFPI_ESTATE, "no restricting burst has run");
+  launch_restrict(ctx->d_reps, ctx->R, ctx->last_burst_steps, d_snap, ctx->d_snap_off, ctx->stream);
+  return hip_check("restrict");
+}
+
+efpi_status efpi_project(efpi_ctx* ctx, const double* d_snap, double* d_coarse_next) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_snap || !d_coarse_next) return fail(EFPI_EINVAL, "NULL array");
+  launch_project(ctx->d_reps, ctx->R, d_snap, ctx->d_snap_off, d_coarse_next, ctx->d_coarse_off,
+                 ctx->d_status, ctx->stream);
+  return hip_check("project");
+}
+
+efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_coarse_out,
+                            const uint32_t* h_shifts) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_coarse_in || !d_coarse_out || !h_shifts) return fail(EFPI_EINVAL, "NULL argument");
+  int k = ctx->h_reps[0].burst_steps;
+  for (int r = 1; r < ctx->R; ++r)
+    if (ctx->h_reps[r].burst_steps != k)
+      return fail(EFPI_EINVAL, "macro_step needs equal burst_steps in every replica");
+  efpi_status st = do_lift(ctx, d_coarse_in, h_shifts);
+  if (st != EFPI_OK) return st;
+  st = do_burst(ctx, k, true);
+  if (st != EFPI_OK) return st;
+  launch_restrict(ctx->d_reps, ctx->R, k, ctx->d_snap, ctx->d_snap_off, ctx->stream);
+  launch_project(ctx->d_reps, ctx->R, ctx->d_snap, ctx->d_snap_off, d_coarse_out, ctx->d_coarse_off,
+                 ctx->d_status, ctx->stream);
+  return hip_check("macro_step");
+}
+
+efpi_status efpi_ensemble_mean(efpi_ctx* ctx, double* d_coarse) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_coarse) return fail(EFPI_EINVAL, "d_coarse is NULL");
+  launch_ensemble_mean(ctx->d_reps, ctx->R, ctx->d_group, d_coarse, ctx->d_coarse_off, ctx->stream);
+  return hip_check("ensemble_mean");
+}
+
+efpi_status efpi_sort(efpi_ctx* ctx) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!(ctx->cfg.flags & EFPI_FLAG_SORT_BUFFER))
+    return fail(EFPI_ESTATE, "efpi_sort needs EFPI_FLAG_SORT_BUFFER at init");
+  launch_sort(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
+              ctx->d_sort_hist, ctx->grid_blocks, ctx->stream);
+  return hip_check("sort");
+}
+
+efpi_status efpi_sync(efpi_ctx* ctx, uint32_t* h_bits) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  uint32_t bits = 0;
+  hipError_t e = hipMemcpyAsync(&bits, ctx->d_status, sizeof bits, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(EFPI_EHIP, std::string("sync: ") + hipGetErrorString(e));
+  launch_fill_u8(ctx->d_status, sizeof(uint32_t), ctx->stream);
+  e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(EFPI_EHIP, std::string("sync: ") + hipGetErrorString(e));
+  if (h_bits) *h_bits = bits;
+  if (bits & EFPI_DEV_NAN) return fail(EFPI_ENUMERIC, "non-finite potential or coarse value");
+  if (bits & EFPI_DEV_NEWTON) return fail(EFPI_ENEWTON, "Newton iteration above tolerance");
+  if (bits & EFPI_DEV_OVERFLOW) return fail(EFPI_EOVERFLOW, "particle capacity exceeded at lift");
+  g_err.clear();
+  return EFPI_OK;
+}
+
+const char* efpi_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

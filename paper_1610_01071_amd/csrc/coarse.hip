@@ -1,0 +1,335 @@
+// Coarse side of the projective cycle: lifting (Sec. 3.3 "Lifting", App. C
+// particle loading), conversion of the restriction bins to Haar coefficients,
+// least-squares projection (eqs. 3.17-3.18) and ensemble means.
+#include "efpi_internal.h"
+
+namespace efpi {
+namespace {
+
+constexpr int kLiftThreads = 256;
+constexpr int kProfThreads = 1024;
+
+// Inverse standard normal CDF, sqrt(2) erfinv(2b - 1).  The Hammersley
+// coordinates are b = (u + 1/2) 2^-32 with integer u, so 2b - 1 is exact in
+// binary64 and no precision is lost in either tail.  Kept out of line so that
+// the polynomial constants are not hoisted into registers across the caller loops.
+__device__ __attribute__((noinline)) double inv_normal(double b) {
+  return 1.4142135623730951 * erfinv(2.0 * b - 1.0);
+}
+
+// ---------------------------------------------------------------- profile --
+// Fine node density and mean velocity from the coarse coefficients: inverse
+// Haar with zero details (block means 2^{-l/2} c_B), optionally linearly
+// interpolated between block centres (periodic wrap; constant past the end
+// centres on walls).
+__global__ __launch_bounds__(kProfThreads) void k_profile(const RepDev* __restrict__ reps,
+                                                          const double* __restrict__ coarse,
+                                                          const int64_t* __restrict__ coff) {
+  const RepDev& R = reps[blockIdx.x];
+  const double* cn = coarse + coff[blockIdx.x];
+  const double* cj = cn + R.n_coarse;
+  const int nc = R.n_coarse;
+  const int bs = 1 << R.levels;
+  const double inv_s = 1.0 / sqrt((double)bs);
+  const bool periodic = R.bc == 0;
+  for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) {
+    double dn, dj;
+    if (!R.lift_linear) {
+      const int B = min(k >> R.levels, nc - 1);
+      dn = cn[B] * inv_s;
+      dj = cj[B] * inv_s;
+    } else {
+      const double u = ((double)k - 0.5 * (bs - 1)) / (double)bs;
+      const double fb = floor(u);
+      int b0 = (int)fb;
+      const double th = u - fb;
+      int b1 = b0 + 1;
+      double w0 = 1.0 - th, w1 = th;
+      if (periodic) {
+        b0 = (b0 % nc + nc) % nc;
+        b1 = (b1 % nc + nc) % nc;
+      } else {
+        if (b0 < 0) { b0 = 0; b1 = 0; w0 = 1.0; w1 = 0.0; }
+        if (b1 > nc - 1) { b0 = nc - 1; b1 = nc - 1; w0 = 1.0; w1 = 0.0; }
+      }
+      dn = (w0 * cn[b0] + w1 * cn[b1]) * inv_s;
+      dj = (w0 * cj[b0] + w1 * cj[b1]) * inv_s;
+    }
+    const double nn = fmax(dn, 0.0);
+    R.prof_n[k] = nn;
+    R.prof_u[k] = nn > R.n_floor ? dj / nn : 0.0;
+  }
+}
+
+// -------------------------------------------------------------- occupancy --
+// A cell is occupied when one of its nodes exceeds n_floor.  Exclusive scan of
+// occupied cells gives each cell's rank; the lift puts ppc ions per rank.
+__global__ __launch_bounds__(kProfThreads) void k_occupancy(const RepDev* __restrict__ reps,
+                                                            int only_rep,
+                                                            uint32_t* __restrict__ status) {
+  __shared__ int s_part[kProfThreads];
+  const int rep = only_rep >= 0 ? only_rep : (int)blockIdx.x;
+  const RepDev& R = reps[rep];
+  const int n = R.n_cells;
+  const int t = threadIdx.x;
+  const int per = (n + kProfThreads - 1) / kProfThreads;
+  const int c0 = t * per;
+  const bool periodic = R.bc == 0;
+  int cnt = 0;
+  for (int c = c0; c < min(c0 + per, n); ++c) {
+    const int cr = periodic ? ((c + 1) & (n - 1)) : c + 1;
+    cnt += fmax(R.prof_n[c], R.prof_n[cr]) > R.n_floor ? 1 : 0;
+  }
+  s_part[t] = cnt;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of the per-thread counts
+  for (int off = 1; off < kProfThreads; off <<= 1) {
+    const int add = t >= off ? s_part[t - off] : 0;
+    __syncthreads();
+    s_part[t] += add;
+    __syncthreads();
+  }
+  const int64_t max_cells = R.capacity / R.ppc;
+  int rank = t > 0 ? s_part[t - 1] : 0;
+  const int lmask = (1 << R.levels) - 1;
+  for (int c = c0; c < min(c0 + per, n); ++c) {
+    const int cr = periodic ? ((c + 1) & (n - 1)) : c + 1;
+    const bool occ = fmax(R.prof_n[c], R.prof_n[cr]) > R.n_floor;
+    if ((c & lmask) == 0) R.block_rank[c >> R.levels] = (int32_t)min((int64_t)rank, max_cells);
+    if (occ) {
+      if (rank < max_cells) R.cell_of_rank[rank] = c;
+      ++rank;
+    }
+  }
+  if (t == kProfThreads - 1) {
+    const int64_t total = s_part[kProfThreads - 1];
+    const int64_t kept = min(total, max_cells);
+    R.block_rank[R.n_coarse] = (int32_t)kept;
+    *R.np = kept * R.ppc;
+    if (total > max_cells) atomicOr(status, 4u);
+  }
+}
+
+// ---------------------------------------------------------- lift particles --
+struct Gen {
+  int cell;
+  float frac;
+  double v, w;
+};
+
+__device__ __forceinline__ Gen generate(const RepDev& R, int rank, int m, uint32_t shift) {
+  Gen g;
+  const int c = R.cell_of_rank[rank];
+  const int ppc = R.ppc;
+  g.cell = c;
+  g.frac = (float)(((double)m + 0.5) / (double)ppc);
+  const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
+  const uint32_t u = __brev(idx) + shift;
+  const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
+  const double th = (double)g.frac;
+  const int cr = R.bc == 0 ? ((c + 1) & (R.n_cells - 1)) : c + 1;
+  const double nx = (1.0 - th) * R.prof_n[c] + th * R.prof_n[cr];
+  const double ux = (1.0 - th) * R.prof_u[c] + th * R.prof_u[cr];
+  g.v = ux + R.vth * inv_normal(b);
+  g.w = nx * R.h / (double)ppc;
+  return g;
+}
+
+__device__ double block_sum(double x, double* s_red) {
+  // fixed-order tree: waves by shuffles, then the wave totals in index order
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[wid] = x;
+  __syncthreads();
+  double tot = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += s_red[k];
+  return tot;
+}
+
+__device__ __forceinline__ int find_rep(const int64_t* prefix, int n, int64_t item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One work item per (replica, coarse block): generate the block's ions, and
+// with coarse targets rescale weights to the block mass h 2^{l/2} max(c^n_B, 0)
+// and shift velocities to the block momentum h 2^{l/2} c^j_B.
+__global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict__ reps,
+                                                       const int64_t* __restrict__ block_prefix,
+                                                       int n_reps, int64_t total, int only_rep,
+                                                       const double* __restrict__ coarse,
+                                                       const int64_t* __restrict__ coff) {
+  __shared__ double s_red[kLiftThreads / 64];
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int r = only_rep >= 0 ? only_rep : find_rep(block_prefix, n_reps, item);
+    const RepDev& R = reps[r];
+    const int B = (int)(item - (only_rep >= 0 ? 0 : R.block_begin));
+    const int rb0 = R.block_rank[B];
+    const int rb1 = R.block_rank[B + 1];
+    const int ppc = R.ppc;
+    const int count = (rb1 - rb0) * ppc;  // at most 2^l cells * ppc < 2^31 (checked at init)
+    const int64_t slot0 = (int64_t)rb0 * ppc;
+    const uint32_t shift = (uint32_t)R.aux[1];  // Cranley-Patterson rotation of this lift
+    double ratio = 1.0, dv = 0.0;
+    if (coarse != nullptr) {
+      double sw = 0.0, swv = 0.0;
+#pragma unroll 1
+      for (int j = threadIdx.x; j < count; j += blockDim.x) {
+        const int jr = j / ppc;
+        const Gen g = generate(R, rb0 + jr, j - jr * ppc, shift);
+        sw += g.w;
+        swv += g.w * g.v;
+      }
+      sw = block_sum(sw, s_red);
+      swv = block_sum(swv, s_red);
+      const double scale = R.h * sqrt((double)(1 << R.levels));
+      const double* cc = coarse + coff[r];
+      const double mt = fmax(cc[B], 0.0) * scale;
+      const double jt = cc[R.n_coarse + B] * scale;
+      if (sw > 0.0) ratio = mt / sw;
+      if (mt > 0.0) dv = (jt - ratio * swv) / mt;
+    }
+#pragma unroll 1
+    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+      const int jr = j / ppc;
+      const Gen g = generate(R, rb0 + jr, j - jr * ppc, shift);
+      const int64_t s = slot0 + j;
+      R.cell[s] = (int16_t)g.cell;
+      R.frac[s] = g.frac;
+      R.v[s] = (float)(g.v + dv);
+      R.w[s] = (float)(g.w * ratio);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------- restrict/project --
+__global__ void k_restrict(const RepDev* __restrict__ reps, int steps, double* __restrict__ snap,
+                           const int64_t* __restrict__ soff) {
+  const RepDev& R = reps[blockIdx.y];
+  const int nc = R.n_coarse;
+  const int64_t count = (int64_t)(steps + 1) * 2 * nc;
+  const double scale = kFxInv / R.h / sqrt((double)(1 << R.levels));
+  double* out = snap + soff[blockIdx.y];
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = (double)R.rbins[k] * scale;
+}
+
+__global__ void k_project(const RepDev* __restrict__ reps, const double* __restrict__ snap,
+                          const int64_t* __restrict__ soff, double* __restrict__ out,
+                          const int64_t* __restrict__ coff, uint32_t* __restrict__ status) {
+  const RepDev& R = reps[blockIdx.y];
+  const int nc = R.n_coarse;
+  const int ne = R.burst_steps;
+  const double* s = snap + soff[blockIdx.y];
+  double* o = out + coff[blockIdx.y];
+  const double den = (double)ne * (ne + 1) * (ne + 2) * R.dt;
+  const double leap = R.macro_dt - ne * R.dt;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
+    double slope = 0.0;
+    for (int p = 0; p <= ne / 2; ++p) {
+      const double coef = 6.0 * (double)(ne - 2 * p) / den;
+      slope += coef * (s[(int64_t)(ne - p) * 2 * nc + k] - s[(int64_t)p * 2 * nc + k]);
+    }
+    const double val = s[(int64_t)ne * 2 * nc + k] + leap * slope;
+    o[k] = val;
+    if (!(fabs(val) < 1e300)) atomicOr(status, 2u);
+    if (k < nc && val < 0.0) atomicOr(status, 8u);
+  }
+}
+
+__global__ void k_ensemble_mean(const RepDev* __restrict__ reps, int n_reps,
+                                const int32_t* __restrict__ group, double* __restrict__ coarse,
+                                const int64_t* __restrict__ coff) {
+  // one block row per group leader; members share n_cells, hence 2 N_c entries
+  const int r = blockIdx.y;
+  if (group[r] != r) return;
+  const int count = 2 * reps[r].n_coarse;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    int m = 0;
+    for (int q = 0; q < n_reps; ++q)
+      if (group[q] == r) {
+        acc += coarse[coff[q] + k];
+        ++m;
+      }
+    const double mean = acc / m;
+    for (int q = 0; q < n_reps; ++q)
+      if (group[q] == r) coarse[coff[q] + k] = mean;
+  }
+}
+
+// Store each replica's lift rotation where the lift kernel reads it.
+__global__ void k_set_shifts(const RepDev* __restrict__ reps, int n_reps, int only_rep,
+                             const ShiftArg shifts) {
+  const int r = threadIdx.x;
+  if (r < n_reps && (only_rep < 0 || r == only_rep)) reps[r].aux[1] = (int64_t)shifts.s[r];
+}
+
+__global__ void k_set_profile(const RepDev* __restrict__ reps, int rep,
+                              const double* __restrict__ dn, const double* __restrict__ du) {
+  const RepDev& R = reps[rep];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < R.n_nodes; k += gridDim.x * blockDim.x) {
+    R.prof_n[k] = fmax(dn[k], 0.0);
+    R.prof_u[k] = du[k];
+  }
+}
+
+}  // namespace
+
+void launch_set_profile(const RepDev* d_reps, int rep, const double* d_n, const double* d_u,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(k_set_profile, dim3(16), dim3(256), 0, stream, d_reps, rep, d_n, d_u);
+}
+
+void launch_profile(const RepDev* d_reps, int n_reps, const double* d_coarse,
+                    const int64_t* d_coff, hipStream_t stream) {
+  hipLaunchKernelGGL(k_profile, dim3(n_reps), dim3(kProfThreads), 0, stream, d_reps, d_coarse,
+                     d_coff);
+}
+
+void launch_occupancy(const RepDev* d_reps, int n_reps, int only_rep, uint32_t* d_status,
+                      hipStream_t stream) {
+  hipLaunchKernelGGL(k_occupancy, dim3(only_rep >= 0 ? 1 : n_reps), dim3(kProfThreads), 0,
+                     stream, d_reps, only_rep, d_status);
+}
+
+void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
+                           int64_t total_blocks, int only_rep, const double* d_coarse,
+                           const int64_t* d_coff, const ShiftArg& shifts, int grid_blocks,
+                           hipStream_t stream) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_set_shifts, dim3(1), dim3(kMaxShiftReplicas), 0, stream, d_reps, n_reps,
+                     only_rep, shifts);
+  const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_blocks) : total_blocks;
+  hipLaunchKernelGGL(k_lift, dim3((unsigned)g), dim3(kLiftThreads), 0, stream, d_reps,
+                     d_block_prefix, n_reps, total_blocks, only_rep, d_coarse, d_coff);
+}
+
+void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap,
+                     const int64_t* d_soff, hipStream_t stream) {
+  hipLaunchKernelGGL(k_restrict, dim3(16, n_reps), dim3(256), 0, stream, d_reps, steps, d_snap,
+                     d_soff);
+}
+
+void launch_project(const RepDev* d_reps, int n_reps, const double* d_snap,
+                    const int64_t* d_soff, double* d_out, const int64_t* d_coff,
+                    uint32_t* d_status, hipStream_t stream) {
+  hipLaunchKernelGGL(k_project, dim3(4, n_reps), dim3(256), 0, stream, d_reps, d_snap, d_soff,
+                     d_out, d_coff, d_status);
+}
+
+void launch_ensemble_mean(const RepDev* d_reps, int n_reps, const int32_t* d_group,
+                          double* d_coarse, const int64_t* d_coff, hipStream_t stream) {
+  hipLaunchKernelGGL(k_ensemble_mean, dim3(4, n_reps), dim3(256), 0, stream, d_reps, n_reps,
+                     d_group, d_coarse, d_coff);
+}
+
+}  // namespace efpi

@@ -1,0 +1,97 @@
+// Internal definitions shared by the HIP kernels and the host side of libefpi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace efpi {
+
+constexpr double kFxScale = 1099511627776.0;     // 2^40: fixed-point charge unit 2^-40
+constexpr double kFxInv = 1.0 / 1099511627776.0;
+constexpr int kWave = 64;
+
+// Per-replica descriptor in device memory: sizes, parameters and the addresses
+// of the replica's arrays inside the workspace.
+struct RepDev {
+  int32_t n_cells, n_nodes, bc, closure;
+  int32_t ppc, levels, n_coarse, burst_steps;
+  int32_t coevolving, lift_linear, log2n, pad0;
+  double h, inv_h, length, vth, dt, macro_dt, n_floor;
+  int64_t capacity;
+  int64_t item_begin;    // first particle work item of this replica
+  int64_t block_begin;   // first coarse-block work item of this replica
+  // particle store (SoA) and its sort copy
+  int16_t* cell;
+  float* frac;
+  float* v;
+  float* w;
+  int16_t* cell2;
+  float* frac2;
+  float* v2;
+  float* w2;
+  int64_t* np;           // live particle slots
+  // grid
+  int64_t* q[2];         // fixed-point node charge, double-buffered
+  double* phi;
+  float* e;              // node field E^p
+  float* en;             // field stored at the start of the burst (App. B step 1)
+  // coarse
+  int64_t* rbins;        // [K+1][2][N_c] fixed-point block sums of the snapshots
+  double* snap;          // [K+1][2][N_c] snapshots (internal macro step)
+  double* coarse_tmp;    // [2][N_c]
+  // lift
+  double* prof_n;        // [N+1] fine density
+  double* prof_u;        // [N+1] fine mean velocity
+  int32_t* cell_of_rank; // [N] occupied cells in order
+  int32_t* block_rank;   // [N_c + 1] first occupied-cell rank of every block
+  int64_t* aux;          // [4] per-replica scratch: [0] absorbed ions of a sort, [1] lift rotation
+};
+
+// Kernel flags of the particle pass.
+enum : int {
+  kFresh = 1,      // velocities are at an integer time level (first pass after load)
+  kRestrict = 2,   // deposit snapshot p along the approximate characteristics
+  kPush = 4,       // leapfrog step and deposit of the new charge
+  kDepositOnly = 8 // deposit the charge of the current positions
+};
+
+// Launchers (defined in the kernel sources), all asynchronous on `stream`.
+constexpr int kMaxShiftReplicas = 256;
+struct ShiftArg {
+  uint32_t s[kMaxShiftReplicas];
+};
+
+void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
+                      int64_t total_items, int tile, int grid_blocks, int p, int flags,
+                      int qsel, hipStream_t stream);
+void launch_newton(const RepDev* d_reps, const int32_t* d_list, int n_list, int M, int threads,
+                   int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
+                   uint32_t* d_status, hipStream_t stream);
+void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream);
+void launch_set_profile(const RepDev* d_reps, int rep, const double* d_n, const double* d_u,
+                        hipStream_t stream);
+void launch_profile(const RepDev* d_reps, int n_reps, const double* d_coarse,
+                    const int64_t* d_coff, hipStream_t stream);
+void launch_occupancy(const RepDev* d_reps, int n_reps, int only_rep, uint32_t* d_status,
+                      hipStream_t stream);
+void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
+                           int64_t total_blocks, int only_rep, const double* d_coarse,
+                           const int64_t* d_coff, const ShiftArg& shifts, int grid_blocks,
+                           hipStream_t stream);
+void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap,
+                     const int64_t* d_soff, hipStream_t stream);
+void launch_project(const RepDev* d_reps, int n_reps, const double* d_snap,
+                    const int64_t* d_soff, double* d_out, const int64_t* d_coff,
+                    uint32_t* d_status, hipStream_t stream);
+void launch_ensemble_mean(const RepDev* d_reps, int n_reps, const int32_t* d_group,
+                          double* d_coarse, const int64_t* d_coff, hipStream_t stream);
+void launch_fill_u8(void* d_ptr, size_t bytes, hipStream_t stream);
+void launch_copy_particles(const RepDev* d_reps, int rep, const int16_t* cell, const float* frac,
+                           const float* v, const float* w, int64_t n, int to_store,
+                           int16_t* ocell, float* ofrac, float* ov, float* ow,
+                           hipStream_t stream);
+void launch_sort(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
+                 int64_t total_items, int tile, int32_t* d_hist, int grid_blocks,
+                 hipStream_t stream);
+
+}  // namespace efpi

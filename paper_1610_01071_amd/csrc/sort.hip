@@ -1,0 +1,198 @@
+// Stable counting sort of the ion store by cell index.
+//
+// Two least-significant-digit passes over 8-bit digits of the key
+// (cell, or 0xFFFF for an absorbed ion, which therefore sorts last and is
+// dropped).  Each pass: (1) per-tile digit histograms, (2) per replica a scan
+// over tiles and digits giving every (tile, digit) its first destination,
+// (3) a scatter in which each wave walks its quarter of the tile in index
+// order and ranks lanes of equal digit by ballot masks, so the order is stable
+// and the result deterministic.  Pass 0 moves the store into the sort copy,
+// pass 1 moves it back.
+#include "efpi_internal.h"
+
+namespace efpi {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kDigits = 256;
+
+__device__ __forceinline__ int find_replica(const int64_t* prefix, int n, int64_t item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ unsigned key_of(int16_t c) {
+  return c < 0 ? 0xFFFFu : (unsigned)(uint16_t)c;
+}
+
+struct Store {
+  const int16_t* cell;
+  const float* frac;
+  const float* v;
+  const float* w;
+  int16_t* ocell;
+  float* ofrac;
+  float* ov;
+  float* ow;
+};
+
+__device__ __forceinline__ Store store_of(const RepDev& R, int pass) {
+  if (pass == 0) return Store{R.cell, R.frac, R.v, R.w, R.cell2, R.frac2, R.v2, R.w2};
+  return Store{R.cell2, R.frac2, R.v2, R.w2, R.cell, R.frac, R.v, R.w};
+}
+
+// Per-wave digit counts of the tile into LDS rows, summed into hist[item][digit].
+__global__ __launch_bounds__(kThreads) void k_hist(const RepDev* __restrict__ reps,
+                                                    const int64_t* __restrict__ item_prefix,
+                                                    int n_reps, int64_t total, int tile, int pass,
+                                                    int32_t* __restrict__ hist) {
+  __shared__ int s_cnt[kWaves][kDigits];
+  const int shift = 8 * pass;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int r = find_replica(item_prefix, n_reps, item);
+    const RepDev& R = reps[r];
+    const Store S = store_of(R, pass);
+    const int64_t np = *R.np;
+    const int64_t i0 = (item - R.item_begin) * (int64_t)tile;
+    for (int k = threadIdx.x; k < kWaves * kDigits; k += kThreads) (&s_cnt[0][0])[k] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t chunk = tile / kWaves;
+    const int64_t a = i0 + wave * chunk;
+    for (int64_t j = a + lane; j < a + chunk; j += 64) {
+      if (j < np) atomicAdd(&s_cnt[wave][(key_of(S.cell[j]) >> shift) & 0xFF], 1);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kDigits; d += kThreads) {
+      int s = 0;
+      for (int q = 0; q < kWaves; ++q) s += s_cnt[q][d];
+      hist[item * kDigits + d] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Per replica: hist[item][d] <- first destination of digit d in that tile.
+// On the last pass, the count of absorbed ions (digit 0xFF of 0xFFFF) is removed from np.
+__global__ __launch_bounds__(kDigits) void k_scan(const RepDev* __restrict__ reps,
+                                                   const int64_t* __restrict__ item_prefix,
+                                                   int pass, int32_t* __restrict__ hist) {
+  __shared__ int64_t s_tot[kDigits];
+  const int r = blockIdx.x;
+  const int64_t b = item_prefix[r], e = item_prefix[r + 1];
+  const int d = threadIdx.x;
+  int64_t run = 0;
+  for (int64_t it = b; it < e; ++it) {
+    const int32_t c = hist[it * kDigits + d];
+    hist[it * kDigits + d] = (int32_t)run;
+    run += c;
+  }
+  s_tot[d] = run;
+  __syncthreads();
+  // exclusive scan of digit totals (digit order)
+  int64_t base = 0;
+  for (int k = 0; k < d; ++k) base += s_tot[k];
+  for (int64_t it = b; it < e; ++it) hist[it * kDigits + d] += (int32_t)base;
+  if (pass == 1 && d == 0) reps[r].aux[0] = s_tot[kDigits - 1];  // absorbed ions, sorted last
+}
+
+__global__ void k_drop_absorbed(const RepDev* __restrict__ reps) {
+  const RepDev& R = reps[blockIdx.x];
+  if (threadIdx.x == 0) *R.np = *R.np - R.aux[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(const RepDev* __restrict__ reps,
+                                                       const int64_t* __restrict__ item_prefix,
+                                                       int n_reps, int64_t total, int tile,
+                                                       int pass, const int32_t* __restrict__ hist) {
+  __shared__ int s_off[kWaves][kDigits];
+  const int shift = 8 * pass;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const int r = find_replica(item_prefix, n_reps, item);
+    const RepDev& R = reps[r];
+    const Store S = store_of(R, pass);
+    const int64_t np = *R.np;
+    const int64_t i0 = (item - R.item_begin) * (int64_t)tile;
+    const int64_t chunk = tile / kWaves;
+    const int64_t a = i0 + wave * chunk;
+    for (int k = threadIdx.x; k < kWaves * kDigits; k += kThreads) (&s_off[0][0])[k] = 0;
+    __syncthreads();
+    for (int64_t j = a + lane; j < a + chunk; j += 64)
+      if (j < np) atomicAdd(&s_off[wave][(key_of(S.cell[j]) >> shift) & 0xFF], 1);
+    __syncthreads();
+    // exclusive prefix over waves, plus the tile's first destination per digit
+    for (int d = threadIdx.x; d < kDigits; d += kThreads) {
+      int run = hist[item * kDigits + d];
+      for (int q = 0; q < kWaves; ++q) {
+        const int c = s_off[q][d];
+        s_off[q][d] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t j0 = a; j0 < a + chunk; j0 += 64) {
+      const int64_t j = j0 + lane;
+      const bool ok = j < np;
+      int dig = -1;
+      int16_t c = 0;
+      float f = 0.f, v = 0.f, w = 0.f;
+      if (ok) {
+        c = S.cell[j];
+        f = S.frac[j];
+        v = S.v[j];
+        w = S.w[j];
+        dig = (int)((key_of(c) >> shift) & 0xFF);
+      }
+      int dest = -1;
+      int key = dig;
+      while (true) {
+        const unsigned long long act = __ballot(key >= 0);
+        if (act == 0ull) break;
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const int lk = __shfl(key, leader, 64);
+        const unsigned long long m = __ballot(key == lk);
+        if (key == lk) {
+          dest = s_off[wave][lk] + __popcll(m & lt);
+          key = -1;
+        }
+        if (lane == leader) s_off[wave][lk] += __popcll(m);
+      }
+      if (ok) {
+        S.ocell[dest] = c;
+        S.ofrac[dest] = f;
+        S.ov[dest] = v;
+        S.ow[dest] = w;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+void launch_sort(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
+                 int64_t total_items, int tile, int32_t* d_hist, int grid_blocks,
+                 hipStream_t stream) {
+  if (total_items <= 0) return;
+  const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_items) : total_items;
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)g), dim3(kThreads), 0, stream, d_reps, d_item_prefix,
+                       n_reps, total_items, tile, pass, d_hist);
+    hipLaunchKernelGGL(k_scan, dim3(n_reps), dim3(kDigits), 0, stream, d_reps, d_item_prefix, pass,
+                       d_hist);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)g), dim3(kThreads), 0, stream, d_reps,
+                       d_item_prefix, n_reps, total_items, tile, pass, d_hist);
+  }
+  hipLaunchKernelGGL(k_drop_absorbed, dim3(n_reps), dim3(64), 0, stream, d_reps);
+}
+
+}  // namespace efpi

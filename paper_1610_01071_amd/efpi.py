@@ -1,0 +1,364 @@
+"""Python binding of libefpi (include/efpi.h): argument marshalling only.
+
+Every function below has the name of the C entry point it calls and passes
+torch CUDA tensors as device pointers.  All arithmetic happens in the HIP
+kernels of the library; if the library is not built this module raises on
+import, and there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libefpi.so")
+
+ABI_VERSION = 1
+BC_PERIODIC, BC_WALLS = 0, 1
+CLOSURE_BOLTZMANN, CLOSURE_NOFIELD = 0, 2
+FLAG_SORT_BUFFER = 1
+DEV_NEWTON, DEV_NAN, DEV_OVERFLOW, DEV_NEGMASS = 1, 2, 4, 8
+
+STATUS_NAMES = {0: "EFPI_OK", -1: "EFPI_EINVAL", -2: "EFPI_ENOMEM", -3: "EFPI_EHIP",
+                -4: "EFPI_ENEWTON", -5: "EFPI_ENUMERIC", -6: "EFPI_ESTATE", -7: "EFPI_EOVERFLOW"}
+
+
+class EfpiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Replica(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", ctypes.c_int32),
+        ("bc", ctypes.c_int32),
+        ("closure", ctypes.c_int32),
+        ("ppc", ctypes.c_int32),
+        ("haar_levels", ctypes.c_int32),
+        ("burst_steps", ctypes.c_int32),
+        ("coevolving", ctypes.c_int32),
+        ("lift_linear", ctypes.c_int32),
+        ("length", ctypes.c_double),
+        ("vth", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("macro_dt", ctypes.c_double),
+        ("n_floor", ctypes.c_double),
+        ("capacity", ctypes.c_int64),
+    ]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32),
+        ("n_replicas", ctypes.c_uint32),
+        ("replicas", ctypes.POINTER(Replica)),
+        ("newton_iters", ctypes.c_int32),
+        ("newton_iters_start", ctypes.c_int32),
+        ("newton_tol", ctypes.c_double),
+        ("tile", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libefpi.so is not built ({LIB_PATH}); run `python -m paper_1610_01071_amd._build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "efpi_workspace_size": [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)],
+        "efpi_init": [ctypes.POINTER(Config), P, ctypes.c_size_t, P, ctypes.POINTER(P)],
+        "efpi_set_stream": [P, P],
+        "efpi_n_coarse": [P, I32, ctypes.POINTER(I32)],
+        "efpi_set_particles": [P, I32, P, P, P, P, I64],
+        "efpi_get_particles": [P, I32, P, P, P, P, ctypes.POINTER(I64)],
+        "efpi_get_grid": [P, I32, P, P, P],
+        "efpi_set_potential": [P, I32, P],
+        "efpi_load_profile": [P, I32, P, P, U32],
+        "efpi_lift": [P, P, ctypes.POINTER(U32)],
+        "efpi_deposit": [P],
+        "efpi_solve_field": [P, I32, I32],
+        "efpi_pic_burst": [P, I32, I32],
+        "efpi_restrict": [P, P],
+        "efpi_project": [P, P, P],
+        "efpi_macro_step": [P, P, P, ctypes.POINTER(U32)],
+        "efpi_ensemble_mean": [P, P],
+        "efpi_sort": [P],
+        "efpi_sync": [P, ctypes.POINTER(U32)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.efpi_destroy.argtypes = [P]
+    lib.efpi_destroy.restype = None
+    lib.efpi_last_error.argtypes = []
+    lib.efpi_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+LIB = _load()
+
+EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream", "efpi_n_coarse",
+            "efpi_set_particles", "efpi_get_particles", "efpi_get_grid", "efpi_set_potential",
+            "efpi_load_profile", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
+            "efpi_restrict", "efpi_project", "efpi_macro_step", "efpi_ensemble_mean", "efpi_sort",
+            "efpi_sync", "efpi_last_error"]
+
+
+def _check(status: int):
+    if status != 0:
+        raise EfpiError(status, LIB.efpi_last_error().decode())
+
+
+def _dev(t, dtype):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype):
+        raise TypeError(f"expected a contiguous CUDA tensor of {dtype}, got {t.dtype} on {t.device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class ReplicaSpec:
+    """Python-side description of one replica (mirrors efpi_replica)."""
+
+    n_cells: int
+    length: float
+    bc: int = BC_PERIODIC
+    closure: int = CLOSURE_BOLTZMANN
+    ppc: int = 100
+    haar_levels: int = 4
+    burst_steps: int = 20
+    coevolving: int = 1
+    lift_linear: int = 1
+    vth: float = 0.316227766016838
+    dt: float = 0.1
+    macro_dt: float = 20.0
+    n_floor: float = 1e-6
+    capacity: int = 0
+
+    def to_c(self) -> Replica:
+        cap = self.capacity if self.capacity > 0 else self.n_cells * self.ppc
+        return Replica(self.n_cells, self.bc, self.closure, self.ppc, self.haar_levels,
+                       self.burst_steps, self.coevolving, self.lift_linear, self.length, self.vth,
+                       self.dt, self.macro_dt, self.n_floor, cap)
+
+    @property
+    def n_coarse(self) -> int:
+        return self.n_cells >> self.haar_levels
+
+    @property
+    def n_nodes(self) -> int:
+        return self.n_cells if self.bc == BC_PERIODIC else self.n_cells + 1
+
+
+@dataclass
+class ConfigSpec:
+    replicas: list
+    newton_iters: int = 2
+    newton_iters_start: int = 6
+    newton_tol: float = 1e-4
+    tile: int = 0
+    grid_blocks: int = 0
+    flags: int = 0
+    _keep: list = field(default_factory=list, repr=False)
+
+    def to_c(self) -> Config:
+        arr = (Replica * len(self.replicas))(*[r.to_c() for r in self.replicas])
+        self._keep = [arr]
+        return Config(ABI_VERSION, len(self.replicas), arr, self.newton_iters,
+                      self.newton_iters_start, self.newton_tol, self.tile, self.grid_blocks,
+                      self.flags)
+
+
+# --------------------------------------------------------------- entry points
+
+def efpi_workspace_size(cfg: Config) -> int:
+    out = ctypes.c_size_t(0)
+    _check(LIB.efpi_workspace_size(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def efpi_init(cfg: Config, workspace: torch.Tensor, stream=None):
+    handle = ctypes.c_void_p()
+    _check(LIB.efpi_init(ctypes.byref(cfg), _dev(workspace, torch.uint8), workspace.numel(),
+                         _stream(stream), ctypes.byref(handle)))
+    return handle
+
+
+def efpi_destroy(ctx):
+    LIB.efpi_destroy(ctx)
+
+
+def efpi_set_stream(ctx, stream=None):
+    _check(LIB.efpi_set_stream(ctx, _stream(stream)))
+
+
+def efpi_n_coarse(ctx, replica: int) -> int:
+    out = ctypes.c_int32(0)
+    _check(LIB.efpi_n_coarse(ctx, replica, ctypes.byref(out)))
+    return out.value
+
+
+def efpi_set_particles(ctx, replica, cell, frac, v, w):
+    n = cell.numel()
+    _check(LIB.efpi_set_particles(ctx, replica, _dev(cell, torch.int16), _dev(frac, torch.float32),
+                                  _dev(v, torch.float32), _dev(w, torch.float32), n))
+
+
+def efpi_get_particles(ctx, replica, cell=None, frac=None, v=None, w=None) -> int:
+    n = ctypes.c_int64(0)
+    _check(LIB.efpi_get_particles(ctx, replica, _dev(cell, torch.int16), _dev(frac, torch.float32),
+                                  _dev(v, torch.float32), _dev(w, torch.float32), ctypes.byref(n)))
+    return n.value
+
+
+def efpi_get_grid(ctx, replica, q=None, phi=None, e=None):
+    _check(LIB.efpi_get_grid(ctx, replica, _dev(q, torch.int64), _dev(phi, torch.float64),
+                             _dev(e, torch.float32)))
+
+
+def efpi_set_potential(ctx, replica, phi):
+    _check(LIB.efpi_set_potential(ctx, replica, _dev(phi, torch.float64)))
+
+
+def efpi_load_profile(ctx, replica, n, u, shift: int):
+    _check(LIB.efpi_load_profile(ctx, replica, _dev(n, torch.float64), _dev(u, torch.float64),
+                                 ctypes.c_uint32(shift)))
+
+
+def _shift_array(shifts):
+    return (ctypes.c_uint32 * len(shifts))(*[int(s) & 0xFFFFFFFF for s in shifts])
+
+
+def efpi_lift(ctx, coarse, shifts):
+    _check(LIB.efpi_lift(ctx, _dev(coarse, torch.float64), _shift_array(shifts)))
+
+
+def efpi_deposit(ctx):
+    _check(LIB.efpi_deposit(ctx))
+
+
+def efpi_solve_field(ctx, iters: int, cold: bool = False):
+    _check(LIB.efpi_solve_field(ctx, iters, 1 if cold else 0))
+
+
+def efpi_pic_burst(ctx, steps: int, restrict: bool):
+    _check(LIB.efpi_pic_burst(ctx, steps, 1 if restrict else 0))
+
+
+def efpi_restrict(ctx, snap):
+    _check(LIB.efpi_restrict(ctx, _dev(snap, torch.float64)))
+
+
+def efpi_project(ctx, snap, coarse_next):
+    _check(LIB.efpi_project(ctx, _dev(snap, torch.float64), _dev(coarse_next, torch.float64)))
+
+
+def efpi_macro_step(ctx, coarse_in, coarse_out, shifts):
+    _check(LIB.efpi_macro_step(ctx, _dev(coarse_in, torch.float64), _dev(coarse_out, torch.float64),
+                               _shift_array(shifts)))
+
+
+def efpi_ensemble_mean(ctx, coarse):
+    _check(LIB.efpi_ensemble_mean(ctx, _dev(coarse, torch.float64)))
+
+
+def efpi_sort(ctx):
+    _check(LIB.efpi_sort(ctx))
+
+
+def efpi_sync(ctx, raise_on_error: bool = True) -> int:
+    bits = ctypes.c_uint32(0)
+    st = LIB.efpi_sync(ctx, ctypes.byref(bits))
+    if raise_on_error:
+        _check(st)
+    return bits.value
+
+
+def efpi_last_error() -> str:
+    return LIB.efpi_last_error().decode()
+
+
+# --------------------------------------------------------------- convenience
+
+class Context:
+    """Owns one library context and its workspace tensor on a CUDA device."""
+
+    def __init__(self, spec: ConfigSpec, device="cuda", stream=None):
+        self.spec = spec
+        self.cfg = spec.to_c()
+        nbytes = efpi_workspace_size(self.cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off: off + nbytes]
+        self.ctx = efpi_init(self.cfg, self.workspace, stream)
+        self.device = self.workspace.device
+        self.coarse_sizes = [r.n_coarse for r in spec.replicas]
+
+    def close(self):
+        if self.ctx is not None:
+            efpi_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # layouts of the concatenated per-replica arrays
+    def coarse_numel(self) -> int:
+        return sum(2 * nc for nc in self.coarse_sizes)
+
+    def snap_numel(self) -> int:
+        return sum((r.burst_steps + 1) * 2 * r.n_coarse for r in self.spec.replicas)
+
+    def new_coarse(self):
+        return torch.zeros(self.coarse_numel(), dtype=torch.float64, device=self.device)
+
+    def new_snap(self):
+        return torch.zeros(self.snap_numel(), dtype=torch.float64, device=self.device)
+
+    def split_coarse(self, flat):
+        out, o = [], 0
+        for nc in self.coarse_sizes:
+            out.append(flat[o: o + 2 * nc].view(2, nc))
+            o += 2 * nc
+        return out
+
+    def split_snap(self, flat):
+        out, o = [], 0
+        for r in self.spec.replicas:
+            k = (r.burst_steps + 1) * 2 * r.n_coarse
+            out.append(flat[o: o + k].view(r.burst_steps + 1, 2, r.n_coarse))
+            o += k
+        return out
+
+    def particles(self, replica=0):
+        cap = self.cfg.replicas[replica].capacity
+        cell = torch.empty(cap, dtype=torch.int16, device=self.device)
+        frac = torch.empty(cap, dtype=torch.float32, device=self.device)
+        v = torch.empty(cap, dtype=torch.float32, device=self.device)
+        w = torch.empty(cap, dtype=torch.float32, device=self.device)
+        n = efpi_get_particles(self.ctx, replica, cell, frac, v, w)
+        return cell[:n], frac[:n], v[:n], w[:n]
+
+    def grid(self, replica=0):
+        nn = self.spec.replicas[replica].n_nodes
+        q = torch.empty(nn, dtype=torch.int64, device=self.device)
+        phi = torch.empty(nn, dtype=torch.float64, device=self.device)
+        e = torch.empty(nn, dtype=torch.float32, device=self.device)
+        efpi_get_grid(self.ctx, replica, q, phi, e)
+        return q, phi, e

@@ -1,0 +1,64 @@
+"""The C-ABI library loads on the CPU and exports every entry point include/efpi.h declares,
+and its host-side argument checks reject bad configurations without touching a GPU."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "efpi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(efpi_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1610_01071_amd.efpi as E
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(E.LIB, n), n
+        assert n in E.EXPORTED, n
+
+
+def test_binding_struct_layout_matches_header():
+    import ctypes
+    import paper_1610_01071_amd.efpi as E
+    # efpi_replica: 8 int32, 5 double, 1 int64 -> 8*4 + 5*8 + 8 = 80 bytes
+    assert ctypes.sizeof(E.Replica) == 80
+    assert E.Replica.length.offset == 32 and E.Replica.capacity.offset == 72
+    # efpi_config: 2 uint32, pointer, 2 int32, double, 2 int32, uint32 (+ padding)
+    assert E.Config.replicas.offset == 8 and E.Config.newton_tol.offset == 24
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_cells", 100, "power of two"),
+    ("n_cells", 32768, "power of two"),
+    ("haar_levels", 12, "haar_levels"),
+    ("dt", 0.0, "dt"),
+    ("macro_dt", 0.5, "macro_dt"),
+    ("ppc", 0, "ppc"),
+    ("closure", 1, "closure"),
+    ("capacity", -5, "capacity"),
+])
+def test_config_validation(field, value, msg):
+    import paper_1610_01071_amd.efpi as E
+    spec = E.ReplicaSpec(1024, 1024.0, ppc=10)
+    cfg = E.ConfigSpec([spec]).to_c()
+    setattr(cfg.replicas[0], field, value)
+    with pytest.raises(E.EfpiError) as ei:
+        E.efpi_workspace_size(cfg)
+    assert ei.value.status == -1 and msg in str(ei.value)
+
+
+def test_workspace_size_scales_with_capacity():
+    import paper_1610_01071_amd.efpi as E
+    a = E.efpi_workspace_size(E.ConfigSpec([E.ReplicaSpec(4096, 4096.0, ppc=1000)]).to_c())
+    b = E.efpi_workspace_size(E.ConfigSpec([E.ReplicaSpec(4096, 4096.0, ppc=2000)]).to_c())
+    # 14 bytes per particle slot (int16 cell + 3 x FP32)
+    assert abs((b - a) - 14 * 4096 * 1000) < 4096
+    c = E.efpi_workspace_size(E.ConfigSpec([E.ReplicaSpec(4096, 4096.0, ppc=1000)],
+                                           flags=E.FLAG_SORT_BUFFER).to_c())
+    assert c > a + 14 * 4096 * 1000

@@ -1,0 +1,278 @@
+"""GPU path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bars: fixed-point grid charge bit-exact; potential within 1e-10 absolute and
+field within 1e-6 relative after converged Newton (FP64 on both sides, the
+field rounded to FP32 on the GPU); one fine step of FP32 particles and field
+within 1e-5 relative of the FP64 oracle; lifted particles: cells and offsets
+bit-exact, velocities and weights within 1e-6 relative; burst-averaged coarse
+coefficients and the projected state within eps = 2e-3 (eq. 4.2).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import efpi as oefpi
+from oracle import metrics
+from oracle import pic as opic
+from helpers import (lib, oracle_grid, oracle_scheme, to_dev, set_particles, particles_np,
+                     grid_np, x_of, periodic_dx, relmax)
+
+pytestmark = pytest.mark.gpu
+
+
+def make_ctx(specs, **kw):
+    E = lib()
+    return E.Context(E.ConfigSpec(list(specs), **kw))
+
+
+def iaw_particles(spec, seed, delta=0.2):
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    n, u = synth.iaw_profile(spec.n_cells, spec.length, delta, n_nodes=g.n_nodes)
+    c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(seed))
+    return (c.astype(np.int16), f.astype(np.float32), v.astype(np.float32), w.astype(np.float32))
+
+
+def slab_particles(spec, seed):
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    n, u = synth.slab_profile(spec.n_cells)
+    c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(seed))
+    return (c.astype(np.int16), f.astype(np.float32), v.astype(np.float32), w.astype(np.float32))
+
+
+# ------------------------------------------------------------------ deposit --
+
+@pytest.mark.parametrize("n_cells,bc,n,srt,dead,tile", [
+    (8, 0, 3000, False, 0.0, 0),
+    (128, 0, 25600 + 123, True, 0.05, 1024),
+    (256, 1, 30001, False, 0.1, 0),
+    (4096, 0, 4096 * 50 + 77, True, 0.0, 0),
+    (16384, 1, 300000, True, 0.02, 8192),
+])
+def test_deposit_bitexact(n_cells, bc, n, srt, dead, tile):
+    E = lib()
+    spec = E.ReplicaSpec(n_cells, 0.75 * n_cells, bc=bc, ppc=1, haar_levels=2, capacity=n)
+    ctx = make_ctx([spec], tile=tile)
+    cell, frac, v, w = synth.random_particles(n, n_cells, seed=n_cells + n, sort=srt,
+                                              dead_fraction=dead)
+    set_particles(ctx, 0, cell, frac, v, w)
+    E.efpi_deposit(ctx.ctx)
+    q, _, _ = grid_np(ctx)
+    ref = opic.deposit_fx(cell, frac, w, oracle_grid(spec))
+    assert np.array_equal(q, ref)
+    alive = cell >= 0
+    assert int(q.sum()) == int(np.rint(w[alive].astype(np.float64) * 2.0 ** 40).astype(np.int64).sum())
+
+
+def test_deposit_empty_store():
+    E = lib()
+    spec = E.ReplicaSpec(64, 64.0, ppc=4)
+    ctx = make_ctx([spec])
+    z16 = torch.zeros(0, dtype=torch.int16, device="cuda")
+    z32 = torch.zeros(0, dtype=torch.float32, device="cuda")
+    E.efpi_set_particles(ctx.ctx, 0, z16, z32, z32, z32)
+    E.efpi_deposit(ctx.ctx)
+    q, _, _ = grid_np(ctx)
+    assert not q.any()
+
+
+# ------------------------------------------------------------------- Newton --
+
+@pytest.mark.parametrize("n_cells,bc", [(8, 0), (128, 0), (1024, 0), (4096, 0), (16384, 0),
+                                        (256, 1), (2048, 1), (16384, 1)])
+def test_newton_matches_oracle(n_cells, bc):
+    E = lib()
+    spec = E.ReplicaSpec(n_cells, float(n_cells), bc=bc, ppc=8 if n_cells > 4096 else 32,
+                         haar_levels=2)
+    ctx = make_ctx([spec])
+    parts = iaw_particles(spec, 3) if bc == 0 else slab_particles(spec, 3)
+    set_particles(ctx, 0, *parts)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 80, cold=True)
+    bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    q, phi, e = grid_np(ctx)
+    g = oracle_grid(spec)
+    rho = opic.fx_to_density(opic.deposit_fx(*parts[:2], parts[3], g), g)
+    phi_ref, _, ok = opic.newton_poisson(rho, g, tol=1e-13, max_iter=200)
+    assert ok
+    assert np.max(np.abs(phi - phi_ref)) < 1e-9
+    assert relmax(e, opic.field(phi_ref, g)) < 1e-6
+    assert bits & E.DEV_NAN == 0
+
+
+# ----------------------------------------------------------------- one step --
+
+@pytest.mark.parametrize("n_cells,bc,ppc", [(256, 0, 100), (1024, 0, 33), (512, 1, 40)])
+def test_one_step_matches_oracle(n_cells, bc, ppc):
+    E = lib()
+    spec = E.ReplicaSpec(n_cells, float(n_cells), bc=bc, ppc=ppc, haar_levels=3,
+                         vth=0.3 if bc == 0 else 0.1)
+    ctx = make_ctx([spec])
+    parts = iaw_particles(spec, 5) if bc == 0 else slab_particles(spec, 5)
+    cell, frac, v, w = parts
+    set_particles(ctx, 0, *parts)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 80)
+    E.efpi_pic_burst(ctx.ctx, 1, False)
+    gc, gf, gv, gw = particles_np(ctx)
+    q, phi, e = grid_np(ctx)
+    # oracle, FP64 from the same FP32 state
+    g = oracle_grid(spec)
+    x0 = x_of(cell, frac, g.h)
+    alive = np.ones(x0.size, bool)
+    _, phi0, e0 = opic.field_from_particles(x0, w.astype(np.float64), alive, g)
+    vh = v.astype(np.float64) + 0.5 * g.dt * opic.gather(e0, x0, g)
+    x1 = x0 + g.dt * vh
+    x1, alive = opic.apply_bc(x1, alive, g)
+    _, phi1, e1 = opic.field_from_particles(x1, w.astype(np.float64), alive, g, phi0)
+    # particle state
+    assert np.array_equal(gc >= 0, alive)
+    assert relmax(gv, vh) < 1e-5
+    xg = x_of(gc, gf, g.h)
+    dx = periodic_dx(xg[alive], x1[alive], g.length) if bc == 0 else xg[alive] - x1[alive]
+    assert np.max(np.abs(dx)) < 1e-5 * g.h
+    assert np.array_equal(gw, w)
+    # field after the step
+    assert relmax(e, e1) < 1e-5
+    # the fused deposit of the pushed particles is bit-exact
+    assert np.array_equal(q, opic.deposit_fx(gc, gf, gw, g))
+
+
+# --------------------------------------------------------------------- lift --
+
+@pytest.mark.parametrize("n_cells,bc,levels,linear,ppc", [(256, 0, 3, 1, 64), (256, 0, 2, 0, 17),
+                                                          (512, 1, 4, 1, 40)])
+def test_lift_matches_oracle(n_cells, bc, levels, linear, ppc):
+    E = lib()
+    spec = E.ReplicaSpec(n_cells, float(n_cells), bc=bc, ppc=ppc, haar_levels=levels,
+                         lift_linear=linear, vth=0.25)
+    ctx = make_ctx([spec])
+    nc = n_cells >> levels
+    coarse = synth.random_coarse(nc, seed=21, levels=levels)
+    if bc == 1:
+        coarse[:, : nc // 4] = 0.0
+        coarse[:, -nc // 4:] = 0.0
+    shift = synth.lift_shift(21)
+    E.efpi_lift(ctx.ctx, to_dev(coarse.ravel(), torch.float64), [shift])
+    gc, gf, gv, gw = particles_np(ctx)
+    oc, of, ov, ow = oefpi.lift(coarse, oracle_grid(spec), oracle_scheme(spec), shift)
+    assert gc.size == oc.size
+    assert np.array_equal(gc.astype(np.int64), oc)
+    assert np.array_equal(gf, of.astype(np.float32))
+    assert relmax(gv, ov) < 1e-6
+    assert relmax(gw, ow) < 1e-6
+
+
+def test_load_profile_matches_oracle():
+    E = lib()
+    spec = E.ReplicaSpec(128, 128.0, ppc=50, haar_levels=2)
+    ctx = make_ctx([spec])
+    n, u = synth.iaw_profile(128, 128.0)
+    shift = synth.lift_shift(4)
+    E.efpi_load_profile(ctx.ctx, 0, to_dev(n, torch.float64), to_dev(u, torch.float64), shift)
+    gc, gf, gv, gw = particles_np(ctx)
+    oc, of, ov, ow = oefpi.load_particles(n, u, oracle_grid(spec), oracle_scheme(spec), shift)
+    assert np.array_equal(gc.astype(np.int64), oc) and np.array_equal(gf, of.astype(np.float32))
+    assert relmax(gv, ov) < 1e-6 and relmax(gw, ow) < 1e-6
+
+
+# ---------------------------------------------------------- burst + project --
+
+def _burst_compare(spec, parts, seed_tag, newton_iters=2):
+    E = lib()
+    ctx = make_ctx([spec], newton_iters=newton_iters)
+    set_particles(ctx, 0, *parts)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 100, cold=True)
+    E.efpi_pic_burst(ctx.ctx, spec.burst_steps, True)
+    snap = ctx.new_snap()
+    E.efpi_restrict(ctx.ctx, snap)
+    nxt = ctx.new_coarse()
+    E.efpi_project(ctx.ctx, snap, nxt)
+    E.efpi_sync(ctx.ctx)
+    gs = snap.view(spec.burst_steps + 1, 2, -1).cpu().numpy()
+    gn = nxt.view(2, -1).cpu().numpy()
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    cell, frac, v, w = parts
+    os_, *_ = oefpi.pic_burst(x_of(cell, frac, g.h), v.astype(np.float64), w.astype(np.float64),
+                              g, sch)
+    on = oefpi.project(os_, g.dt, sch.macro_dt)
+    for m in range(2):
+        assert metrics.rel_l2(gs[:, m].mean(axis=0), os_[:, m].mean(axis=0)) < 2e-3
+        assert metrics.rel_l2(gn[m], on[m]) < 2e-3
+    return gs, gn, os_, on
+
+
+@pytest.mark.parametrize("coev", [1, 0])
+def test_burst_restriction_periodic(coev):
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, ppc=100, haar_levels=4, burst_steps=20, macro_dt=20.0,
+                         coevolving=coev)
+    _burst_compare(spec, iaw_particles(spec, 8), "iaw")
+
+
+def test_burst_restriction_walls():
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, bc=1, ppc=60, haar_levels=3, burst_steps=10, macro_dt=8.0,
+                         vth=0.1)
+    # the slab edge accelerates: three Newton iterations per step keep the last
+    # update below the status threshold (remaining error ~1e-10)
+    _burst_compare(spec, slab_particles(spec, 9), "slab", newton_iters=3)
+
+
+def test_free_streaming_snapshots_equal():
+    # App. B pin on the GPU: with E = 0 every co-evolving snapshot is the same.
+    E = lib()
+    spec = E.ReplicaSpec(256, 256.0, closure=E.CLOSURE_NOFIELD, ppc=40, haar_levels=3,
+                         burst_steps=8, macro_dt=6.0)
+    ctx = make_ctx([spec])
+    set_particles(ctx, 0, *iaw_particles(spec, 10))
+    E.efpi_pic_burst(ctx.ctx, spec.burst_steps, True)
+    snap = ctx.new_snap()
+    E.efpi_restrict(ctx.ctx, snap)
+    s = snap.view(spec.burst_steps + 1, 2, -1).cpu().numpy()
+    assert metrics.rel_l2(s, np.broadcast_to(s[0], s.shape)) < 1e-6
+
+
+def test_macro_step_matches_oracle():
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, ppc=100, haar_levels=4, burst_steps=20, macro_dt=20.0)
+    ctx = make_ctx([spec])
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    parts = iaw_particles(spec, 11)
+    x = x_of(parts[0], parts[1], g.h)
+    c0 = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                              np.ones(x.size, bool), g, sch)
+    shift = synth.lift_shift(12)
+    cin = to_dev(c0.ravel(), torch.float64)
+    cout = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, cin, cout, [shift])
+    E.efpi_sync(ctx.ctx)
+    ref, _, _ = oefpi.macro_step(c0, g, sch, shift)
+    got = cout.view(2, -1).cpu().numpy()
+    for m in range(2):
+        assert metrics.rel_l2(got[m], ref[m]) < 2e-3
+    # second call from the same input: identical bits (deterministic)
+    cout2 = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, cin, cout2, [shift])
+    torch.cuda.synchronize()
+    assert torch.equal(cout, cout2)
+
+
+# -------------------------------------------------------------- status/error --
+
+def test_invalid_config_rejected():
+    E = lib()
+    with pytest.raises(E.EfpiError):
+        make_ctx([E.ReplicaSpec(100, 100.0)])  # not a power of two
+
+
+def test_newton_status_flag():
+    E = lib()
+    spec = E.ReplicaSpec(256, 256.0, bc=1, ppc=16, haar_levels=2, vth=0.1)
+    ctx = make_ctx([spec], newton_tol=1e-30)
+    set_particles(ctx, 0, *slab_particles(spec, 2))
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 1, cold=True)
+    bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    assert bits & E.DEV_NEWTON
