@@ -201,6 +201,12 @@ efpi_status efpi_project(efpi_ctx* ctx, const double* d_snap, double* d_coarse_n
 efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_coarse_out,
                             const uint32_t* h_shifts);
 
+/* Plain restriction (no co-evolving frame) of the current particles of every
+ * replica: d_coarse[r][2][N_c] = coarse (density, momentum) coefficients at the
+ * current time, with time-centred velocities after a burst.  Overwrites the
+ * snapshots of the last burst. */
+efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse);
+
 /* Replace every replica's coarse state in d_coarse[r][2][N_c] by the mean over
  * the replicas with the same n_cells and length (replica-index order). */
 efpi_status efpi_ensemble_mean(efpi_ctx* ctx, double* d_coarse);
@@ -215,6 +221,15 @@ efpi_status efpi_sort(efpi_ctx* ctx);
  * and clear them.  Returns EFPI_ENUMERIC / EFPI_ENEWTON / EFPI_EOVERFLOW when the
  * matching bit was set (first in that order), else EFPI_OK. */
 efpi_status efpi_sync(efpi_ctx* ctx, uint32_t* h_bits);
+
+/* Measurement aid: with enable != 0, every later burst-step particle launch (the
+ * pass that pushes, deposits and restricts) is bracketed by HIP events on the
+ * context's stream.  Enabling resets the record. */
+efpi_status efpi_timing(efpi_ctx* ctx, int32_t enable);
+
+/* Synchronous: wait for the stream, then return the summed event time in ms and
+ * the number of timed launches since the last read or enable, and reset them. */
+efpi_status efpi_timing_read(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launches);
 
 /* Message for the last failed call on this thread ("" when none). */
 const char* efpi_last_error(void);

@@ -77,6 +77,13 @@ struct efpi_ctx {
   bool field_valid = false;
   bool fresh = true;       // velocities at an integer time level
   int last_burst_steps = -1;
+  // optional event timing of the burst-step particle launches
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  size_t events_used = 0;
+  ~efpi_ctx() {
+    for (hipEvent_t e : events) hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -306,6 +313,15 @@ efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shift
   return hip_check("lift");
 }
 
+hipEvent_t next_event(efpi_ctx* c) {
+  if (c->events_used == c->events.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->events.push_back(e);
+  }
+  return c->events[c->events_used++];
+}
+
 efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
   if (!c->field_valid) {
     if (!c->deposited) {
@@ -330,8 +346,15 @@ efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
       flags |= kPush;
       deposit_into_next(c);
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing && push) {
+      e0 = next_event(c);
+      e1 = next_event(c);
+      if (e0 && e1) hipEventRecord(e0, c->stream);
+    }
     launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, p,
                      flags, c->cur ^ 1, c->stream);
+    if (e0 && e1) hipEventRecord(e1, c->stream);
     if (push) {
       c->cur ^= 1;
       c->other_zero = false;
@@ -406,8 +429,9 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
         break;
       }
   }
-  // Newton launch groups by rows per thread M (N <= 1024: M = 1; else N / 1024)
-  std::vector<int> ms = {1, 2, 4, 8, 16};
+  // Newton launch groups by rows per thread M: 256 threads of N / 256 rows up to
+  // N = 4096, then 32 rows per thread (512 threads at N = 16384)
+  std::vector<int> ms = {1, 2, 4, 8, 16, 32};
   c->h_newton_list.clear();
   for (int M : ms) {
     NewtonGroup g;
@@ -416,7 +440,7 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
     int maxT = 0;
     for (int r = 0; r < c->R; ++r) {
       const int n = c->reps[r].n_cells;
-      const int m = n <= 1024 ? 1 : n / 1024;
+      const int m = n <= 256 ? 1 : (n <= 4096 ? n / 256 : 32);
       if (m == M) {
         c->h_newton_list.push_back(r);
         maxT = std::max(maxT, n / m);
@@ -599,6 +623,20 @@ efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_
   return hip_check("macro_step");
 }
 
+efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_coarse) return fail(EFPI_EINVAL, "d_coarse is NULL");
+  if (!ctx->fresh && !ctx->field_valid)
+    return fail(EFPI_ESTATE, "restrict_state needs integer-time velocities or a current field");
+  launch_prep_burst(ctx->d_reps, ctx->R, ctx->stream);
+  launch_particles(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
+                   ctx->grid_blocks, -1, kRestrict | (ctx->fresh ? kFresh : 0), ctx->cur ^ 1,
+                   ctx->stream);
+  launch_restrict(ctx->d_reps, ctx->R, 0, d_coarse, ctx->d_coarse_off, ctx->stream);
+  ctx->last_burst_steps = -1;
+  return hip_check("restrict_state");
+}
+
 efpi_status efpi_ensemble_mean(efpi_ctx* ctx, double* d_coarse) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   if (!d_coarse) return fail(EFPI_EINVAL, "d_coarse is NULL");
@@ -629,6 +667,32 @@ efpi_status efpi_sync(efpi_ctx* ctx, uint32_t* h_bits) {
   if (bits & EFPI_DEV_NEWTON) return fail(EFPI_ENEWTON, "Newton iteration above tolerance");
   if (bits & EFPI_DEV_OVERFLOW) return fail(EFPI_EOVERFLOW, "particle capacity exceeded at lift");
   g_err.clear();
+  return EFPI_OK;
+}
+
+efpi_status efpi_timing(efpi_ctx* ctx, int32_t enable) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  ctx->timing = enable != 0;
+  ctx->events_used = 0;
+  return EFPI_OK;
+}
+
+efpi_status efpi_timing_read(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launches) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(EFPI_EHIP, std::string("timing_read: ") + hipGetErrorString(e));
+  double total = 0.0;
+  int64_t n = 0;
+  for (size_t k = 0; k + 1 < ctx->events_used; k += 2) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ctx->events[k], ctx->events[k + 1]);
+    if (e != hipSuccess) return fail(EFPI_EHIP, std::string("timing_read: ") + hipGetErrorString(e));
+    total += ms;
+    ++n;
+  }
+  ctx->events_used = 0;
+  if (h_total_ms) *h_total_ms = total;
+  if (h_launches) *h_launches = n;
   return EFPI_OK;
 }
 

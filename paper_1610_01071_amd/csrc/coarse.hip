@@ -6,15 +6,17 @@
 namespace efpi {
 namespace {
 
-constexpr int kLiftThreads = 256;
+constexpr int kLiftThreads = 1024;
 constexpr int kProfThreads = 1024;
 
-// Inverse standard normal CDF, sqrt(2) erfinv(2b - 1).  The Hammersley
-// coordinates are b = (u + 1/2) 2^-32 with integer u, so 2b - 1 is exact in
-// binary64 and no precision is lost in either tail.  Kept out of line so that
-// the polynomial constants are not hoisted into registers across the caller loops.
-__device__ __attribute__((noinline)) double inv_normal(double b) {
-  return 1.4142135623730951 * erfinv(2.0 * b - 1.0);
+// Inverse standard normal CDF of b in (0, 1), from the inverse complementary
+// error function of the smaller tail (FP32: the velocity is stored in FP32).
+// For b = (u + 1/2) 2^-32 with integer u, 2b and 2(1 - b) are exact in binary64
+// and representable in FP32, so neither tail loses precision.  Kept out of line
+// so that its constants are not hoisted into registers across the caller loops.
+__device__ __attribute__((noinline)) float inv_normal(double b) {
+  const float r2 = 1.41421356237f;
+  return b < 0.5 ? -r2 * erfcinvf((float)(2.0 * b)) : r2 * erfcinvf((float)(2.0 * (1.0 - b)));
 }
 
 // ---------------------------------------------------------------- profile --
@@ -130,7 +132,7 @@ __device__ __forceinline__ Gen generate(const RepDev& R, int rank, int m, uint32
   const int cr = R.bc == 0 ? ((c + 1) & (R.n_cells - 1)) : c + 1;
   const double nx = (1.0 - th) * R.prof_n[c] + th * R.prof_n[cr];
   const double ux = (1.0 - th) * R.prof_u[c] + th * R.prof_u[cr];
-  g.v = ux + R.vth * inv_normal(b);
+  g.v = ux + R.vth * (double)inv_normal(b);
   g.w = nx * R.h / (double)ppc;
   return g;
 }

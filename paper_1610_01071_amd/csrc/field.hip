@@ -22,8 +22,17 @@ constexpr int kMaxT = 1024;
 
 __device__ __forceinline__ double clamp2(double x) { return fmin(2.0, fmax(-2.0, x)); }
 
-template <int M>
-__global__ __launch_bounds__(kMaxT) void k_newton(const RepDev* __restrict__ reps,
+// 1/b from the hardware reciprocal estimate and two Newton-Raphson corrections
+// (the error squares each time); the solver only needs full FP64 precision,
+// not correct rounding.
+__device__ __forceinline__ double rcp(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return fma(r, fma(-b, r, 1.0), r);
+}
+
+template <int M, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ reps,
                                                    const int32_t* __restrict__ list, int iters,
                                                    int cold, int qsel, int save_en,
                                                    int zero_bins, double tol,
@@ -110,8 +119,9 @@ __global__ __launch_bounds__(kMaxT) void k_newton(const RepDev* __restrict__ rep
           dn = -((phin - phi[M - 1]) * ih2 + 0.5 * ex - (double)Q[n] * qscale);
           bn = ih2 + 0.5 * ex;
           // eliminate node N into row N-1
-          b[M - 1] -= alpha * alpha / bn;
-          d[M - 1] -= alpha * dn / bn;
+          const double rbn = rcp(bn);
+          b[M - 1] -= alpha * alpha * rbn;
+          d[M - 1] -= alpha * dn * rbn;
         }
       }
 
@@ -120,34 +130,38 @@ __global__ __launch_bounds__(kMaxT) void k_newton(const RepDev* __restrict__ rep
       double y0 = 0.0, gl0 = 0.0, gr0 = 0.0;  // row 0
       if (M >= 2 && act) {
         double den = b[0];
-        double c = alpha / den;
-        double y = d[0] / den;
-        double gl = -aL / den;
+        const double r0 = rcp(den);
+        double c = alpha * r0;
+        double y = d[0] * r0;
+        double gl = -aL * r0;
 #pragma unroll
         for (int j = 1; j <= M - 2; ++j) {
           den = b[j] - alpha * c;
-          y = (d[j] - alpha * y) / den;
-          gl = (-alpha * gl) / den;
-          c = alpha / den;
+          const double rj = rcp(den);
+          y = (d[j] - alpha * y) * rj;
+          gl = (-alpha * gl) * rj;
+          c = alpha * rj;
         }
         yl = y;
         gll = gl;
-        grl = -alpha / den;
+        grl = -alpha * rcp(den);
         // upward sweep for row 0
         double dn2 = b[M - 2];
-        double ch = -alpha / dn2;
-        double yh = d[M - 2] / dn2;
-        double grh = -alpha / dn2;
+        double rh = rcp(dn2);
+        double ch = -alpha * rh;
+        double yh = d[M - 2] * rh;
+        double grh = -alpha * rh;
 #pragma unroll
         for (int j = M - 3; j >= 0; --j) {
           dn2 = b[j] + alpha * ch;
-          yh = (d[j] - alpha * yh) / dn2;
-          grh = (-alpha * grh) / dn2;
-          ch = -alpha / dn2;
+          rh = rcp(dn2);
+          yh = (d[j] - alpha * yh) * rh;
+          grh = (-alpha * grh) * rh;
+          ch = -alpha * rh;
         }
         y0 = yh;
         gr0 = grh;
-        gl0 = -aL / dn2;
+        gl0 = -aL * rh;
         s_y0[t] = y0;
         s_gl0[t] = gl0;
         s_gr0[t] = gr0;
@@ -192,13 +206,13 @@ __global__ __launch_bounds__(kMaxT) void k_newton(const RepDev* __restrict__ rep
           nA = 0.0;
           nC = 0.0;
           if (vm) {
-            const double k1 = A / s_b[im];
+            const double k1 = A * rcp(s_b[im]);
             nA = -s_a[im] * k1;
             nB -= s_c[im] * k1;
             nD -= s_d[im] * k1;
           }
           if (vp) {
-            const double k2 = C / s_b[ip];
+            const double k2 = C * rcp(s_b[ip]);
             nC = -s_c[ip] * k2;
             nB -= s_a[ip] * k2;
             nD -= s_d[ip] * k2;
@@ -218,7 +232,7 @@ __global__ __launch_bounds__(kMaxT) void k_newton(const RepDev* __restrict__ rep
       }
       double X = 0.0;
       if (act) {
-        X = D / (A + B + C);
+        X = D * rcp(A + B + C);
         s_first[t] = X;  // reuse as the separator values
       }
       __syncthreads();
@@ -232,14 +246,14 @@ __global__ __launch_bounds__(kMaxT) void k_newton(const RepDev* __restrict__ rep
           d[0] -= aL * XL;
           d[M - 2] -= alpha * X;
           // forward: b[j] <- c'_j, d[j] <- z'_j
-          double den = b[0];
-          b[0] = alpha / den;
-          d[0] = d[0] / den;
+          double rd = rcp(b[0]);
+          b[0] = alpha * rd;
+          d[0] = d[0] * rd;
 #pragma unroll
           for (int j = 1; j <= M - 2; ++j) {
-            den = b[j] - alpha * b[j - 1];
-            d[j] = (d[j] - alpha * d[j - 1]) / den;
-            b[j] = alpha / den;
+            rd = rcp(b[j] - alpha * b[j - 1]);
+            d[j] = (d[j] - alpha * d[j - 1]) * rd;
+            b[j] = alpha * rd;
           }
 #pragma unroll
           for (int j = M - 3; j >= 0; --j) d[j] -= b[j] * d[j + 1];
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(kMaxT) void k_newton(const RepDev* __restrict__ rep
           phi[j] += dl;
         }
         if (owns_n) {
-          const double dN = clamp2((dn - alpha * X) / bn);
+          const double dN = clamp2((dn - alpha * X) * rcp(bn));
           bad |= !(fabs(dN) < 1e300);
           local_max = fmax(local_max, fabs(dN));
           phin += dN;
@@ -331,14 +345,17 @@ void launch_newton(const RepDev* d_reps, const int32_t* d_list, int n_list, int 
                    int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
                    uint32_t* d_status, hipStream_t stream) {
   if (n_list <= 0) return;
-  const dim3 grid(n_list), block(threads);
-  switch (M) {
-    case 1: hipLaunchKernelGGL(k_newton<1>, grid, block, 0, stream, d_reps, d_list, iters, cold, qsel, save_en, zero_bins, tol, d_status); break;
-    case 2: hipLaunchKernelGGL(k_newton<2>, grid, block, 0, stream, d_reps, d_list, iters, cold, qsel, save_en, zero_bins, tol, d_status); break;
-    case 4: hipLaunchKernelGGL(k_newton<4>, grid, block, 0, stream, d_reps, d_list, iters, cold, qsel, save_en, zero_bins, tol, d_status); break;
-    case 8: hipLaunchKernelGGL(k_newton<8>, grid, block, 0, stream, d_reps, d_list, iters, cold, qsel, save_en, zero_bins, tol, d_status); break;
-    default: hipLaunchKernelGGL(k_newton<16>, grid, block, 0, stream, d_reps, d_list, iters, cold, qsel, save_en, zero_bins, tol, d_status); break;
-  }
+  const dim3 grid(n_list);
+#define EFPI_NEWTON(MM, TT)                                                                   \
+  hipLaunchKernelGGL((k_newton<MM, TT>), grid, dim3(threads), 0, stream, d_reps, d_list, iters, \
+                     cold, qsel, save_en, zero_bins, tol, d_status)
+  if (M == 1) EFPI_NEWTON(1, 256);
+  else if (M == 2) EFPI_NEWTON(2, 256);
+  else if (M == 4) EFPI_NEWTON(4, 256);
+  else if (M == 8) EFPI_NEWTON(8, 256);
+  else if (M == 16) EFPI_NEWTON(16, 256);
+  else EFPI_NEWTON(32, 512);
+#undef EFPI_NEWTON
 }
 
 void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream) {

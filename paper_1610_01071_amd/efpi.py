@@ -88,8 +88,11 @@ def _load():
         "efpi_project": [P, P, P],
         "efpi_macro_step": [P, P, P, ctypes.POINTER(U32)],
         "efpi_ensemble_mean": [P, P],
+        "efpi_restrict_state": [P, P],
         "efpi_sort": [P],
         "efpi_sync": [P, ctypes.POINTER(U32)],
+        "efpi_timing": [P, I32],
+        "efpi_timing_read": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -108,7 +111,8 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_set_particles", "efpi_get_particles", "efpi_get_grid", "efpi_set_potential",
             "efpi_load_profile", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
             "efpi_restrict", "efpi_project", "efpi_macro_step", "efpi_ensemble_mean", "efpi_sort",
-            "efpi_sync", "efpi_last_error"]
+            "efpi_restrict_state",
+            "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error"]
 
 
 def _check(status: int):
@@ -271,6 +275,10 @@ def efpi_macro_step(ctx, coarse_in, coarse_out, shifts):
                                _shift_array(shifts)))
 
 
+def efpi_restrict_state(ctx, coarse):
+    _check(LIB.efpi_restrict_state(ctx, _dev(coarse, torch.float64)))
+
+
 def efpi_ensemble_mean(ctx, coarse):
     _check(LIB.efpi_ensemble_mean(ctx, _dev(coarse, torch.float64)))
 
@@ -285,6 +293,17 @@ def efpi_sync(ctx, raise_on_error: bool = True) -> int:
     if raise_on_error:
         _check(st)
     return bits.value
+
+
+def efpi_timing(ctx, enable: bool):
+    _check(LIB.efpi_timing(ctx, 1 if enable else 0))
+
+
+def efpi_timing_read(ctx):
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(LIB.efpi_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def efpi_last_error() -> str:

@@ -276,3 +276,28 @@ def test_newton_status_flag():
     E.efpi_solve_field(ctx.ctx, 1, cold=True)
     bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
     assert bits & E.DEV_NEWTON
+
+
+def test_restrict_state_matches_oracle():
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, ppc=64, haar_levels=4)
+    ctx = make_ctx([spec])
+    parts = iaw_particles(spec, 13)
+    set_particles(ctx, 0, *parts)
+    c = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c)
+    got = c.view(2, -1).cpu().numpy()
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    x = x_of(parts[0], parts[1], g.h)
+    ref = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                               np.ones(x.size, bool), g, sch)
+    assert metrics.rel_l2(got, ref) < 1e-7
+    # after a plain PIC burst (half-step velocities re-centred with the current field)
+    E.efpi_pic_burst(ctx.ctx, 7, False)
+    E.efpi_restrict_state(ctx.ctx, c)
+    got = c.view(2, -1).cpu().numpy()
+    xp, vh, al, phi = opic.pic_run(x, parts[2].astype(np.float64), parts[3].astype(np.float64), g, 7)
+    vi = vh + 0.5 * g.dt * opic.gather(opic.field(phi, g), xp, g)
+    ref = oefpi.restrict_state(xp, vi, parts[3].astype(np.float64), al, g, sch)
+    for m in range(2):
+        assert metrics.rel_l2(got[m], ref[m]) < 1e-5
