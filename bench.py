@@ -33,6 +33,32 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-updates/s + EFPI wall-time speedup vs full PIC at fixed moment error"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 24  # read cell(2) frac v w (4 each), write cell frac v
+TILE = 2048  # ions per work item of the particle pass
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_particles_hbm_traffic_iaw4096.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the particle pass from the committed counter record.
+
+    The record holds FETCH_SIZE and WRITE_SIZE of the pass, scaled by a plain
+    copy of known size, and the hash of the kernel source they were taken on;
+    the figure is reported only while the source is unchanged.
+    """
+    import hashlib
+    try:
+        rec = {}
+        for line in open(TRAFFIC_RECORD):
+            if ":" in line and not line.startswith(("#", "|", " ", "`")):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+        src = os.path.join(ROOT, rec["kernel_source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def workload_spec(E):
@@ -114,6 +140,8 @@ def main():
     ap.add_argument("--cpu-ppc", type=int, default=1000, help="ions/cell of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-speedup", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB three times (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -126,8 +154,15 @@ def main():
     import paper_1610_01071_amd.efpi as E
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     spec = workload_spec(E)
-    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4,
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4, tile=TILE,
                                  flags=E.FLAG_SORT_BUFFER))
     n_ions = spec.n_cells * spec.ppc
     K = spec.burst_steps
@@ -183,7 +218,7 @@ def main():
             "n_ions": n_ions,
             "burst_steps": K,
             "newton_iters_per_step": 2,
-            "tile": 4096,
+            "tile": TILE,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -192,7 +227,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "k_particles<kRestrict|kPush> (burst step)",
             "bytes_per_launch": BYTES_PER_UPDATE * n_ions,
             "avg_launch_us": avg_launch_s * 1e6,
@@ -241,7 +276,7 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
     for mult in (50, 100, 200):
         sp = workload_spec(E)
         sp.macro_dt = mult * spec.dt
-        cx = E.Context(E.ConfigSpec([sp], newton_iters=2, newton_iters_start=4))
+        cx = E.Context(E.ConfigSpec([sp], newton_iters=2, newton_iters_start=4, tile=TILE))
         m = int(round(args.horizon / sp.macro_dt))
         a, b = cx.new_coarse(), cx.new_coarse()
         a.copy_(c0)

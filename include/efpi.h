@@ -223,8 +223,9 @@ efpi_status efpi_sort(efpi_ctx* ctx);
 efpi_status efpi_sync(efpi_ctx* ctx, uint32_t* h_bits);
 
 /* Measurement aid: with enable != 0, every later burst-step particle launch (the
- * pass that pushes, deposits and restricts) is bracketed by HIP events on the
- * context's stream.  Enabling resets the record. */
+ * pass that pushes, deposits and restricts) records the kernel's own start and
+ * end timestamps in a pair of HIP events (extended launch), so the summed time
+ * is kernel execution only.  Enabling resets the record. */
 efpi_status efpi_timing(efpi_ctx* ctx, int32_t enable);
 
 /* Synchronous: wait for the stream, then return the summed event time in ms and

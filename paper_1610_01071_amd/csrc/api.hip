@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/efpi.h"
+#include "efpi.h"
 #include "efpi_internal.h"
 
 using namespace efpi;
@@ -33,7 +33,7 @@ int ilog2(int64_t x) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int kDefaultTile = 4096;
+constexpr int kDefaultTile = 2048;
 constexpr int kDefaultGrid = 2048;
 
 struct NewtonGroup {
@@ -42,6 +42,14 @@ struct NewtonGroup {
   int first = 0;  // offset into the list array
   int count = 0;
 };
+
+// First failure among the enqueue calls of the current entry point; hip_check()
+// reports it (or else the runtime's last error) and clears it.
+thread_local hipError_t t_enqueue_error = hipSuccess;
+
+void note(hipError_t e) {
+  if (e != hipSuccess && t_enqueue_error == hipSuccess) t_enqueue_error = e;
+}
 
 }  // namespace
 
@@ -82,7 +90,7 @@ struct efpi_ctx {
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
   ~efpi_ctx() {
-    for (hipEvent_t e : events) hipEventDestroy(e);
+    for (hipEvent_t e : events) note(hipEventDestroy(e));
   }
 };
 
@@ -259,7 +267,10 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
 }
 
 efpi_status hip_check(const char* where) {
-  const hipError_t e = hipGetLastError();
+  hipError_t e = t_enqueue_error;
+  t_enqueue_error = hipSuccess;
+  const hipError_t last = hipGetLastError();
+  if (e == hipSuccess) e = last;
   if (e != hipSuccess) return fail(EFPI_EHIP, std::string(where) + ": " + hipGetErrorString(e));
   return EFPI_OK;
 }
@@ -350,11 +361,9 @@ efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
     if (c->timing && push) {
       e0 = next_event(c);
       e1 = next_event(c);
-      if (e0 && e1) hipEventRecord(e0, c->stream);
     }
     launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, p,
-                     flags, c->cur ^ 1, c->stream);
-    if (e0 && e1) hipEventRecord(e1, c->stream);
+                     flags, c->cur ^ 1, c->stream, e0, e1);
     if (push) {
       c->cur ^= 1;
       c->other_zero = false;
@@ -452,19 +461,19 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
   }
   // clear the workspace, then upload descriptors and tables
   launch_fill_u8(c->ws, need, c->stream);
-  hipMemcpyAsync(c->d_reps, c->h_reps.data(), sizeof(RepDev) * c->R, hipMemcpyHostToDevice, c->stream);
-  hipMemcpyAsync(c->d_item_prefix, c->h_item_prefix.data(), sizeof(int64_t) * (c->R + 1),
-                 hipMemcpyHostToDevice, c->stream);
-  hipMemcpyAsync(c->d_block_prefix, c->h_block_prefix.data(), sizeof(int64_t) * (c->R + 1),
-                 hipMemcpyHostToDevice, c->stream);
-  hipMemcpyAsync(c->d_snap_off, c->h_snap_off.data(), sizeof(int64_t) * c->R, hipMemcpyHostToDevice,
-                 c->stream);
-  hipMemcpyAsync(c->d_coarse_off, c->h_coarse_off.data(), sizeof(int64_t) * c->R,
-                 hipMemcpyHostToDevice, c->stream);
-  hipMemcpyAsync(c->d_group, c->h_group.data(), sizeof(int32_t) * c->R, hipMemcpyHostToDevice,
-                 c->stream);
-  hipMemcpyAsync(c->d_newton_list, c->h_newton_list.data(), sizeof(int32_t) * c->R,
-                 hipMemcpyHostToDevice, c->stream);
+  note(hipMemcpyAsync(c->d_reps, c->h_reps.data(), sizeof(RepDev) * c->R, hipMemcpyHostToDevice, c->stream));
+  note(hipMemcpyAsync(c->d_item_prefix, c->h_item_prefix.data(), sizeof(int64_t) * (c->R + 1),
+                 hipMemcpyHostToDevice, c->stream));
+  note(hipMemcpyAsync(c->d_block_prefix, c->h_block_prefix.data(), sizeof(int64_t) * (c->R + 1),
+                 hipMemcpyHostToDevice, c->stream));
+  note(hipMemcpyAsync(c->d_snap_off, c->h_snap_off.data(), sizeof(int64_t) * c->R, hipMemcpyHostToDevice,
+                 c->stream));
+  note(hipMemcpyAsync(c->d_coarse_off, c->h_coarse_off.data(), sizeof(int64_t) * c->R,
+                 hipMemcpyHostToDevice, c->stream));
+  note(hipMemcpyAsync(c->d_group, c->h_group.data(), sizeof(int32_t) * c->R, hipMemcpyHostToDevice,
+                 c->stream));
+  note(hipMemcpyAsync(c->d_newton_list, c->h_newton_list.data(), sizeof(int32_t) * c->R,
+                 hipMemcpyHostToDevice, c->stream));
   const hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;
@@ -512,7 +521,7 @@ efpi_status efpi_get_particles(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, 
   launch_copy_particles(ctx->d_reps, replica, nullptr, nullptr, nullptr, nullptr, d.capacity, 0,
                         d_cell, d_frac, d_v, d_w, ctx->stream);
   int64_t n = 0;
-  hipMemcpyAsync(&n, d.np, sizeof n, hipMemcpyDeviceToHost, ctx->stream);
+  note(hipMemcpyAsync(&n, d.np, sizeof n, hipMemcpyDeviceToHost, ctx->stream));
   const hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(EFPI_EHIP, std::string("get_particles: ") + hipGetErrorString(e));
   if (h_n) *h_n = n;
@@ -522,9 +531,9 @@ efpi_status efpi_get_particles(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, 
 efpi_status efpi_get_grid(efpi_ctx* ctx, int32_t replica, int64_t* d_q, double* d_phi, float* d_e) {
   if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
   const RepDev& d = ctx->h_reps[replica];
-  if (d_q) hipMemcpyAsync(d_q, d.q[ctx->cur], sizeof(int64_t) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
-  if (d_phi) hipMemcpyAsync(d_phi, d.phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
-  if (d_e) hipMemcpyAsync(d_e, d.e, sizeof(float) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (d_q) note(hipMemcpyAsync(d_q, d.q[ctx->cur], sizeof(int64_t) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (d_phi) note(hipMemcpyAsync(d_phi, d.phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (d_e) note(hipMemcpyAsync(d_e, d.e, sizeof(float) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
   return hip_check("get_grid");
 }
 
@@ -532,7 +541,7 @@ efpi_status efpi_set_potential(efpi_ctx* ctx, int32_t replica, const double* d_p
   if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
   if (!d_phi) return fail(EFPI_EINVAL, "d_phi is NULL");
   const RepDev& d = ctx->h_reps[replica];
-  hipMemcpyAsync(d.phi, d_phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream);
+  note(hipMemcpyAsync(d.phi, d_phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
   ctx->field_valid = false;
   return hip_check("set_potential");
 }

@@ -63,7 +63,8 @@ struct ShiftArg {
 
 void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
                       int64_t total_items, int tile, int grid_blocks, int p, int flags,
-                      int qsel, hipStream_t stream);
+                      int qsel, hipStream_t stream, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 void launch_newton(const RepDev* d_reps, const int32_t* d_list, int n_list, int M, int threads,
                    int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
                    uint32_t* d_status, hipStream_t stream);

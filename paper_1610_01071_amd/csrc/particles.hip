@@ -13,15 +13,45 @@
 // sums are of integers, so the result is independent of scheduling order.
 #include "efpi_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace efpi {
 namespace {
 
+// Pointers read from the replica descriptor are generic; casting them to the
+// global address space lets the compiler use global (not flat) memory
+// instructions, which do not couple the LDS and memory wait counters.
+#define EFPI_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ EFPI_GLOBAL T* gptr(T* p) {
+  return (EFPI_GLOBAL T*)p;
+}
+typedef EFPI_GLOBAL unsigned long long gu64;
+
+// A value that is the same in every lane, read so that the compiler knows it is
+// uniform (scalar registers, uniform control flow).
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void gatomic_add(long long* p, long long v) {
+  __hip_atomic_fetch_add((gu64*)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kThreads = 256;
+constexpr int kWave = 64;
+constexpr int kWaves = kThreads / kWave;
 constexpr int kBatch = 4;       // particles per thread loaded ahead of use
 constexpr int kQWin = 256;      // node window (int64 bins)
 constexpr int kQMargin = 16;
-constexpr int kRWin = 64;       // coarse block window per moment
+constexpr int kQSlotMargin = 4;  // node slots per wave start this far below the tile
+constexpr int kRWin = kWave;    // coarse block slots per wave (one per lane)
 constexpr int kRMargin = 8;
+constexpr int kEWin = 128;      // node field window staged in LDS (cells)
+constexpr int kEMargin = 32;
 
 // Wave-wide sums with a fixed DPP pattern (inclusive scan by row shifts 1, 2, 3
 // of the input, then 4 and 8 inside each 16-lane row, then row broadcasts 15 and
@@ -101,22 +131,21 @@ __device__ __forceinline__ void add_to(const Window& w, int idx, long long val) 
   if (k >= 0 && k < w.size)
     atomicAdd(reinterpret_cast<unsigned long long*>(&w.lds[k]), (unsigned long long)val);
   else
-    atomicAdd(reinterpret_cast<unsigned long long*>(&w.glob[idx]), (unsigned long long)val);
+    gatomic_add(&w.glob[idx], val);
 }
 
-// Each lane holds kBatch ions.  Targets shared by many lanes are merged: the
-// lowest active lane's target is taken, every lane sums its own ions with that
-// target, the sums are reduced across the wave and one lane adds the result to
-// the bins.  When fewer than kMinMerge lanes hold the target (scattered ions),
-// every lane adds all of its remaining ions directly instead, so a scattered
-// wave costs one atomic per ion rather than one merge round per distinct target.
-constexpr int kMinMerge = 8;
-
+// Each lane holds kBatch ions.  Every distinct target of the wave is merged:
+// the lowest active lane's target is taken, every lane sums its own ions with
+// that target, the sums are reduced across the wave and the result is added to
+// a per-lane slot register (lane s owns target base + s).  A target outside the
+// 64-slot window is added to the LDS window, else to global memory.  Per-lane
+// 64-bit LDS atomics are slow on this hardware, so the merge is never skipped.
+//
 // Charge deposit: ion j adds a[j] to node key[j] and b[j] to node key[j] + 1
 // (wrapping to 0 at `wrap`, or no wrap when wrap = -1).  Exact int64 sums.
 __device__ __forceinline__ void merge_charge(int (&key)[kBatch], const long long (&a)[kBatch],
-                                             const long long (&b)[kBatch], int wrap,
-                                             const Window& win) {
+                                             const long long (&b)[kBatch], int wrap, int base,
+                                             long long& acc, const Window& win) {
   const int lane = __lane_id();
   while (true) {
     int mine = -1;
@@ -128,52 +157,38 @@ __device__ __forceinline__ void merge_charge(int (&key)[kBatch], const long long
     const int leader = __ffsll((unsigned long long)act) - 1;
     const int lk = __builtin_amdgcn_readlane(mine, leader);
     long long sa = 0, sb = 0;
-    bool has = false;
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j)
-      if (key[j] == lk) {
-        sa += a[j];
-        sb += b[j];
-        has = true;
-        key[j] = -1;
-      }
-    if (__popcll(__ballot(has)) < kMinMerge) {
-      int r = lk + 1;
-      if (r == wrap) r = 0;
-      if (has) {
-        add_to(win, lk, sa);
-        add_to(win, r, sb);
-      }
-#pragma unroll
-      for (int j = 0; j < kBatch; ++j)
-        if (key[j] >= 0) {
-          int rr = key[j] + 1;
-          if (rr == wrap) rr = 0;
-          add_to(win, key[j], a[j]);
-          add_to(win, rr, b[j]);
-          key[j] = -1;
-        }
-      break;
+    for (int j = 0; j < kBatch; ++j) {
+      const bool m = key[j] == lk;
+      sa += m ? a[j] : 0ll;
+      sb += m ? b[j] : 0ll;
+      key[j] = m ? -1 : key[j];
     }
     const long long ta = wave_sum_i64(sa);
     const long long tb = wave_sum_i64(sb);
-    if (lane == leader) {
-      int r = lk + 1;
-      if (r == wrap) r = 0;
-      add_to(win, lk, ta);
-      add_to(win, r, tb);
-    }
+    int r = lk + 1;
+    if (r == wrap) r = 0;
+    const int sl = lk - base;
+    const int sr = r - base;
+    acc += lane == sl ? ta : 0ll;
+    acc += lane == sr ? tb : 0ll;
+    if ((unsigned)sl >= (unsigned)kWave && lane == 0) add_to(win, lk, ta);
+    if ((unsigned)sr >= (unsigned)kWave && lane == 0) add_to(win, r, tb);
   }
 }
 
 // Restriction snapshot: ion j adds (a0, a1)[j] to block key[j] and (b0, b1)[j]
-// to block key[j] + 1 for the (density, momentum) moments.  FP32 partial sums
-// in a fixed order, converted to fixed point before the integer atomics.
+// to block key[j] + 1 for the (density, momentum) moments.  Every distinct
+// block of the wave is merged (FP32 partial sums in a fixed order, converted to
+// fixed point); the merged values go to per-lane slot registers, lane s of the
+// wave owning block base + s, so that no LDS atomics are needed.  Blocks outside
+// the 64-block slot window go to global atomics.
 __device__ __forceinline__ void merge_moments(int (&key)[kBatch], const float (&a0)[kBatch],
                                               const float (&a1)[kBatch],
                                               const float (&b0)[kBatch],
-                                              const float (&b1)[kBatch], int wrap,
-                                              const Window& w0, const Window& w1) {
+                                              const float (&b1)[kBatch], int wrap, int base,
+                                              long long& acc0, long long& acc1,
+                                              long long* g0, long long* g1) {
   const int lane = __lane_id();
   while (true) {
     int mine = -1;
@@ -185,50 +200,34 @@ __device__ __forceinline__ void merge_moments(int (&key)[kBatch], const float (&
     const int leader = __ffsll((unsigned long long)act) - 1;
     const int lk = __builtin_amdgcn_readlane(mine, leader);
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    bool has = false;
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j)
-      if (key[j] == lk) {
-        s0 += a0[j];
-        s1 += a1[j];
-        s2 += b0[j];
-        s3 += b1[j];
-        has = true;
-        key[j] = -1;
-      }
-    if (__popcll(__ballot(has)) < kMinMerge) {
-      int r = lk + 1;
-      if (r == wrap) r = 0;
-      if (has) {
-        add_to(w0, lk, fx_of(s0));
-        add_to(w1, lk, fx_of(s1));
-        add_to(w0, r, fx_of(s2));
-        add_to(w1, r, fx_of(s3));
-      }
-#pragma unroll
-      for (int j = 0; j < kBatch; ++j)
-        if (key[j] >= 0) {
-          int rr = key[j] + 1;
-          if (rr == wrap) rr = 0;
-          add_to(w0, key[j], fx_of(a0[j]));
-          add_to(w1, key[j], fx_of(a1[j]));
-          add_to(w0, rr, fx_of(b0[j]));
-          add_to(w1, rr, fx_of(b1[j]));
-          key[j] = -1;
-        }
-      break;
+    for (int j = 0; j < kBatch; ++j) {
+      const bool m = key[j] == lk;
+      s0 += m ? a0[j] : 0.f;
+      s1 += m ? a1[j] : 0.f;
+      s2 += m ? b0[j] : 0.f;
+      s3 += m ? b1[j] : 0.f;
+      key[j] = m ? -1 : key[j];
     }
-    const float t0 = wave_sum_f32(s0);
-    const float t1 = wave_sum_f32(s1);
-    const float t2 = wave_sum_f32(s2);
-    const float t3 = wave_sum_f32(s3);
-    if (lane == leader) {
-      int r = lk + 1;
-      if (r == wrap) r = 0;
-      add_to(w0, lk, fx_of(t0));
-      add_to(w1, lk, fx_of(t1));
-      add_to(w0, r, fx_of(t2));
-      add_to(w1, r, fx_of(t3));
+    const long long f0 = fx_of(wave_sum_f32(s0));
+    const long long f1 = fx_of(wave_sum_f32(s1));
+    const long long f2 = fx_of(wave_sum_f32(s2));
+    const long long f3 = fx_of(wave_sum_f32(s3));
+    int r = lk + 1;
+    if (r == wrap) r = 0;
+    const int sl = lk - base;
+    const int sr = r - base;
+    acc0 += lane == sl ? f0 : 0ll;
+    acc1 += lane == sl ? f1 : 0ll;
+    acc0 += lane == sr ? f2 : 0ll;
+    acc1 += lane == sr ? f3 : 0ll;
+    if ((unsigned)sl >= (unsigned)kWave && lane == 0) {
+      gatomic_add(g0 + lk, f0);
+      gatomic_add(g1 + lk, f1);
+    }
+    if ((unsigned)sr >= (unsigned)kWave && (f2 | f3) != 0 && lane == 0) {
+      gatomic_add(g0 + r, f2);
+      gatomic_add(g1 + r, f3);
     }
   }
 }
@@ -242,7 +241,10 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
                                                          int tile, int p, int fresh_flag,
                                                          int qsel) {
   __shared__ long long lds_q[kQWin];
-  __shared__ long long lds_r[2][kRWin];
+  __shared__ long long lds_qs[kWaves][kWave];
+  __shared__ long long lds_r[kWaves][2][kRWin];
+  __shared__ float lds_e[kEWin + 1];
+  __shared__ float lds_en[kEWin + 1];
   const int tid = threadIdx.x;
   const bool fresh = fresh_flag != 0;
   constexpr bool restrict_ = (MODE & kRestrict) != 0;
@@ -252,10 +254,10 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
   for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
     const int r = find_replica(item_prefix, n_reps, item);
     const RepDev& R = reps[r];
-    const int64_t np = *R.np;
+    const int64_t np = uniform_i64(*R.np);
     const int64_t i0 = (item - R.item_begin) * (int64_t)tile;
     if (i0 >= np) continue;
-    const int64_t i1 = min(i0 + (int64_t)tile, np);
+    const unsigned cnt = (unsigned)min((int64_t)tile, np - i0);
     const int n = R.n_cells;
     const bool periodic = (R.bc == 0);
     const int nmask = n - 1;
@@ -266,40 +268,90 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
     // p < 0: plain restriction of the current state (tau = 0, snapshot slot 0)
     const float tau = p < 0 ? 0.f : (float)(R.macro_dt - (double)p * R.dt);
     const bool coev = R.coevolving != 0 && p >= 0;
-    const float* __restrict__ e = R.e;
-    const float* __restrict__ en = R.en;
-    int16_t* __restrict__ cellp = R.cell;
-    float* __restrict__ fracp = R.frac;
-    float* __restrict__ vp_ = R.v;
-    const float* __restrict__ wp = R.w;
+    const EFPI_GLOBAL float* __restrict__ e = gptr(R.e);
+    const EFPI_GLOBAL float* __restrict__ en = gptr(R.en);
+    EFPI_GLOBAL int16_t* __restrict__ cellp = gptr(R.cell + i0);
+    EFPI_GLOBAL float* __restrict__ fracp = gptr(R.frac + i0);
+    EFPI_GLOBAL float* __restrict__ vp_ = gptr(R.v + i0);
+    const EFPI_GLOBAL float* __restrict__ wp = gptr(R.w + i0);
+    const float half_dt = 0.5f * dt;
+    const float dt_inv_h = dt * inv_h;
+    const float tau_inv_h = coev ? tau * inv_h : 0.f;
+    const float tau_e = coev ? tau : 0.f;
 
-    const int c_first = cellp[i0];
+    const int c_first = __builtin_amdgcn_readfirstlane((int)cellp[0]);
     Window wq{lds_q, c_first - kQMargin, kQWin, reinterpret_cast<long long*>(R.q[qsel])};
     long long* rb = reinterpret_cast<long long*>(R.rbins) + (int64_t)(p < 0 ? 0 : p) * 2 * nc;
     const int rbase = (c_first >> levels) - kRMargin;
-    Window wr0{lds_r[0], rbase, kRWin, rb};
-    Window wr1{lds_r[1], rbase, kRWin, rb + nc};
+    long long racc0 = 0, racc1 = 0;
+    const int qbase = c_first - kQSlotMargin;
+    long long qacc = 0;
 
     for (int k = tid; k < kQWin; k += kThreads) lds_q[k] = 0;
-    for (int k = tid; k < 2 * kRWin; k += kThreads) (&lds_r[0][0])[k] = 0;
+    // Field window: nodes ebase .. ebase + kEWin (wrapped, or clamped to the wall
+    // nodes), so that a cell c in [ebase, ebase + kEWin) finds E_c and E_{c+1}.
+    const int ebase = c_first - kEMargin;
+    if (restrict_ || push) {
+      for (int k = tid; k <= kEWin; k += kThreads) {
+        const int g = periodic ? ((ebase + k) & nmask) : min(max(ebase + k, 0), n);
+        lds_e[k] = e[g];
+        if (restrict_) lds_en[k] = coev ? en[g] : 0.f;
+      }
+    }
     __syncthreads();
 
-    for (int64_t b0 = i0; b0 < i1; b0 += (int64_t)kThreads * kBatch) {
+    for (unsigned b0 = 0; b0 < cnt; b0 += kThreads * kBatch) {
+      // loads use a clamped index so that they are unconditional; slots past the
+      // end of the tile are marked dead and never stored
       int cl[kBatch];
       float fr[kBatch], vv[kBatch], ww[kBatch];
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
-        const int64_t idx = b0 + (int64_t)j * kThreads + tid;
-        if (idx < i1) {
-          cl[j] = cellp[idx];
-          fr[j] = fracp[idx];
-          vv[j] = vp_[idx];
-          ww[j] = wp[idx];
-        } else {
-          cl[j] = -1;
-          fr[j] = 0.f;
-          vv[j] = 0.f;
-          ww[j] = 0.f;
+        const unsigned idx = b0 + j * kThreads + tid;
+        const unsigned ci = min(idx, cnt - 1u);
+        __builtin_assume(ci < 65536u);  // tiles hold at most 65536 ions
+        const int c = cellp[ci];
+        cl[j] = idx < cnt ? c : -1;
+        fr[j] = fracp[ci];
+        vv[j] = vp_[ci];
+        ww[j] = wp[ci];
+      }
+      // Node fields at both ends of each ion's cell, from the LDS window; ions
+      // outside it (rare: unsorted or far-drifted stores) read global memory.
+      float e0[kBatch], e1[kBatch], n0[kBatch], n1[kBatch];
+      bool outside = false;
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const int c = cl[j];
+        const bool alive = c >= 0 && c < n;
+        const int k = alive ? c - ebase : 0;
+        const bool inw = (unsigned)k < (unsigned)kEWin;
+        const int kk = inw ? k : 0;
+        outside |= !inw;
+        e0[j] = e1[j] = n0[j] = n1[j] = 0.f;
+        if (restrict_ || push) {
+          e0[j] = lds_e[kk];
+          e1[j] = lds_e[kk + 1];
+        }
+        if (restrict_) {
+          n0[j] = lds_en[kk];
+          n1[j] = lds_en[kk + 1];
+        }
+      }
+      if ((restrict_ || push) && __ballot(outside) != 0ull) {
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+          const int c = cl[j];
+          const bool alive = c >= 0 && c < n;
+          if (alive && (unsigned)(c - ebase) >= (unsigned)kEWin) {
+            const int cr = periodic ? ((c + 1) & nmask) : c + 1;
+            e0[j] = e[c];
+            e1[j] = e[cr];
+            if (restrict_ && coev) {
+              n0[j] = en[c];
+              n1[j] = en[cr];
+            }
+          }
         }
       }
       int rkey[kBatch], dkey[kBatch];
@@ -307,104 +359,101 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
       long long da[kBatch], db[kBatch];
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
-        const int64_t idx = b0 + (int64_t)j * kThreads + tid;
-        int c = cl[j];
-        float f = fr[j];
-        float v = vv[j];
+        const unsigned idx = b0 + j * kThreads + tid;
+        __builtin_assume(idx < 65536u + kThreads * kBatch);
+        const int c = cl[j];
+        const float f = fr[j];
+        const float v = vv[j];
         const float w = ww[j];
         const bool alive = c >= 0 && c < n;  // cells outside [0, N) are treated as absorbed
+        const int cs = alive ? c : 0;         // safe cell index
         float ep = 0.f;
-        if (alive && (restrict_ || push)) {
-          const int cr = periodic ? ((c + 1) & nmask) : c + 1;
-          ep = (1.f - f) * e[c] + f * e[cr];
-        }
+        if (restrict_ || push) ep = (1.f - f) * e0[j] + f * e1[j];
         rkey[j] = -1;
         ra0[j] = ra1[j] = rb0[j] = rb1[j] = 0.f;
-        if (restrict_ && alive) {
+        if (restrict_) {
           // Snapshot p: time-centred velocity, then the approximate characteristic
           // over tau = Delta t - p dt (eq. B.4) and CIC at the moved position (eq. B.5).
-          const float vp = fresh ? v : v + 0.5f * dt * ep;
-          float xt = f;
-          float vt = vp;
-          if (coev) {
-            const int cr = periodic ? ((c + 1) & nmask) : c + 1;
-            const float enx = (1.f - f) * en[c] + f * en[cr];
-            xt = f + tau * vp * inv_h;
-            vt = vp + tau * enx;
-          }
+          const float vpc = fresh ? v : v + half_dt * ep;
+          const float enx = (1.f - f) * n0[j] + f * n1[j];
+          const float xt = f + tau_inv_h * vpc;
+          const float vt = vpc + tau_e * enx;
           const float fl = floorf(xt);
-          int ct = c + (int)fl;
-          float th = xt - fl;
-          if (th >= 1.f) { th = 0.f; ct += 1; }
-          bool in = true;
-          if (periodic) ct &= nmask;
-          else in = (ct >= 0 && ct < n);
-          if (in) {
-            const float wv = w * vt;
-            const int bl = ct >> levels;
-            int nr = ct + 1;
-            if (periodic) nr &= nmask;
-            int br = nr >> levels;
-            if (br >= nc) br = nc - 1;  // wall node N joins the last block
-            rkey[j] = bl;
-            if (br == bl) {
-              ra0[j] = w;
-              ra1[j] = wv;
-            } else {
-              ra0[j] = w - w * th;
-              ra1[j] = wv - wv * th;
-              rb0[j] = w * th;
-              rb1[j] = wv * th;
-            }
-          }
+          const bool wrap_up = (xt - fl) >= 1.f;
+          const float th = wrap_up ? 0.f : xt - fl;
+          const int ct0 = cs + (int)fl + (wrap_up ? 1 : 0);
+          const int ct = periodic ? (ct0 & nmask) : ct0;
+          const bool in = alive && (periodic || (ct >= 0 && ct < n));
+          const float wv = w * vt;
+          const int bl = ct >> levels;
+          const int nr = periodic ? ((ct + 1) & nmask) : ct + 1;
+          const int br = min(nr >> levels, nc - 1);  // wall node N joins the last block
+          const bool same = br == bl;
+          const float nrs = w * th, jrs = wv * th;
+          rkey[j] = in ? bl : -1;
+          ra0[j] = same ? w : w - nrs;
+          ra1[j] = same ? wv : wv - jrs;
+          rb0[j] = same ? 0.f : nrs;
+          rb1[j] = same ? 0.f : jrs;
         }
         dkey[j] = -1;
         da[j] = db[j] = 0;
-        if (deposit && alive) {
+        if (deposit) {
+          int cn = cs;
+          float fn = f, vn = v;
           if (push) {
-            v = fresh ? v + 0.5f * dt * ep : v + dt * ep;
-            const float xn = f + dt * v * inv_h;
+            vn = fresh ? v + half_dt * ep : v + dt * ep;
+            const float xn = f + dt_inv_h * vn;
             const float fl = floorf(xn);
-            c += (int)fl;
-            f = xn - fl;
-            if (f >= 1.f) { f = 0.f; c += 1; }
-            if (periodic) c &= nmask;
-            else if (c < 0 || c >= n) c = -1;  // absorbed by a wall
+            const bool wrap_up = (xn - fl) >= 1.f;
+            fn = wrap_up ? 0.f : xn - fl;
+            cn = cs + (int)fl + (wrap_up ? 1 : 0);
+            cn = periodic ? (cn & nmask) : ((cn < 0 || cn >= n) ? -1 : cn);  // walls absorb
+            if (alive && idx < cnt) {
+              cellp[idx] = (int16_t)cn;
+              fracp[idx] = fn;
+              vp_[idx] = vn;
+            }
           }
-          if (c >= 0) {
-            const long long q = fx_charge(w);
-            const long long qr = fx_share(f, q);
-            dkey[j] = c;
-            da[j] = q - qr;
-            db[j] = qr;
-          }
-        }
-        if (push && alive && idx < i1) {
-          cellp[idx] = (int16_t)c;
-          fracp[idx] = f;
-          vp_[idx] = v;
+          const bool dep = alive && cn >= 0;
+          const long long q = fx_charge(w);
+          const long long qr = fx_share(fn, q);
+          dkey[j] = dep ? cn : -1;
+          da[j] = q - qr;
+          db[j] = qr;
         }
       }
-      if (restrict_) merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, wr0, wr1);
-      if (deposit) merge_charge(dkey, da, db, periodic ? n : -1, wq);
+      if (restrict_)
+        merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, rbase, racc0, racc1, rb,
+                      rb + nc);
+      if (deposit) merge_charge(dkey, da, db, periodic ? n : -1, qbase, qacc, wq);
+    }
+    if (deposit) lds_qs[tid / kWave][tid % kWave] = qacc;
+    if (restrict_) {
+      lds_r[tid / kWave][0][tid % kWave] = racc0;
+      lds_r[tid / kWave][1][tid % kWave] = racc1;
     }
     __syncthreads();
     if (deposit) {
       long long* gq = reinterpret_cast<long long*>(R.q[qsel]);
       for (int k = tid; k < kQWin; k += kThreads) {
-        const long long val = lds_q[k];
-        if (val != 0)
-          atomicAdd(reinterpret_cast<unsigned long long*>(&gq[wq.base + k]), (unsigned long long)val);
+        long long val = lds_q[k];
+        const int s = k - (kQMargin - kQSlotMargin);  // slot of node wq.base + k
+        if (s >= 0 && s < kWave) {
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) val += lds_qs[w][s];
+        }
+        if (val != 0) gatomic_add(&gq[wq.base + k], val);
       }
     }
     if (restrict_) {
       for (int k = tid; k < 2 * kRWin; k += kThreads) {
         const int m = k / kRWin;
         const int kk = k - m * kRWin;
-        const long long val = lds_r[m][kk];
-        if (val != 0)
-          atomicAdd(reinterpret_cast<unsigned long long*>(&rb[(int64_t)m * nc + rbase + kk]),
-                    (unsigned long long)val);
+        long long val = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) val += lds_r[w][m][kk];
+        if (val != 0) gatomic_add(&rb[(int64_t)m * nc + rbase + kk], val);
       }
     }
     __syncthreads();
@@ -449,30 +498,46 @@ __global__ void k_copy_particles(const RepDev* reps, int rep, const int16_t* cel
 
 }  // namespace
 
+namespace {
+// With both events given, the launch records the kernel's own start and end
+// timestamps in them (the same interval a kernel trace reports).
+template <int MODE>
+void launch_mode(dim3 grid, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1,
+                 const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
+                 int64_t total_items, int tile, int p, int fresh, int qsel) {
+  if (ev0 && ev1)
+    hipExtLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, ev0, ev1, 0, d_reps,
+                          d_item_prefix, n_reps, total_items, tile, p, fresh, qsel);
+  else
+    hipLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, d_reps, d_item_prefix,
+                       n_reps, total_items, tile, p, fresh, qsel);
+}
+}  // namespace
+
 void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
                       int64_t total_items, int tile, int grid_blocks, int p, int flags,
-                      int qsel, hipStream_t stream) {
+                      int qsel, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
   if (total_items <= 0) return;
   const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_items) : total_items;
   const int fresh = (flags & kFresh) ? 1 : 0;
   const int mode = flags & (kRestrict | kPush | kDepositOnly);
-  const dim3 grid((unsigned)g), block(kThreads);
+  const dim3 grid((unsigned)g);
   switch (mode) {
     case kRestrict | kPush:
-      hipLaunchKernelGGL(k_particles<kRestrict | kPush>, grid, block, 0, stream, d_reps,
-                         d_item_prefix, n_reps, total_items, tile, p, fresh, qsel);
+      launch_mode<kRestrict | kPush>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps,
+                                     total_items, tile, p, fresh, qsel);
       break;
     case kPush:
-      hipLaunchKernelGGL(k_particles<kPush>, grid, block, 0, stream, d_reps, d_item_prefix, n_reps,
-                         total_items, tile, p, fresh, qsel);
+      launch_mode<kPush>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps, total_items, tile,
+                         p, fresh, qsel);
       break;
     case kRestrict:
-      hipLaunchKernelGGL(k_particles<kRestrict>, grid, block, 0, stream, d_reps, d_item_prefix,
-                         n_reps, total_items, tile, p, fresh, qsel);
+      launch_mode<kRestrict>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps, total_items,
+                             tile, p, fresh, qsel);
       break;
     default:
-      hipLaunchKernelGGL(k_particles<kDepositOnly>, grid, block, 0, stream, d_reps, d_item_prefix,
-                         n_reps, total_items, tile, p, fresh, qsel);
+      launch_mode<kDepositOnly>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps,
+                                total_items, tile, p, fresh, qsel);
       break;
   }
 }

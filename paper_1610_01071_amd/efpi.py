@@ -14,7 +14,8 @@ from dataclasses import dataclass, field
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libefpi.so")
+# EFPI_LIBRARY may name another build of the same library (e.g. to compare builds).
+LIB_PATH = os.environ.get("EFPI_LIBRARY") or os.path.join(HERE, "libefpi.so")
 
 ABI_VERSION = 1
 BC_PERIODIC, BC_WALLS = 0, 1
