@@ -215,6 +215,80 @@ efpi_status efpi_ensemble_mean(efpi_ctx* ctx, double* d_coarse);
  * ions (cell -1) are dropped.  Needs EFPI_FLAG_SORT_BUFFER. */
 efpi_status efpi_sort(efpi_ctx* ctx);
 
+/* ------------------------------------------------- learned projection -- */
+/*
+ * A small network replaces the least-squares slope (eq. 3.18) in the
+ * projective step (eq. 3.17) on macro steps that skip the fine burst:
+ *   x = features(c_{n-2}, c_{n-1}, c_n),  y = net(x),  c_{n+1} = c_n + delta * y.
+ * Features, per moment m (0 density, 1 momentum) and coarse index k:
+ *   x[m]   = (c_n - mu_m) / sigma_m,
+ *   x[2+m] = (c_n - c_{n-1}) / delta_m,   x[4+m] = (c_{n-1} - c_{n-2}) / delta_m.
+ * Network: 1D convolutions over k, widths 6 -> 64 -> 64 -> 64 -> 2, kernel 3,
+ * SiLU after the first three, circular padding (periodic) or zero padding
+ * (walls).  Parameters: one FP32 vector of EFPI_NN_PARAMS values, per layer
+ * W[c_out][c_in][3] followed by b[c_out].  The matrix cores take bfloat16
+ * weights and activations with FP32 accumulation; efpi_nn_pack and
+ * efpi_nn_adam keep the bfloat16 weight pack (EFPI_NN_PACK_BYTES, 16-byte
+ * aligned, caller-owned) in step with the FP32 parameters.  Activations are
+ * FP32 [batch][channel][n_c].  These calls take the HIP stream directly and
+ * need no context; none allocates memory.
+ */
+#define EFPI_NN_CIN 6
+#define EFPI_NN_HIDDEN 64
+#define EFPI_NN_COUT 2
+#define EFPI_NN_PARAMS 26306
+#define EFPI_NN_PACK_BYTES 112640
+
+typedef struct {
+  float mu[2];     /* feature shift of c_n per moment                          */
+  float sigma[2];  /* feature scale of c_n per moment                          */
+  float delta[2];  /* scale of the increments (inputs 2..5 and the output)     */
+} efpi_nn_norm;
+
+/* Bytes of device workspace (activations, gradient partials) for `batch`
+ * samples of n_c coarse points (host only). */
+efpi_status efpi_nn_workspace_size(int32_t batch, int32_t n_c, size_t* h_bytes);
+
+/* Write the bfloat16 weight pack from FP32 parameters. */
+efpi_status efpi_nn_pack(const float* d_params, void* d_pack, void* hip_stream);
+
+/* Forward pass: d_y[batch][2][n_c] = net(d_x[batch][6][n_c]).  Keeps the layer
+ * activations in d_ws for a following efpi_nn_backward of the same batch. */
+efpi_status efpi_nn_forward(const float* d_params, const void* d_pack, const float* d_x,
+                            float* d_y, int32_t batch, int32_t n_c, int32_t periodic, void* d_ws,
+                            size_t ws_bytes, void* hip_stream);
+
+/* Backward pass of the last forward on d_ws: d_grad[EFPI_NN_PARAMS] = gradient
+ * of sum(d_dy * y).  Summation order is fixed, so the result is deterministic. */
+efpi_status efpi_nn_backward(const void* d_pack, const float* d_x, const float* d_dy,
+                             float* d_grad, int32_t batch, int32_t n_c, int32_t periodic,
+                             void* d_ws, size_t ws_bytes, void* hip_stream);
+
+/* Mean squared error over `count` values: *d_loss = mean((y - t)^2) and
+ * d_dy = 2 (y - t) / count (FP32; one workgroup, fixed order). */
+efpi_status efpi_nn_mse(const float* d_y, const float* d_t, float* d_dy, float* d_loss,
+                        int64_t count, void* hip_stream);
+
+/* One Adam step (Kingma & Ba 2015; `step` counts from 1) on the FP32
+ * parameters with moments d_m, d_v, then refresh the bfloat16 pack. */
+efpi_status efpi_nn_adam(float* d_params, const float* d_grad, float* d_m, float* d_v,
+                         int32_t step, float lr, float beta1, float beta2, float eps,
+                         void* d_pack, void* hip_stream);
+
+/* Features of `batch` samples from a state sequence d_states[n_states][2][n_c]
+ * (FP64): sample b uses states n-2, n-1, n with n = d_index[b] (device int32,
+ * clamped to [2, n_states - 1], or to [2, n_states - 2] when d_t is given).
+ * Writes d_x[batch][6][n_c] and, when d_t is not NULL, the training target
+ * d_t[batch][2][n_c] = (c_{n+1} - c_n) / delta. */
+efpi_status efpi_nn_features(const double* d_states, int32_t n_states, const int32_t* d_index,
+                             int32_t batch, int32_t n_c, const efpi_nn_norm* h_norm, float* d_x,
+                             float* d_t, void* hip_stream);
+
+/* Learned projective step: d_c_next = d_c_n + delta * d_y, all [batch][2][n_c]
+ * (states FP64, d_y FP32).  d_c_next may alias d_c_n. */
+efpi_status efpi_nn_step(const double* d_c_n, const float* d_y, int32_t batch, int32_t n_c,
+                         const efpi_nn_norm* h_norm, double* d_c_next, void* hip_stream);
+
 /* ---------------------------------------------------------------- status -- */
 
 /* Wait for the stream, return the device status bits in *h_bits (may be NULL)

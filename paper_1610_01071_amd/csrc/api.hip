@@ -705,6 +705,113 @@ efpi_status efpi_timing_read(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launc
   return EFPI_OK;
 }
 
+// ------------------------------------------------------ learned projection
+
+efpi_status efpi_nn_workspace_size(int32_t batch, int32_t n_c, size_t* h_bytes) {
+  if (!h_bytes) return fail(EFPI_EINVAL, "h_bytes is NULL");
+  if (batch < 1 || n_c < 1) return fail(EFPI_EINVAL, "batch and n_c must be >= 1");
+  *h_bytes = sizeof(float) * nn::workspace_floats(batch, n_c);
+  return EFPI_OK;
+}
+
+namespace {
+efpi_status check_nn_shape(int32_t batch, int32_t n_c, void* d_ws, size_t ws_bytes) {
+  if (batch < 1 || n_c < 1) return fail(EFPI_EINVAL, "batch and n_c must be >= 1");
+  if (batch > 65535) return fail(EFPI_EINVAL, "batch must be <= 65535");
+  if (!d_ws) return fail(EFPI_EINVAL, "workspace is NULL");
+  if (ws_bytes < sizeof(float) * nn::workspace_floats(batch, n_c))
+    return fail(EFPI_ENOMEM, "nn workspace smaller than efpi_nn_workspace_size");
+  return EFPI_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+}  // namespace
+
+efpi_status efpi_nn_pack(const float* d_params, void* d_pack, void* hip_stream) {
+  if (!d_params || !d_pack) return fail(EFPI_EINVAL, "NULL parameter or pack pointer");
+  if (!aligned16(d_pack)) return fail(EFPI_EINVAL, "pack must be 16-byte aligned");
+  nn::launch_pack(d_params, static_cast<uint16_t*>(d_pack), static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_pack");
+}
+
+efpi_status efpi_nn_forward(const float* d_params, const void* d_pack, const float* d_x,
+                            float* d_y, int32_t batch, int32_t n_c, int32_t periodic, void* d_ws,
+                            size_t ws_bytes, void* hip_stream) {
+  if (!d_params || !d_pack || !d_x || !d_y) return fail(EFPI_EINVAL, "NULL pointer");
+  if (!aligned16(d_pack)) return fail(EFPI_EINVAL, "pack must be 16-byte aligned");
+  const efpi_status st = check_nn_shape(batch, n_c, d_ws, ws_bytes);
+  if (st != EFPI_OK) return st;
+  nn::launch_forward(d_params, static_cast<const uint16_t*>(d_pack), d_x, d_y, batch, n_c,
+                     periodic != 0, static_cast<float*>(d_ws), static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_forward");
+}
+
+efpi_status efpi_nn_backward(const void* d_pack, const float* d_x, const float* d_dy,
+                             float* d_grad, int32_t batch, int32_t n_c, int32_t periodic,
+                             void* d_ws, size_t ws_bytes, void* hip_stream) {
+  if (!d_pack || !d_x || !d_dy || !d_grad) return fail(EFPI_EINVAL, "NULL pointer");
+  if (!aligned16(d_pack)) return fail(EFPI_EINVAL, "pack must be 16-byte aligned");
+  const efpi_status st = check_nn_shape(batch, n_c, d_ws, ws_bytes);
+  if (st != EFPI_OK) return st;
+  nn::launch_backward(static_cast<const uint16_t*>(d_pack), d_x, d_dy, d_grad, batch, n_c,
+                      periodic != 0, static_cast<float*>(d_ws),
+                      static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_backward");
+}
+
+efpi_status efpi_nn_mse(const float* d_y, const float* d_t, float* d_dy, float* d_loss,
+                        int64_t count, void* hip_stream) {
+  if (!d_y || !d_t || !d_dy || !d_loss) return fail(EFPI_EINVAL, "NULL pointer");
+  if (count < 1) return fail(EFPI_EINVAL, "count must be >= 1");
+  nn::launch_mse(d_y, d_t, d_dy, d_loss, count, static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_mse");
+}
+
+efpi_status efpi_nn_adam(float* d_params, const float* d_grad, float* d_m, float* d_v,
+                         int32_t step, float lr, float beta1, float beta2, float eps,
+                         void* d_pack, void* hip_stream) {
+  if (!d_params || !d_grad || !d_m || !d_v || !d_pack) return fail(EFPI_EINVAL, "NULL pointer");
+  if (!aligned16(d_pack)) return fail(EFPI_EINVAL, "pack must be 16-byte aligned");
+  if (step < 1) return fail(EFPI_EINVAL, "step counts from 1");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(EFPI_EINVAL, "Adam hyper-parameters out of range");
+  nn::launch_adam(d_params, d_grad, d_m, d_v, step, lr, beta1, beta2, eps,
+                  static_cast<uint16_t*>(d_pack), static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_adam");
+}
+
+namespace {
+efpi_status check_norm(const efpi_nn_norm* n) {
+  if (!n) return fail(EFPI_EINVAL, "norm is NULL");
+  for (int m = 0; m < 2; ++m)
+    if (!(n->sigma[m] > 0.f) || !(n->delta[m] > 0.f) || !std::isfinite(n->mu[m]))
+      return fail(EFPI_EINVAL, "norm scales must be positive and finite");
+  return EFPI_OK;
+}
+}  // namespace
+
+efpi_status efpi_nn_features(const double* d_states, int32_t n_states, const int32_t* d_index,
+                             int32_t batch, int32_t n_c, const efpi_nn_norm* h_norm, float* d_x,
+                             float* d_t, void* hip_stream) {
+  if (!d_states || !d_index || !d_x) return fail(EFPI_EINVAL, "NULL pointer");
+  if (batch < 1 || n_c < 1) return fail(EFPI_EINVAL, "batch and n_c must be >= 1");
+  if (n_states < (d_t ? 4 : 3)) return fail(EFPI_EINVAL, "too few states");
+  if (check_norm(h_norm) != EFPI_OK) return EFPI_EINVAL;
+  nn::launch_features(d_states, n_states, d_index, batch, n_c, *h_norm, d_x, d_t,
+                      static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_features");
+}
+
+efpi_status efpi_nn_step(const double* d_c_n, const float* d_y, int32_t batch, int32_t n_c,
+                         const efpi_nn_norm* h_norm, double* d_c_next, void* hip_stream) {
+  if (!d_c_n || !d_y || !d_c_next) return fail(EFPI_EINVAL, "NULL pointer");
+  if (batch < 1 || n_c < 1) return fail(EFPI_EINVAL, "batch and n_c must be >= 1");
+  if (check_norm(h_norm) != EFPI_OK) return EFPI_EINVAL;
+  nn::launch_step(d_c_n, d_y, batch, n_c, *h_norm, d_c_next, static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_step");
+}
+
 const char* efpi_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "efpi.h"
+
 namespace efpi {
 
 constexpr double kFxScale = 1099511627776.0;     // 2^40: fixed-point charge unit 2^-40
@@ -94,5 +96,30 @@ void launch_copy_particles(const RepDev* d_reps, int rep, const int16_t* cell, c
 void launch_sort(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
                  int64_t total_items, int tile, int32_t* d_hist, int grid_blocks,
                  hipStream_t stream);
+
+// Learned projection network (nn.hip).
+constexpr int kNnCin = EFPI_NN_CIN;
+constexpr int kNnHidden = EFPI_NN_HIDDEN;
+constexpr int kNnCout = EFPI_NN_COUT;
+constexpr int kNnParams = EFPI_NN_PARAMS;
+constexpr int kNnPackForward = 29696;  // bf16 elements of the four forward packs
+constexpr int kNnPackElems = EFPI_NN_PACK_BYTES / 2;
+
+namespace nn {
+size_t workspace_floats(int batch, int nc);
+void launch_pack(const float* params, uint16_t* pack, hipStream_t stream);
+void launch_forward(const float* params, const uint16_t* pack, const float* x, float* y,
+                    int batch, int nc, int periodic, float* ws, hipStream_t stream);
+void launch_backward(const uint16_t* pack, const float* x, const float* dy, float* grad,
+                     int batch, int nc, int periodic, float* ws, hipStream_t stream);
+void launch_mse(const float* y, const float* t, float* dy, float* loss, int64_t count,
+                hipStream_t stream);
+void launch_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
+                 float b1, float b2, float eps, uint16_t* pack, hipStream_t stream);
+void launch_features(const double* states, int n_states, const int32_t* index, int batch, int nc,
+                     const efpi_nn_norm& nm, float* x, float* t, hipStream_t stream);
+void launch_step(const double* cn, const float* y, int batch, int nc, const efpi_nn_norm& nm,
+                 double* out, hipStream_t stream);
+}  // namespace nn
 
 }  // namespace efpi

@@ -66,6 +66,16 @@ class Config(ctypes.Structure):
     ]
 
 
+class NnNorm(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_float * 2), ("sigma", ctypes.c_float * 2),
+                ("delta", ctypes.c_float * 2)]
+
+
+NN_CIN, NN_HIDDEN, NN_COUT = 6, 64, 2
+NN_PARAMS = 26306
+NN_PACK_BYTES = 112640
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libefpi.so is not built ({LIB_PATH}); run `python -m paper_1610_01071_amd._build`")
@@ -94,6 +104,15 @@ def _load():
         "efpi_sync": [P, ctypes.POINTER(U32)],
         "efpi_timing": [P, I32],
         "efpi_timing_read": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)],
+        "efpi_nn_workspace_size": [I32, I32, ctypes.POINTER(ctypes.c_size_t)],
+        "efpi_nn_pack": [P, P, P],
+        "efpi_nn_forward": [P, P, P, P, I32, I32, I32, P, ctypes.c_size_t, P],
+        "efpi_nn_backward": [P, P, P, P, I32, I32, I32, P, ctypes.c_size_t, P],
+        "efpi_nn_mse": [P, P, P, P, I64, P],
+        "efpi_nn_adam": [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         ctypes.c_float, P, P],
+        "efpi_nn_features": [P, I32, P, I32, I32, ctypes.POINTER(NnNorm), P, P, P],
+        "efpi_nn_step": [P, P, I32, I32, ctypes.POINTER(NnNorm), P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -113,7 +132,9 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_load_profile", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
             "efpi_restrict", "efpi_project", "efpi_macro_step", "efpi_ensemble_mean", "efpi_sort",
             "efpi_restrict_state",
-            "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error"]
+            "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error",
+            "efpi_nn_workspace_size", "efpi_nn_pack", "efpi_nn_forward", "efpi_nn_backward",
+            "efpi_nn_mse", "efpi_nn_adam", "efpi_nn_features", "efpi_nn_step"]
 
 
 def _check(status: int):
@@ -309,6 +330,61 @@ def efpi_timing_read(ctx):
 
 def efpi_last_error() -> str:
     return LIB.efpi_last_error().decode()
+
+
+def nn_norm(mu, sigma, delta) -> NnNorm:
+    f2 = ctypes.c_float * 2
+    return NnNorm(f2(*[float(a) for a in mu]), f2(*[float(a) for a in sigma]),
+                  f2(*[float(a) for a in delta]))
+
+
+def efpi_nn_workspace_size(batch: int, n_c: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(LIB.efpi_nn_workspace_size(batch, n_c, ctypes.byref(out)))
+    return out.value
+
+
+def efpi_nn_pack(params, pack, stream=None):
+    _check(LIB.efpi_nn_pack(_dev(params, torch.float32), _dev(pack, torch.uint8), _stream(stream)))
+
+
+def efpi_nn_forward(params, pack, x, y, batch, n_c, periodic, ws, stream=None):
+    _check(LIB.efpi_nn_forward(_dev(params, torch.float32), _dev(pack, torch.uint8),
+                               _dev(x, torch.float32), _dev(y, torch.float32), batch, n_c,
+                               1 if periodic else 0, _dev(ws, torch.uint8), ws.numel(),
+                               _stream(stream)))
+
+
+def efpi_nn_backward(pack, x, dy, grad, batch, n_c, periodic, ws, stream=None):
+    _check(LIB.efpi_nn_backward(_dev(pack, torch.uint8), _dev(x, torch.float32),
+                                _dev(dy, torch.float32), _dev(grad, torch.float32), batch, n_c,
+                                1 if periodic else 0, _dev(ws, torch.uint8), ws.numel(),
+                                _stream(stream)))
+
+
+def efpi_nn_mse(y, t, dy, loss, stream=None):
+    _check(LIB.efpi_nn_mse(_dev(y, torch.float32), _dev(t, torch.float32),
+                           _dev(dy, torch.float32), _dev(loss, torch.float32), y.numel(),
+                           _stream(stream)))
+
+
+def efpi_nn_adam(params, grad, m, v, step, lr, pack, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+    _check(LIB.efpi_nn_adam(_dev(params, torch.float32), _dev(grad, torch.float32),
+                            _dev(m, torch.float32), _dev(v, torch.float32), step, lr, beta1,
+                            beta2, eps, _dev(pack, torch.uint8), _stream(stream)))
+
+
+def efpi_nn_features(states, index, n_c, norm: NnNorm, x, t=None, stream=None):
+    n_states = states.numel() // (2 * n_c)
+    _check(LIB.efpi_nn_features(_dev(states, torch.float64), n_states, _dev(index, torch.int32),
+                                index.numel(), n_c, ctypes.byref(norm), _dev(x, torch.float32),
+                                _dev(t, torch.float32), _stream(stream)))
+
+
+def efpi_nn_step(c_n, y, batch, n_c, norm: NnNorm, c_next, stream=None):
+    _check(LIB.efpi_nn_step(_dev(c_n, torch.float64), _dev(y, torch.float32), batch, n_c,
+                            ctypes.byref(norm), _dev(c_next, torch.float64), _stream(stream)))
 
 
 # --------------------------------------------------------------- convenience
