@@ -289,6 +289,13 @@ efpi_status efpi_nn_features(const double* d_states, int32_t n_states, const int
 efpi_status efpi_nn_step(const double* d_c_n, const float* d_y, int32_t batch, int32_t n_c,
                          const efpi_nn_norm* h_norm, double* d_c_next, void* hip_stream);
 
+/* Relative error of eq. 4.2 between two FP64 arrays of n values:
+ * *d_eps = sqrt(sum (a - b)^2 / sum (a^2 + b^2)) (0 when both are zero), FP64,
+ * one workgroup with a fixed summation order.  The learned projection's judge
+ * compares a learned step with a fine-burst step by it. */
+efpi_status efpi_rel_l2(const double* d_a, const double* d_b, int64_t n, double* d_eps,
+                        void* hip_stream);
+
 /* ---------------------------------------------------------------- status -- */
 
 /* Wait for the stream, return the device status bits in *h_bits (may be NULL)

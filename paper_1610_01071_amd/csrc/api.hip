@@ -812,6 +812,14 @@ efpi_status efpi_nn_step(const double* d_c_n, const float* d_y, int32_t batch, i
   return hip_check("nn_step");
 }
 
+efpi_status efpi_rel_l2(const double* d_a, const double* d_b, int64_t n, double* d_eps,
+                        void* hip_stream) {
+  if (!d_a || !d_b || !d_eps) return fail(EFPI_EINVAL, "NULL pointer");
+  if (n < 1) return fail(EFPI_EINVAL, "n must be >= 1");
+  nn::launch_rel_l2(d_a, d_b, n, d_eps, static_cast<hipStream_t>(hip_stream));
+  return hip_check("rel_l2");
+}
+
 const char* efpi_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

@@ -380,7 +380,35 @@ __global__ void k_step(const double* __restrict__ cn, const float* __restrict__ 
   out[i] = cn[i] + (double)nm.delta[m] * (double)y[i];
 }
 
+// eps(a, b) = sqrt(sum (a - b)^2 / sum (a^2 + b^2)) (eq. 4.2), FP64, fixed order.
+__global__ __launch_bounds__(1024) void k_rel_l2(const double* __restrict__ a,
+                                                 const double* __restrict__ b, int64_t n,
+                                                 double* __restrict__ out) {
+  __shared__ double num[1024], den[1024];
+  double sn = 0.0, sd = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double d = a[i] - b[i];
+    sn += d * d;
+    sd += a[i] * a[i] + b[i] * b[i];
+  }
+  num[threadIdx.x] = sn;
+  den[threadIdx.x] = sd;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      num[threadIdx.x] += num[threadIdx.x + w];
+      den[threadIdx.x] += den[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = den[0] > 0.0 ? sqrt(num[0] / den[0]) : 0.0;
+}
+
 }  // namespace
+
+void launch_rel_l2(const double* a, const double* b, int64_t n, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_rel_l2, dim3(1), dim3(1024), 0, stream, a, b, n, out);
+}
 
 size_t workspace_floats(int batch, int nc) {
   const size_t act = (size_t)batch * kNnHidden * nc;

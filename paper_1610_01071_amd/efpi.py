@@ -113,6 +113,7 @@ def _load():
                          ctypes.c_float, P, P],
         "efpi_nn_features": [P, I32, P, I32, I32, ctypes.POINTER(NnNorm), P, P, P],
         "efpi_nn_step": [P, P, I32, I32, ctypes.POINTER(NnNorm), P, P],
+        "efpi_rel_l2": [P, P, I64, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -134,7 +135,7 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_restrict_state",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error",
             "efpi_nn_workspace_size", "efpi_nn_pack", "efpi_nn_forward", "efpi_nn_backward",
-            "efpi_nn_mse", "efpi_nn_adam", "efpi_nn_features", "efpi_nn_step"]
+            "efpi_nn_mse", "efpi_nn_adam", "efpi_nn_features", "efpi_nn_step", "efpi_rel_l2"]
 
 
 def _check(status: int):
@@ -385,6 +386,14 @@ def efpi_nn_features(states, index, n_c, norm: NnNorm, x, t=None, stream=None):
 def efpi_nn_step(c_n, y, batch, n_c, norm: NnNorm, c_next, stream=None):
     _check(LIB.efpi_nn_step(_dev(c_n, torch.float64), _dev(y, torch.float32), batch, n_c,
                             ctypes.byref(norm), _dev(c_next, torch.float64), _stream(stream)))
+
+
+def efpi_rel_l2(a, b, eps, stream=None):
+    """eps[0] = relative L2 difference of a and b (eq. 4.2), computed on the device."""
+    if a.numel() != b.numel():
+        raise ValueError("a and b differ in size")
+    _check(LIB.efpi_rel_l2(_dev(a, torch.float64), _dev(b, torch.float64), a.numel(),
+                           _dev(eps, torch.float64), _stream(stream)))
 
 
 # --------------------------------------------------------------- convenience

@@ -1,0 +1,105 @@
+"""Learned projective integration on the GPU: trained on coarse trajectories
+that the GPU's own EFPI bursts generate, then run with a fine burst every
+fourth macro step as fallback and judge (paper_1610_01071_amd/learned.py).
+
+Workload: ion-acoustic wave (eq. 4.1) on 1024 cells, 200 ions per cell, l = 4
+(64 coarse points per moment), N_e = 20, dt = 0.1, Delta t = 50 dt, 40 macro
+steps (t = 200).  Training amplitudes delta in {0.1, 0.12, 0.15, 0.25, 0.28,
+0.3}; the test run uses delta = 0.2 and lift rotations no training run used.
+
+What the network gains: the learned run takes most macro steps without a fine
+burst, so its wall time is below that of plain EFPI, while its coarse density
+stays within eps = 2e-3 (eq. 4.2) of plain EFPI at the final time.  The
+momentum coefficients are compared against the spread of plain EFPI itself
+(two plain runs that differ only in their lift rotations).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import lib
+
+pytestmark = pytest.mark.gpu
+
+N, PPC, STEPS = 1024, 200, 40
+
+
+def eps(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(a * a + b * b)))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    E = lib()
+    import paper_1610_01071_amd.learned as L
+    spec = E.ReplicaSpec(N, float(N), ppc=PPC, haar_levels=4, burst_steps=20, macro_dt=5.0,
+                         vth=math.sqrt(0.1))
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4))
+
+    def c0_for(delta, seed):
+        n0, u0 = synth.iaw_profile(N, float(N), delta)
+        E.efpi_load_profile(ctx.ctx, 0, torch.as_tensor(n0, device="cuda"),
+                            torch.as_tensor(u0, device="cuda"), synth.lift_shift(seed))
+        E.efpi_deposit(ctx.ctx)
+        E.efpi_solve_field(ctx.ctx, 30, cold=True)
+        c = ctx.new_coarse()
+        E.efpi_restrict_state(ctx.ctx, c)
+        return c
+
+    trajs = [L.plain_run(ctx, c0_for(d, 100 + k), STEPS, seed=500 + k)
+             for k, d in enumerate([0.1, 0.15, 0.25, 0.3, 0.12, 0.28])]
+    norm = L.fit_norm(trajs)
+    states = torch.cat(trajs, 0).contiguous()
+    T = STEPS + 1
+    train_idx = np.concatenate([np.arange(2, T - 1) + r * T for r in range(len(trajs) - 1)])
+    val_idx = np.arange(2, T - 1) + (len(trajs) - 1) * T
+    tr = L.Trainer(spec.n_coarse, True, batch=32)
+    untrained = tr.evaluate(states, val_idx, norm)
+    tr.train(states, train_idx, norm, 2000)
+    trained = tr.evaluate(states, val_idx, norm)
+    c0 = c0_for(0.2, 999)
+    return dict(E=E, L=L, ctx=ctx, tr=tr, norm=norm, c0=c0, untrained=untrained, trained=trained)
+
+
+def test_training_generalises_to_held_out_run(setup):
+    # the untrained network predicts no change (loss ~ 1 in normalised units)
+    assert setup["untrained"] > 0.5
+    assert setup["trained"] < 0.05 * setup["untrained"]
+
+
+def test_learned_run_matches_plain_efpi_and_is_faster(setup):
+    L, ctx, tr, norm, c0 = setup["L"], setup["ctx"], setup["tr"], setup["norm"], setup["c0"]
+    L.plain_run(ctx, c0, 4, seed=1)  # warm-up
+    torch.cuda.synchronize()
+    import time
+    t0 = time.perf_counter()
+    ref = L.plain_run(ctx, c0, STEPS, seed=77)
+    torch.cuda.synchronize()
+    wall_plain = (time.perf_counter() - t0) * 1e3
+    run = L.run_learned(ctx, tr, norm, c0, STEPS, seed=77, judge_period=4, threshold=2e-3)
+    other = L.plain_run(ctx, c0, STEPS, seed=78)
+    a = run.states[-1].cpu().numpy().reshape(2, -1)
+    b = ref[-1].cpu().numpy().reshape(2, -1)
+    o = other[-1].cpu().numpy().reshape(2, -1)
+    assert eps(a[0], b[0]) <= 2e-3
+    assert eps(a[1], b[1]) <= 3.0 * max(eps(o[1], b[1]), 1e-3)
+    assert run.learned >= STEPS // 2
+    assert run.wall_ms < wall_plain
+
+
+def test_learned_run_is_deterministic(setup):
+    L, ctx, tr, norm, c0 = setup["L"], setup["ctx"], setup["tr"], setup["norm"], setup["c0"]
+    r1 = L.run_learned(ctx, tr, norm, c0, 12, seed=5)
+    r2 = L.run_learned(ctx, tr, norm, c0, 12, seed=5)
+    assert torch.equal(r1.states, r2.states)
+
+
+def test_judge_falls_back_when_threshold_is_tight(setup):
+    L, ctx, tr, norm, c0 = setup["L"], setup["ctx"], setup["tr"], setup["norm"], setup["c0"]
+    run = L.run_learned(ctx, tr, norm, c0, 20, seed=9, judge_period=4, threshold=0.0)
+    assert run.judged >= 1 and run.fallback >= 4
+    # every judged step disagrees with the burst by more than zero
+    assert all(e > 0.0 for e in run.eps)
