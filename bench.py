@@ -14,8 +14,9 @@ Printed: one JSON line with particle-updates/s (K x ions per macro step over
 the macro-step wall time, lift included), the roofline of the dominant kernel
 (the fused push/deposit/restrict particle pass, timed by HIP events inside the
 timed region), the EFPI speedup over full PIC for the same physical time with
-the coarse-density error between them (eq. 4.2), and the CPU oracle timed on a
-bounded sample of the same workload on this host.
+the coarse-density error between them (eq. 4.2), the learned projection
+against plain EFPI (wall time and error at the same physical time), and the
+CPU oracle timed on a bounded sample of the same workload on this host.
 """
 from __future__ import annotations
 
@@ -140,6 +141,7 @@ def main():
     ap.add_argument("--cpu-ppc", type=int, default=1000, help="ions/cell of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-speedup", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB three times (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -239,6 +241,8 @@ def main():
 
     if not args.no_speedup:
         out.update(speedup_sweep(E, torch, np, synth, ctx, spec, c0, args))
+    if not args.no_learned:
+        out["learned_vs_plain"] = learned_leg(E, torch, np, synth, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_ppc, 2016)
     print(json.dumps(out), flush=True)
@@ -309,6 +313,77 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
             "fixed_error_macro_dt_over_dt": best["macro_dt_over_dt"] if best else None,
             "sweep": rows,
         },
+    }
+
+
+def learned_leg(E, torch, np, synth, args):
+    """Learned projection against plain EFPI on the benchmark grid.
+
+    Training data: plain EFPI trajectories (40 macro steps of Delta t = 50 dt,
+    the largest stable step of the sweep) of the ion-acoustic wave at six
+    amplitudes other than 0.2; 2000 Adam steps of batch 32 on the GPU.  Test:
+    delta = 0.2 from the benchmark's initial state, 40 macro steps, plain EFPI
+    against the learned run (fine burst every 4th step as judge and fallback,
+    threshold 2e-3 on the coarse density, eq. 4.2).
+    """
+    import paper_1610_01071_amd.learned as L
+    spec = workload_spec(E)
+    spec.macro_dt = 50 * spec.dt
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4, tile=TILE))
+    steps = 40
+
+    def c0_for(delta, seed):
+        n0, u0 = synth.iaw_profile(spec.n_cells, spec.length, delta)
+        E.efpi_load_profile(ctx.ctx, 0, torch.as_tensor(n0, device="cuda"),
+                            torch.as_tensor(u0, device="cuda"), synth.lift_shift(seed))
+        E.efpi_deposit(ctx.ctx)
+        E.efpi_solve_field(ctx.ctx, 30, cold=True)
+        c = ctx.new_coarse()
+        E.efpi_restrict_state(ctx.ctx, c)
+        return c
+
+    t_gen = time.perf_counter()
+    trajs = [L.plain_run(ctx, c0_for(d, 100 + k), steps, seed=500 + k)
+             for k, d in enumerate([0.1, 0.15, 0.25, 0.3, 0.12, 0.28])]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    norm = L.fit_norm(trajs)
+    states = torch.cat(trajs, 0).contiguous()
+    T = steps + 1
+    train_idx = np.concatenate([np.arange(2, T - 1) + r * T for r in range(len(trajs) - 1)])
+    val_idx = np.arange(2, T - 1) + (len(trajs) - 1) * T
+    tr = L.Trainer(spec.n_coarse, True, batch=32)
+    t_train = time.perf_counter()
+    tr.train(states, train_idx, norm, 2000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    val = tr.evaluate(states, val_idx, norm)
+
+    c0 = c0_for(0.2, 2016)
+    L.plain_run(ctx, c0, 4, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = L.plain_run(ctx, c0, steps, seed=77)
+    torch.cuda.synchronize()
+    wall_plain = (time.perf_counter() - t0) * 1e3
+    run = L.run_learned(ctx, tr, norm, c0, steps, seed=77, judge_period=4, threshold=2e-3)
+    other = L.plain_run(ctx, c0, steps, seed=78)
+    a = run.states[-1].cpu().numpy().reshape(2, -1)
+    b = ref[-1].cpu().numpy().reshape(2, -1)
+    o = other[-1].cpu().numpy().reshape(2, -1)
+
+    def eps(u, w):
+        return float(np.sqrt(np.sum((u - w) ** 2) / np.sum(u * u + w * w)))
+
+    ctx.close()
+    return {
+        "macro_dt_over_dt": 50, "macro_steps": steps, "judge_period": 4, "threshold": 2e-3,
+        "plain_ms": wall_plain, "learned_ms": run.wall_ms, "speedup": wall_plain / run.wall_ms,
+        "eps_density": eps(a[0], b[0]), "eps_momentum": eps(a[1], b[1]),
+        "plain_spread_density": eps(o[0], b[0]), "plain_spread_momentum": eps(o[1], b[1]),
+        "learned_steps": run.learned, "judged_steps": run.judged, "fallback_steps": run.fallback,
+        "judge_eps_max": max(run.eps) if run.eps else None,
+        "datagen_s": t_gen, "train_s": t_train, "train_iters": 2000, "val_loss": val,
     }
 
 

@@ -289,6 +289,15 @@ efpi_status efpi_nn_features(const double* d_states, int32_t n_states, const int
 efpi_status efpi_nn_step(const double* d_c_n, const float* d_y, int32_t batch, int32_t n_c,
                          const efpi_nn_norm* h_norm, double* d_c_next, void* hip_stream);
 
+/* One learned projective step in one call: features of the three consecutive
+ * states d_states[3][2][n_c] (c_{n-2}, c_{n-1}, c_n; FP64), forward pass, and
+ * d_c_next[2][n_c] = c_n + delta * y.  d_ws holds at least
+ * efpi_nn_workspace_size(1, n_c) bytes; d_c_next must not overlap d_states. */
+efpi_status efpi_nn_predict_step(const float* d_params, const void* d_pack,
+                                 const double* d_states, int32_t n_c, int32_t periodic,
+                                 const efpi_nn_norm* h_norm, double* d_c_next, void* d_ws,
+                                 size_t ws_bytes, void* hip_stream);
+
 /* Relative error of eq. 4.2 between two FP64 arrays of n values:
  * *d_eps = sqrt(sum (a - b)^2 / sum (a^2 + b^2)) (0 when both are zero), FP64,
  * one workgroup with a fixed summation order.  The learned projection's judge

@@ -812,6 +812,25 @@ efpi_status efpi_nn_step(const double* d_c_n, const float* d_y, int32_t batch, i
   return hip_check("nn_step");
 }
 
+efpi_status efpi_nn_predict_step(const float* d_params, const void* d_pack,
+                                 const double* d_states, int32_t n_c, int32_t periodic,
+                                 const efpi_nn_norm* h_norm, double* d_c_next, void* d_ws,
+                                 size_t ws_bytes, void* hip_stream) {
+  if (!d_params || !d_pack || !d_states || !d_c_next) return fail(EFPI_EINVAL, "NULL pointer");
+  if (!aligned16(d_pack)) return fail(EFPI_EINVAL, "pack must be 16-byte aligned");
+  const efpi_status st = check_nn_shape(1, n_c, d_ws, ws_bytes);
+  if (st != EFPI_OK) return st;
+  if (check_norm(h_norm) != EFPI_OK) return EFPI_EINVAL;
+  const double* lo = d_states;
+  const double* hi = d_states + 6 * (size_t)n_c;
+  if (d_c_next + 2 * (size_t)n_c > lo && d_c_next < hi)
+    return fail(EFPI_EINVAL, "d_c_next overlaps d_states");
+  nn::launch_predict_step(d_params, static_cast<const uint16_t*>(d_pack), d_states, n_c,
+                          periodic != 0, *h_norm, d_c_next, static_cast<float*>(d_ws),
+                          static_cast<hipStream_t>(hip_stream));
+  return hip_check("nn_predict_step");
+}
+
 efpi_status efpi_rel_l2(const double* d_a, const double* d_b, int64_t n, double* d_eps,
                         void* hip_stream) {
   if (!d_a || !d_b || !d_eps) return fail(EFPI_EINVAL, "NULL pointer");

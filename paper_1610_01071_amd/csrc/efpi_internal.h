@@ -120,6 +120,9 @@ void launch_features(const double* states, int n_states, const int32_t* index, i
                      const efpi_nn_norm& nm, float* x, float* t, hipStream_t stream);
 void launch_step(const double* cn, const float* y, int batch, int nc, const efpi_nn_norm& nm,
                  double* out, hipStream_t stream);
+void launch_predict_step(const float* params, const uint16_t* pack, const double* states, int nc,
+                         int periodic, const efpi_nn_norm& nm, double* out, float* ws,
+                         hipStream_t stream);
 void launch_rel_l2(const double* a, const double* b, int64_t n, double* out, hipStream_t stream);
 }  // namespace nn
 

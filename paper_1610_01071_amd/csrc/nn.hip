@@ -359,7 +359,7 @@ __global__ void k_features(const double* __restrict__ states, int n_states,
   const int m = r / nc;
   const int k = r - m * nc;
   const int hi = t ? n_states - 2 : n_states - 1;
-  const int n = min(max(index[b], 2), hi);
+  const int n = index ? min(max(index[b], 2), hi) : 2;
   const size_t st = 2 * (size_t)nc;
   const double cn = states[n * st + r];
   const double c1 = states[(n - 1) * st + r];
@@ -413,12 +413,12 @@ void launch_rel_l2(const double* a, const double* b, int64_t n, double* out, hip
 size_t workspace_floats(int batch, int nc) {
   const size_t act = (size_t)batch * kNnHidden * nc;
   const size_t nblk = (size_t)batch * ((nc + kTile - 1) / kTile);
-  return 8 * act + nblk * (64 * 192 + 64);
+  return 8 * act + nblk * (64 * 192 + 64) + (size_t)batch * 8 * nc;
 }
 
 namespace {
 struct Ws {
-  float *z0, *a0, *z1, *a1, *z2, *a2, *dza, *dzb, *pw, *pb;
+  float *z0, *a0, *z1, *a1, *z2, *a2, *dza, *dzb, *pw, *pb, *x, *y;
 };
 Ws carve(float* ws, int batch, int nc) {
   const size_t act = (size_t)batch * kNnHidden * nc;
@@ -433,6 +433,8 @@ Ws carve(float* ws, int batch, int nc) {
   w.dzb = w.dza + act;
   w.pw = w.dzb + act;
   w.pb = w.pw + (size_t)batch * ((nc + kTile - 1) / kTile) * 64 * 192;
+  w.x = w.pb + (size_t)batch * ((nc + kTile - 1) / kTile) * 64;
+  w.y = w.x + (size_t)batch * kNnCin * nc;
   return w;
 }
 }  // namespace
@@ -527,6 +529,19 @@ void launch_step(const double* cn, const float* y, int batch, int nc, const efpi
   const int64_t n = (int64_t)batch * 2 * nc;
   hipLaunchKernelGGL(k_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, cn, y, n,
                      nc, nm, out);
+}
+
+void launch_predict_step(const float* params, const uint16_t* pack, const double* states, int nc,
+                         int periodic, const efpi_nn_norm& nm, double* out, float* ws,
+                         hipStream_t stream) {
+  const Ws w = carve(ws, 1, nc);
+  const int64_t n = 2 * (int64_t)nc;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, states,
+                     3, nullptr, 1, nc, nm, w.x, nullptr);
+  launch_forward(params, pack, w.x, w.y, 1, nc, periodic, ws, stream);
+  // states[2] is c_n of the single sample window
+  hipLaunchKernelGGL(k_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                     states + 2 * (size_t)2 * nc, w.y, n, nc, nm, out);
 }
 
 }  // namespace nn

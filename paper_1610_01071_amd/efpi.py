@@ -114,6 +114,8 @@ def _load():
         "efpi_nn_features": [P, I32, P, I32, I32, ctypes.POINTER(NnNorm), P, P, P],
         "efpi_nn_step": [P, P, I32, I32, ctypes.POINTER(NnNorm), P, P],
         "efpi_rel_l2": [P, P, I64, P, P],
+        "efpi_nn_predict_step": [P, P, P, I32, I32, ctypes.POINTER(NnNorm), P, P, ctypes.c_size_t,
+                                 P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -135,7 +137,8 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_restrict_state",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error",
             "efpi_nn_workspace_size", "efpi_nn_pack", "efpi_nn_forward", "efpi_nn_backward",
-            "efpi_nn_mse", "efpi_nn_adam", "efpi_nn_features", "efpi_nn_step", "efpi_rel_l2"]
+            "efpi_nn_mse", "efpi_nn_adam", "efpi_nn_features", "efpi_nn_step", "efpi_rel_l2",
+            "efpi_nn_predict_step"]
 
 
 def _check(status: int):
@@ -386,6 +389,16 @@ def efpi_nn_features(states, index, n_c, norm: NnNorm, x, t=None, stream=None):
 def efpi_nn_step(c_n, y, batch, n_c, norm: NnNorm, c_next, stream=None):
     _check(LIB.efpi_nn_step(_dev(c_n, torch.float64), _dev(y, torch.float32), batch, n_c,
                             ctypes.byref(norm), _dev(c_next, torch.float64), _stream(stream)))
+
+
+def efpi_nn_predict_step(params, pack, states3, n_c, periodic, norm: NnNorm, c_next, ws,
+                         stream=None):
+    if states3.numel() != 6 * n_c:
+        raise ValueError("states3 must hold three coarse states")
+    _check(LIB.efpi_nn_predict_step(_dev(params, torch.float32), _dev(pack, torch.uint8),
+                                    _dev(states3, torch.float64), n_c, 1 if periodic else 0,
+                                    ctypes.byref(norm), _dev(c_next, torch.float64),
+                                    _dev(ws, torch.uint8), ws.numel(), _stream(stream)))
 
 
 def efpi_rel_l2(a, b, eps, stream=None):

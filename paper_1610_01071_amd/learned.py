@@ -160,11 +160,8 @@ def run_learned(ctx: E.Context, trainer: Trainer, norm: E.NnNorm, c0: torch.Tens
     dev = c0.device
     traj = torch.empty(steps + 1, nc2, dtype=torch.float64, device=dev)
     traj[0].copy_(c0)
-    x = torch.empty(1, 6, nc, dtype=torch.float32, device=dev)
-    y = torch.empty(1, 2, nc, dtype=torch.float32, device=dev)
     cand = torch.empty(nc2, dtype=torch.float64, device=dev)
     eps_dev = torch.zeros(2, dtype=torch.float64, device=dev)
-    index = torch.full((1,), 2, dtype=torch.int32, device=dev)
     ws = trainer.workspace(1)
     judged = fallback = learned = 0
     eps_log, eps_mom = [], []
@@ -178,11 +175,10 @@ def run_learned(ctx: E.Context, trainer: Trainer, norm: E.NnNorm, c0: torch.Tens
                 plain_left -= 1
                 fallback += 1
             continue
-        # learned candidate from states n-2, n-1, n
-        E.efpi_nn_features(traj[n - 2:n + 1], index, nc, norm, x)
-        E.efpi_nn_forward(trainer.params, trainer.pack, x, y, 1, nc, trainer.periodic, ws)
+        # learned step from states n-2, n-1, n
         if (n - bootstrap) % judge_period == judge_period - 1:
-            E.efpi_nn_step(traj[n], y, 1, nc, norm, cand)
+            E.efpi_nn_predict_step(trainer.params, trainer.pack, traj[n - 2:n + 1], nc,
+                                   trainer.periodic, norm, cand, ws)
             E.efpi_macro_step(ctx.ctx, traj[n], traj[n + 1], [lift_shift(seed, n)])
             E.efpi_rel_l2(cand[:nc], traj[n + 1][:nc], eps_dev[0:1])
             E.efpi_rel_l2(cand[nc:], traj[n + 1][nc:], eps_dev[1:2])
@@ -193,7 +189,8 @@ def run_learned(ctx: E.Context, trainer: Trainer, norm: E.NnNorm, c0: torch.Tens
             if e > threshold:
                 plain_left = judge_period
         else:
-            E.efpi_nn_step(traj[n], y, 1, nc, norm, traj[n + 1])
+            E.efpi_nn_predict_step(trainer.params, trainer.pack, traj[n - 2:n + 1], nc,
+                                   trainer.periodic, norm, traj[n + 1], ws)
             learned += 1
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3

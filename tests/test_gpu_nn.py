@@ -180,3 +180,24 @@ def test_training_reduces_loss():
         if step in (1, 500):
             losses.append(loss.item())
     assert losses[1] < 0.1 * losses[0]
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_predict_step_matches_oracle(periodic):
+    """Fused features + forward + step against the oracle's learned step."""
+    E = lib()
+    g = np.random.default_rng(21)
+    n_c = 96
+    theta = theta_f32(21)
+    states = 1.0 + 0.1 * g.standard_normal((3, 2, n_c))
+    norm_t = ([1.0, 0.05], [0.1, 0.08], [2e-3, 3e-3])
+    norm32 = tuple(np.array(a, np.float32).astype(np.float64) for a in norm_t)
+    net = Net(theta, 1, n_c)
+    out = torch.empty(2 * n_c, dtype=torch.float64, device="cuda")
+    E.efpi_nn_predict_step(net.params, net.pack, to_dev(states, torch.float64), n_c, periodic,
+                           E.nn_norm(*norm_t), out, net.ws)
+    got = out.cpu().numpy().reshape(2, n_c)
+    ref = onn.learned_step(theta, states[0:1], states[1:2], states[2:3], norm32, periodic,
+                           bf16=True)[0]
+    # compare the increments (the states themselves agree to ~1e-3 trivially)
+    assert rel(got - states[2], ref - states[2]) < 3e-4
