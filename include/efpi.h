@@ -201,6 +201,18 @@ efpi_status efpi_project(efpi_ctx* ctx, const double* d_snap, double* d_coarse_n
 efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_coarse_out,
                             const uint32_t* h_shifts);
 
+/* efpi_macro_step replayed from a captured HIP graph.  The first call for a
+ * given (d_coarse_in, d_coarse_out) pair and starting state captures the whole
+ * macro step (lift, restricted burst, restriction, projection) on the
+ * context's stream and instantiates it; later calls only upload the lift
+ * rotations h_shifts and launch the graph, so the host enqueues two
+ * operations per macro step instead of one per kernel.  Results are identical
+ * to efpi_macro_step.  Needs a non-null stream and timing disabled
+ * (EFPI_ESTATE otherwise).  Captured graphs live until efpi_destroy; the
+ * buffers they name must stay allocated while they are used. */
+efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in,
+                                  double* d_coarse_out, const uint32_t* h_shifts);
+
 /* Plain restriction (no co-evolving frame) of the current particles of every
  * replica: d_coarse[r][2][N_c] = coarse (density, momentum) coefficients at the
  * current time, with time-centred velocities after a burst.  Overwrites the

@@ -89,8 +89,35 @@ struct efpi_ctx {
   bool timing = false;
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
+  // captured macro steps, keyed by their arguments and the state they start from
+  struct HostState {
+    int cur;
+    bool other_zero, deposited, field_valid, fresh;
+    int last_burst_steps;
+  };
+  HostState state() const {
+    return {cur, other_zero, deposited, field_valid, fresh, last_burst_steps};
+  }
+  void set_state(const HostState& s) {
+    cur = s.cur;
+    other_zero = s.other_zero;
+    deposited = s.deposited;
+    field_valid = s.field_valid;
+    fresh = s.fresh;
+    last_burst_steps = s.last_burst_steps;
+  }
+  struct MacroGraph {
+    const double* in;
+    double* out;
+    int cur0;            // the captured launches depend only on these two fields
+    bool other_zero0;
+    HostState after;     // state the macro step leaves
+    hipGraphExec_t exec;
+  };
+  std::vector<MacroGraph> graphs;
   ~efpi_ctx() {
     for (hipEvent_t e : events) note(hipEventDestroy(e));
+    for (MacroGraph& g : graphs) note(hipGraphExecDestroy(g.exec));
   }
 };
 
@@ -315,11 +342,14 @@ ShiftArg shifts_of(const efpi_ctx* c, const uint32_t* h_shifts) {
   return s;
 }
 
+// Lift of every replica; with h_shifts == nullptr the rotations already stored
+// on the device (launch_set_shifts) are used.
 efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shifts) {
   launch_profile(c->d_reps, c->R, d_coarse, c->d_coarse_off, c->stream);
   launch_occupancy(c->d_reps, c->R, -1, c->d_status, c->stream);
+  const ShiftArg sh = shifts_of(c, h_shifts);
   launch_lift_particles(c->d_reps, c->d_block_prefix, c->R, c->total_blocks, -1, d_coarse,
-                        c->d_coarse_off, shifts_of(c, h_shifts), c->grid_blocks, c->stream);
+                        c->d_coarse_off, h_shifts ? &sh : nullptr, c->grid_blocks, c->stream);
   mark_new_particles(c);
   return hip_check("lift");
 }
@@ -556,7 +586,7 @@ efpi_status efpi_load_profile(efpi_ctx* ctx, int32_t replica, const double* d_n,
   std::memset(&s, 0, sizeof s);
   s.s[replica] = shift;
   launch_lift_particles(ctx->d_reps, ctx->d_block_prefix, ctx->R, ctx->h_reps[replica].n_coarse,
-                        replica, nullptr, ctx->d_coarse_off, s, ctx->grid_blocks, ctx->stream);
+                        replica, nullptr, ctx->d_coarse_off, &s, ctx->grid_blocks, ctx->stream);
   mark_new_particles(ctx);
   return hip_check("load_profile");
 }
@@ -630,6 +660,51 @@ efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_
   launch_project(ctx->d_reps, ctx->R, ctx->d_snap, ctx->d_snap_off, d_coarse_out, ctx->d_coarse_off,
                  ctx->d_status, ctx->stream);
   return hip_check("macro_step");
+}
+
+efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in, double* d_coarse_out,
+                                  const uint32_t* h_shifts) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_coarse_in || !d_coarse_out || !h_shifts) return fail(EFPI_EINVAL, "NULL argument");
+  if (!ctx->stream) return fail(EFPI_ESTATE, "graph capture needs a non-null stream");
+  if (ctx->timing) return fail(EFPI_ESTATE, "disable timing before using captured macro steps");
+  const int k = ctx->h_reps[0].burst_steps;
+  for (int r = 1; r < ctx->R; ++r)
+    if (ctx->h_reps[r].burst_steps != k)
+      return fail(EFPI_EINVAL, "macro_step needs equal burst_steps in every replica");
+  // the rotations change every step: they are stored outside the graph
+  launch_set_shifts(ctx->d_reps, ctx->R, -1, shifts_of(ctx, h_shifts), ctx->stream);
+  efpi_ctx::MacroGraph* g = nullptr;
+  for (efpi_ctx::MacroGraph& m : ctx->graphs)
+    if (m.in == d_coarse_in && m.out == d_coarse_out && m.cur0 == ctx->cur &&
+        m.other_zero0 == ctx->other_zero)
+      g = &m;
+  if (!g) {
+    const efpi_ctx::HostState before = ctx->state();
+    efpi_ctx::MacroGraph m{d_coarse_in, d_coarse_out, ctx->cur, ctx->other_zero, before, nullptr};
+    hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return fail(EFPI_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
+    // the same launches as efpi_macro_step, lift rotations read from the device
+    efpi_status st = do_lift(ctx, d_coarse_in, nullptr);
+    if (st == EFPI_OK) st = do_burst(ctx, k, true);
+    launch_restrict(ctx->d_reps, ctx->R, k, ctx->d_snap, ctx->d_snap_off, ctx->stream);
+    launch_project(ctx->d_reps, ctx->R, ctx->d_snap, ctx->d_snap_off, d_coarse_out,
+                   ctx->d_coarse_off, ctx->d_status, ctx->stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->stream, &graph);
+    m.after = ctx->state();
+    ctx->set_state(before);  // nothing has run yet
+    if (e == hipSuccess && st == EFPI_OK) e = hipGraphInstantiate(&m.exec, graph, nullptr, nullptr, 0);
+    if (graph) note(hipGraphDestroy(graph));
+    if (st != EFPI_OK) return st;
+    if (e != hipSuccess) return fail(EFPI_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    ctx->graphs.push_back(m);
+    g = &ctx->graphs.back();
+  }
+  const hipError_t e = hipGraphLaunch(g->exec, ctx->stream);
+  if (e != hipSuccess) return fail(EFPI_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+  ctx->set_state(g->after);
+  return hip_check("macro_step_graph");
 }
 
 efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {

@@ -303,13 +303,18 @@ void launch_occupancy(const RepDev* d_reps, int n_reps, int only_rep, uint32_t* 
                      stream, d_reps, only_rep, d_status);
 }
 
-void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
-                           int64_t total_blocks, int only_rep, const double* d_coarse,
-                           const int64_t* d_coff, const ShiftArg& shifts, int grid_blocks,
-                           hipStream_t stream) {
-  if (total_blocks <= 0) return;
+void launch_set_shifts(const RepDev* d_reps, int n_reps, int only_rep, const ShiftArg& shifts,
+                       hipStream_t stream) {
   hipLaunchKernelGGL(k_set_shifts, dim3(1), dim3(kMaxShiftReplicas), 0, stream, d_reps, n_reps,
                      only_rep, shifts);
+}
+
+void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
+                           int64_t total_blocks, int only_rep, const double* d_coarse,
+                           const int64_t* d_coff, const ShiftArg* shifts, int grid_blocks,
+                           hipStream_t stream) {
+  if (total_blocks <= 0) return;
+  if (shifts) launch_set_shifts(d_reps, n_reps, only_rep, *shifts, stream);
   const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_blocks) : total_blocks;
   hipLaunchKernelGGL(k_lift, dim3((unsigned)g), dim3(kLiftThreads), 0, stream, d_reps,
                      d_block_prefix, n_reps, total_blocks, only_rep, d_coarse, d_coff);

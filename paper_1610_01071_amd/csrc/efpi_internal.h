@@ -77,9 +77,13 @@ void launch_profile(const RepDev* d_reps, int n_reps, const double* d_coarse,
                     const int64_t* d_coff, hipStream_t stream);
 void launch_occupancy(const RepDev* d_reps, int n_reps, int only_rep, uint32_t* d_status,
                       hipStream_t stream);
+// Store each replica's lift rotation (R.aux[1]) for the next lift.
+void launch_set_shifts(const RepDev* d_reps, int n_reps, int only_rep, const ShiftArg& shifts,
+                       hipStream_t stream);
+// Lift; with shifts == nullptr the rotations stored by launch_set_shifts are used.
 void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
                            int64_t total_blocks, int only_rep, const double* d_coarse,
-                           const int64_t* d_coff, const ShiftArg& shifts, int grid_blocks,
+                           const int64_t* d_coff, const ShiftArg* shifts, int grid_blocks,
                            hipStream_t stream);
 void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap,
                      const int64_t* d_soff, hipStream_t stream);

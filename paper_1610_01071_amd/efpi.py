@@ -98,6 +98,7 @@ def _load():
         "efpi_restrict": [P, P],
         "efpi_project": [P, P, P],
         "efpi_macro_step": [P, P, P, ctypes.POINTER(U32)],
+        "efpi_macro_step_graph": [P, P, P, ctypes.POINTER(U32)],
         "efpi_ensemble_mean": [P, P],
         "efpi_restrict_state": [P, P],
         "efpi_sort": [P],
@@ -133,7 +134,8 @@ LIB = _load()
 EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream", "efpi_n_coarse",
             "efpi_set_particles", "efpi_get_particles", "efpi_get_grid", "efpi_set_potential",
             "efpi_load_profile", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
-            "efpi_restrict", "efpi_project", "efpi_macro_step", "efpi_ensemble_mean", "efpi_sort",
+            "efpi_restrict", "efpi_project", "efpi_macro_step", "efpi_macro_step_graph",
+            "efpi_ensemble_mean", "efpi_sort",
             "efpi_restrict_state",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error",
             "efpi_nn_workspace_size", "efpi_nn_pack", "efpi_nn_forward", "efpi_nn_backward",
@@ -299,6 +301,11 @@ def efpi_project(ctx, snap, coarse_next):
 def efpi_macro_step(ctx, coarse_in, coarse_out, shifts):
     _check(LIB.efpi_macro_step(ctx, _dev(coarse_in, torch.float64), _dev(coarse_out, torch.float64),
                                _shift_array(shifts)))
+
+
+def efpi_macro_step_graph(ctx, coarse_in, coarse_out, shifts):
+    _check(LIB.efpi_macro_step_graph(ctx, _dev(coarse_in, torch.float64),
+                                     _dev(coarse_out, torch.float64), _shift_array(shifts)))
 
 
 def efpi_restrict_state(ctx, coarse):
