@@ -468,8 +468,9 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
         break;
       }
   }
-  // Newton launch groups by rows per thread M: 256 threads of N / 256 rows up to
-  // N = 4096, then 32 rows per thread (512 threads at N = 16384)
+  // Newton launch groups by rows per thread M: N rows over at most 256 threads
+  // up to N = 4096 (M = max(1, N / 256)), then over 512 threads (M = 16 at
+  // N = 8192, 32 at N = 16384)
   std::vector<int> ms = {1, 2, 4, 8, 16, 32};
   c->h_newton_list.clear();
   for (int M : ms) {
@@ -479,7 +480,7 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
     int maxT = 0;
     for (int r = 0; r < c->R; ++r) {
       const int n = c->reps[r].n_cells;
-      const int m = n <= 256 ? 1 : (n <= 4096 ? n / 256 : 32);
+      const int m = n <= 256 ? 1 : (n <= 4096 ? n / 256 : n / 512);
       if (m == M) {
         c->h_newton_list.push_back(r);
         maxT = std::max(maxT, n / m);

@@ -2,7 +2,11 @@
 // equation -phi'' + exp(phi) = rho (eq. 3.15; Boltzmann electrons of eqs. 3.2 and
 // 3.16) on the node grid, then the node field E_k = -(phi_{k+1} - phi_{k-1}) / 2h.
 //
-// One workgroup per replica, FP64.  Rows are scaled by the node volume so that
+// One workgroup per replica.  The residual F and the potential are FP64; each
+// Newton correction J delta = -F is solved in FP32 (the Jacobian is diagonally
+// dominant, so the FP32 solve adds a relative error of ~1e-7 to delta, which the
+// next iteration removes with the FP64 residual: the iteration still converges
+// to the FP64 solution).  Rows are scaled by the node volume so that
 // the Jacobian is symmetric with constant off-diagonals alpha = -1/h^2:
 //   interior rows:  (2 phi_k - phi_{k-1} - phi_{k+1}) / h^2 + exp(phi_k) - Q_k / h
 //   wall rows:      (phi_0 - phi_1) / h^2 + exp(phi_0) / 2 - Q_0 / h   (and row N)
@@ -22,13 +26,135 @@ constexpr int kMaxT = 1024;
 
 __device__ __forceinline__ double clamp2(double x) { return fmin(2.0, fmax(-2.0, x)); }
 
-// 1/b from the hardware reciprocal estimate and two Newton-Raphson corrections
-// (the error squares each time); the solver only needs full FP64 precision,
-// not correct rounding.
-__device__ __forceinline__ double rcp(double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  r = fma(r, fma(-b, r, 1.0), r);
-  return fma(r, fma(-b, r, 1.0), r);
+// 1/b for the FP32 correction solve: the hardware reciprocal (1 ulp).
+__device__ __forceinline__ float rcp(float b) { return __builtin_amdgcn_rcpf(b); }
+
+// Tridiagonal separator system a_i X_{i-1} + b_i X_i + c_i X_{i+1} = d_i,
+// i = 0..T-1 (cyclic when periodic; a_0 = c_{T-1} = 0 otherwise), solved by the
+// 64 lanes of one wave.  Lane l owns rows [l S, (l + 1) S) with W = min(T, 64)
+// lanes and S = T / W: it eliminates its first S - 1 rows (expressing them by
+// the last row of the previous lane and its own last row), which leaves one
+// equation per lane for its last row; those W equations are solved by cyclic
+// reduction with lane shuffles, and the eliminated rows follow by one Thomas
+// pass with both ends known.  Writes x to sx[0..T).  Call with all 64 lanes.
+__device__ void solve_separators(int l, int T, bool periodic, const float* sa, const float* sb,
+                                 const float* sc, const float* sd, float* scp, float* syp,
+                                 float* sx) {
+  const int W = T < kWave ? T : kWave;
+  const int S = T / W;
+  const bool on = l < W;
+  const int i0 = on ? l * S : 0;
+  // rows 0..S-2 of the chunk in terms of XL (previous lane's X) and XR (own X)
+  float yl = 0.f, gll = 0.f, grl = 0.f, y0 = 0.f, gl0 = 0.f, gr0 = 0.f;
+  if (on && S >= 2) {
+    float r = rcp(sb[i0]);
+    float cp = sc[i0] * r, yp = sd[i0] * r, glp = -sa[i0] * r;
+    for (int j = 1; j <= S - 2; ++j) {
+      const float aj = sa[i0 + j];
+      r = rcp(sb[i0 + j] - aj * cp);
+      yp = (sd[i0 + j] - aj * yp) * r;
+      glp = -aj * glp * r;
+      cp = sc[i0 + j] * r;
+    }
+    yl = yp;
+    gll = glp;
+    grl = -cp;
+    r = rcp(sb[i0 + S - 2]);
+    float ch = sa[i0 + S - 2] * r, yh = sd[i0 + S - 2] * r, grh = -sc[i0 + S - 2] * r;
+    for (int j = S - 3; j >= 0; --j) {
+      const float cj = sc[i0 + j];
+      r = rcp(sb[i0 + j] - cj * ch);
+      yh = (sd[i0 + j] - cj * yh) * r;
+      grh = -cj * grh * r;
+      ch = sa[i0 + j] * r;
+    }
+    y0 = yh;
+    gl0 = -ch;
+    gr0 = grh;
+  }
+  // one equation per lane for its last row
+  const int nxt = (l + 1) & (W - 1);
+  const float y0n = __shfl(y0, nxt), gl0n = __shfl(gl0, nxt), gr0n = __shfl(gr0, nxt);
+  float A = 0.f, B = 1.f, C = 0.f, D = 0.f;
+  if (on) {
+    const int il = i0 + S - 1;
+    const float al = sa[il], bl = sb[il], cl = sc[il], dl = sd[il];
+    if (S >= 2) {
+      A = al * gll;
+      B = bl + al * grl + cl * gl0n;
+      C = cl * gr0n;
+      D = dl - al * yl - cl * y0n;
+    } else {
+      A = al;
+      B = bl;
+      C = cl;
+      D = dl;
+    }
+  }
+  // cyclic reduction over the W lane equations
+  for (int st = 1; st < W; st <<= 1) {
+    int im = l - st, ip = l + st;
+    bool vm = true, vp = true;
+    if (periodic) {
+      im &= (W - 1);
+      ip &= (W - 1);
+    } else {
+      vm = im >= 0;
+      vp = ip < W;
+      im = vm ? im : l;
+      ip = vp ? ip : l;
+    }
+    const float Am = __shfl(A, im), Bm = __shfl(B, im), Cm = __shfl(C, im), Dm = __shfl(D, im);
+    const float Ap = __shfl(A, ip), Bp = __shfl(B, ip), Cp = __shfl(C, ip), Dp = __shfl(D, ip);
+    float nA = 0.f, nB = B, nC = 0.f, nD = D;
+    if (vm) {
+      const float k1 = A * rcp(Bm);
+      nA = -Am * k1;
+      nB -= Cm * k1;
+      nD -= Dm * k1;
+    }
+    if (vp) {
+      const float k2 = C * rcp(Bp);
+      nC = -Cp * k2;
+      nB -= Ap * k2;
+      nD -= Dp * k2;
+    }
+    A = nA;
+    B = nB;
+    C = nC;
+    D = nD;
+  }
+  // after the reduction the couplings reach the lane itself (cyclic) or vanish
+  const float X = D * rcp(A + B + C);
+  const float XL = __shfl(X, (l - 1) & (W - 1));
+  if (!on) return;
+  sx[i0 + S - 1] = X;
+  if (S >= 2) {
+    // rows 0..S-2 with x_{-1} = XL and x_{S-1} = X known
+    float dj = sd[i0] - sa[i0] * XL;
+    if (S == 2) dj -= sc[i0] * X;
+    float r = rcp(sb[i0]);
+    float cp = sc[i0] * r;
+    float yp = dj * r;
+    scp[i0] = cp;
+    syp[i0] = yp;
+    for (int j = 1; j <= S - 2; ++j) {
+      dj = sd[i0 + j];
+      if (j == S - 2) dj -= sc[i0 + j] * X;
+      const float aj = sa[i0 + j];
+      r = rcp(sb[i0 + j] - aj * cp);
+      yp = (dj - aj * yp) * r;
+      cp = sc[i0 + j] * r;
+      scp[i0 + j] = cp;
+      syp[i0 + j] = yp;
+    }
+    float x = syp[i0 + S - 2];
+    sx[i0 + S - 2] = x;
+    for (int j = S - 3; j >= 0; --j) {
+      x = syp[i0 + j] - scp[i0 + j] * x;
+      sx[i0 + j] = x;
+    }
+  }
 }
 
 template <int M, int THREADS>
@@ -38,8 +164,9 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
                                                    int zero_bins, double tol,
                                                    uint32_t* __restrict__ status) {
   __shared__ double s_first[kMaxT], s_last[kMaxT];
-  __shared__ double s_a[kMaxT], s_b[kMaxT], s_c[kMaxT], s_d[kMaxT];
-  __shared__ double s_y0[kMaxT], s_gl0[kMaxT], s_gr0[kMaxT];
+  __shared__ float s_a[kMaxT], s_b[kMaxT], s_c[kMaxT], s_d[kMaxT];
+  __shared__ float s_y0[kMaxT], s_gl0[kMaxT], s_gr0[kMaxT], s_x[kMaxT];
+  __shared__ float s_cp[kMaxT], s_yp[kMaxT];
   __shared__ double s_phin;
   __shared__ unsigned long long s_maxd;
   __shared__ int s_nan;
@@ -52,12 +179,12 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   const bool periodic = R.bc == 0;
   const double h = R.h;
   const double ih2 = 1.0 / (h * h);
-  const double alpha = -ih2;
+  const float alpha = (float)-ih2;
   const double qscale = kFxInv / h;
   const long long* __restrict__ Q = reinterpret_cast<const long long*>(R.q[qsel]);
   const bool owns_n = !periodic && act && t == T - 1;
-  const double aL = (periodic || t > 0) ? alpha : 0.0;
-  const double aR = (periodic || t < T - 1) ? alpha : 0.0;
+  const float aL = (periodic || t > 0) ? alpha : 0.f;
+  const float aR = (periodic || t < T - 1) ? alpha : 0.f;
 
   if (t == 0) {
     s_maxd = 0ull;
@@ -89,8 +216,8 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
       }
       if (owns_n) s_phin = phin;
       __syncthreads();
-      double b[M], d[M];
-      double bn = 1.0, dn = 0.0;
+      float b[M], d[M];
+      float bn = 1.f, dn = 0.f;
       if (act) {
         const double pl = t > 0 ? s_last[t - 1] : (periodic ? s_last[T - 1] : 0.0);
         const double pr = t < T - 1 ? s_first[t + 1] : (periodic ? s_first[0] : s_phin);
@@ -111,33 +238,33 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
             s = 1.0;
             diag = 2.0 * ih2;
           }
-          d[j] = -(lap + s * ex - qv);
-          b[j] = diag + s * ex;
+          d[j] = (float)-(lap + s * ex - qv);
+          b[j] = (float)(diag + s * ex);
         }
         if (owns_n) {
           const double ex = exp(phin);
-          dn = -((phin - phi[M - 1]) * ih2 + 0.5 * ex - (double)Q[n] * qscale);
-          bn = ih2 + 0.5 * ex;
+          dn = (float)-((phin - phi[M - 1]) * ih2 + 0.5 * ex - (double)Q[n] * qscale);
+          bn = (float)(ih2 + 0.5 * ex);
           // eliminate node N into row N-1
-          const double rbn = rcp(bn);
+          const float rbn = rcp(bn);
           b[M - 1] -= alpha * alpha * rbn;
           d[M - 1] -= alpha * dn * rbn;
         }
       }
 
       // --- local elimination of the interior rows 0..M-2
-      double yl = 0.0, gll = 0.0, grl = 0.0;  // row M-2 in terms of (X_{t-1}, X_t)
-      double y0 = 0.0, gl0 = 0.0, gr0 = 0.0;  // row 0
+      float yl = 0.f, gll = 0.f, grl = 0.f;  // row M-2 in terms of (X_{t-1}, X_t)
+      float y0 = 0.f, gl0 = 0.f, gr0 = 0.f;  // row 0
       if (M >= 2 && act) {
-        double den = b[0];
-        const double r0 = rcp(den);
-        double c = alpha * r0;
-        double y = d[0] * r0;
-        double gl = -aL * r0;
+        float den = b[0];
+        const float r0 = rcp(den);
+        float c = alpha * r0;
+        float y = d[0] * r0;
+        float gl = -aL * r0;
 #pragma unroll
         for (int j = 1; j <= M - 2; ++j) {
           den = b[j] - alpha * c;
-          const double rj = rcp(den);
+          const float rj = rcp(den);
           y = (d[j] - alpha * y) * rj;
           gl = (-alpha * gl) * rj;
           c = alpha * rj;
@@ -146,11 +273,11 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
         gll = gl;
         grl = -alpha * rcp(den);
         // upward sweep for row 0
-        double dn2 = b[M - 2];
-        double rh = rcp(dn2);
-        double ch = -alpha * rh;
-        double yh = d[M - 2] * rh;
-        double grh = -alpha * rh;
+        float dn2 = b[M - 2];
+        float rh = rcp(dn2);
+        float ch = -alpha * rh;
+        float yh = d[M - 2] * rh;
+        float grh = -alpha * rh;
 #pragma unroll
         for (int j = M - 3; j >= 0; --j) {
           dn2 = b[j] + alpha * ch;
@@ -169,11 +296,11 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
       __syncthreads();
 
       // --- one equation per thread for its last row
-      double A = 0.0, B = 1.0, C = 0.0, D = 0.0;
+      float A = 0.f, B = 1.f, C = 0.f, D = 0.f;
       if (act) {
         if (M >= 2) {
           const int tn = t < T - 1 ? t + 1 : 0;
-          const double yn = s_y0[tn], gln = s_gl0[tn], grn = s_gr0[tn];
+          const float yn = s_y0[tn], gln = s_gl0[tn], grn = s_gr0[tn];
           A = alpha * gll;
           B = b[M - 1] + alpha * grl + aR * gln;
           C = aR * grn;
@@ -189,64 +316,23 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
         s_c[t] = C;
         s_d[t] = D;
       }
-      // --- parallel cyclic reduction over the T separator rows
-      for (int st = 1; st < T; st <<= 1) {
-        __syncthreads();
-        double nA = A, nB = B, nC = C, nD = D;
-        if (act) {
-          int im = t - st, ip = t + st;
-          bool vm = true, vp = true;
-          if (periodic) {
-            im &= (T - 1);
-            ip &= (T - 1);
-          } else {
-            vm = im >= 0;
-            vp = ip < T;
-          }
-          nA = 0.0;
-          nC = 0.0;
-          if (vm) {
-            const double k1 = A * rcp(s_b[im]);
-            nA = -s_a[im] * k1;
-            nB -= s_c[im] * k1;
-            nD -= s_d[im] * k1;
-          }
-          if (vp) {
-            const double k2 = C * rcp(s_b[ip]);
-            nC = -s_c[ip] * k2;
-            nB -= s_a[ip] * k2;
-            nD -= s_d[ip] * k2;
-          }
-        }
-        __syncthreads();
-        if (act) {
-          A = nA;
-          B = nB;
-          C = nC;
-          D = nD;
-          s_a[t] = A;
-          s_b[t] = B;
-          s_c[t] = C;
-          s_d[t] = D;
-        }
-      }
-      double X = 0.0;
-      if (act) {
-        X = D * rcp(A + B + C);
-        s_first[t] = X;  // reuse as the separator values
-      }
       __syncthreads();
+      // --- the T separator rows: wave 0 solves them (no workgroup barriers inside)
+      if (t < kWave) solve_separators(t, T, periodic, s_a, s_b, s_c, s_d, s_cp, s_yp, s_x);
+      __syncthreads();
+      float X = 0.f;
+      if (act) X = s_x[t];
 
       // --- interior rows by one Thomas pass with both ends known
       double local_max = 0.0;
       bool bad = false;
       if (act) {
-        const double XL = t > 0 ? s_first[t - 1] : (periodic ? s_first[T - 1] : 0.0);
+        const float XL = t > 0 ? s_x[t - 1] : (periodic ? s_x[T - 1] : 0.f);
         if (M >= 2) {
           d[0] -= aL * XL;
           d[M - 2] -= alpha * X;
           // forward: b[j] <- c'_j, d[j] <- z'_j
-          double rd = rcp(b[0]);
+          float rd = rcp(b[0]);
           b[0] = alpha * rd;
           d[0] = d[0] * rd;
 #pragma unroll
@@ -261,14 +347,15 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
         d[M - 1] = X;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          const double dl = clamp2(d[j]);
-          bad |= !(fabs(d[j]) < 1e300);
+          const double dl = clamp2((double)d[j]);
+          bad |= !(fabsf(d[j]) < 3e38f);
           local_max = fmax(local_max, fabs(dl));
           phi[j] += dl;
         }
         if (owns_n) {
-          const double dN = clamp2((dn - alpha * X) * rcp(bn));
-          bad |= !(fabs(dN) < 1e300);
+          const float dNf = (dn - alpha * X) * rcp(bn);
+          const double dN = clamp2((double)dNf);
+          bad |= !(fabsf(dNf) < 3e38f);
           local_max = fmax(local_max, fabs(dN));
           phin += dN;
         }
@@ -353,7 +440,8 @@ void launch_newton(const RepDev* d_reps, const int32_t* d_list, int n_list, int 
   else if (M == 2) EFPI_NEWTON(2, 256);
   else if (M == 4) EFPI_NEWTON(4, 256);
   else if (M == 8) EFPI_NEWTON(8, 256);
-  else if (M == 16) EFPI_NEWTON(16, 256);
+  else if (M == 16 && threads <= 256) EFPI_NEWTON(16, 256);
+  else if (M == 16) EFPI_NEWTON(16, 512);
   else EFPI_NEWTON(32, 512);
 #undef EFPI_NEWTON
 }
