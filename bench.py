@@ -142,6 +142,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-speedup", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB three times (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -262,6 +263,8 @@ def run_bench(args, np, torch, synth, E):
 
     if not args.no_speedup:
         out.update(speedup_sweep(E, torch, np, synth, ctx, spec, c0, args))
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_leg(E, torch, np, synth, args)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_leg(E, torch, np, synth, args)
     if not args.no_cpu:
@@ -334,6 +337,57 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
             "fixed_error_macro_dt_over_dt": best["macro_dt_over_dt"] if best else None,
             "sweep": rows,
         },
+    }
+
+
+def ensemble_leg(E, torch, np, synth, args):
+    """64 uneven ion-acoustic replicas (1024..16384 cells, 100..2000 ions per cell,
+    about 148 M ions) advanced together: one particle launch per fine step for all
+    replicas, launch shape from the autotuner, macro steps replayed from a
+    captured graph, ensemble mean over replicas of equal grids after each step."""
+    from paper_1610_01071_amd import autotune
+    sizes = synth.ensemble_sizes()
+    specs = [E.ReplicaSpec(n, float(n), ppc=p, haar_levels=int(round(math.log2(n // 256))),
+                           burst_steps=20, macro_dt=20.0, dt=0.1, vth=math.sqrt(0.1))
+             for n, p in sizes]
+    n_ions = sum(n * p for n, p in sizes)
+    t0 = time.perf_counter()
+    choice = autotune.autotune(specs, tiles=(2048, 4096, 8192), grids=(2048, 4096, 1 << 20),
+                               steps=2, warmup=1)
+    t_tune = time.perf_counter() - t0
+    ctx = E.Context(E.ConfigSpec(specs, newton_iters=2, newton_iters_start=4, tile=choice.tile,
+                                 grid_blocks=choice.grid_blocks))
+    for r, (n, _) in enumerate(sizes):
+        n0, u0 = synth.iaw_profile(n, float(n))
+        E.efpi_load_profile(ctx.ctx, r, torch.as_tensor(n0, device="cuda"),
+                            torch.as_tensor(u0, device="cuda"), synth.lift_shift(2016 + r))
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 30, cold=True)
+    a = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, a)
+    b = ctx.new_coarse()
+    shifts = lambda i: [synth.lift_shift(30_000 + 64 * i + r) for r in range(len(specs))]
+
+    def step(i, graph):
+        (E.efpi_macro_step_graph if graph else E.efpi_macro_step)(ctx.ctx, a, b, shifts(i))
+        E.efpi_ensemble_mean(ctx.ctx, b)
+
+    res = {}
+    for graph in (False, True):
+        step(0, graph)
+        torch.cuda.synchronize()
+        ms = timed(torch, lambda: [step(1 + i, graph) for i in range(3)]) / 3
+        res["graph" if graph else "eager"] = ms
+    status = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    ctx.close()
+    best = min(res.values())
+    return {
+        "replicas": len(specs), "n_ions": n_ions, "cells": "1024..16384", "ppc": "100..2000",
+        "burst_steps": 20, "ms_per_macro_step_eager": res["eager"],
+        "ms_per_macro_step_graph": res["graph"],
+        "particle_updates_per_s": n_ions * 20 / (best * 1e-3),
+        "tile": choice.tile, "grid_blocks": choice.grid_blocks, "autotune_s": t_tune,
+        "autotune_table": choice.table, "device_status": status,
     }
 
 

@@ -82,3 +82,36 @@ def random_coarse(n_coarse: int, seed: int, levels: int, mean_density: float = 1
         mom += u_amp / m * b * np.cos(2 * np.pi * m * k / n_coarse + ph)
     scale = 2.0 ** (levels / 2.0)
     return np.stack([dens * scale, mom * dens * scale])
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output for state x (Steele, Lea and Flood, 2014)."""
+    z = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return z ^ (z >> 31)
+
+
+def ensemble_sizes(n_replicas: int = 64, seed: int = SEED, target: float = 150e6,
+                   lo: float = 140e6, hi: float = 160e6):
+    """Uneven ensemble of ion-acoustic replicas: [(n_cells, ppc)] per replica.
+
+    n_cells = 1024 * 2^(r mod 5) (1024 .. 16384), ppc from a uniform draw
+    u_r in [0.5, 1.5) of SplitMix64(seed + r): ppc = clamp(round(2,343,750 u_r /
+    n_cells), 100, 2000), rescaled once so that the total ion count lies in
+    [lo, hi] (about 150 M ions).
+    """
+    cells = [1024 << (r % 5) for r in range(n_replicas)]
+    u = [0.5 + splitmix64(seed + r) / 2.0 ** 64 for r in range(n_replicas)]
+
+    def ppcs(scale):
+        return [int(min(2000, max(100, round(2_343_750 * ur * scale / n)))) for ur, n in
+                zip(u, cells)]
+
+    scale = 1.0
+    for _ in range(20):
+        total = sum(n * p for n, p in zip(cells, ppcs(scale)))
+        if lo <= total <= hi:
+            break
+        scale *= target / total
+    return list(zip(cells, ppcs(scale)))

@@ -62,3 +62,16 @@ def test_workspace_size_scales_with_capacity():
     c = E.efpi_workspace_size(E.ConfigSpec([E.ReplicaSpec(4096, 4096.0, ppc=1000)],
                                            flags=E.FLAG_SORT_BUFFER).to_c())
     assert c > a + 14 * 4096 * 1000
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    """Cache keys and files of the autotuner (host only)."""
+    from paper_1610_01071_amd import autotune
+    import paper_1610_01071_amd.efpi as E
+    specs = [E.ReplicaSpec(256, 256.0, ppc=10), E.ReplicaSpec(1024, 1024.0, ppc=20, bc=1)]
+    k = autotune.cache_key(specs)
+    assert "256x10x20x0" in k and "1024x20x20x1" in k
+    path = str(tmp_path / "sub" / "t.json")
+    autotune.save_cache(path, {k: {"tile": 2048, "grid_blocks": 4096, "ms_per_step": 1.0}})
+    assert autotune.load_cache(path)[k]["tile"] == 2048
+    assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
