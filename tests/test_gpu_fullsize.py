@@ -1,0 +1,101 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+Workload: the ion-acoustic wave (eq. 4.1) on 4096 cells with 1000 ions per cell
+(4,096,000 ions), l = 4, N_e = 20, dt = 0.1, Delta t = 200 dt, the default tile
+and grid that bench.py times.  The oracle loads the ions itself (quiet start of
+App. C from the same profile and rotation) and the GPU receives the same FP32
+state.  Bars as in the small-size tests: charge bit-exact; one step sampled
+particle by particle within 1e-5; restriction within 1e-7; the macro step's
+coarse state within eps = 2e-3 (eq. 4.2).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import efpi as oefpi
+from oracle import metrics
+from oracle import pic as opic
+from helpers import (lib, oracle_grid, oracle_scheme, to_dev, set_particles, particles_np,
+                     grid_np, x_of, periodic_dx, relmax)
+
+pytestmark = pytest.mark.gpu
+
+N, PPC = 4096, 1000
+
+
+@pytest.fixture(scope="module")
+def full():
+    E = lib()
+    spec = E.ReplicaSpec(N, float(N), ppc=PPC, haar_levels=4, burst_steps=20, macro_dt=20.0,
+                         dt=0.1, vth=math.sqrt(0.1))
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4, tile=2048))
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    n, u = synth.iaw_profile(N, float(N))
+    c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(2016))
+    parts = (c.astype(np.int16), f.astype(np.float32), v.astype(np.float32), w.astype(np.float32))
+    return dict(E=E, spec=spec, ctx=ctx, g=g, sch=sch, parts=parts)
+
+
+def test_fullsize_deposit_bitexact(full):
+    E, ctx, g, parts = full["E"], full["ctx"], full["g"], full["parts"]
+    set_particles(ctx, 0, *parts)
+    E.efpi_deposit(ctx.ctx)
+    q, _, _ = grid_np(ctx)
+    assert np.array_equal(q, opic.deposit_fx(*parts[:2], parts[3], g))
+
+
+def test_fullsize_one_step_sampled(full):
+    E, ctx, g, parts = full["E"], full["ctx"], full["g"], full["parts"]
+    cell, frac, v, w = parts
+    set_particles(ctx, 0, *parts)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 80)
+    E.efpi_pic_burst(ctx.ctx, 1, False)
+    gc, gf, gv, gw = particles_np(ctx)
+    q, _, e = grid_np(ctx)
+    x0 = x_of(cell, frac, g.h)
+    alive = np.ones(x0.size, bool)
+    _, phi0, e0 = opic.field_from_particles(x0, w.astype(np.float64), alive, g)
+    idx = np.random.default_rng(1).choice(x0.size, 20000, replace=False)
+    vh = v[idx].astype(np.float64) + 0.5 * g.dt * opic.gather(e0, x0[idx], g)
+    x1, _ = opic.apply_bc(x0[idx] + g.dt * vh, np.ones(idx.size, bool), g)
+    assert relmax(gv[idx], vh) < 1e-5
+    assert np.max(np.abs(periodic_dx(x_of(gc[idx], gf[idx], g.h), x1, g.length))) < 1e-5 * g.h
+    # the field after the step, from the oracle's own push of every ion
+    x1all, al = opic.apply_bc(x0 + g.dt * (v.astype(np.float64) + 0.5 * g.dt *
+                                           opic.gather(e0, x0, g)), alive, g)
+    _, _, e1 = opic.field_from_particles(x1all, w.astype(np.float64), al, g, phi0)
+    assert relmax(e, e1) < 1e-5
+    # charge is conserved exactly by the fused deposit of the pushed ions
+    qtot = int(np.sum(np.rint(w.astype(np.float64) * 2.0 ** 40).astype(np.int64)))
+    assert int(q.sum()) == qtot
+
+
+def test_fullsize_restriction(full):
+    E, ctx, g, sch, parts = full["E"], full["ctx"], full["g"], full["sch"], full["parts"]
+    set_particles(ctx, 0, *parts)
+    c = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c)
+    got = c.view(2, -1).cpu().numpy()
+    x = x_of(parts[0], parts[1], g.h)
+    ref = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                               np.ones(x.size, bool), g, sch)
+    assert metrics.rel_l2(got, ref) < 1e-7
+
+
+def test_fullsize_macro_step(full):
+    E, ctx, g, sch, parts = full["E"], full["ctx"], full["g"], full["sch"], full["parts"]
+    x = x_of(parts[0], parts[1], g.h)
+    c0 = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                              np.ones(x.size, bool), g, sch)
+    shift = synth.lift_shift(7)
+    cout = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, to_dev(c0.ravel(), torch.float64), cout, [shift])
+    E.efpi_sync(ctx.ctx, raise_on_error=False)
+    ref, _, _ = oefpi.macro_step(c0, g, sch, shift)
+    got = cout.view(2, -1).cpu().numpy()
+    for m in range(2):
+        assert metrics.rel_l2(got[m], ref[m]) < 2e-3
