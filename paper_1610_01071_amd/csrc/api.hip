@@ -74,6 +74,7 @@ struct efpi_ctx {
   double* d_snap = nullptr;
   double* d_coarse = nullptr;
   int32_t* d_sort_hist = nullptr;
+  int64_t* d_sort_base = nullptr;
   std::vector<int64_t> h_item_prefix, h_block_prefix, h_snap_off, h_coarse_off;
   std::vector<int32_t> h_group, h_newton_list;
   std::vector<NewtonGroup> ngroups;
@@ -158,7 +159,7 @@ efpi_status check_config(const efpi_config* cfg) {
       return bad("macro_dt must be >= burst_steps * dt");
     if (!(p.vth >= 0.0) || !std::isfinite(p.vth)) return bad("vth must be >= 0");
     if (!(p.n_floor > 0.0)) return bad("n_floor must be > 0");
-    if (p.capacity < 1 || p.capacity > (int64_t(1) << 31)) return bad("capacity must be in [1, 2^31]");
+    if (p.capacity < 1 || p.capacity >= (int64_t(1) << 31)) return bad("capacity must be in [1, 2^31 - 1]");
   }
   return EFPI_OK;
 }
@@ -190,11 +191,13 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
   uint8_t* p_snap = take(sizeof(double) * snap_total);
   uint8_t* p_coarse = take(sizeof(double) * coarse_total);
   uint8_t* p_hist = nullptr;
+  uint8_t* p_base = nullptr;
   if (cfg->flags & EFPI_FLAG_SORT_BUFFER) {
     const int tile = cfg->tile > 0 ? cfg->tile : kDefaultTile;
     int64_t items = 0;
     for (int r = 0; r < R; ++r) items += (cfg->replicas[r].capacity + tile - 1) / tile;
     p_hist = take(sizeof(int32_t) * 256 * items);
+    p_base = take(sizeof(int64_t) * 256 * R);
   }
   if (ctx) {
     ctx->d_status = reinterpret_cast<uint32_t*>(p_status);
@@ -208,6 +211,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     ctx->d_snap = reinterpret_cast<double*>(p_snap);
     ctx->d_coarse = reinterpret_cast<double*>(p_coarse);
     ctx->d_sort_hist = reinterpret_cast<int32_t*>(p_hist);
+    ctx->d_sort_base = reinterpret_cast<int64_t*>(p_base);
     ctx->snap_total = snap_total;
     ctx->coarse_total = coarse_total;
     ctx->h_reps.assign(R, RepDev{});
@@ -734,7 +738,7 @@ efpi_status efpi_sort(efpi_ctx* ctx) {
   if (!(ctx->cfg.flags & EFPI_FLAG_SORT_BUFFER))
     return fail(EFPI_ESTATE, "efpi_sort needs EFPI_FLAG_SORT_BUFFER at init");
   launch_sort(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
-              ctx->d_sort_hist, ctx->grid_blocks, ctx->stream);
+              ctx->d_sort_hist, ctx->d_sort_base, ctx->grid_blocks, ctx->stream);
   return hip_check("sort");
 }
 

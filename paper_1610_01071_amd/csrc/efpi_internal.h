@@ -98,8 +98,8 @@ void launch_copy_particles(const RepDev* d_reps, int rep, const int16_t* cell, c
                            int16_t* ocell, float* ofrac, float* ov, float* ow,
                            hipStream_t stream);
 void launch_sort(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
-                 int64_t total_items, int tile, int32_t* d_hist, int grid_blocks,
-                 hipStream_t stream);
+                 int64_t total_items, int tile, int32_t* d_hist, int64_t* d_base,
+                 int grid_blocks, hipStream_t stream);
 
 // Learned projection network (nn.hip).
 constexpr int kNnCin = EFPI_NN_CIN;

@@ -2,8 +2,9 @@
 //
 // Two least-significant-digit passes over 8-bit digits of the key
 // (cell, or 0xFFFF for an absorbed ion, which therefore sorts last and is
-// dropped).  Each pass: (1) per-tile digit histograms, (2) per replica a scan
-// over tiles and digits giving every (tile, digit) its first destination,
+// dropped).  Each pass: (1) per-tile digit histograms, (2) per replica and
+// digit a parallel scan over tiles, then a scan over digits, giving every
+// (tile, digit) its first destination,
 // (3) a scatter in which each wave walks its quarter of the tile in index
 // order and ranks lanes of equal digit by ballot masks, so the order is stable
 // and the result deterministic.  Pass 0 moves the store into the sort copy,
@@ -78,28 +79,54 @@ __global__ __launch_bounds__(kThreads) void k_hist(const RepDev* __restrict__ re
   }
 }
 
-// Per replica: hist[item][d] <- first destination of digit d in that tile.
-// On the last pass, the count of absorbed ions (digit 0xFF of 0xFFFF) is removed from np.
-__global__ __launch_bounds__(kDigits) void k_scan(const RepDev* __restrict__ reps,
-                                                   const int64_t* __restrict__ item_prefix,
-                                                   int pass, int32_t* __restrict__ hist) {
-  __shared__ int64_t s_tot[kDigits];
-  const int r = blockIdx.x;
+// Per (digit d, replica r): hist[item][d] <- number of ions with digit d in the
+// replica's earlier tiles (exclusive scan over tiles), and tot[r][d] <- the
+// digit's total.  Each thread scans a contiguous run of tiles; the run totals
+// are combined by a scan in LDS.
+__global__ __launch_bounds__(kDigits) void k_scan_items(const int64_t* __restrict__ item_prefix,
+                                                         int32_t* __restrict__ hist,
+                                                         int64_t* __restrict__ tot) {
+  __shared__ int64_t s_run[kDigits];
+  const int d = blockIdx.x;
+  const int r = blockIdx.y;
+  const int t = threadIdx.x;
   const int64_t b = item_prefix[r], e = item_prefix[r + 1];
-  const int d = threadIdx.x;
-  int64_t run = 0;
-  for (int64_t it = b; it < e; ++it) {
+  const int64_t per = (e - b + kDigits - 1) / kDigits;
+  const int64_t lo = min(b + t * per, e), hi = min(lo + per, e);
+  int64_t sum = 0;
+  for (int64_t it = lo; it < hi; ++it) sum += hist[it * kDigits + d];
+  s_run[t] = sum;
+  __syncthreads();
+  // inclusive scan of the run totals (Hillis-Steele)
+  for (int off = 1; off < kDigits; off <<= 1) {
+    const int64_t add = t >= off ? s_run[t - off] : 0;
+    __syncthreads();
+    s_run[t] += add;
+    __syncthreads();
+  }
+  int64_t run = s_run[t] - sum;
+  for (int64_t it = lo; it < hi; ++it) {
     const int32_t c = hist[it * kDigits + d];
     hist[it * kDigits + d] = (int32_t)run;
     run += c;
   }
-  s_tot[d] = run;
+  if (t == kDigits - 1) tot[(int64_t)r * kDigits + d] = s_run[t];
+}
+
+// Per replica: base[r][d] <- first destination of digit d (exclusive scan of
+// the digit totals in digit order).  On the last pass the count of absorbed
+// ions (digit 0xFF of the key 0xFFFF, sorted last) is kept in aux[0].
+__global__ __launch_bounds__(kDigits) void k_scan_digits(const RepDev* __restrict__ reps, int pass,
+                                                          int64_t* __restrict__ tot) {
+  __shared__ int64_t s_tot[kDigits];
+  const int r = blockIdx.x;
+  const int d = threadIdx.x;
+  s_tot[d] = tot[(int64_t)r * kDigits + d];
   __syncthreads();
-  // exclusive scan of digit totals (digit order)
   int64_t base = 0;
   for (int k = 0; k < d; ++k) base += s_tot[k];
-  for (int64_t it = b; it < e; ++it) hist[it * kDigits + d] += (int32_t)base;
-  if (pass == 1 && d == 0) reps[r].aux[0] = s_tot[kDigits - 1];  // absorbed ions, sorted last
+  tot[(int64_t)r * kDigits + d] = base;
+  if (pass == 1 && d == 0) reps[r].aux[0] = s_tot[kDigits - 1];
 }
 
 __global__ void k_drop_absorbed(const RepDev* __restrict__ reps) {
@@ -110,7 +137,8 @@ __global__ void k_drop_absorbed(const RepDev* __restrict__ reps) {
 __global__ __launch_bounds__(kThreads) void k_scatter(const RepDev* __restrict__ reps,
                                                        const int64_t* __restrict__ item_prefix,
                                                        int n_reps, int64_t total, int tile,
-                                                       int pass, const int32_t* __restrict__ hist) {
+                                                       int pass, const int32_t* __restrict__ hist,
+                                                       const int64_t* __restrict__ base) {
   __shared__ int s_off[kWaves][kDigits];
   const int shift = 8 * pass;
   const int wave = threadIdx.x >> 6;
@@ -130,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const RepDev* __restrict__
     __syncthreads();
     // exclusive prefix over waves, plus the tile's first destination per digit
     for (int d = threadIdx.x; d < kDigits; d += kThreads) {
-      int run = hist[item * kDigits + d];
+      int run = hist[item * kDigits + d] + (int)base[(int64_t)r * kDigits + d];
       for (int q = 0; q < kWaves; ++q) {
         const int c = s_off[q][d];
         s_off[q][d] = run;
@@ -180,17 +208,18 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const RepDev* __restrict__
 }  // namespace
 
 void launch_sort(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
-                 int64_t total_items, int tile, int32_t* d_hist, int grid_blocks,
-                 hipStream_t stream) {
+                 int64_t total_items, int tile, int32_t* d_hist, int64_t* d_base,
+                 int grid_blocks, hipStream_t stream) {
   if (total_items <= 0) return;
   const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_items) : total_items;
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(k_hist, dim3((unsigned)g), dim3(kThreads), 0, stream, d_reps, d_item_prefix,
                        n_reps, total_items, tile, pass, d_hist);
-    hipLaunchKernelGGL(k_scan, dim3(n_reps), dim3(kDigits), 0, stream, d_reps, d_item_prefix, pass,
-                       d_hist);
+    hipLaunchKernelGGL(k_scan_items, dim3(kDigits, n_reps), dim3(kDigits), 0, stream,
+                       d_item_prefix, d_hist, d_base);
+    hipLaunchKernelGGL(k_scan_digits, dim3(n_reps), dim3(kDigits), 0, stream, d_reps, pass, d_base);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)g), dim3(kThreads), 0, stream, d_reps,
-                       d_item_prefix, n_reps, total_items, tile, pass, d_hist);
+                       d_item_prefix, n_reps, total_items, tile, pass, d_hist, d_base);
   }
   hipLaunchKernelGGL(k_drop_absorbed, dim3(n_reps), dim3(64), 0, stream, d_reps);
 }
