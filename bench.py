@@ -143,6 +143,7 @@ def main():
     ap.add_argument("--no-speedup", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-slab", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB three times (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -263,6 +264,8 @@ def run_bench(args, np, torch, synth, E):
 
     if not args.no_speedup:
         out.update(speedup_sweep(E, torch, np, synth, ctx, spec, c0, args))
+    if not args.no_slab:
+        out["slab"] = slab_leg(E, torch, np, synth, args)
     if not args.no_ensemble:
         out["ensemble"] = ensemble_leg(E, torch, np, synth, args)
     if not args.no_learned:
@@ -276,7 +279,7 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
     """EFPI against full PIC over the same physical time from the same lifted state.
 
     Full PIC: the plain leapfrog burst with a cell sort every `sort_period` steps.
-    EFPI: chained macro steps with Delta t in {50, 100, 200} dt (K = 20).  The
+    EFPI: chained macro steps with Delta t in {50, 75, 100, 200} dt (K = 20).  The
     fixed-error point is the largest Delta t whose coarse density stays within
     eps_max of full PIC (eq. 4.2) at the horizon.
     """
@@ -301,7 +304,7 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
     ref = c_pic.view(2, -1)[0].cpu().numpy()
 
     rows = []
-    for mult in (50, 100, 200):
+    for mult in (50, 75, 100, 200):
         sp = workload_spec(E)
         sp.macro_dt = mult * spec.dt
         cx = E.Context(E.ConfigSpec([sp], newton_iters=2, newton_iters_start=4, tile=TILE))
@@ -337,6 +340,73 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
             "fixed_error_macro_dt_over_dt": best["macro_dt_over_dt"] if best else None,
             "sweep": rows,
         },
+    }
+
+
+def slab_leg(E, torch, np, synth, args):
+    """Plasma slab expanding into vacuum (the setting of Sec. 4.2): 16384 cells,
+    absorbing walls, n = 1 on the central quarter, 4096 ions per occupied cell
+    (about 16.8 M ions), T_i/T_e = 0.01, l = 4 (1024 coarse points per moment),
+    N_e = 20.  Full PIC (sort every 25 steps) against EFPI with Delta t = 50 dt
+    over t = 200 from the same lifted state; eps (eq. 4.2) on the coarse density."""
+    n_cells, ppc, horizon, mult = 16384, 4096, 200.0, 50
+
+    def make():
+        sp = E.ReplicaSpec(n_cells, float(n_cells), bc=E.BC_WALLS, ppc=ppc, haar_levels=4,
+                           burst_steps=20, macro_dt=mult * 0.1, dt=0.1, vth=0.1)
+        return sp, E.Context(E.ConfigSpec([sp], newton_iters=3, newton_iters_start=6, tile=TILE,
+                                          flags=E.FLAG_SORT_BUFFER))
+
+    spec, ctx = make()
+    n0, u0 = synth.slab_profile(n_cells)
+    E.efpi_load_profile(ctx.ctx, 0, torch.as_tensor(n0, device="cuda"),
+                        torch.as_tensor(u0, device="cuda"), synth.lift_shift(2016))
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 60, cold=True)
+    c0 = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c0)
+    n_ions = ctx.particles()[0].numel()
+    fine = int(round(horizon / spec.dt))
+    shift0 = synth.lift_shift(40_000)
+
+    def pic_run():
+        E.efpi_lift(ctx.ctx, c0, [shift0])
+        done = 0
+        while done < fine:
+            k = min(args.sort_period, fine - done)
+            E.efpi_pic_burst(ctx.ctx, k, False)
+            done += k
+            if done < fine:
+                E.efpi_sort(ctx.ctx)
+
+    t_pic = timed(torch, pic_run)
+    cp = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, cp)
+    pic_bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    ref = cp.view(2, -1)[0].cpu().numpy()
+    steps = int(round(horizon / spec.macro_dt))
+    a, b = ctx.new_coarse(), ctx.new_coarse()
+    a.copy_(c0)
+    st = {"a": a, "b": b}
+
+    def efpi_run():
+        for i in range(steps):
+            sh = shift0 if i == 0 else synth.lift_shift(40_000 + i)
+            E.efpi_macro_step(ctx.ctx, st["a"], st["b"], [sh])
+            st["a"], st["b"] = st["b"], st["a"]
+
+    t_efpi = timed(torch, efpi_run)
+    bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    got = st["a"].view(2, -1)[0].cpu().numpy()
+    eps = float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(got * got + ref * ref)))
+    ctx.close()
+    return {
+        "n_cells": n_cells, "ppc": ppc, "n_ions_t0": n_ions, "horizon": horizon,
+        "pic_fine_steps": fine, "pic_ms": t_pic,
+        "pic_particle_updates_per_s": n_ions * fine / (t_pic * 1e-3),
+        "efpi_macro_dt_over_dt": mult, "efpi_macro_steps": steps, "efpi_ms": t_efpi,
+        "efpi_ms_per_macro_step": t_efpi / steps, "speedup": t_pic / t_efpi,
+        "eps_density": eps, "device_status_pic": pic_bits, "device_status_efpi": bits,
     }
 
 
