@@ -119,9 +119,10 @@ struct Gen {
   double v, w;
 };
 
-__device__ __forceinline__ Gen generate(const RepDev& R, int rank, int m, uint32_t shift) {
+// Ion m of cell c, from the profile values at the cell's two nodes.
+__device__ __forceinline__ Gen generate(const RepDev& R, int c, double nl, double nr, double ul,
+                                       double ur, int m, uint32_t shift) {
   Gen g;
-  const int c = R.cell_of_rank[rank];
   const int ppc = R.ppc;
   g.cell = c;
   g.frac = (float)(((double)m + 0.5) / (double)ppc);
@@ -129,13 +130,19 @@ __device__ __forceinline__ Gen generate(const RepDev& R, int rank, int m, uint32
   const uint32_t u = __brev(idx) + shift;
   const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
   const double th = (double)g.frac;
-  const int cr = R.bc == 0 ? ((c + 1) & (R.n_cells - 1)) : c + 1;
-  const double nx = (1.0 - th) * R.prof_n[c] + th * R.prof_n[cr];
-  const double ux = (1.0 - th) * R.prof_u[c] + th * R.prof_u[cr];
+  const double nx = (1.0 - th) * nl + th * nr;
+  const double ux = (1.0 - th) * ul + th * ur;
   g.v = ux + R.vth * (double)inv_normal(b);
   g.w = nx * R.h / (double)ppc;
   return g;
 }
+
+__device__ __forceinline__ int right_node(const RepDev& R, int c) {
+  return R.bc == 0 ? ((c + 1) & (R.n_cells - 1)) : c + 1;
+}
+
+// Occupied cells of a block staged in LDS (one round of loads per block).
+constexpr int kLiftCache = 256;
 
 __device__ double block_sum(double x, double* s_red) {
   // fixed-order tree: waves by shuffles, then the wave totals in index order
@@ -168,6 +175,8 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
                                                        const double* __restrict__ coarse,
                                                        const int64_t* __restrict__ coff) {
   __shared__ double s_red[kLiftThreads / 64];
+  __shared__ int s_c[kLiftCache];
+  __shared__ double s_nl[kLiftCache], s_nr[kLiftCache], s_ul[kLiftCache], s_ur[kLiftCache];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int r = only_rep >= 0 ? only_rep : find_rep(block_prefix, n_reps, item);
     const RepDev& R = reps[r];
@@ -178,13 +187,34 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const int count = (rb1 - rb0) * ppc;  // at most 2^l cells * ppc < 2^31 (checked at init)
     const int64_t slot0 = (int64_t)rb0 * ppc;
     const uint32_t shift = (uint32_t)R.aux[1];  // Cranley-Patterson rotation of this lift
+    const int ncell = rb1 - rb0;
+    const bool cached = ncell <= kLiftCache;
+    if (cached) {
+      for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int c = R.cell_of_rank[rb0 + k];
+        const int cr = right_node(R, c);
+        s_c[k] = c;
+        s_nl[k] = R.prof_n[c];
+        s_nr[k] = R.prof_n[cr];
+        s_ul[k] = R.prof_u[c];
+        s_ur[k] = R.prof_u[cr];
+      }
+      __syncthreads();
+    }
+    auto gen = [&](int j) {
+      const int jr = j / ppc;
+      const int m = j - jr * ppc;
+      if (cached) return generate(R, s_c[jr], s_nl[jr], s_nr[jr], s_ul[jr], s_ur[jr], m, shift);
+      const int c = R.cell_of_rank[rb0 + jr];
+      const int cr = right_node(R, c);
+      return generate(R, c, R.prof_n[c], R.prof_n[cr], R.prof_u[c], R.prof_u[cr], m, shift);
+    };
     double ratio = 1.0, dv = 0.0;
     if (coarse != nullptr) {
       double sw = 0.0, swv = 0.0;
 #pragma unroll 1
       for (int j = threadIdx.x; j < count; j += blockDim.x) {
-        const int jr = j / ppc;
-        const Gen g = generate(R, rb0 + jr, j - jr * ppc, shift);
+        const Gen g = gen(j);
         sw += g.w;
         swv += g.w * g.v;
       }
@@ -199,8 +229,7 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     }
 #pragma unroll 1
     for (int j = threadIdx.x; j < count; j += blockDim.x) {
-      const int jr = j / ppc;
-      const Gen g = generate(R, rb0 + jr, j - jr * ppc, shift);
+      const Gen g = gen(j);
       const int64_t s = slot0 + j;
       R.cell[s] = (int16_t)g.cell;
       R.frac[s] = g.frac;

@@ -42,9 +42,8 @@ __device__ __forceinline__ void gatomic_add(long long* p, long long v) {
 }
 
 constexpr int kThreads = 256;
-constexpr int kWave = 64;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kBatch = 4;       // particles per thread loaded ahead of use
+constexpr int kBatch = 8;       // particles per thread loaded ahead of use
 constexpr int kQWin = 256;      // node window (int64 bins)
 constexpr int kQMargin = 16;
 constexpr int kQSlotMargin = 4;  // node slots per wave start this far below the tile
