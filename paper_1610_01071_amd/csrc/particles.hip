@@ -5,12 +5,15 @@
 //
 // Work decomposition: every replica's particle slots are cut into tiles of
 // `tile` consecutive particles; a persistent grid walks the (replica, tile)
-// items.  Inside a tile, 64-lane waves first merge lanes that hit the same node
-// or coarse block (wave-wide integer sums), then one lane adds the merged value
-// into int64 bins held in LDS for a window of nodes/blocks around the tile; the
-// window is flushed to global memory with 64-bit integer atomics at the end of
-// the tile.  Targets outside the window go straight to global atomics.  All
-// sums are of integers, so the result is independent of scheduling order.
+// items.  The node field around the tile is staged in LDS.  Inside a tile,
+// each 64-lane wave merges all of its ions that hit the same node (deposit) or
+// coarse block (restriction) with fixed-order wave reductions, and adds the
+// merged value to a register owned by one lane (lane s holds node or block
+// base + s).  At the end of the tile the four waves' registers are summed
+// through LDS and flushed with one 64-bit integer atomic per non-zero target.
+// Rare targets outside a wave's 64 slots go to an LDS window (deposit) or to
+// global atomics.  Every sum that reaches memory is an integer sum, so the
+// result does not depend on scheduling order.
 #include "efpi_internal.h"
 
 #include <hip/hip_ext.h>
