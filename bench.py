@@ -270,6 +270,8 @@ def run_bench(args, np, torch, synth, E):
         out["ensemble"] = ensemble_leg(E, torch, np, synth, args)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_leg(E, torch, np, synth, args)
+        if not args.no_slab:
+            out["learned_slab"] = learned_slab_leg(E, torch, np, synth, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_ppc, 2016)
     print(json.dumps(out), flush=True)
@@ -459,6 +461,74 @@ def ensemble_leg(E, torch, np, synth, args):
         "tile": choice.tile, "grid_blocks": choice.grid_blocks, "autotune_s": t_tune,
         "autotune_table": choice.table, "device_status": status,
     }
+
+
+def learned_slab_leg(E, torch, np, synth, args):
+    """Learned projection driving the expanding slab (16384 cells, walls, 4096 ions per
+    occupied cell, l = 4, Delta t = 50 dt, 40 macro steps to t = 200).
+
+    Training data: plain EFPI trajectories of slabs of 12 other widths (0.18 .. 0.32 of
+    the domain); 10,000 Adam steps of batch 16 with input-state noise of one increment
+    scale, so that chained learned steps stay on the trajectory.  Test: width 0.25,
+    plain EFPI against the learned run with a fine burst every 2nd (and every 4th) step
+    as judge and fallback (threshold 2e-3 on the coarse density, eq. 4.2).
+    """
+    import paper_1610_01071_amd.learned as L
+    n_cells, steps = 16384, 40
+    spec = E.ReplicaSpec(n_cells, float(n_cells), bc=E.BC_WALLS, ppc=4096, haar_levels=4,
+                         burst_steps=20, macro_dt=5.0, dt=0.1, vth=0.1)
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=3, newton_iters_start=6, tile=TILE))
+
+    def c0_for(width, seed):
+        n0, u0 = synth.slab_profile(n_cells, width)
+        E.efpi_load_profile(ctx.ctx, 0, torch.as_tensor(n0, device="cuda"),
+                            torch.as_tensor(u0, device="cuda"), synth.lift_shift(seed))
+        E.efpi_deposit(ctx.ctx)
+        E.efpi_solve_field(ctx.ctx, 60, cold=True)
+        c = ctx.new_coarse()
+        E.efpi_restrict_state(ctx.ctx, c)
+        return c
+
+    widths = [0.18, 0.2, 0.21, 0.22, 0.23, 0.24, 0.26, 0.27, 0.28, 0.29, 0.3, 0.32]
+    t_gen = time.perf_counter()
+    trajs = [L.plain_run(ctx, c0_for(w, 100 + k), steps, seed=500 + k)
+             for k, w in enumerate(widths)]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    norm = L.fit_norm(trajs)
+    states = torch.cat(trajs, 0).contiguous()
+    T = steps + 1
+    train_idx = np.concatenate([np.arange(2, T - 1) + r * T for r in range(len(trajs))])
+    tr = L.Trainer(spec.n_coarse, False, batch=16)
+    t_train = time.perf_counter()
+    tr.train(states, train_idx, norm, 10_000, noise=1.0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+
+    c0 = c0_for(0.25, 999)
+    L.plain_run(ctx, c0, 3, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = L.plain_run(ctx, c0, steps, seed=77)
+    torch.cuda.synchronize()
+    wall_plain = (time.perf_counter() - t0) * 1e3
+    b = ref[-1].cpu().numpy().reshape(2, -1)
+
+    def eps(u, w):
+        return float(np.sqrt(np.sum((u - w) ** 2) / np.sum(u * u + w * w)))
+
+    out = {"macro_dt_over_dt": 50, "macro_steps": steps, "threshold": 2e-3, "train_noise": 1.0,
+           "plain_ms": wall_plain, "datagen_s": t_gen, "train_s": t_train, "train_iters": 10_000}
+    for jp in (2, 4):
+        run = L.run_learned(ctx, tr, norm, c0, steps, seed=77, judge_period=jp, threshold=2e-3)
+        a = run.states[-1].cpu().numpy().reshape(2, -1)
+        out[f"judge_period_{jp}"] = {
+            "learned_ms": run.wall_ms, "speedup": wall_plain / run.wall_ms,
+            "eps_density": eps(a[0], b[0]), "eps_momentum": eps(a[1], b[1]),
+            "learned_steps": run.learned, "judged_steps": run.judged,
+            "fallback_steps": run.fallback, "judge_eps_max": max(run.eps) if run.eps else None}
+    ctx.close()
+    return out
 
 
 def learned_leg(E, torch, np, synth, args):

@@ -291,10 +291,14 @@ efpi_status efpi_nn_adam(float* d_params, const float* d_grad, float* d_m, float
  * (FP64): sample b uses states n-2, n-1, n with n = d_index[b] (device int32,
  * clamped to [2, n_states - 1], or to [2, n_states - 2] when d_t is given).
  * Writes d_x[batch][6][n_c] and, when d_t is not NULL, the training target
- * d_t[batch][2][n_c] = (c_{n+1} - c_n) / delta. */
+ * d_t[batch][2][n_c] = (c_{n+1} - c_n) / delta.  With noise > 0 (training), the
+ * three input states are first perturbed by noise * delta_m times a unit-
+ * variance uniform variate (counter-based hash of seed and element), and the
+ * target is taken from the perturbed c_n, so the network learns to steer back
+ * toward the trajectory; noise = 0 gives the exact features. */
 efpi_status efpi_nn_features(const double* d_states, int32_t n_states, const int32_t* d_index,
-                             int32_t batch, int32_t n_c, const efpi_nn_norm* h_norm, float* d_x,
-                             float* d_t, void* hip_stream);
+                             int32_t batch, int32_t n_c, const efpi_nn_norm* h_norm, float noise,
+                             uint32_t seed, float* d_x, float* d_t, void* hip_stream);
 
 /* Learned projective step: d_c_next = d_c_n + delta * d_y, all [batch][2][n_c]
  * (states FP64, d_y FP32).  d_c_next may alias d_c_n. */

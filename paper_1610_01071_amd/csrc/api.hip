@@ -872,13 +872,14 @@ efpi_status check_norm(const efpi_nn_norm* n) {
 }  // namespace
 
 efpi_status efpi_nn_features(const double* d_states, int32_t n_states, const int32_t* d_index,
-                             int32_t batch, int32_t n_c, const efpi_nn_norm* h_norm, float* d_x,
-                             float* d_t, void* hip_stream) {
+                             int32_t batch, int32_t n_c, const efpi_nn_norm* h_norm, float noise,
+                             uint32_t seed, float* d_x, float* d_t, void* hip_stream) {
   if (!d_states || !d_index || !d_x) return fail(EFPI_EINVAL, "NULL pointer");
+  if (!(noise >= 0.f) || !std::isfinite(noise)) return fail(EFPI_EINVAL, "noise must be >= 0");
   if (batch < 1 || n_c < 1) return fail(EFPI_EINVAL, "batch and n_c must be >= 1");
   if (n_states < (d_t ? 4 : 3)) return fail(EFPI_EINVAL, "too few states");
   if (check_norm(h_norm) != EFPI_OK) return EFPI_EINVAL;
-  nn::launch_features(d_states, n_states, d_index, batch, n_c, *h_norm, d_x, d_t,
+  nn::launch_features(d_states, n_states, d_index, batch, n_c, *h_norm, noise, seed, d_x, d_t,
                       static_cast<hipStream_t>(hip_stream));
   return hip_check("nn_features");
 }

@@ -121,7 +121,8 @@ void launch_mse(const float* y, const float* t, float* dy, float* loss, int64_t 
 void launch_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
                  float b1, float b2, float eps, uint16_t* pack, hipStream_t stream);
 void launch_features(const double* states, int n_states, const int32_t* index, int batch, int nc,
-                     const efpi_nn_norm& nm, float* x, float* t, hipStream_t stream);
+                     const efpi_nn_norm& nm, float noise, uint32_t seed, float* x, float* t,
+                     hipStream_t stream);
 void launch_step(const double* cn, const float* y, int batch, int nc, const efpi_nn_norm& nm,
                  double* out, hipStream_t stream);
 void launch_predict_step(const float* params, const uint16_t* pack, const double* states, int nc,

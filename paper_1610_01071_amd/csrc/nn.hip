@@ -349,9 +349,22 @@ __global__ __launch_bounds__(1024) void k_mse(const float* __restrict__ y,
 
 // x[b][6][N_c] (and optionally t[b][2][N_c]) from states[n-2], states[n-1],
 // states[n] (and states[n+1]) with n = index[b], clamped to [2, n_states - 2].
+// Uniform variate with mean 0 and variance 1 from a counter (the "lowbias32"
+// integer hash of C. Wellons' hash prospector, then scaled to [-sqrt 3, sqrt 3)).
+__device__ __forceinline__ float unit_noise(uint32_t seed, uint32_t counter) {
+  uint32_t x = seed ^ (counter * 0x9E3779B1u);
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return ((float)x * 2.3283064365386963e-10f - 0.5f) * 3.4641016151377544f;
+}
+
 __global__ void k_features(const double* __restrict__ states, int n_states,
                            const int32_t* __restrict__ index, int batch, int nc, efpi_nn_norm nm,
-                           float* __restrict__ x, float* __restrict__ t) {
+                           float noise, uint32_t seed, float* __restrict__ x,
+                           float* __restrict__ t) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)batch * 2 * nc) return;
   const int b = (int)(i / (2 * nc));
@@ -361,9 +374,17 @@ __global__ void k_features(const double* __restrict__ states, int n_states,
   const int hi = t ? n_states - 2 : n_states - 1;
   const int n = index ? min(max(index[b], 2), hi) : 2;
   const size_t st = 2 * (size_t)nc;
-  const double cn = states[n * st + r];
-  const double c1 = states[(n - 1) * st + r];
-  const double c2 = states[(n - 2) * st + r];
+  double cn = states[n * st + r];
+  double c1 = states[(n - 1) * st + r];
+  double c2 = states[(n - 2) * st + r];
+  if (noise > 0.f) {
+    // training noise on the input states, in units of the increment scale
+    const uint32_t base = 3u * (uint32_t)i;
+    const double a = (double)noise * nm.delta[m];
+    cn += a * unit_noise(seed, base);
+    c1 += a * unit_noise(seed, base + 1u);
+    c2 += a * unit_noise(seed, base + 2u);
+  }
   float* xb = x + (size_t)b * 6 * nc;
   xb[m * nc + k] = (float)((cn - nm.mu[m]) / nm.sigma[m]);
   xb[(2 + m) * nc + k] = (float)((cn - c1) / nm.delta[m]);
@@ -518,10 +539,11 @@ void launch_adam(float* params, const float* grad, float* m, float* v, int step,
 }
 
 void launch_features(const double* states, int n_states, const int32_t* index, int batch, int nc,
-                     const efpi_nn_norm& nm, float* x, float* t, hipStream_t stream) {
+                     const efpi_nn_norm& nm, float noise, uint32_t seed, float* x, float* t,
+                     hipStream_t stream) {
   const int64_t n = (int64_t)batch * 2 * nc;
   hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, states,
-                     n_states, index, batch, nc, nm, x, t);
+                     n_states, index, batch, nc, nm, noise, seed, x, t);
 }
 
 void launch_step(const double* cn, const float* y, int batch, int nc, const efpi_nn_norm& nm,
@@ -537,7 +559,7 @@ void launch_predict_step(const float* params, const uint16_t* pack, const double
   const Ws w = carve(ws, 1, nc);
   const int64_t n = 2 * (int64_t)nc;
   hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, states,
-                     3, nullptr, 1, nc, nm, w.x, nullptr);
+                     3, nullptr, 1, nc, nm, 0.f, 0u, w.x, nullptr);
   launch_forward(params, pack, w.x, w.y, 1, nc, periodic, ws, stream);
   // states[2] is c_n of the single sample window
   hipLaunchKernelGGL(k_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,

@@ -112,7 +112,8 @@ def _load():
         "efpi_nn_mse": [P, P, P, P, I64, P],
         "efpi_nn_adam": [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, P, P],
-        "efpi_nn_features": [P, I32, P, I32, I32, ctypes.POINTER(NnNorm), P, P, P],
+        "efpi_nn_features": [P, I32, P, I32, I32, ctypes.POINTER(NnNorm), ctypes.c_float, U32, P,
+                             P, P],
         "efpi_nn_step": [P, P, I32, I32, ctypes.POINTER(NnNorm), P, P],
         "efpi_rel_l2": [P, P, I64, P, P],
         "efpi_nn_predict_step": [P, P, P, I32, I32, ctypes.POINTER(NnNorm), P, P, ctypes.c_size_t,
@@ -386,10 +387,12 @@ def efpi_nn_adam(params, grad, m, v, step, lr, pack, beta1=0.9, beta2=0.999, eps
                             beta2, eps, _dev(pack, torch.uint8), _stream(stream)))
 
 
-def efpi_nn_features(states, index, n_c, norm: NnNorm, x, t=None, stream=None):
+def efpi_nn_features(states, index, n_c, norm: NnNorm, x, t=None, noise=0.0, seed=0,
+                     stream=None):
     n_states = states.numel() // (2 * n_c)
     _check(LIB.efpi_nn_features(_dev(states, torch.float64), n_states, _dev(index, torch.int32),
-                                index.numel(), n_c, ctypes.byref(norm), _dev(x, torch.float32),
+                                index.numel(), n_c, ctypes.byref(norm), float(noise),
+                                ctypes.c_uint32(int(seed) & 0xFFFFFFFF), _dev(x, torch.float32),
                                 _dev(t, torch.float32), _stream(stream)))
 
 

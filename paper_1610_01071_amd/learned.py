@@ -97,8 +97,12 @@ class Trainer:
         return self._ws[batch]
 
     def train(self, states: torch.Tensor, valid_index: np.ndarray, norm: E.NnNorm, iters: int,
-              lr: float = 2e-3, lr_final: float = 2e-4):
-        """Adam over random mini-batches of the samples n in valid_index of `states`."""
+              lr: float = 2e-3, lr_final: float = 2e-4, noise: float = 0.0):
+        """Adam over random mini-batches of the samples n in valid_index of `states`.
+
+        noise > 0 perturbs the input states of every batch (in units of the
+        increment scale) so that the network learns to correct its own errors
+        when its steps are chained."""
         g = np.random.default_rng(self.seed + 1)
         B, nc = self.batch, self.n_c
         idx_all = torch.as_tensor(
@@ -110,7 +114,8 @@ class Trainer:
         loss = torch.empty(iters, dtype=torch.float32, device="cuda")
         ws = self.workspace(B)
         for i in range(iters):
-            E.efpi_nn_features(states, idx_all[i], nc, norm, x, t)
+            E.efpi_nn_features(states, idx_all[i], nc, norm, x, t, noise=noise,
+                               seed=self.seed * 1_000_003 + self.step_count)
             E.efpi_nn_forward(self.params, self.pack, x, y, B, nc, self.periodic, ws)
             E.efpi_nn_mse(y, t, dy, loss[i:i + 1])
             E.efpi_nn_backward(self.pack, x, dy, self.grad, B, nc, self.periodic, ws)

@@ -201,3 +201,34 @@ def test_predict_step_matches_oracle(periodic):
                            bf16=True)[0]
     # compare the increments (the states themselves agree to ~1e-3 trivially)
     assert rel(got - states[2], ref - states[2]) < 3e-4
+
+
+def test_training_noise_statistics():
+    """Input-state noise of the training features: zero mean, the requested
+    scale (noise * delta), independent of the exact features, deterministic."""
+    E = lib()
+    g = np.random.default_rng(31)
+    n_c, T = 512, 6
+    states = 1.0 + 0.1 * g.standard_normal((T, 2, n_c))
+    norm_t = ([1.0, 0.0], [0.5, 0.25], [2e-3, 4e-3])
+    norm = E.nn_norm(*norm_t)
+    idx = to_dev(np.full(64, 3, np.int32), torch.int32)
+    sd = to_dev(states, torch.float64)
+    x0 = torch.empty(64, 6, n_c, dtype=torch.float32, device="cuda")
+    t0 = torch.empty(64, 2, n_c, dtype=torch.float32, device="cuda")
+    x1, t1, x2 = torch.empty_like(x0), torch.empty_like(t0), torch.empty_like(x0)
+    E.efpi_nn_features(sd, idx, n_c, norm, x0, t0)
+    E.efpi_nn_features(sd, idx, n_c, norm, x1, t1, noise=0.5, seed=9)
+    E.efpi_nn_features(sd, idx, n_c, norm, x2, noise=0.5, seed=9)
+    d = (x1 - x0).cpu().numpy().astype(np.float64)
+    # channel 0: perturbation of c_n in units of sigma: std = 0.5 * delta / sigma
+    for m in range(2):
+        s = d[:, m].std()
+        expect = 0.5 * norm_t[2][m] / norm_t[1][m]
+        assert abs(s - expect) < 0.03 * expect
+        assert abs(d[:, m].mean()) < 0.05 * expect
+    # target from the perturbed c_n
+    assert torch.allclose(t1 + (x1[:, 0:2] - x0[:, 0:2]) * torch.tensor(
+        [norm_t[1][0] / norm_t[2][0], norm_t[1][1] / norm_t[2][1]], device="cuda").view(1, 2, 1),
+        t0, rtol=0, atol=1e-3)
+    assert torch.equal(x1, x2)
