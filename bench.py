@@ -216,6 +216,22 @@ def run_bench(args, np, torch, synth, E):
 
     ms_graph = timed(torch, run_graph) / args.steps
     E.efpi_sync(ctx.ctx, raise_on_error=False)
+
+    # the lift alone (profile, occupancy, quiet load, block correction), to
+    # quote the burst rate without it
+    def lifts():
+        for i in range(args.steps):
+            E.efpi_lift(ctx.ctx, c0, [synth.lift_shift(50_000 + i)])
+
+    ms_lift = timed(torch, lifts) / args.steps
+
+    # a plain device copy of 1 GiB: the practical HBM ceiling of this machine
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_ms = timed(torch, lambda: [dst.copy_(src) for _ in range(5)]) / 5
+    copy_gbs = 2 * src.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del src, dst
     value = n_ions * K / (ms_per_step * 1e-3)
     avg_launch_s = kern_ms / max(kern_n, 1) * 1e-3
     achieved = BYTES_PER_UPDATE * n_ions / avg_launch_s / 1e9
@@ -256,8 +272,12 @@ def run_bench(args, np, torch, synth, E):
             "bytes_per_launch": BYTES_PER_UPDATE * n_ions,
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": kern_n,
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "ms_per_step_graph": ms_graph,
+        "lift_ms": ms_lift,
+        "burst_particle_updates_per_s": n_ions * K / ((ms_per_step - ms_lift) * 1e-3),
         "wall_s_timed": wall,
         "device_status": status,
     }
