@@ -208,8 +208,9 @@ efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_
  * rotations h_shifts and launch the graph, so the host enqueues two
  * operations per macro step instead of one per kernel.  Results are identical
  * to efpi_macro_step.  Needs a non-null stream and timing disabled
- * (EFPI_ESTATE otherwise).  Captured graphs live until efpi_destroy; the
- * buffers they name must stay allocated while they are used. */
+ * (EFPI_ESTATE otherwise).  A context keeps its 8 most recently captured
+ * graphs (until efpi_destroy); the buffers they name must stay allocated while
+ * they are used. */
 efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in,
                                   double* d_coarse_out, const uint32_t* h_shifts);
 

@@ -34,6 +34,7 @@ int ilog2(int64_t x) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kDefaultTile = 2048;
+constexpr size_t kMaxGraphs = 8;  // captured macro steps kept per context
 constexpr int kDefaultGrid = 2048;
 
 struct NewtonGroup {
@@ -703,6 +704,11 @@ efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in, doub
     if (graph) note(hipGraphDestroy(graph));
     if (st != EFPI_OK) return st;
     if (e != hipSuccess) return fail(EFPI_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    if (ctx->graphs.size() >= kMaxGraphs) {  // keep the cache bounded: drop the oldest
+      note(hipStreamSynchronize(ctx->stream));  // it may still be running
+      note(hipGraphExecDestroy(ctx->graphs.front().exec));
+      ctx->graphs.erase(ctx->graphs.begin());
+    }
     ctx->graphs.push_back(m);
     g = &ctx->graphs.back();
   }

@@ -96,3 +96,25 @@ def test_graph_ensemble_equals_eager():
             assert torch.equal(be, bg)
             a, be = be, a
             ag, bg = bg, ag
+
+
+def test_graph_cache_is_bounded():
+    """More distinct (input, output) pairs than the cache holds: every call still
+    equals the eager macro step."""
+    E = lib()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        spec = E.ReplicaSpec(128, 128.0, ppc=32, haar_levels=2, burst_steps=4, macro_dt=1.0)
+        ce = E.Context(E.ConfigSpec([spec]))
+        cg = E.Context(E.ConfigSpec([spec]))
+        a = start(E, ce, spec, 4)
+        start(E, cg, spec, 4)
+        outs_e = [ce.new_coarse() for _ in range(10)]
+        outs_g = [cg.new_coarse() for _ in range(10)]
+        for rnd in range(2):
+            for i in range(10):
+                E.efpi_macro_step(ce.ctx, a, outs_e[i], [100 * rnd + i])
+                E.efpi_macro_step_graph(cg.ctx, a, outs_g[i], [100 * rnd + i])
+            side.synchronize()
+            for i in range(10):
+                assert torch.equal(outs_e[i], outs_g[i]), (rnd, i)
