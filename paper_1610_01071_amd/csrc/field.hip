@@ -14,9 +14,13 @@
 // condition phi' = 0).  Each Newton step J delta = -F is solved by a partition
 // method: thread t owns M consecutive rows; the M-1 interior rows are eliminated
 // in registers (downward and upward sweeps), leaving one tridiagonal equation per
-// thread for its last row, solved by parallel cyclic reduction in LDS; then the
-// interior rows follow by one Thomas pass.  Periodic grids give cyclic systems; on
-// walls, node N is eliminated into row N-1 first so every system has N rows.
+// thread for its last row.  Those T equations are split again by wave: the last
+// lane of each wave is a separator, the other lanes are reduced by parallel
+// cyclic reduction over lane shuffles (in terms of the two separators around the
+// wave), and the small cyclic system of the separators is solved redundantly by
+// every wave, so a Newton step takes three workgroup barriers.  The interior rows
+// then follow by one Thomas pass.  Periodic grids give cyclic systems; on walls,
+// node N is eliminated into row N-1 first so every system has N rows.
 #include "efpi_internal.h"
 
 namespace efpi {
@@ -29,81 +33,69 @@ __device__ __forceinline__ double clamp2(double x) { return fmin(2.0, fmax(-2.0,
 // 1/b for the FP32 correction solve: the hardware reciprocal (1 ulp).
 __device__ __forceinline__ float rcp(float b) { return __builtin_amdgcn_rcpf(b); }
 
-// Tridiagonal separator system a_i X_{i-1} + b_i X_i + c_i X_{i+1} = d_i,
-// i = 0..T-1 (cyclic when periodic; a_0 = c_{T-1} = 0 otherwise), solved by the
-// 64 lanes of one wave.  Lane l owns rows [l S, (l + 1) S) with W = min(T, 64)
-// lanes and S = T / W: it eliminates its first S - 1 rows (expressing them by
-// the last row of the previous lane and its own last row), which leaves one
-// equation per lane for its last row; those W equations are solved by cyclic
-// reduction with lane shuffles, and the eliminated rows follow by one Thomas
-// pass with both ends known.  Writes x to sx[0..T).  Call with all 64 lanes.
-__device__ void solve_separators(int l, int T, bool periodic, const float* sa, const float* sb,
-                                 const float* sc, const float* sd, float* scp, float* syp,
-                                 float* sx) {
-  const int W = T < kWave ? T : kWave;
-  const int S = T / W;
-  const bool on = l < W;
-  const int i0 = on ? l * S : 0;
-  // rows 0..S-2 of the chunk in terms of XL (previous lane's X) and XR (own X)
-  float yl = 0.f, gll = 0.f, grl = 0.f, y0 = 0.f, gl0 = 0.f, gr0 = 0.f;
-  if (on && S >= 2) {
-    float r = rcp(sb[i0]);
-    float cp = sc[i0] * r, yp = sd[i0] * r, glp = -sa[i0] * r;
-    for (int j = 1; j <= S - 2; ++j) {
-      const float aj = sa[i0 + j];
-      r = rcp(sb[i0 + j] - aj * cp);
-      yp = (sd[i0 + j] - aj * yp) * r;
-      glp = -aj * glp * r;
-      cp = sc[i0 + j] * r;
-    }
-    yl = yp;
-    gll = glp;
-    grl = -cp;
-    r = rcp(sb[i0 + S - 2]);
-    float ch = sa[i0 + S - 2] * r, yh = sd[i0 + S - 2] * r, grh = -sc[i0 + S - 2] * r;
-    for (int j = S - 3; j >= 0; --j) {
-      const float cj = sc[i0 + j];
-      r = rcp(sb[i0 + j] - cj * ch);
-      yh = (sd[i0 + j] - cj * yh) * r;
-      grh = -cj * grh * r;
-      ch = sa[i0 + j] * r;
-    }
-    y0 = yh;
-    gl0 = -ch;
-    gr0 = grh;
+// Wave-level solve of the thread equations.  Lane l of wave w (thread t = 64 w + l)
+// holds the equation A X_{t-1} + B X_t + C X_{t+1} = D of its last row.  The last
+// active lane of each wave is that wave's separator G_w; lanes 0..L-2 are solved
+// by parallel cyclic reduction over lane shuffles in terms of the two separators
+// around them, X_t = y + gl G_{w-1} + gr G_w (three right-hand sides: D, and the
+// couplings of lane 0 to G_{w-1} and of lane L-2 to G_w moved to the right).
+// Rows outside 0..L-2 act as identity rows.  Returns (y, gl, gr).
+__device__ __forceinline__ void wave_pcr(int lane, int L, bool inb, float A, float B, float C,
+                                         float D, float& y, float& gl, float& gr) {
+  float pa = lane == 0 ? 0.f : A;
+  float pc = lane == L - 2 ? 0.f : C;
+  float pb = B, r0 = D;
+  float r1 = lane == 0 ? -A : 0.f;
+  float r2 = lane == L - 2 ? -C : 0.f;
+  if (!inb) {
+    pa = pc = r0 = r1 = r2 = 0.f;
+    pb = 1.f;
   }
-  // one equation per lane for its last row
-  const int nxt = (l + 1) & (W - 1);
-  const float y0n = __shfl(y0, nxt), gl0n = __shfl(gl0, nxt), gr0n = __shfl(gr0, nxt);
-  float A = 0.f, B = 1.f, C = 0.f, D = 0.f;
-  if (on) {
-    const int il = i0 + S - 1;
-    const float al = sa[il], bl = sb[il], cl = sc[il], dl = sd[il];
-    if (S >= 2) {
-      A = al * gll;
-      B = bl + al * grl + cl * gl0n;
-      C = cl * gr0n;
-      D = dl - al * yl - cl * y0n;
-    } else {
-      A = al;
-      B = bl;
-      C = cl;
-      D = dl;
-    }
+  for (int st = 1; st < L - 1; st <<= 1) {
+    const bool vm = lane - st >= 0 && inb;
+    const bool vp = lane + st <= L - 2 && inb;
+    const int im = vm ? lane - st : lane;
+    const int ip = vp ? lane + st : lane;
+    const float Am = __shfl(pa, im), Bm = __shfl(pb, im), Cm = __shfl(pc, im);
+    const float Rm0 = __shfl(r0, im), Rm1 = __shfl(r1, im), Rm2 = __shfl(r2, im);
+    const float Ap = __shfl(pa, ip), Bp = __shfl(pb, ip), Cp = __shfl(pc, ip);
+    const float Rp0 = __shfl(r0, ip), Rp1 = __shfl(r1, ip), Rp2 = __shfl(r2, ip);
+    const float k1 = vm ? pa * rcp(Bm) : 0.f;
+    const float k2 = vp ? pc * rcp(Bp) : 0.f;
+    pa = -Am * k1;
+    pc = -Cp * k2;
+    pb = pb - Cm * k1 - Ap * k2;
+    r0 = r0 - Rm0 * k1 - Rp0 * k2;
+    r1 = r1 - Rm1 * k1 - Rp1 * k2;
+    r2 = r2 - Rm2 * k1 - Rp2 * k2;
   }
-  // cyclic reduction over the W lane equations
-  for (int st = 1; st < W; st <<= 1) {
-    int im = l - st, ip = l + st;
-    bool vm = true, vp = true;
+  const float inv = rcp(pb);
+  y = r0 * inv;
+  gl = r1 * inv;
+  gr = r2 * inv;
+}
+
+// Separator system of the waves: lane i < nw holds alpha G_{i-1} + beta G_i +
+// gamma G_{i+1} = delta (cyclic when periodic), solved by cyclic reduction over
+// lane shuffles; returns G_i in lane i.
+__device__ __forceinline__ float wave_cr(int lane, int nw, bool periodic, float A, float B,
+                                         float C, float D) {
+  if (lane >= nw) {
+    A = C = D = 0.f;
+    B = 1.f;
+  }
+  for (int st = 1; st < nw; st <<= 1) {
+    int im = lane - st, ip = lane + st;
+    bool vm = lane < nw, vp = lane < nw;
     if (periodic) {
-      im &= (W - 1);
-      ip &= (W - 1);
+      im &= (nw - 1);
+      ip &= (nw - 1);
     } else {
-      vm = im >= 0;
-      vp = ip < W;
-      im = vm ? im : l;
-      ip = vp ? ip : l;
+      vm = vm && im >= 0;
+      vp = vp && ip < nw;
     }
+    im = vm ? im : lane;
+    ip = vp ? ip : lane;
     const float Am = __shfl(A, im), Bm = __shfl(B, im), Cm = __shfl(C, im), Dm = __shfl(D, im);
     const float Ap = __shfl(A, ip), Bp = __shfl(B, ip), Cp = __shfl(C, ip), Dp = __shfl(D, ip);
     float nA = 0.f, nB = B, nC = 0.f, nD = D;
@@ -125,36 +117,7 @@ __device__ void solve_separators(int l, int T, bool periodic, const float* sa, c
     D = nD;
   }
   // after the reduction the couplings reach the lane itself (cyclic) or vanish
-  const float X = D * rcp(A + B + C);
-  const float XL = __shfl(X, (l - 1) & (W - 1));
-  if (!on) return;
-  sx[i0 + S - 1] = X;
-  if (S >= 2) {
-    // rows 0..S-2 with x_{-1} = XL and x_{S-1} = X known
-    float dj = sd[i0] - sa[i0] * XL;
-    if (S == 2) dj -= sc[i0] * X;
-    float r = rcp(sb[i0]);
-    float cp = sc[i0] * r;
-    float yp = dj * r;
-    scp[i0] = cp;
-    syp[i0] = yp;
-    for (int j = 1; j <= S - 2; ++j) {
-      dj = sd[i0 + j];
-      if (j == S - 2) dj -= sc[i0 + j] * X;
-      const float aj = sa[i0 + j];
-      r = rcp(sb[i0 + j] - aj * cp);
-      yp = (dj - aj * yp) * r;
-      cp = sc[i0 + j] * r;
-      scp[i0 + j] = cp;
-      syp[i0 + j] = yp;
-    }
-    float x = syp[i0 + S - 2];
-    sx[i0 + S - 2] = x;
-    for (int j = S - 3; j >= 0; --j) {
-      x = syp[i0 + j] - scp[i0 + j] * x;
-      sx[i0 + j] = x;
-    }
-  }
+  return D * rcp(A + B + C);
 }
 
 template <int M, int THREADS>
@@ -163,18 +126,23 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
                                                    int cold, int qsel, int save_en,
                                                    int zero_bins, double tol,
                                                    uint32_t* __restrict__ status) {
-  __shared__ double s_first[kMaxT], s_last[kMaxT];
-  __shared__ float s_a[kMaxT], s_b[kMaxT], s_c[kMaxT], s_d[kMaxT];
-  __shared__ float s_y0[kMaxT], s_gl0[kMaxT], s_gr0[kMaxT], s_x[kMaxT];
-  __shared__ float s_cp[kMaxT], s_yp[kMaxT];
+  constexpr int kW = THREADS / kWave;
+  __shared__ double s_first[THREADS], s_last[THREADS];
+  __shared__ float s_row0[kW][3];  // row 0 of each wave's lane 0, in terms of (X_{t-1}, X_t)
+  __shared__ float s_sol0[kW][3];  // lane 0's X in terms of the separators around its wave
+  __shared__ float s_if[kW][4];    // separator equation of each wave
+  __shared__ double s_wmax[kW];
+  __shared__ int s_wbad[kW];
   __shared__ double s_phin;
-  __shared__ unsigned long long s_maxd;
-  __shared__ int s_nan;
 
   const RepDev& R = reps[list[blockIdx.x]];
   const int n = R.n_cells;
   const int T = n / M;
   const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int w = t / kWave;
+  const int L = T < kWave ? T : kWave;      // active lanes of an active wave
+  const int nw = (T + kWave - 1) / kWave;   // active waves
   const bool act = t < T;
   const bool periodic = R.bc == 0;
   const double h = R.h;
@@ -186,24 +154,46 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   const float aL = (periodic || t > 0) ? alpha : 0.f;
   const float aR = (periodic || t < T - 1) ? alpha : 0.f;
 
-  if (t == 0) {
-    s_maxd = 0ull;
-    s_nan = 0;
-  }
-
+  // the charge is held in registers up to 16 rows per thread (above, it is
+  // re-read from L2 each iteration to keep the kernel free of spills)
+  constexpr bool kHoist = M <= 16;
   double phi[M];
+  double qv[kHoist ? M : 1];
+  auto charge = [&](int j) -> double {
+    if constexpr (kHoist) return qv[j];
+    else return (double)Q[t * M + j] * qscale;
+  };
   double phin = 0.0;
   if (R.closure != 2) {
     if (act) {
+      if constexpr (!kHoist) {
+      } else if constexpr (M >= 2) {
+        const longlong2* q2 = reinterpret_cast<const longlong2*>(Q + t * M);
 #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const int g = t * M + j;
-        if (cold) {
-          const double s = (!periodic && g == 0) ? 0.5 : 1.0;
-          phi[j] = log(fmax((double)Q[g] * qscale / s, 1e-8));
-        } else {
-          phi[j] = R.phi[g];
+        for (int j = 0; j < M / 2; ++j) {
+          const longlong2 v = q2[j];
+          qv[2 * j] = (double)v.x * qscale;
+          qv[2 * j + 1] = (double)v.y * qscale;
         }
+      } else {
+        qv[0] = (double)Q[t] * qscale;
+      }
+      if (cold) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const double s = (!periodic && t * M + j == 0) ? 0.5 : 1.0;
+          phi[j] = log(fmax(charge(j) / s, 1e-8));
+        }
+      } else if constexpr (M >= 2) {
+        const double2* p2 = reinterpret_cast<const double2*>(R.phi + t * M);
+#pragma unroll
+        for (int j = 0; j < M / 2; ++j) {
+          const double2 v = p2[j];
+          phi[2 * j] = v.x;
+          phi[2 * j + 1] = v.y;
+        }
+      } else {
+        phi[0] = R.phi[t];
       }
       if (owns_n) phin = cold ? log(fmax((double)Q[n] * qscale / 0.5, 1e-8)) : R.phi[n];
     }
@@ -227,7 +217,6 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
           const double left = j > 0 ? phi[j - 1] : pl;
           const double right = j < M - 1 ? phi[j + 1] : pr;
           const double ex = exp(phi[j]);
-          const double qv = (double)Q[g] * qscale;
           double lap, s, diag;
           if (!periodic && g == 0) {
             lap = (phi[j] - right) * ih2;
@@ -238,7 +227,7 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
             s = 1.0;
             diag = 2.0 * ih2;
           }
-          d[j] = (float)-(lap + s * ex - qv);
+          d[j] = (float)-(lap + s * ex - charge(j));
           b[j] = (float)(diag + s * ex);
         }
         if (owns_n) {
@@ -289,18 +278,15 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
         y0 = yh;
         gr0 = grh;
         gl0 = -aL * rh;
-        s_y0[t] = y0;
-        s_gl0[t] = gl0;
-        s_gr0[t] = gr0;
       }
-      __syncthreads();
 
-      // --- one equation per thread for its last row
+      // --- one equation per thread for its last row (row 0 of the next thread
+      // comes from the next lane; the wave's last lane takes it after the barrier)
+      const float yn = __shfl(y0, lane + 1), gln = __shfl(gl0, lane + 1);
+      const float grn = __shfl(gr0, lane + 1);
       float A = 0.f, B = 1.f, C = 0.f, D = 0.f;
       if (act) {
         if (M >= 2) {
-          const int tn = t < T - 1 ? t + 1 : 0;
-          const float yn = s_y0[tn], gln = s_gl0[tn], grn = s_gr0[tn];
           A = alpha * gll;
           B = b[M - 1] + alpha * grl + aR * gln;
           C = aR * grn;
@@ -311,23 +297,57 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
           C = aR;
           D = d[0];
         }
-        s_a[t] = A;
-        s_b[t] = B;
-        s_c[t] = C;
-        s_d[t] = D;
+      }
+      // --- lanes 0..L-2 of every wave in terms of the separators G_{w-1}, G_w
+      float xy, xgl, xgr;
+      wave_pcr(lane, L, act && lane <= L - 2, A, B, C, D, xy, xgl, xgr);
+      const float py = __shfl(xy, L - 2), pgl = __shfl(xgl, L - 2), pgr = __shfl(xgr, L - 2);
+      if (act && lane == 0) {
+        s_row0[w][0] = y0;
+        s_row0[w][1] = gl0;
+        s_row0[w][2] = gr0;
+        s_sol0[w][0] = xy;
+        s_sol0[w][1] = xgl;
+        s_sol0[w][2] = xgr;
       }
       __syncthreads();
-      // --- the T separator rows: wave 0 solves them (no workgroup barriers inside)
-      if (t < kWave) solve_separators(t, T, periodic, s_a, s_b, s_c, s_d, s_cp, s_yp, s_x);
+      // --- separator equation of each wave (its last lane)
+      if (act && lane == L - 1) {
+        const int wn = w + 1 < nw ? w + 1 : 0;
+        float Aw = aL, Bw = b[0], Cw = aR, Dw = d[0];
+        if (M >= 2) {
+          Aw = alpha * gll;
+          Bw = b[M - 1] + alpha * grl + aR * s_row0[wn][1];
+          Cw = aR * s_row0[wn][2];
+          Dw = d[M - 1] - alpha * yl - aR * s_row0[wn][0];
+        }
+        const float y2 = s_sol0[wn][0], gl2 = s_sol0[wn][1], gr2 = s_sol0[wn][2];
+        s_if[w][0] = Aw * pgl;
+        s_if[w][1] = Bw + Aw * pgr + Cw * gl2;
+        s_if[w][2] = Cw * gr2;
+        s_if[w][3] = Dw - Aw * py - Cw * y2;
+      }
       __syncthreads();
-      float X = 0.f;
-      if (act) X = s_x[t];
+      // --- the nw separators, solved redundantly by every wave
+      float IA = 0.f, IB = 1.f, IC = 0.f, ID = 0.f;
+      if (lane < nw) {
+        IA = s_if[lane][0];
+        IB = s_if[lane][1];
+        IC = s_if[lane][2];
+        ID = s_if[lane][3];
+      }
+      const float G = wave_cr(lane, nw, periodic, IA, IB, IC, ID);
+      const int wl = w > 0 ? w - 1 : (periodic ? nw - 1 : 0);
+      const float Gw = __shfl(G, w < nw ? w : 0);
+      const float Gl = (w > 0 || periodic) ? __shfl(G, wl) : 0.f;
+      const float X = lane == L - 1 ? Gw : xy + xgl * Gl + xgr * Gw;
+      const float Xp = __shfl(X, lane > 0 ? lane - 1 : 0);
 
       // --- interior rows by one Thomas pass with both ends known
       double local_max = 0.0;
       bool bad = false;
       if (act) {
-        const float XL = t > 0 ? s_x[t - 1] : (periodic ? s_x[T - 1] : 0.f);
+        const float XL = lane > 0 ? Xp : Gl;
         if (M >= 2) {
           d[0] -= aL * XL;
           d[M - 2] -= alpha * X;
@@ -361,39 +381,64 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
         }
       }
       if (it == iters - 1) {
-        if (bad) atomicOr(&s_nan, 1);
-        if (local_max > 0.0) atomicMax(&s_maxd, (unsigned long long)__double_as_longlong(local_max));
+        // largest correction and NaN flag of the wave, one LDS slot per wave
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) local_max = fmax(local_max, __shfl_xor(local_max, o));
+        const bool wbad = __any(bad);
+        if (lane == 0) {
+          s_wmax[w] = local_max;
+          s_wbad[w] = wbad ? 1 : 0;
+        }
       }
-      __syncthreads();
     }
   } else if (act) {
 #pragma unroll
     for (int j = 0; j < M; ++j) phi[j] = 0.0;
   }
 
-  // --- store phi, then the centred-difference field
+  // --- centred-difference field (the potential is stored after the barrier)
   if (act) {
-#pragma unroll
-    for (int j = 0; j < M; ++j) R.phi[t * M + j] = phi[j];
-    if (owns_n) R.phi[n] = phin;
     s_first[t] = phi[0];
     s_last[t] = phi[M - 1];
   }
   if (owns_n) s_phin = phin;
   __syncthreads();
   if (act) {
+    if constexpr (M >= 2) {
+      double2* p2 = reinterpret_cast<double2*>(R.phi + t * M);
+#pragma unroll
+      for (int j = 0; j < M / 2; ++j) p2[j] = make_double2(phi[2 * j], phi[2 * j + 1]);
+    } else {
+      R.phi[t] = phi[0];
+    }
+    if (owns_n) R.phi[n] = phin;
     const double pl = t > 0 ? s_last[t - 1] : (periodic ? s_last[T - 1] : 0.0);
     const double pr = t < T - 1 ? s_first[t + 1] : (periodic ? s_first[0] : s_phin);
     const double inv2h = 0.5 / h;
+    float ev[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const int g = t * M + j;
       const double left = j > 0 ? phi[j - 1] : pl;
       const double right = j < M - 1 ? phi[j + 1] : pr;
-      float ev = (float)(-(right - left) * inv2h);
-      if (!periodic && g == 0) ev = 0.f;
-      R.e[g] = ev;
-      if (save_en) R.en[g] = ev;
+      ev[j] = (float)(-(right - left) * inv2h);
+      if (!periodic && g == 0) ev[j] = 0.f;
+    }
+    if constexpr (M >= 4) {
+      float4* e4 = reinterpret_cast<float4*>(R.e + t * M);
+      float4* n4 = reinterpret_cast<float4*>(R.en + t * M);
+#pragma unroll
+      for (int j = 0; j < M / 4; ++j) {
+        const float4 v = make_float4(ev[4 * j], ev[4 * j + 1], ev[4 * j + 2], ev[4 * j + 3]);
+        e4[j] = v;
+        if (save_en) n4[j] = v;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        R.e[t * M + j] = ev[j];
+        if (save_en) R.en[t * M + j] = ev[j];
+      }
     }
     if (owns_n) {
       R.e[n] = 0.f;
@@ -411,9 +456,14 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
     }
   }
   if (t == 0 && R.closure != 2) {
-    const double md = __longlong_as_double((long long)s_maxd);
-    if (s_nan) atomicOr(status, 2u);
-    if (md > tol || s_nan) atomicOr(status, 1u);
+    double md = 0.0;
+    int nan = 0;
+    for (int k = 0; k < nw; ++k) {
+      md = fmax(md, s_wmax[k]);
+      nan |= s_wbad[k];
+    }
+    if (nan) atomicOr(status, 2u);
+    if (md > tol || nan) atomicOr(status, 1u);
   }
 }
 

@@ -78,7 +78,11 @@ def test_deposit_empty_store():
 
 # ------------------------------------------------------------------- Newton --
 
-@pytest.mark.parametrize("n_cells,bc", [(8, 0), (128, 0), (1024, 0), (4096, 0), (16384, 0),
+# Sizes cover every launch shape of the solve: fewer threads than one wave (8,
+# 32), exactly one wave (64), two to eight waves (128 .. 16384), 1 to 32 rows
+# per thread, both boundary conditions.
+@pytest.mark.parametrize("n_cells,bc", [(8, 0), (32, 0), (64, 0), (128, 0), (1024, 0), (4096, 0),
+                                        (8192, 0), (16384, 0), (32, 1), (64, 1), (128, 1),
                                         (256, 1), (2048, 1), (16384, 1)])
 def test_newton_matches_oracle(n_cells, bc):
     E = lib()
@@ -98,6 +102,32 @@ def test_newton_matches_oracle(n_cells, bc):
     assert np.max(np.abs(phi - phi_ref)) < 1e-9
     assert relmax(e, opic.field(phi_ref, g)) < 1e-6
     assert bits & E.DEV_NAN == 0
+
+
+def test_newton_mixed_launch_group():
+    """Replicas of 8 .. 256 cells share one launch of the solve (one row per
+    thread), so the smaller ones leave lanes and whole waves idle."""
+    E = lib()
+    sizes = [(256, 0), (8, 0), (64, 1), (32, 0), (128, 1), (16, 1)]
+    specs = [E.ReplicaSpec(n, float(n), bc=bc, ppc=24, haar_levels=2) for n, bc in sizes]
+    ctx = make_ctx(specs)
+    parts = []
+    for r, sp in enumerate(specs):
+        pr = iaw_particles(sp, 11 + r) if sp.bc == 0 else slab_particles(sp, 11 + r)
+        set_particles(ctx, r, *pr)
+        parts.append(pr)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 80, cold=True)
+    bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    assert bits & E.DEV_NAN == 0
+    for r, sp in enumerate(specs):
+        q, phi, e = grid_np(ctx, r)
+        g = oracle_grid(sp)
+        rho = opic.fx_to_density(opic.deposit_fx(*parts[r][:2], parts[r][3], g), g)
+        phi_ref, _, ok = opic.newton_poisson(rho, g, tol=1e-13, max_iter=200)
+        assert ok
+        assert np.max(np.abs(phi - phi_ref)) < 1e-9, (r, sp.n_cells, sp.bc)
+        assert relmax(e, opic.field(phi_ref, g)) < 1e-6, (r, sp.n_cells, sp.bc)
 
 
 # ----------------------------------------------------------------- one step --
