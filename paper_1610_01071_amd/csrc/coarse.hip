@@ -58,8 +58,8 @@ __global__ __launch_bounds__(kProfThreads) void k_profile(const RepDev* __restri
       dj = (w0 * cj[b0] + w1 * cj[b1]) * inv_s;
     }
     const double nn = fmax(dn, 0.0);
-    R.prof_n[k] = nn;
-    R.prof_u[k] = nn > R.n_floor ? dj / nn : 0.0;
+    gmem(R.prof_n)[k] = nn;
+    gmem(R.prof_u)[k] = nn > R.n_floor ? dj / nn : 0.0;
   }
 }
 
@@ -77,10 +77,13 @@ __global__ __launch_bounds__(kProfThreads) void k_occupancy(const RepDev* __rest
   const int per = (n + kProfThreads - 1) / kProfThreads;
   const int c0 = t * per;
   const bool periodic = R.bc == 0;
+  const auto prof_n = gmem(R.prof_n);
+  const auto block_rank = gmem(R.block_rank);
+  const auto cell_of_rank = gmem(R.cell_of_rank);
   int cnt = 0;
   for (int c = c0; c < min(c0 + per, n); ++c) {
     const int cr = periodic ? ((c + 1) & (n - 1)) : c + 1;
-    cnt += fmax(R.prof_n[c], R.prof_n[cr]) > R.n_floor ? 1 : 0;
+    cnt += fmax(prof_n[c], prof_n[cr]) > R.n_floor ? 1 : 0;
   }
   s_part[t] = cnt;
   __syncthreads();
@@ -96,18 +99,18 @@ __global__ __launch_bounds__(kProfThreads) void k_occupancy(const RepDev* __rest
   const int lmask = (1 << R.levels) - 1;
   for (int c = c0; c < min(c0 + per, n); ++c) {
     const int cr = periodic ? ((c + 1) & (n - 1)) : c + 1;
-    const bool occ = fmax(R.prof_n[c], R.prof_n[cr]) > R.n_floor;
-    if ((c & lmask) == 0) R.block_rank[c >> R.levels] = (int32_t)min((int64_t)rank, max_cells);
+    const bool occ = fmax(prof_n[c], prof_n[cr]) > R.n_floor;
+    if ((c & lmask) == 0) block_rank[c >> R.levels] = (int32_t)min((int64_t)rank, max_cells);
     if (occ) {
-      if (rank < max_cells) R.cell_of_rank[rank] = c;
+      if (rank < max_cells) cell_of_rank[rank] = c;
       ++rank;
     }
   }
   if (t == kProfThreads - 1) {
     const int64_t total = s_part[kProfThreads - 1];
     const int64_t kept = min(total, max_cells);
-    R.block_rank[R.n_coarse] = (int32_t)kept;
-    *R.np = kept * R.ppc;
+    block_rank[R.n_coarse] = (int32_t)kept;
+    *gmem(R.np) = kept * R.ppc;
     if (total > max_cells) atomicOr(status, 4u);
   }
 }
@@ -181,23 +184,27 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const int r = only_rep >= 0 ? only_rep : find_rep(block_prefix, n_reps, item);
     const RepDev& R = reps[r];
     const int B = (int)(item - (only_rep >= 0 ? 0 : R.block_begin));
-    const int rb0 = R.block_rank[B];
-    const int rb1 = R.block_rank[B + 1];
+    const auto block_rank = gmem(R.block_rank);
+    const auto cell_of_rank = gmem(R.cell_of_rank);
+    const auto prof_n = gmem(R.prof_n);
+    const auto prof_u = gmem(R.prof_u);
+    const int rb0 = block_rank[B];
+    const int rb1 = block_rank[B + 1];
     const int ppc = R.ppc;
     const int count = (rb1 - rb0) * ppc;  // at most 2^l cells * ppc < 2^31 (checked at init)
     const int64_t slot0 = (int64_t)rb0 * ppc;
-    const uint32_t shift = (uint32_t)R.aux[1];  // Cranley-Patterson rotation of this lift
+    const uint32_t shift = (uint32_t)gmem(R.aux)[1];  // Cranley-Patterson rotation of this lift
     const int ncell = rb1 - rb0;
     const bool cached = ncell <= kLiftCache;
     if (cached) {
       for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
-        const int c = R.cell_of_rank[rb0 + k];
+        const int c = cell_of_rank[rb0 + k];
         const int cr = right_node(R, c);
         s_c[k] = c;
-        s_nl[k] = R.prof_n[c];
-        s_nr[k] = R.prof_n[cr];
-        s_ul[k] = R.prof_u[c];
-        s_ur[k] = R.prof_u[cr];
+        s_nl[k] = prof_n[c];
+        s_nr[k] = prof_n[cr];
+        s_ul[k] = prof_u[c];
+        s_ur[k] = prof_u[cr];
       }
       __syncthreads();
     }
@@ -205,9 +212,9 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
       const int jr = j / ppc;
       const int m = j - jr * ppc;
       if (cached) return generate(R, s_c[jr], s_nl[jr], s_nr[jr], s_ul[jr], s_ur[jr], m, shift);
-      const int c = R.cell_of_rank[rb0 + jr];
+      const int c = cell_of_rank[rb0 + jr];
       const int cr = right_node(R, c);
-      return generate(R, c, R.prof_n[c], R.prof_n[cr], R.prof_u[c], R.prof_u[cr], m, shift);
+      return generate(R, c, prof_n[c], prof_n[cr], prof_u[c], prof_u[cr], m, shift);
     };
     double ratio = 1.0, dv = 0.0;
     if (coarse != nullptr) {
@@ -221,20 +228,24 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
       sw = block_sum(sw, s_red);
       swv = block_sum(swv, s_red);
       const double scale = R.h * sqrt((double)(1 << R.levels));
-      const double* cc = coarse + coff[r];
+      const auto cc = gmem(coarse + coff[r]);
       const double mt = fmax(cc[B], 0.0) * scale;
       const double jt = cc[R.n_coarse + B] * scale;
       if (sw > 0.0) ratio = mt / sw;
       if (mt > 0.0) dv = (jt - ratio * swv) / mt;
     }
+    const auto cell = gmem(R.cell);
+    const auto frac = gmem(R.frac);
+    const auto vel = gmem(R.v);
+    const auto wgt = gmem(R.w);
 #pragma unroll 1
     for (int j = threadIdx.x; j < count; j += blockDim.x) {
       const Gen g = gen(j);
       const int64_t s = slot0 + j;
-      R.cell[s] = (int16_t)g.cell;
-      R.frac[s] = g.frac;
-      R.v[s] = (float)(g.v + dv);
-      R.w[s] = (float)(g.w * ratio);
+      cell[s] = (int16_t)g.cell;
+      frac[s] = g.frac;
+      vel[s] = (float)(g.v + dv);
+      wgt[s] = (float)(g.w * ratio);
     }
     __syncthreads();
   }
@@ -250,7 +261,7 @@ __global__ void k_restrict(const RepDev* __restrict__ reps, int steps, double* _
   double* out = snap + soff[blockIdx.y];
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
        k += (int64_t)gridDim.x * blockDim.x)
-    out[k] = (double)R.rbins[k] * scale;
+    out[k] = (double)gmem(R.rbins)[k] * scale;
 }
 
 __global__ void k_project(const RepDev* __restrict__ reps, const double* __restrict__ snap,
@@ -301,15 +312,15 @@ __global__ void k_ensemble_mean(const RepDev* __restrict__ reps, int n_reps,
 __global__ void k_set_shifts(const RepDev* __restrict__ reps, int n_reps, int only_rep,
                              const ShiftArg shifts) {
   const int r = threadIdx.x;
-  if (r < n_reps && (only_rep < 0 || r == only_rep)) reps[r].aux[1] = (int64_t)shifts.s[r];
+  if (r < n_reps && (only_rep < 0 || r == only_rep)) gmem(reps[r].aux)[1] = (int64_t)shifts.s[r];
 }
 
 __global__ void k_set_profile(const RepDev* __restrict__ reps, int rep,
                               const double* __restrict__ dn, const double* __restrict__ du) {
   const RepDev& R = reps[rep];
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < R.n_nodes; k += gridDim.x * blockDim.x) {
-    R.prof_n[k] = fmax(dn[k], 0.0);
-    R.prof_u[k] = du[k];
+    gmem(R.prof_n)[k] = fmax(dn[k], 0.0);
+    gmem(R.prof_u)[k] = du[k];
   }
 }
 

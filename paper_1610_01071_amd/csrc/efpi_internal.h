@@ -12,6 +12,15 @@ constexpr double kFxScale = 1099511627776.0;     // 2^40: fixed-point charge uni
 constexpr double kFxInv = 1.0 / 1099511627776.0;
 constexpr int kWave = 64;
 
+// Global-memory view of an array address taken from a descriptor.  Accesses
+// through it compile to global_* instructions; through the plain (generic)
+// pointer they become flat_* ones, which also count against the LDS wait
+// counter, so every later LDS wait would wait for the memory access as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Per-replica descriptor in device memory: sizes, parameters and the addresses
 // of the replica's arrays inside the workspace.
 struct RepDev {

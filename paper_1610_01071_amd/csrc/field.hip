@@ -26,7 +26,10 @@
 namespace efpi {
 namespace {
 
-constexpr int kMaxT = 1024;
+// 16-byte vector types for the row loads and stores
+typedef long long i64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double clamp2(double x) { return fmin(2.0, fmax(-2.0, x)); }
 
@@ -149,7 +152,8 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   const double ih2 = 1.0 / (h * h);
   const float alpha = (float)-ih2;
   const double qscale = kFxInv / h;
-  const long long* __restrict__ Q = reinterpret_cast<const long long*>(R.q[qsel]);
+  const auto Q = gmem(reinterpret_cast<const long long*>(R.q[qsel]));
+  const auto phig = gmem(R.phi);
   const bool owns_n = !periodic && act && t == T - 1;
   const float aL = (periodic || t > 0) ? alpha : 0.f;
   const float aR = (periodic || t < T - 1) ? alpha : 0.f;
@@ -168,10 +172,10 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
     if (act) {
       if constexpr (!kHoist) {
       } else if constexpr (M >= 2) {
-        const longlong2* q2 = reinterpret_cast<const longlong2*>(Q + t * M);
+        const auto q2 = gmem(reinterpret_cast<const i64x2*>(R.q[qsel])) + t * (M / 2);
 #pragma unroll
         for (int j = 0; j < M / 2; ++j) {
-          const longlong2 v = q2[j];
+          const i64x2 v = q2[j];
           qv[2 * j] = (double)v.x * qscale;
           qv[2 * j + 1] = (double)v.y * qscale;
         }
@@ -185,17 +189,17 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
           phi[j] = log(fmax(charge(j) / s, 1e-8));
         }
       } else if constexpr (M >= 2) {
-        const double2* p2 = reinterpret_cast<const double2*>(R.phi + t * M);
+        const auto p2 = gmem(reinterpret_cast<const f64x2*>(R.phi)) + t * (M / 2);
 #pragma unroll
         for (int j = 0; j < M / 2; ++j) {
-          const double2 v = p2[j];
+          const f64x2 v = p2[j];
           phi[2 * j] = v.x;
           phi[2 * j + 1] = v.y;
         }
       } else {
-        phi[0] = R.phi[t];
+        phi[0] = phig[t];
       }
-      if (owns_n) phin = cold ? log(fmax((double)Q[n] * qscale / 0.5, 1e-8)) : R.phi[n];
+      if (owns_n) phin = cold ? log(fmax((double)Q[n] * qscale / 0.5, 1e-8)) : phig[n];
     }
 
     for (int it = 0; it < iters; ++it) {
@@ -405,13 +409,13 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   __syncthreads();
   if (act) {
     if constexpr (M >= 2) {
-      double2* p2 = reinterpret_cast<double2*>(R.phi + t * M);
+      const auto p2 = gmem(reinterpret_cast<f64x2*>(R.phi)) + t * (M / 2);
 #pragma unroll
-      for (int j = 0; j < M / 2; ++j) p2[j] = make_double2(phi[2 * j], phi[2 * j + 1]);
+      for (int j = 0; j < M / 2; ++j) p2[j] = f64x2{phi[2 * j], phi[2 * j + 1]};
     } else {
-      R.phi[t] = phi[0];
+      phig[t] = phi[0];
     }
-    if (owns_n) R.phi[n] = phin;
+    if (owns_n) phig[n] = phin;
     const double pl = t > 0 ? s_last[t - 1] : (periodic ? s_last[T - 1] : 0.0);
     const double pr = t < T - 1 ? s_first[t + 1] : (periodic ? s_first[0] : s_phin);
     const double inv2h = 0.5 / h;
@@ -425,33 +429,33 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
       if (!periodic && g == 0) ev[j] = 0.f;
     }
     if constexpr (M >= 4) {
-      float4* e4 = reinterpret_cast<float4*>(R.e + t * M);
-      float4* n4 = reinterpret_cast<float4*>(R.en + t * M);
+      const auto e4 = gmem(reinterpret_cast<f32x4*>(R.e)) + t * (M / 4);
+      const auto n4 = gmem(reinterpret_cast<f32x4*>(R.en)) + t * (M / 4);
 #pragma unroll
       for (int j = 0; j < M / 4; ++j) {
-        const float4 v = make_float4(ev[4 * j], ev[4 * j + 1], ev[4 * j + 2], ev[4 * j + 3]);
+        const f32x4 v = {ev[4 * j], ev[4 * j + 1], ev[4 * j + 2], ev[4 * j + 3]};
         e4[j] = v;
         if (save_en) n4[j] = v;
       }
     } else {
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        R.e[t * M + j] = ev[j];
-        if (save_en) R.en[t * M + j] = ev[j];
+        gmem(R.e)[t * M + j] = ev[j];
+        if (save_en) gmem(R.en)[t * M + j] = ev[j];
       }
     }
     if (owns_n) {
-      R.e[n] = 0.f;
-      if (save_en) R.en[n] = 0.f;
+      gmem(R.e)[n] = 0.f;
+      if (save_en) gmem(R.en)[n] = 0.f;
     }
   }
   // --- clear the next deposit buffer and, at a burst start, the snapshot bins
   {
-    long long* other = reinterpret_cast<long long*>(R.q[qsel ^ 1]);
+    const auto other = gmem(reinterpret_cast<long long*>(R.q[qsel ^ 1]));
     for (int k = t; k < R.n_nodes; k += blockDim.x) other[k] = 0;
     if (zero_bins) {
       const int nb = (R.burst_steps + 1) * 2 * R.n_coarse;
-      long long* rb = reinterpret_cast<long long*>(R.rbins);
+      const auto rb = gmem(reinterpret_cast<long long*>(R.rbins));
       for (int k = t; k < nb; k += blockDim.x) rb[k] = 0;
     }
   }
@@ -470,9 +474,11 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
 // Burst start when the field is already current: store E_n and clear the bins.
 __global__ void k_prep_burst(const RepDev* __restrict__ reps) {
   const RepDev& R = reps[blockIdx.x];
-  for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) R.en[k] = R.e[k];
+  const auto e = gmem(R.e);
+  const auto en = gmem(R.en);
+  for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) en[k] = e[k];
   const int nb = (R.burst_steps + 1) * 2 * R.n_coarse;
-  long long* rb = reinterpret_cast<long long*>(R.rbins);
+  const auto rb = gmem(reinterpret_cast<long long*>(R.rbins));
   for (int k = threadIdx.x; k < nb; k += blockDim.x) rb[k] = 0;
 }
 

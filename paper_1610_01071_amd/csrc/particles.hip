@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
   for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
     const int r = find_replica(item_prefix, n_reps, item);
     const RepDev& R = reps[r];
-    const int64_t np = uniform_i64(*R.np);
+    const int64_t np = uniform_i64(*gmem(R.np));
     const int64_t i0 = (item - R.item_begin) * (int64_t)tile;
     if (i0 >= np) continue;
     const unsigned cnt = (unsigned)min((int64_t)tile, np - i0);
@@ -356,24 +356,27 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
           }
         }
       }
-      int rkey[kBatch], dkey[kBatch];
-      float ra0[kBatch], ra1[kBatch], rb0[kBatch], rb1[kBatch];
-      long long da[kBatch], db[kBatch];
+      // E^p at the ions; then the snapshot values are computed and merged, and only
+      // after that the push and the new charge (the two phases' value arrays are
+      // never live together, which keeps the kernel at 4 waves per SIMD)
+      float epa[kBatch];
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
-        const unsigned idx = b0 + j * kThreads + tid;
-        __builtin_assume(idx < 65536u + kThreads * kBatch);
-        const int c = cl[j];
         const float f = fr[j];
-        const float v = vv[j];
-        const float w = ww[j];
-        const bool alive = c >= 0 && c < n;  // cells outside [0, N) are treated as absorbed
-        const int cs = alive ? c : 0;         // safe cell index
-        float ep = 0.f;
-        if (restrict_ || push) ep = (1.f - f) * e0[j] + f * e1[j];
-        rkey[j] = -1;
-        ra0[j] = ra1[j] = rb0[j] = rb1[j] = 0.f;
-        if (restrict_) {
+        epa[j] = (restrict_ || push) ? (1.f - f) * e0[j] + f * e1[j] : 0.f;
+      }
+      if (restrict_) {
+        int rkey[kBatch];
+        float ra0[kBatch], ra1[kBatch], rb0[kBatch], rb1[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+          const int c = cl[j];
+          const float f = fr[j];
+          const float v = vv[j];
+          const float w = ww[j];
+          const bool alive = c >= 0 && c < n;  // cells outside [0, N) are treated as absorbed
+          const int cs = alive ? c : 0;         // safe cell index
+          const float ep = epa[j];
           // Snapshot p: time-centred velocity, then the approximate characteristic
           // over tau = Delta t - p dt (eq. B.4) and CIC at the moved position (eq. B.5).
           const float vpc = fresh ? v : v + half_dt * ep;
@@ -398,9 +401,23 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
           rb0[j] = same ? 0.f : nrs;
           rb1[j] = same ? 0.f : jrs;
         }
-        dkey[j] = -1;
-        da[j] = db[j] = 0;
-        if (deposit) {
+        merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, rbase, racc0, racc1, rb,
+                      rb + nc);
+      }
+      if (deposit) {
+        int dkey[kBatch];
+        long long da[kBatch], db[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+          const unsigned idx = b0 + j * kThreads + tid;
+          __builtin_assume(idx < 65536u + kThreads * kBatch);
+          const int c = cl[j];
+          const float f = fr[j];
+          const float v = vv[j];
+          const float w = ww[j];
+          const bool alive = c >= 0 && c < n;
+          const int cs = alive ? c : 0;
+          const float ep = epa[j];
           int cn = cs;
           float fn = f, vn = v;
           if (push) {
@@ -424,11 +441,8 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
           da[j] = q - qr;
           db[j] = qr;
         }
+        merge_charge(dkey, da, db, periodic ? n : -1, qbase, qacc, wq);
       }
-      if (restrict_)
-        merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, rbase, racc0, racc1, rb,
-                      rb + nc);
-      if (deposit) merge_charge(dkey, da, db, periodic ? n : -1, qbase, qacc, wq);
     }
     if (deposit) lds_qs[tid / kWave][tid % kWave] = qacc;
     if (restrict_) {

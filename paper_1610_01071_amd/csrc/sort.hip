@@ -31,20 +31,25 @@ __device__ __forceinline__ unsigned key_of(int16_t c) {
   return c < 0 ? 0xFFFFu : (unsigned)(uint16_t)c;
 }
 
+#define EFPI_G __attribute__((address_space(1)))
 struct Store {
-  const int16_t* cell;
-  const float* frac;
-  const float* v;
-  const float* w;
-  int16_t* ocell;
-  float* ofrac;
-  float* ov;
-  float* ow;
+  const EFPI_G int16_t* cell;
+  const EFPI_G float* frac;
+  const EFPI_G float* v;
+  const EFPI_G float* w;
+  EFPI_G int16_t* ocell;
+  EFPI_G float* ofrac;
+  EFPI_G float* ov;
+  EFPI_G float* ow;
 };
+#undef EFPI_G
 
 __device__ __forceinline__ Store store_of(const RepDev& R, int pass) {
-  if (pass == 0) return Store{R.cell, R.frac, R.v, R.w, R.cell2, R.frac2, R.v2, R.w2};
-  return Store{R.cell2, R.frac2, R.v2, R.w2, R.cell, R.frac, R.v, R.w};
+  if (pass == 0)
+    return Store{gmem(R.cell), gmem(R.frac), gmem(R.v), gmem(R.w),
+                 gmem(R.cell2), gmem(R.frac2), gmem(R.v2), gmem(R.w2)};
+  return Store{gmem(R.cell2), gmem(R.frac2), gmem(R.v2), gmem(R.w2),
+               gmem(R.cell), gmem(R.frac), gmem(R.v), gmem(R.w)};
 }
 
 // Per-wave digit counts of the tile into LDS rows, summed into hist[item][digit].
@@ -58,7 +63,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const RepDev* __restrict__ re
     const int r = find_replica(item_prefix, n_reps, item);
     const RepDev& R = reps[r];
     const Store S = store_of(R, pass);
-    const int64_t np = *R.np;
+    const int64_t np = *gmem(R.np);
     const int64_t i0 = (item - R.item_begin) * (int64_t)tile;
     for (int k = threadIdx.x; k < kWaves * kDigits; k += kThreads) (&s_cnt[0][0])[k] = 0;
     __syncthreads();
@@ -126,12 +131,12 @@ __global__ __launch_bounds__(kDigits) void k_scan_digits(const RepDev* __restric
   int64_t base = 0;
   for (int k = 0; k < d; ++k) base += s_tot[k];
   tot[(int64_t)r * kDigits + d] = base;
-  if (pass == 1 && d == 0) reps[r].aux[0] = s_tot[kDigits - 1];
+  if (pass == 1 && d == 0) gmem(reps[r].aux)[0] = s_tot[kDigits - 1];
 }
 
 __global__ void k_drop_absorbed(const RepDev* __restrict__ reps) {
   const RepDev& R = reps[blockIdx.x];
-  if (threadIdx.x == 0) *R.np = *R.np - R.aux[0];
+  if (threadIdx.x == 0) *gmem(R.np) = *gmem(R.np) - *gmem(R.aux);
 }
 
 __global__ __launch_bounds__(kThreads) void k_scatter(const RepDev* __restrict__ reps,
@@ -147,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const RepDev* __restrict__
     const int r = find_replica(item_prefix, n_reps, item);
     const RepDev& R = reps[r];
     const Store S = store_of(R, pass);
-    const int64_t np = *R.np;
+    const int64_t np = *gmem(R.np);
     const int64_t i0 = (item - R.item_begin) * (int64_t)tile;
     const int64_t chunk = tile / kWaves;
     const int64_t a = i0 + wave * chunk;
