@@ -71,13 +71,14 @@ struct efpi_ctx {
   int64_t* d_snap_off = nullptr;
   int64_t* d_coarse_off = nullptr;
   int32_t* d_group = nullptr;
-  int32_t* d_newton_list = nullptr;
+  RepDev* d_newton_reps = nullptr;  // descriptors in Newton launch order
   double* d_snap = nullptr;
   double* d_coarse = nullptr;
   int32_t* d_sort_hist = nullptr;
   int64_t* d_sort_base = nullptr;
   std::vector<int64_t> h_item_prefix, h_block_prefix, h_snap_off, h_coarse_off;
   std::vector<int32_t> h_group, h_newton_list;
+  std::vector<RepDev> h_newton_reps;
   std::vector<NewtonGroup> ngroups;
   int64_t total_items = 0, total_blocks = 0, snap_total = 0, coarse_total = 0;
   // state
@@ -181,7 +182,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
   uint8_t* p_soff = take(sizeof(int64_t) * R);
   uint8_t* p_coff = take(sizeof(int64_t) * R);
   uint8_t* p_group = take(sizeof(int32_t) * R);
-  uint8_t* p_nlist = take(sizeof(int32_t) * R);
+  uint8_t* p_nreps = take(sizeof(RepDev) * R);
   int64_t snap_total = 0, coarse_total = 0;
   for (int r = 0; r < R; ++r) {
     const efpi_replica& p = cfg->replicas[r];
@@ -208,7 +209,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     ctx->d_snap_off = reinterpret_cast<int64_t*>(p_soff);
     ctx->d_coarse_off = reinterpret_cast<int64_t*>(p_coff);
     ctx->d_group = reinterpret_cast<int32_t*>(p_group);
-    ctx->d_newton_list = reinterpret_cast<int32_t*>(p_nlist);
+    ctx->d_newton_reps = reinterpret_cast<RepDev*>(p_nreps);
     ctx->d_snap = reinterpret_cast<double*>(p_snap);
     ctx->d_coarse = reinterpret_cast<double*>(p_coarse);
     ctx->d_sort_hist = reinterpret_cast<int32_t*>(p_hist);
@@ -328,7 +329,7 @@ void deposit_into_next(efpi_ctx* c) {
 
 void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
   for (const NewtonGroup& g : c->ngroups)
-    launch_newton(c->d_reps, c->d_newton_list + g.first, g.count, g.M, g.threads, iters, cold,
+    launch_newton(c->d_newton_reps + g.first, g.count, g.M, g.threads, iters, cold,
                   c->cur, save_en, zero_bins, c->cfg.newton_tol, c->d_status, c->stream);
   c->other_zero = true;
   c->field_valid = true;
@@ -350,11 +351,11 @@ ShiftArg shifts_of(const efpi_ctx* c, const uint32_t* h_shifts) {
 // Lift of every replica; with h_shifts == nullptr the rotations already stored
 // on the device (launch_set_shifts) are used.
 efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shifts) {
-  launch_profile(c->d_reps, c->R, d_coarse, c->d_coarse_off, c->stream);
-  launch_occupancy(c->d_reps, c->R, -1, c->d_status, c->stream);
   const ShiftArg sh = shifts_of(c, h_shifts);
+  launch_lift_prep(c->d_reps, c->R, d_coarse, c->d_coarse_off, c->d_status,
+                   h_shifts ? &sh : nullptr, c->stream);
   launch_lift_particles(c->d_reps, c->d_block_prefix, c->R, c->total_blocks, -1, d_coarse,
-                        c->d_coarse_off, h_shifts ? &sh : nullptr, c->grid_blocks, c->stream);
+                        c->d_coarse_off, nullptr, c->grid_blocks, c->stream);
   mark_new_particles(c);
   return hip_check("lift");
 }
@@ -508,7 +509,9 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
                  hipMemcpyHostToDevice, c->stream));
   note(hipMemcpyAsync(c->d_group, c->h_group.data(), sizeof(int32_t) * c->R, hipMemcpyHostToDevice,
                  c->stream));
-  note(hipMemcpyAsync(c->d_newton_list, c->h_newton_list.data(), sizeof(int32_t) * c->R,
+  c->h_newton_reps.clear();
+  for (int32_t r : c->h_newton_list) c->h_newton_reps.push_back(c->h_reps[r]);
+  note(hipMemcpyAsync(c->d_newton_reps, c->h_newton_reps.data(), sizeof(RepDev) * c->R,
                  hipMemcpyHostToDevice, c->stream));
   const hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -662,9 +665,8 @@ efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_
   if (st != EFPI_OK) return st;
   st = do_burst(ctx, k, true);
   if (st != EFPI_OK) return st;
-  launch_restrict(ctx->d_reps, ctx->R, k, ctx->d_snap, ctx->d_snap_off, ctx->stream);
-  launch_project(ctx->d_reps, ctx->R, ctx->d_snap, ctx->d_snap_off, d_coarse_out, ctx->d_coarse_off,
-                 ctx->d_status, ctx->stream);
+  launch_restrict_project(ctx->d_reps, ctx->R, ctx->d_snap, ctx->d_snap_off, d_coarse_out,
+                          ctx->d_coarse_off, ctx->d_status, ctx->stream);
   return hip_check("macro_step");
 }
 
@@ -693,9 +695,8 @@ efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in, doub
     // the same launches as efpi_macro_step, lift rotations read from the device
     efpi_status st = do_lift(ctx, d_coarse_in, nullptr);
     if (st == EFPI_OK) st = do_burst(ctx, k, true);
-    launch_restrict(ctx->d_reps, ctx->R, k, ctx->d_snap, ctx->d_snap_off, ctx->stream);
-    launch_project(ctx->d_reps, ctx->R, ctx->d_snap, ctx->d_snap_off, d_coarse_out,
-                   ctx->d_coarse_off, ctx->d_status, ctx->stream);
+    launch_restrict_project(ctx->d_reps, ctx->R, ctx->d_snap, ctx->d_snap_off, d_coarse_out,
+                            ctx->d_coarse_off, ctx->d_status, ctx->stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->stream, &graph);
     m.after = ctx->state();

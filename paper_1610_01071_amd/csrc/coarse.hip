@@ -12,9 +12,8 @@ constexpr int kProfThreads = 1024;
 // Inverse standard normal CDF of b in (0, 1), from the inverse complementary
 // error function of the smaller tail (FP32: the velocity is stored in FP32).
 // For b = (u + 1/2) 2^-32 with integer u, 2b and 2(1 - b) are exact in binary64
-// and representable in FP32, so neither tail loses precision.  Kept out of line
-// so that its constants are not hoisted into registers across the caller loops.
-__device__ __attribute__((noinline)) float inv_normal(double b) {
+// and representable in FP32, so neither tail loses precision.
+__device__ __forceinline__ float inv_normal(double b) {
   const float r2 = 1.41421356237f;
   return b < 0.5 ? -r2 * erfcinvf((float)(2.0 * b)) : r2 * erfcinvf((float)(2.0 * (1.0 - b)));
 }
@@ -24,11 +23,7 @@ __device__ __attribute__((noinline)) float inv_normal(double b) {
 // Haar with zero details (block means 2^{-l/2} c_B), optionally linearly
 // interpolated between block centres (periodic wrap; constant past the end
 // centres on walls).
-__global__ __launch_bounds__(kProfThreads) void k_profile(const RepDev* __restrict__ reps,
-                                                          const double* __restrict__ coarse,
-                                                          const int64_t* __restrict__ coff) {
-  const RepDev& R = reps[blockIdx.x];
-  const double* cn = coarse + coff[blockIdx.x];
+__device__ void profile_of(const RepDev& R, const double* __restrict__ cn) {
   const double* cj = cn + R.n_coarse;
   const int nc = R.n_coarse;
   const int bs = 1 << R.levels;
@@ -66,12 +61,7 @@ __global__ __launch_bounds__(kProfThreads) void k_profile(const RepDev* __restri
 // -------------------------------------------------------------- occupancy --
 // A cell is occupied when one of its nodes exceeds n_floor.  Exclusive scan of
 // occupied cells gives each cell's rank; the lift puts ppc ions per rank.
-__global__ __launch_bounds__(kProfThreads) void k_occupancy(const RepDev* __restrict__ reps,
-                                                            int only_rep,
-                                                            uint32_t* __restrict__ status) {
-  __shared__ int s_part[kProfThreads];
-  const int rep = only_rep >= 0 ? only_rep : (int)blockIdx.x;
-  const RepDev& R = reps[rep];
+__device__ void occupancy_of(const RepDev& R, uint32_t* __restrict__ status, int* s_part) {
   const int n = R.n_cells;
   const int t = threadIdx.x;
   const int per = (n + kProfThreads - 1) / kProfThreads;
@@ -115,6 +105,29 @@ __global__ __launch_bounds__(kProfThreads) void k_occupancy(const RepDev* __rest
   }
 }
 
+__global__ __launch_bounds__(kProfThreads) void k_occupancy(const RepDev* __restrict__ reps,
+                                                            int only_rep,
+                                                            uint32_t* __restrict__ status) {
+  __shared__ int s_part[kProfThreads];
+  occupancy_of(reps[only_rep >= 0 ? only_rep : (int)blockIdx.x], status, s_part);
+}
+
+// Lift preparation of every replica in one launch: the fine profile from the
+// coarse state, then the occupied cells and their ranks, and (with set_shift)
+// the replica's rotation of the quiet start.
+__global__ __launch_bounds__(kProfThreads) void k_lift_prep(const RepDev* __restrict__ reps,
+                                                            const double* __restrict__ coarse,
+                                                            const int64_t* __restrict__ coff,
+                                                            uint32_t* __restrict__ status,
+                                                            int set_shift, const ShiftArg shifts) {
+  __shared__ int s_part[kProfThreads];
+  const RepDev& R = reps[blockIdx.x];
+  profile_of(R, coarse + coff[blockIdx.x]);
+  __syncthreads();  // the profile written above is read by other threads below
+  occupancy_of(R, status, s_part);
+  if (set_shift && threadIdx.x == 0) gmem(R.aux)[1] = (int64_t)shifts.s[blockIdx.x];
+}
+
 // ---------------------------------------------------------- lift particles --
 struct Gen {
   int cell;
@@ -122,20 +135,25 @@ struct Gen {
   double v, w;
 };
 
-// Ion m of cell c, from the profile values at the cell's two nodes.
+// Standard normal deviate of ion m of cell c from its Hammersley point (quiet
+// start), and the ion itself from the profile values at the cell's nodes.
+__device__ __forceinline__ float normal_of(int c, int m, int ppc, uint32_t shift) {
+  const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
+  const uint32_t u = __brev(idx) + shift;
+  const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
+  return inv_normal(b);
+}
+
 __device__ __forceinline__ Gen generate(const RepDev& R, int c, double nl, double nr, double ul,
-                                       double ur, int m, uint32_t shift) {
+                                       double ur, int m, float z) {
   Gen g;
   const int ppc = R.ppc;
   g.cell = c;
   g.frac = (float)(((double)m + 0.5) / (double)ppc);
-  const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
-  const uint32_t u = __brev(idx) + shift;
-  const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
   const double th = (double)g.frac;
   const double nx = (1.0 - th) * nl + th * nr;
   const double ux = (1.0 - th) * ul + th * ur;
-  g.v = ux + R.vth * (double)inv_normal(b);
+  g.v = ux + R.vth * (double)z;
   g.w = nx * R.h / (double)ppc;
   return g;
 }
@@ -208,20 +226,43 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
       }
       __syncthreads();
     }
-    auto gen = [&](int j) {
+    // ion j of the block; a deviate z equal to kNone is computed and returned in z
+    constexpr float kNone = -3e38f;
+    auto gen = [&](int j, float& z) {
       const int jr = j / ppc;
       const int m = j - jr * ppc;
-      if (cached) return generate(R, s_c[jr], s_nl[jr], s_nr[jr], s_ul[jr], s_ur[jr], m, shift);
+      if (cached) {
+        const int c = s_c[jr];
+        if (z == kNone) z = normal_of(c, m, ppc, shift);
+        return generate(R, c, s_nl[jr], s_nr[jr], s_ul[jr], s_ur[jr], m, z);
+      }
       const int c = cell_of_rank[rb0 + jr];
       const int cr = right_node(R, c);
-      return generate(R, c, prof_n[c], prof_n[cr], prof_u[c], prof_u[cr], m, shift);
+      if (z == kNone) z = normal_of(c, m, ppc, shift);
+      return generate(R, c, prof_n[c], prof_n[cr], prof_u[c], prof_u[cr], m, z);
     };
+    // the first kKeep ions of every thread keep their deviate in registers
+    // between the correction sums and the stores
+    constexpr int kKeep = 16;
+    float keep[kKeep];
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) keep[k] = kNone;
     double ratio = 1.0, dv = 0.0;
     if (coarse != nullptr) {
       double sw = 0.0, swv = 0.0;
+#pragma unroll
+      for (int k = 0; k < kKeep; ++k) {
+        const int j = threadIdx.x + k * kLiftThreads;
+        if (j < count) {
+          const Gen g = gen(j, keep[k]);
+          sw += g.w;
+          swv += g.w * g.v;
+        }
+      }
 #pragma unroll 1
-      for (int j = threadIdx.x; j < count; j += blockDim.x) {
-        const Gen g = gen(j);
+      for (int j = threadIdx.x + kKeep * kLiftThreads; j < count; j += kLiftThreads) {
+        float z = kNone;
+        const Gen g = gen(j, z);
         sw += g.w;
         swv += g.w * g.v;
       }
@@ -238,14 +279,22 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const auto frac = gmem(R.frac);
     const auto vel = gmem(R.v);
     const auto wgt = gmem(R.w);
-#pragma unroll 1
-    for (int j = threadIdx.x; j < count; j += blockDim.x) {
-      const Gen g = gen(j);
+    auto put = [&](int j, const Gen& g) {
       const int64_t s = slot0 + j;
       cell[s] = (int16_t)g.cell;
       frac[s] = g.frac;
       vel[s] = (float)(g.v + dv);
       wgt[s] = (float)(g.w * ratio);
+    };
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) {
+      const int j = threadIdx.x + k * kLiftThreads;
+      if (j < count) put(j, gen(j, keep[k]));
+    }
+#pragma unroll 1
+    for (int j = threadIdx.x + kKeep * kLiftThreads; j < count; j += kLiftThreads) {
+      float z = kNone;
+      put(j, gen(j, z));
     }
     __syncthreads();
   }
@@ -284,6 +333,39 @@ __global__ void k_project(const RepDev* __restrict__ reps, const double* __restr
     o[k] = val;
     if (!(fabs(val) < 1e300)) atomicOr(status, 2u);
     if (k < nc && val < 0.0) atomicOr(status, 8u);
+  }
+}
+
+// Restriction of every snapshot of the burst into coefficients and, in the same
+// pass, the least-squares slope (eq. 3.18) and projective step (eq. 3.17): the
+// thread of coefficient k converts that coefficient of all K + 1 snapshots, so
+// the projection needs no second launch.  The same arithmetic as k_restrict
+// followed by k_project.
+__global__ void k_restrict_project(const RepDev* __restrict__ reps, double* __restrict__ snap,
+                                   const int64_t* __restrict__ soff, double* __restrict__ out,
+                                   const int64_t* __restrict__ coff,
+                                   uint32_t* __restrict__ status) {
+  const RepDev& R = reps[blockIdx.y];
+  const int nc = R.n_coarse;
+  const int ne = R.burst_steps;
+  const double scale = kFxInv / R.h / sqrt((double)(1 << R.levels));
+  const auto rb = gmem(R.rbins);
+  double* s = snap + soff[blockIdx.y];
+  double* o = out + coff[blockIdx.y];
+  const double den = (double)ne * (ne + 1) * (ne + 2) * R.dt;
+  const double leap = R.macro_dt - ne * R.dt;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
+    auto val = [&](int p) { return (double)rb[(int64_t)p * 2 * nc + k] * scale; };
+    for (int p = 0; p <= ne; ++p) s[(int64_t)p * 2 * nc + k] = val(p);
+    double slope = 0.0;
+    for (int p = 0; p <= ne / 2; ++p) {
+      const double coef = 6.0 * (double)(ne - 2 * p) / den;
+      slope += coef * (val(ne - p) - val(p));
+    }
+    const double v = val(ne) + leap * slope;
+    o[k] = v;
+    if (!(fabs(v) < 1e300)) atomicOr(status, 2u);
+    if (k < nc && v < 0.0) atomicOr(status, 8u);
   }
 }
 
@@ -331,10 +413,12 @@ void launch_set_profile(const RepDev* d_reps, int rep, const double* d_n, const 
   hipLaunchKernelGGL(k_set_profile, dim3(16), dim3(256), 0, stream, d_reps, rep, d_n, d_u);
 }
 
-void launch_profile(const RepDev* d_reps, int n_reps, const double* d_coarse,
-                    const int64_t* d_coff, hipStream_t stream) {
-  hipLaunchKernelGGL(k_profile, dim3(n_reps), dim3(kProfThreads), 0, stream, d_reps, d_coarse,
-                     d_coff);
+void launch_lift_prep(const RepDev* d_reps, int n_reps, const double* d_coarse,
+                      const int64_t* d_coff, uint32_t* d_status, const ShiftArg* shifts,
+                      hipStream_t stream) {
+  const ShiftArg none{};
+  hipLaunchKernelGGL(k_lift_prep, dim3(n_reps), dim3(kProfThreads), 0, stream, d_reps, d_coarse,
+                     d_coff, d_status, shifts ? 1 : 0, shifts ? *shifts : none);
 }
 
 void launch_occupancy(const RepDev* d_reps, int n_reps, int only_rep, uint32_t* d_status,
@@ -371,6 +455,13 @@ void launch_project(const RepDev* d_reps, int n_reps, const double* d_snap,
                     uint32_t* d_status, hipStream_t stream) {
   hipLaunchKernelGGL(k_project, dim3(4, n_reps), dim3(256), 0, stream, d_reps, d_snap, d_soff,
                      d_out, d_coff, d_status);
+}
+
+void launch_restrict_project(const RepDev* d_reps, int n_reps, double* d_snap,
+                             const int64_t* d_soff, double* d_out, const int64_t* d_coff,
+                             uint32_t* d_status, hipStream_t stream) {
+  hipLaunchKernelGGL(k_restrict_project, dim3(4, n_reps), dim3(256), 0, stream, d_reps, d_snap,
+                     d_soff, d_out, d_coff, d_status);
 }
 
 void launch_ensemble_mean(const RepDev* d_reps, int n_reps, const int32_t* d_group,

@@ -76,14 +76,18 @@ void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_
                       int64_t total_items, int tile, int grid_blocks, int p, int flags,
                       int qsel, hipStream_t stream, hipEvent_t ev0 = nullptr,
                       hipEvent_t ev1 = nullptr);
-void launch_newton(const RepDev* d_reps, const int32_t* d_list, int n_list, int M, int threads,
+// d_reps: the descriptors of the replicas solved by this launch, one workgroup each.
+void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
                    int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
                    uint32_t* d_status, hipStream_t stream);
 void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream);
 void launch_set_profile(const RepDev* d_reps, int rep, const double* d_n, const double* d_u,
                         hipStream_t stream);
-void launch_profile(const RepDev* d_reps, int n_reps, const double* d_coarse,
-                    const int64_t* d_coff, hipStream_t stream);
+// Fine profile and occupied-cell ranks of every replica before a lift; with
+// shifts != nullptr also the lift rotations (as launch_set_shifts).
+void launch_lift_prep(const RepDev* d_reps, int n_reps, const double* d_coarse,
+                      const int64_t* d_coff, uint32_t* d_status, const ShiftArg* shifts,
+                      hipStream_t stream);
 void launch_occupancy(const RepDev* d_reps, int n_reps, int only_rep, uint32_t* d_status,
                       hipStream_t stream);
 // Store each replica's lift rotation (R.aux[1]) for the next lift.
@@ -99,6 +103,10 @@ void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap
 void launch_project(const RepDev* d_reps, int n_reps, const double* d_snap,
                     const int64_t* d_soff, double* d_out, const int64_t* d_coff,
                     uint32_t* d_status, hipStream_t stream);
+// launch_restrict of all burst_steps + 1 snapshots followed by launch_project, in one launch.
+void launch_restrict_project(const RepDev* d_reps, int n_reps, double* d_snap,
+                             const int64_t* d_soff, double* d_out, const int64_t* d_coff,
+                             uint32_t* d_status, hipStream_t stream);
 void launch_ensemble_mean(const RepDev* d_reps, int n_reps, const int32_t* d_group,
                           double* d_coarse, const int64_t* d_coff, hipStream_t stream);
 void launch_fill_u8(void* d_ptr, size_t bytes, hipStream_t stream);

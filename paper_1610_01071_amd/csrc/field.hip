@@ -124,8 +124,7 @@ __device__ __forceinline__ float wave_cr(int lane, int nw, bool periodic, float 
 }
 
 template <int M, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ reps,
-                                                   const int32_t* __restrict__ list, int iters,
+__global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ reps, int iters,
                                                    int cold, int qsel, int save_en,
                                                    int zero_bins, double tol,
                                                    uint32_t* __restrict__ status) {
@@ -138,7 +137,7 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   __shared__ int s_wbad[kW];
   __shared__ double s_phin;
 
-  const RepDev& R = reps[list[blockIdx.x]];
+  const RepDev& R = reps[blockIdx.x];
   const int n = R.n_cells;
   const int T = n / M;
   const int t = threadIdx.x;
@@ -484,13 +483,13 @@ __global__ void k_prep_burst(const RepDev* __restrict__ reps) {
 
 }  // namespace
 
-void launch_newton(const RepDev* d_reps, const int32_t* d_list, int n_list, int M, int threads,
+void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
                    int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
                    uint32_t* d_status, hipStream_t stream) {
   if (n_list <= 0) return;
   const dim3 grid(n_list);
 #define EFPI_NEWTON(MM, TT)                                                                   \
-  hipLaunchKernelGGL((k_newton<MM, TT>), grid, dim3(threads), 0, stream, d_reps, d_list, iters, \
+  hipLaunchKernelGGL((k_newton<MM, TT>), grid, dim3(threads), 0, stream, d_reps, iters,         \
                      cold, qsel, save_en, zero_bins, tol, d_status)
   if (M == 1) EFPI_NEWTON(1, 256);
   else if (M == 2) EFPI_NEWTON(2, 256);
