@@ -31,6 +31,14 @@ __device__ __forceinline__ EFPI_GLOBAL T* gptr(T* p) {
 }
 typedef EFPI_GLOBAL unsigned long long gu64;
 
+// Element i of a tile array, addressed as a 32-bit byte offset from the tile's
+// base address (uniform, in scalar registers): one vector add per access instead
+// of 64-bit address arithmetic.  Tiles hold at most 65536 ions.
+template <typename T>
+__device__ __forceinline__ EFPI_GLOBAL T* at(EFPI_GLOBAL T* base, unsigned i) {
+  return (EFPI_GLOBAL T*)((EFPI_GLOBAL const char*)base + i * (unsigned)sizeof(T));
+}
+
 // A value that is the same in every lane, read so that the compiler knows it is
 // uniform (scalar registers, uniform control flow).
 __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
@@ -102,11 +110,18 @@ __device__ __forceinline__ long long rint_i64(double x) {
   return (long long)(__double_as_longlong(x + magic) - __double_as_longlong(magic));
 }
 
-// q = rint(w 2^40): the particle's charge in fixed point.
-__device__ __forceinline__ long long fx_charge(float w) { return rint_i64((double)w * kFxScale); }
+// rint(x) for |x| < 2^51 as a binary64 value (the same rounding as rint_i64).
+__device__ __forceinline__ double rint_d(double x) {
+  const double magic = 6755399441055744.0;
+  return (x + magic) - magic;
+}
+
+// q = rint(w 2^40): the particle's charge in fixed point, as an exact binary64
+// integer value.
+__device__ __forceinline__ double fx_charge(float w) { return rint_d((double)w * kFxScale); }
 // Right-node share rint(theta q) in binary64 (one rounded product, then ties-to-even).
-__device__ __forceinline__ long long fx_share(float theta, long long q) {
-  return rint_i64((double)theta * (double)q);
+__device__ __forceinline__ double fx_share(float theta, double q) {
+  return rint_d((double)theta * q);
 }
 // Fixed-point value of an FP32 partial sum.
 __device__ __forceinline__ long long fx_of(float x) { return rint_i64((double)x * kFxScale); }
@@ -145,8 +160,8 @@ __device__ __forceinline__ void add_to(const Window& w, int idx, long long val) 
 //
 // Charge deposit: ion j adds a[j] to node key[j] and b[j] to node key[j] + 1
 // (wrapping to 0 at `wrap`, or no wrap when wrap = -1).  Exact int64 sums.
-__device__ __forceinline__ void merge_charge(int (&key)[kBatch], const long long (&a)[kBatch],
-                                             const long long (&b)[kBatch], int wrap, int base,
+__device__ __forceinline__ void merge_charge(int (&key)[kBatch], const double (&a)[kBatch],
+                                             const double (&b)[kBatch], int wrap, int base,
                                              long long& acc, const Window& win) {
   const int lane = __lane_id();
   while (true) {
@@ -158,16 +173,18 @@ __device__ __forceinline__ void merge_charge(int (&key)[kBatch], const long long
     if (act == 0ull) break;
     const int leader = __ffsll((unsigned long long)act) - 1;
     const int lk = __builtin_amdgcn_readlane(mine, leader);
-    long long sa = 0, sb = 0;
+    // integer-valued binary64 lane sums: exact, since every lane sum stays below 2^49
+    double sa = 0.0, sb = 0.0;
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       const bool m = key[j] == lk;
-      sa += m ? a[j] : 0ll;
-      sb += m ? b[j] : 0ll;
+      const double one = m ? 1.0 : 0.0;
+      sa = fma(one, a[j], sa);
+      sb = fma(one, b[j], sb);
       key[j] = m ? -1 : key[j];
     }
-    const long long ta = wave_sum_i64(sa);
-    const long long tb = wave_sum_i64(sb);
+    const long long ta = wave_sum_i64(rint_i64(sa));
+    const long long tb = wave_sum_i64(rint_i64(sb));
     int r = lk + 1;
     if (r == wrap) r = 0;
     const int sl = lk - base;
@@ -205,10 +222,11 @@ __device__ __forceinline__ void merge_moments(int (&key)[kBatch], const float (&
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       const bool m = key[j] == lk;
-      s0 += m ? a0[j] : 0.f;
-      s1 += m ? a1[j] : 0.f;
-      s2 += m ? b0[j] : 0.f;
-      s3 += m ? b1[j] : 0.f;
+      const float one = m ? 1.f : 0.f;  // 1 * x + s and 0 * x + s round as the plain sums
+      s0 = fmaf(one, a0[j], s0);
+      s1 = fmaf(one, a1[j], s1);
+      s2 = fmaf(one, b0[j], s2);
+      s3 = fmaf(one, b1[j], s3);
       key[j] = m ? -1 : key[j];
     }
     const long long f0 = fx_of(wave_sum_f32(s0));
@@ -236,12 +254,12 @@ __device__ __forceinline__ void merge_moments(int (&key)[kBatch], const float (&
 
 // MODE (compile time): kRestrict | kPush for a burst step, kPush for plain PIC,
 // kRestrict for the last snapshot of a burst, kDepositOnly for a charge deposit.
+// Four waves per SIMD: the register budget is held at 128 (the pass is bound by
+// vector instruction issue, so it needs the occupancy to keep every SIMD busy).
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict__ reps,
-                                                         const int64_t* __restrict__ item_prefix,
-                                                         int n_reps, int64_t total_items,
-                                                         int tile, int p, int fresh_flag,
-                                                         int qsel) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ item_prefix,
+                 int n_reps, int64_t total_items, int tile, int p, int fresh_flag, int qsel) {
   __shared__ long long lds_q[kQWin];
   __shared__ long long lds_qs[kWaves][kWave];
   __shared__ long long lds_r[kWaves][2][kRWin];
@@ -312,11 +330,11 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
         const unsigned idx = b0 + j * kThreads + tid;
         const unsigned ci = min(idx, cnt - 1u);
         __builtin_assume(ci < 65536u);  // tiles hold at most 65536 ions
-        const int c = cellp[ci];
+        const int c = *at(cellp, ci);
         cl[j] = idx < cnt ? c : -1;
-        fr[j] = fracp[ci];
-        vv[j] = vp_[ci];
-        ww[j] = wp[ci];
+        fr[j] = *at(fracp, ci);
+        vv[j] = *at(vp_, ci);
+        ww[j] = *at(wp, ci);
       }
       // Node fields at both ends of each ion's cell, from the LDS window; ions
       // outside it (rare: unsorted or far-drifted stores) read global memory.
@@ -406,7 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
       }
       if (deposit) {
         int dkey[kBatch];
-        long long da[kBatch], db[kBatch];
+        double da[kBatch], db[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
           const unsigned idx = b0 + j * kThreads + tid;
@@ -429,14 +447,14 @@ __global__ __launch_bounds__(kThreads) void k_particles(const RepDev* __restrict
             cn = cs + (int)fl + (wrap_up ? 1 : 0);
             cn = periodic ? (cn & nmask) : ((cn < 0 || cn >= n) ? -1 : cn);  // walls absorb
             if (alive && idx < cnt) {
-              cellp[idx] = (int16_t)cn;
-              fracp[idx] = fn;
-              vp_[idx] = vn;
+              *at(cellp, idx) = (int16_t)cn;
+              *at(fracp, idx) = fn;
+              *at(vp_, idx) = vn;
             }
           }
           const bool dep = alive && cn >= 0;
-          const long long q = fx_charge(w);
-          const long long qr = fx_share(fn, q);
+          const double q = fx_charge(w);
+          const double qr = fx_share(fn, q);
           dkey[j] = dep ? cn : -1;
           da[j] = q - qr;
           db[j] = qr;
