@@ -5,8 +5,10 @@
 //
 // Work decomposition: every replica's particle slots are cut into tiles of
 // `tile` consecutive particles; a persistent grid walks the (replica, tile)
-// items.  The node field around the tile is staged in LDS.  Inside a tile,
-// each 64-lane wave merges all of its ions that hit the same node (deposit) or
+// items.  The node field around the tile is staged in LDS.  Inside a tile, each
+// wave takes runs of 512 consecutive ions (8 per lane), so that in a cell-sorted
+// store its ions touch few distinct nodes, and merges all of its ions that hit
+// the same node (deposit) or
 // coarse block (restriction) with fixed-order wave reductions, and adds the
 // merged value to a register owned by one lane (lane s holds node or block
 // base + s).  At the end of the tile the four waves' registers are summed
@@ -266,6 +268,10 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
   __shared__ float lds_e[kEWin + 1];
   __shared__ float lds_en[kEWin + 1];
   const int tid = threadIdx.x;
+  // a batch is kThreads * kBatch consecutive ions; wave w takes the w-th run of
+  // kWave * kBatch of them, lane l its ions l, l + 64, ... (coalesced loads, and
+  // each wave's ions span as few cells as possible)
+  const unsigned toff = (unsigned)(tid / kWave) * (kWave * kBatch) + (unsigned)(tid % kWave);
   const bool fresh = fresh_flag != 0;
   constexpr bool restrict_ = (MODE & kRestrict) != 0;
   constexpr bool push = (MODE & kPush) != 0;
@@ -327,7 +333,7 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
       float fr[kBatch], vv[kBatch], ww[kBatch];
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
-        const unsigned idx = b0 + j * kThreads + tid;
+        const unsigned idx = b0 + j * kWave + toff;
         const unsigned ci = min(idx, cnt - 1u);
         __builtin_assume(ci < 65536u);  // tiles hold at most 65536 ions
         const int c = *at(cellp, ci);
@@ -427,7 +433,7 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
         double da[kBatch], db[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
-          const unsigned idx = b0 + j * kThreads + tid;
+          const unsigned idx = b0 + j * kWave + toff;
           __builtin_assume(idx < 65536u + kThreads * kBatch);
           const int c = cl[j];
           const float f = fr[j];
