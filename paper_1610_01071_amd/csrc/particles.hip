@@ -7,11 +7,10 @@
 // `tile` consecutive particles; a persistent grid walks the (replica, tile)
 // items.  The node field around the tile is staged in LDS.  Inside a tile, each
 // wave takes runs of 512 consecutive ions (8 per lane), so that in a cell-sorted
-// store its ions touch few distinct nodes, and merges all of its ions that hit
-// the same node (deposit) or
-// coarse block (restriction) with fixed-order wave reductions, and adds the
-// merged value to a register owned by one lane (lane s holds node or block
-// base + s).  At the end of the tile the four waves' registers are summed
+// store its ions touch few distinct nodes.  It merges all of its ions that hit
+// the same node (deposit) or coarse block (restriction) with fixed-order wave
+// reductions, and adds the merged value to a register owned by one lane (lane s
+// holds node or block base + s).  At the end of the tile the four waves' registers are summed
 // through LDS and flushed with one 64-bit integer atomic per non-zero target.
 // Rare targets outside a wave's 64 slots go to an LDS window (deposit) or to
 // global atomics.  Every sum that reaches memory is an integer sum, so the
