@@ -19,6 +19,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 namespace efpi {
 namespace {
 
@@ -284,218 +286,223 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
     if (i0 >= np) continue;
     const unsigned cnt = (unsigned)min((int64_t)tile, np - i0);
     const int n = R.n_cells;
-    const bool periodic = (R.bc == 0);
-    const int nmask = n - 1;
-    const float dt = (float)R.dt;
-    const float inv_h = (float)R.inv_h;
-    const int levels = R.levels;
-    const int nc = R.n_coarse;
-    // p < 0: plain restriction of the current state (tau = 0, snapshot slot 0)
-    const float tau = p < 0 ? 0.f : (float)(R.macro_dt - (double)p * R.dt);
-    const bool coev = R.coevolving != 0 && p >= 0;
-    const EFPI_GLOBAL float* __restrict__ e = gptr(R.e);
-    const EFPI_GLOBAL float* __restrict__ en = gptr(R.en);
-    EFPI_GLOBAL int16_t* __restrict__ cellp = gptr(R.cell + i0);
-    EFPI_GLOBAL float* __restrict__ fracp = gptr(R.frac + i0);
-    EFPI_GLOBAL float* __restrict__ vp_ = gptr(R.v + i0);
-    const EFPI_GLOBAL float* __restrict__ wp = gptr(R.w + i0);
-    const float half_dt = 0.5f * dt;
-    const float dt_inv_h = dt * inv_h;
-    const float tau_inv_h = coev ? tau * inv_h : 0.f;
-    const float tau_e = coev ? tau : 0.f;
+    // the tile body, compiled once for periodic grids and once for walls
+    auto tile_pass = [&](auto bc_tag) {
+      constexpr bool periodic = decltype(bc_tag)::value;
+      const int nmask = n - 1;
+      const float dt = (float)R.dt;
+      const float inv_h = (float)R.inv_h;
+      const int levels = R.levels;
+      const int nc = R.n_coarse;
+      // p < 0: plain restriction of the current state (tau = 0, snapshot slot 0)
+      const float tau = p < 0 ? 0.f : (float)(R.macro_dt - (double)p * R.dt);
+      const bool coev = R.coevolving != 0 && p >= 0;
+      const EFPI_GLOBAL float* __restrict__ e = gptr(R.e);
+      const EFPI_GLOBAL float* __restrict__ en = gptr(R.en);
+      EFPI_GLOBAL int16_t* __restrict__ cellp = gptr(R.cell + i0);
+      EFPI_GLOBAL float* __restrict__ fracp = gptr(R.frac + i0);
+      EFPI_GLOBAL float* __restrict__ vp_ = gptr(R.v + i0);
+      const EFPI_GLOBAL float* __restrict__ wp = gptr(R.w + i0);
+      const float half_dt = 0.5f * dt;
+      const float dt_inv_h = dt * inv_h;
+      const float tau_inv_h = coev ? tau * inv_h : 0.f;
+      const float tau_e = coev ? tau : 0.f;
 
-    const int c_first = __builtin_amdgcn_readfirstlane((int)cellp[0]);
-    Window wq{lds_q, c_first - kQMargin, kQWin, reinterpret_cast<long long*>(R.q[qsel])};
-    long long* rb = reinterpret_cast<long long*>(R.rbins) + (int64_t)(p < 0 ? 0 : p) * 2 * nc;
-    const int rbase = (c_first >> levels) - kRMargin;
-    long long racc0 = 0, racc1 = 0;
-    const int qbase = c_first - kQSlotMargin;
-    long long qacc = 0;
+      const int c_first = __builtin_amdgcn_readfirstlane((int)cellp[0]);
+      Window wq{lds_q, c_first - kQMargin, kQWin, reinterpret_cast<long long*>(R.q[qsel])};
+      long long* rb = reinterpret_cast<long long*>(R.rbins) + (int64_t)(p < 0 ? 0 : p) * 2 * nc;
+      const int rbase = (c_first >> levels) - kRMargin;
+      long long racc0 = 0, racc1 = 0;
+      const int qbase = c_first - kQSlotMargin;
+      long long qacc = 0;
 
-    for (int k = tid; k < kQWin; k += kThreads) lds_q[k] = 0;
-    // Field window: nodes ebase .. ebase + kEWin (wrapped, or clamped to the wall
-    // nodes), so that a cell c in [ebase, ebase + kEWin) finds E_c and E_{c+1}.
-    const int ebase = c_first - kEMargin;
-    if (restrict_ || push) {
-      for (int k = tid; k <= kEWin; k += kThreads) {
-        const int g = periodic ? ((ebase + k) & nmask) : min(max(ebase + k, 0), n);
-        lds_e[k] = e[g];
-        if (restrict_) lds_en[k] = coev ? en[g] : 0.f;
+      for (int k = tid; k < kQWin; k += kThreads) lds_q[k] = 0;
+      // Field window: nodes ebase .. ebase + kEWin (wrapped, or clamped to the wall
+      // nodes), so that a cell c in [ebase, ebase + kEWin) finds E_c and E_{c+1}.
+      const int ebase = c_first - kEMargin;
+      if (restrict_ || push) {
+        for (int k = tid; k <= kEWin; k += kThreads) {
+          const int g = periodic ? ((ebase + k) & nmask) : min(max(ebase + k, 0), n);
+          lds_e[k] = e[g];
+          if (restrict_) lds_en[k] = coev ? en[g] : 0.f;
+        }
       }
-    }
-    __syncthreads();
+      __syncthreads();
 
-    for (unsigned b0 = 0; b0 < cnt; b0 += kThreads * kBatch) {
-      // loads use a clamped index so that they are unconditional; slots past the
-      // end of the tile are marked dead and never stored
-      int cl[kBatch];
-      float fr[kBatch], vv[kBatch], ww[kBatch];
-#pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const unsigned idx = b0 + j * kWave + toff;
-        const unsigned ci = min(idx, cnt - 1u);
-        __builtin_assume(ci < 65536u);  // tiles hold at most 65536 ions
-        const int c = *at(cellp, ci);
-        cl[j] = idx < cnt ? c : -1;
-        fr[j] = *at(fracp, ci);
-        vv[j] = *at(vp_, ci);
-        ww[j] = *at(wp, ci);
-      }
-      // Node fields at both ends of each ion's cell, from the LDS window; ions
-      // outside it (rare: unsorted or far-drifted stores) read global memory.
-      float e0[kBatch], e1[kBatch], n0[kBatch], n1[kBatch];
-      bool outside = false;
-#pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const int c = cl[j];
-        const bool alive = c >= 0 && c < n;
-        const int k = alive ? c - ebase : 0;
-        const bool inw = (unsigned)k < (unsigned)kEWin;
-        const int kk = inw ? k : 0;
-        outside |= !inw;
-        e0[j] = e1[j] = n0[j] = n1[j] = 0.f;
-        if (restrict_ || push) {
-          e0[j] = lds_e[kk];
-          e1[j] = lds_e[kk + 1];
-        }
-        if (restrict_) {
-          n0[j] = lds_en[kk];
-          n1[j] = lds_en[kk + 1];
-        }
-      }
-      if ((restrict_ || push) && __ballot(outside) != 0ull) {
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-          const int c = cl[j];
-          const bool alive = c >= 0 && c < n;
-          if (alive && (unsigned)(c - ebase) >= (unsigned)kEWin) {
-            const int cr = periodic ? ((c + 1) & nmask) : c + 1;
-            e0[j] = e[c];
-            e1[j] = e[cr];
-            if (restrict_ && coev) {
-              n0[j] = en[c];
-              n1[j] = en[cr];
-            }
-          }
-        }
-      }
-      // E^p at the ions; then the snapshot values are computed and merged, and only
-      // after that the push and the new charge (the two phases' value arrays are
-      // never live together, which keeps the kernel at 4 waves per SIMD)
-      float epa[kBatch];
-#pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const float f = fr[j];
-        epa[j] = (restrict_ || push) ? (1.f - f) * e0[j] + f * e1[j] : 0.f;
-      }
-      if (restrict_) {
-        int rkey[kBatch];
-        float ra0[kBatch], ra1[kBatch], rb0[kBatch], rb1[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-          const int c = cl[j];
-          const float f = fr[j];
-          const float v = vv[j];
-          const float w = ww[j];
-          const bool alive = c >= 0 && c < n;  // cells outside [0, N) are treated as absorbed
-          const int cs = alive ? c : 0;         // safe cell index
-          const float ep = epa[j];
-          // Snapshot p: time-centred velocity, then the approximate characteristic
-          // over tau = Delta t - p dt (eq. B.4) and CIC at the moved position (eq. B.5).
-          const float vpc = fresh ? v : v + half_dt * ep;
-          const float enx = (1.f - f) * n0[j] + f * n1[j];
-          const float xt = f + tau_inv_h * vpc;
-          const float vt = vpc + tau_e * enx;
-          const float fl = floorf(xt);
-          const bool wrap_up = (xt - fl) >= 1.f;
-          const float th = wrap_up ? 0.f : xt - fl;
-          const int ct0 = cs + (int)fl + (wrap_up ? 1 : 0);
-          const int ct = periodic ? (ct0 & nmask) : ct0;
-          const bool in = alive && (periodic || (ct >= 0 && ct < n));
-          const float wv = w * vt;
-          const int bl = ct >> levels;
-          const int nr = periodic ? ((ct + 1) & nmask) : ct + 1;
-          const int br = min(nr >> levels, nc - 1);  // wall node N joins the last block
-          const bool same = br == bl;
-          const float nrs = w * th, jrs = wv * th;
-          rkey[j] = in ? bl : -1;
-          ra0[j] = same ? w : w - nrs;
-          ra1[j] = same ? wv : wv - jrs;
-          rb0[j] = same ? 0.f : nrs;
-          rb1[j] = same ? 0.f : jrs;
-        }
-        merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, rbase, racc0, racc1, rb,
-                      rb + nc);
-      }
-      if (deposit) {
-        int dkey[kBatch];
-        double da[kBatch], db[kBatch];
+      for (unsigned b0 = 0; b0 < cnt; b0 += kThreads * kBatch) {
+        // loads use a clamped index so that they are unconditional; slots past the
+        // end of the tile are marked dead and never stored
+        int cl[kBatch];
+        float fr[kBatch], vv[kBatch], ww[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
           const unsigned idx = b0 + j * kWave + toff;
-          __builtin_assume(idx < 65536u + kThreads * kBatch);
+          const unsigned ci = min(idx, cnt - 1u);
+          __builtin_assume(ci < 65536u);  // tiles hold at most 65536 ions
+          const int c = *at(cellp, ci);
+          cl[j] = idx < cnt ? c : -1;
+          fr[j] = *at(fracp, ci);
+          vv[j] = *at(vp_, ci);
+          ww[j] = *at(wp, ci);
+        }
+        // Node fields at both ends of each ion's cell, from the LDS window; ions
+        // outside it (rare: unsorted or far-drifted stores) read global memory.
+        float e0[kBatch], e1[kBatch], n0[kBatch], n1[kBatch];
+        bool outside = false;
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
           const int c = cl[j];
-          const float f = fr[j];
-          const float v = vv[j];
-          const float w = ww[j];
           const bool alive = c >= 0 && c < n;
-          const int cs = alive ? c : 0;
-          const float ep = epa[j];
-          int cn = cs;
-          float fn = f, vn = v;
-          if (push) {
-            vn = fresh ? v + half_dt * ep : v + dt * ep;
-            const float xn = f + dt_inv_h * vn;
-            const float fl = floorf(xn);
-            const bool wrap_up = (xn - fl) >= 1.f;
-            fn = wrap_up ? 0.f : xn - fl;
-            cn = cs + (int)fl + (wrap_up ? 1 : 0);
-            cn = periodic ? (cn & nmask) : ((cn < 0 || cn >= n) ? -1 : cn);  // walls absorb
-            if (alive && idx < cnt) {
-              *at(cellp, idx) = (int16_t)cn;
-              *at(fracp, idx) = fn;
-              *at(vp_, idx) = vn;
+          const int k = alive ? c - ebase : 0;
+          const bool inw = (unsigned)k < (unsigned)kEWin;
+          const int kk = inw ? k : 0;
+          outside |= !inw;
+          e0[j] = e1[j] = n0[j] = n1[j] = 0.f;
+          if (restrict_ || push) {
+            e0[j] = lds_e[kk];
+            e1[j] = lds_e[kk + 1];
+          }
+          if (restrict_) {
+            n0[j] = lds_en[kk];
+            n1[j] = lds_en[kk + 1];
+          }
+        }
+        if ((restrict_ || push) && __ballot(outside) != 0ull) {
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j) {
+            const int c = cl[j];
+            const bool alive = c >= 0 && c < n;
+            if (alive && (unsigned)(c - ebase) >= (unsigned)kEWin) {
+              const int cr = periodic ? ((c + 1) & nmask) : c + 1;
+              e0[j] = e[c];
+              e1[j] = e[cr];
+              if (restrict_ && coev) {
+                n0[j] = en[c];
+                n1[j] = en[cr];
+              }
             }
           }
-          const bool dep = alive && cn >= 0;
-          const double q = fx_charge(w);
-          const double qr = fx_share(fn, q);
-          dkey[j] = dep ? cn : -1;
-          da[j] = q - qr;
-          db[j] = qr;
         }
-        merge_charge(dkey, da, db, periodic ? n : -1, qbase, qacc, wq);
-      }
-    }
-    if (deposit) lds_qs[tid / kWave][tid % kWave] = qacc;
-    if (restrict_) {
-      lds_r[tid / kWave][0][tid % kWave] = racc0;
-      lds_r[tid / kWave][1][tid % kWave] = racc1;
-    }
-    __syncthreads();
-    if (deposit) {
-      long long* gq = reinterpret_cast<long long*>(R.q[qsel]);
-      for (int k = tid; k < kQWin; k += kThreads) {
-        long long val = lds_q[k];
-        const int s = k - (kQMargin - kQSlotMargin);  // slot of node wq.base + k
-        if (s >= 0 && s < kWave) {
+        // E^p at the ions; then the snapshot values are computed and merged, and only
+        // after that the push and the new charge (the two phases' value arrays are
+        // never live together, which keeps the kernel at 4 waves per SIMD)
+        float epa[kBatch];
 #pragma unroll
-          for (int w = 0; w < kWaves; ++w) val += lds_qs[w][s];
+        for (int j = 0; j < kBatch; ++j) {
+          const float f = fr[j];
+          epa[j] = (restrict_ || push) ? (1.f - f) * e0[j] + f * e1[j] : 0.f;
         }
-        if (val != 0) gatomic_add(&gq[wq.base + k], val);
-      }
-    }
-    if (restrict_) {
-      for (int k = tid; k < 2 * kRWin; k += kThreads) {
-        const int m = k / kRWin;
-        const int kk = k - m * kRWin;
-        long long val = 0;
+        if (restrict_) {
+          int rkey[kBatch];
+          float ra0[kBatch], ra1[kBatch], rb0[kBatch], rb1[kBatch];
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) val += lds_r[w][m][kk];
-        if (val != 0) gatomic_add(&rb[(int64_t)m * nc + rbase + kk], val);
+          for (int j = 0; j < kBatch; ++j) {
+            const int c = cl[j];
+            const float f = fr[j];
+            const float v = vv[j];
+            const float w = ww[j];
+            const bool alive = c >= 0 && c < n;  // cells outside [0, N) are treated as absorbed
+            const int cs = alive ? c : 0;         // safe cell index
+            const float ep = epa[j];
+            // Snapshot p: time-centred velocity, then the approximate characteristic
+            // over tau = Delta t - p dt (eq. B.4) and CIC at the moved position (eq. B.5).
+            const float vpc = fresh ? v : v + half_dt * ep;
+            const float enx = (1.f - f) * n0[j] + f * n1[j];
+            const float xt = f + tau_inv_h * vpc;
+            const float vt = vpc + tau_e * enx;
+            const float fl = floorf(xt);
+            const bool wrap_up = (xt - fl) >= 1.f;
+            const float th = wrap_up ? 0.f : xt - fl;
+            const int ct0 = cs + (int)fl + (wrap_up ? 1 : 0);
+            const int ct = periodic ? (ct0 & nmask) : ct0;
+            const bool in = alive && (periodic || (ct >= 0 && ct < n));
+            const float wv = w * vt;
+            const int bl = ct >> levels;
+            const int nr = periodic ? ((ct + 1) & nmask) : ct + 1;
+            const int br = min(nr >> levels, nc - 1);  // wall node N joins the last block
+            const bool same = br == bl;
+            const float nrs = w * th, jrs = wv * th;
+            rkey[j] = in ? bl : -1;
+            ra0[j] = same ? w : w - nrs;
+            ra1[j] = same ? wv : wv - jrs;
+            rb0[j] = same ? 0.f : nrs;
+            rb1[j] = same ? 0.f : jrs;
+          }
+          merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, rbase, racc0, racc1, rb,
+                        rb + nc);
+        }
+        if (deposit) {
+          int dkey[kBatch];
+          double da[kBatch], db[kBatch];
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j) {
+            const unsigned idx = b0 + j * kWave + toff;
+            __builtin_assume(idx < 65536u + kThreads * kBatch);
+            const int c = cl[j];
+            const float f = fr[j];
+            const float v = vv[j];
+            const float w = ww[j];
+            const bool alive = c >= 0 && c < n;
+            const int cs = alive ? c : 0;
+            const float ep = epa[j];
+            int cn = cs;
+            float fn = f, vn = v;
+            if (push) {
+              vn = fresh ? v + half_dt * ep : v + dt * ep;
+              const float xn = f + dt_inv_h * vn;
+              const float fl = floorf(xn);
+              const bool wrap_up = (xn - fl) >= 1.f;
+              fn = wrap_up ? 0.f : xn - fl;
+              cn = cs + (int)fl + (wrap_up ? 1 : 0);
+              cn = periodic ? (cn & nmask) : ((cn < 0 || cn >= n) ? -1 : cn);  // walls absorb
+              if (alive && idx < cnt) {
+                *at(cellp, idx) = (int16_t)cn;
+                *at(fracp, idx) = fn;
+                *at(vp_, idx) = vn;
+              }
+            }
+            const bool dep = alive && cn >= 0;
+            const double q = fx_charge(w);
+            const double qr = fx_share(fn, q);
+            dkey[j] = dep ? cn : -1;
+            da[j] = q - qr;
+            db[j] = qr;
+          }
+          merge_charge(dkey, da, db, periodic ? n : -1, qbase, qacc, wq);
+        }
       }
-    }
-    __syncthreads();
+      if (deposit) lds_qs[tid / kWave][tid % kWave] = qacc;
+      if (restrict_) {
+        lds_r[tid / kWave][0][tid % kWave] = racc0;
+        lds_r[tid / kWave][1][tid % kWave] = racc1;
+      }
+      __syncthreads();
+      if (deposit) {
+        long long* gq = reinterpret_cast<long long*>(R.q[qsel]);
+        for (int k = tid; k < kQWin; k += kThreads) {
+          long long val = lds_q[k];
+          const int s = k - (kQMargin - kQSlotMargin);  // slot of node wq.base + k
+          if (s >= 0 && s < kWave) {
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) val += lds_qs[w][s];
+          }
+          if (val != 0) gatomic_add(&gq[wq.base + k], val);
+        }
+      }
+      if (restrict_) {
+        for (int k = tid; k < 2 * kRWin; k += kThreads) {
+          const int m = k / kRWin;
+          const int kk = k - m * kRWin;
+          long long val = 0;
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) val += lds_r[w][m][kk];
+          if (val != 0) gatomic_add(&rb[(int64_t)m * nc + rbase + kk], val);
+        }
+      }
+      __syncthreads();
+    };
+    if (R.bc == 0) tile_pass(std::true_type{});
+    else tile_pass(std::false_type{});
   }
 }
 
