@@ -66,36 +66,44 @@ constexpr int kRMargin = 8;
 constexpr int kEWin = 128;      // node field window staged in LDS (cells)
 constexpr int kEMargin = 32;
 
-// Wave-wide sums with a fixed DPP pattern (inclusive scan by row shifts 1, 2, 3
-// of the input, then 4 and 8 inside each 16-lane row, then row broadcasts 15 and
-// 31 across rows; lane 63 holds the total).  The pattern, and therefore the
-// order of every addition, does not depend on scheduling, so FP32 sums are
-// reproducible bit for bit.  All 64 lanes must be active.
-template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND>
-__device__ __forceinline__ int dpp_i(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, BANK_MASK, BOUND);
+// Wave-wide sums with a fixed pattern: inside each 16-lane row an inclusive scan
+// by row shifts 1, 2, 3 of the input, then 4 and 8 (lanes shifted in from
+// outside the row read 0), which leaves each row's total in its lane 15; the
+// four row totals are read into scalar registers and added as (r3 + r2) + (r1 +
+// r0).  The order of every addition is fixed, so FP32 sums are reproducible bit
+// for bit.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_shr(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, true);
+}
+
+__device__ __forceinline__ int row_scan_i32(int x) {
+  int t = x + dpp_shr<0x111>(x);
+  t += dpp_shr<0x112>(x);
+  t += dpp_shr<0x113>(x);
+  t += dpp_shr<0x114>(t);
+  t += dpp_shr<0x118>(t);
+  return t;
 }
 
 __device__ __forceinline__ int wave_sum_i32(int x) {
-  int t = x + dpp_i<0x111, 0xf, 0xf, true>(x);
-  t += dpp_i<0x112, 0xf, 0xf, true>(x);
-  t += dpp_i<0x113, 0xf, 0xf, true>(x);
-  t += dpp_i<0x114, 0xf, 0xe, false>(t);
-  t += dpp_i<0x118, 0xf, 0xc, false>(t);
-  t += dpp_i<0x142, 0xa, 0xf, false>(t);
-  t += dpp_i<0x143, 0xc, 0xf, false>(t);
-  return __builtin_amdgcn_readlane(t, 63);
+  const int t = row_scan_i32(x);
+  const int r0 = __builtin_amdgcn_readlane(t, 15), r1 = __builtin_amdgcn_readlane(t, 31);
+  const int r2 = __builtin_amdgcn_readlane(t, 47), r3 = __builtin_amdgcn_readlane(t, 63);
+  return (r3 + r2) + (r1 + r0);
 }
 
 __device__ __forceinline__ float wave_sum_f32(float x) {
-  float t = x + __int_as_float(dpp_i<0x111, 0xf, 0xf, true>(__float_as_int(x)));
-  t += __int_as_float(dpp_i<0x112, 0xf, 0xf, true>(__float_as_int(x)));
-  t += __int_as_float(dpp_i<0x113, 0xf, 0xf, true>(__float_as_int(x)));
-  t += __int_as_float(dpp_i<0x114, 0xf, 0xe, false>(__float_as_int(t)));
-  t += __int_as_float(dpp_i<0x118, 0xf, 0xc, false>(__float_as_int(t)));
-  t += __int_as_float(dpp_i<0x142, 0xa, 0xf, false>(__float_as_int(t)));
-  t += __int_as_float(dpp_i<0x143, 0xc, 0xf, false>(__float_as_int(t)));
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 63));
+  float t = x + __int_as_float(dpp_shr<0x111>(__float_as_int(x)));
+  t += __int_as_float(dpp_shr<0x112>(__float_as_int(x)));
+  t += __int_as_float(dpp_shr<0x113>(__float_as_int(x)));
+  t += __int_as_float(dpp_shr<0x114>(__float_as_int(t)));
+  t += __int_as_float(dpp_shr<0x118>(__float_as_int(t)));
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 15));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 31));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 47));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 63));
+  return (r3 + r2) + (r1 + r0);
 }
 
 // Exact wave sum of int64 values with |v| < 2^49: the low 24 bits and the rest
@@ -168,10 +176,9 @@ __device__ __forceinline__ void merge_charge(int (&key)[kBatch], const double (&
                                              long long& acc, const Window& win) {
   const int lane = __lane_id();
   while (true) {
-    int mine = -1;
+    int mine = key[0];  // any remaining key of the lane (-1 when none is left)
 #pragma unroll
-    for (int j = kBatch - 1; j >= 0; --j)
-      if (key[j] >= 0) mine = key[j];
+    for (int j = 1; j < kBatch; ++j) mine = max(mine, key[j]);
     const unsigned long long act = __ballot(mine >= 0);
     if (act == 0ull) break;
     const int leader = __ffsll((unsigned long long)act) - 1;
@@ -213,10 +220,9 @@ __device__ __forceinline__ void merge_moments(int (&key)[kBatch], const float (&
                                               long long* g0, long long* g1) {
   const int lane = __lane_id();
   while (true) {
-    int mine = -1;
+    int mine = key[0];  // any remaining key of the lane (-1 when none is left)
 #pragma unroll
-    for (int j = kBatch - 1; j >= 0; --j)
-      if (key[j] >= 0) mine = key[j];
+    for (int j = 1; j < kBatch; ++j) mine = max(mine, key[j]);
     const unsigned long long act = __ballot(mine >= 0);
     if (act == 0ull) break;
     const int leader = __ffsll((unsigned long long)act) - 1;
