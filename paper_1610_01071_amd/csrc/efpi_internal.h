@@ -12,13 +12,24 @@ constexpr double kFxScale = 1099511627776.0;     // 2^40: fixed-point charge uni
 constexpr double kFxInv = 1.0 / 1099511627776.0;
 constexpr int kWave = 64;
 
+#define EFPI_GLOBAL __attribute__((address_space(1)))
+
 // Global-memory view of an array address taken from a descriptor.  Accesses
 // through it compile to global_* instructions; through the plain (generic)
 // pointer they become flat_* ones, which also count against the LDS wait
 // counter, so every later LDS wait would wait for the memory access as well.
 template <class T>
-__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
-  return (__attribute__((address_space(1))) T*)p;
+__device__ __forceinline__ EFPI_GLOBAL T* gmem(T* p) {
+  return (EFPI_GLOBAL T*)p;
+}
+
+// Element i of a global array addressed as a 32-bit byte offset (i * sizeof(T)
+// below 2^32) from a base that is the same in every lane: the access takes the
+// base from scalar registers and one vector offset, with no 64-bit address
+// arithmetic per lane.
+template <class T>
+__device__ __forceinline__ EFPI_GLOBAL T* at(EFPI_GLOBAL T* base, unsigned i) {
+  return (EFPI_GLOBAL T*)((EFPI_GLOBAL const char*)base + i * (unsigned)sizeof(T));
 }
 
 // Per-replica descriptor in device memory: sizes, parameters and the addresses

@@ -153,6 +153,18 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   const double qscale = kFxInv / h;
   const auto Q = gmem(reinterpret_cast<const long long*>(R.q[qsel]));
   const auto phig = gmem(R.phi);
+  // fields used only after the iterations, read now with the others (a scalar
+  // load issued at the end would cost one more memory round trip there)
+  const int n_nodes = R.n_nodes;
+  const auto other = gmem(reinterpret_cast<long long*>(R.q[qsel ^ 1]));
+  const int n_bins = zero_bins ? (R.burst_steps + 1) * 2 * R.n_coarse : 0;
+  const auto bins = gmem(reinterpret_cast<long long*>(R.rbins));
+  const auto eg = gmem(R.e);
+  const auto eng = gmem(R.en);
+  const bool no_field = R.closure == 2;
+  // the convergence check's arguments are needed only at the end; have them in
+  // registers from the start as well
+  asm volatile("" ::"s"(status), "s"(tol));
   const bool owns_n = !periodic && act && t == T - 1;
   const float aL = (periodic || t > 0) ? alpha : 0.f;
   const float aR = (periodic || t < T - 1) ? alpha : 0.f;
@@ -167,7 +179,7 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
     else return (double)Q[t * M + j] * qscale;
   };
   double phin = 0.0;
-  if (R.closure != 2) {
+  if (!no_field) {
     if (act) {
       if constexpr (!kHoist) {
       } else if constexpr (M >= 2) {
@@ -408,7 +420,7 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   __syncthreads();
   if (act) {
     if constexpr (M >= 2) {
-      const auto p2 = gmem(reinterpret_cast<f64x2*>(R.phi)) + t * (M / 2);
+      const auto p2 = reinterpret_cast<EFPI_GLOBAL f64x2*>(phig) + t * (M / 2);
 #pragma unroll
       for (int j = 0; j < M / 2; ++j) p2[j] = f64x2{phi[2 * j], phi[2 * j + 1]};
     } else {
@@ -428,8 +440,8 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
       if (!periodic && g == 0) ev[j] = 0.f;
     }
     if constexpr (M >= 4) {
-      const auto e4 = gmem(reinterpret_cast<f32x4*>(R.e)) + t * (M / 4);
-      const auto n4 = gmem(reinterpret_cast<f32x4*>(R.en)) + t * (M / 4);
+      const auto e4 = reinterpret_cast<EFPI_GLOBAL f32x4*>(eg) + t * (M / 4);
+      const auto n4 = reinterpret_cast<EFPI_GLOBAL f32x4*>(eng) + t * (M / 4);
 #pragma unroll
       for (int j = 0; j < M / 4; ++j) {
         const f32x4 v = {ev[4 * j], ev[4 * j + 1], ev[4 * j + 2], ev[4 * j + 3]};
@@ -439,26 +451,24 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
     } else {
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        gmem(R.e)[t * M + j] = ev[j];
-        if (save_en) gmem(R.en)[t * M + j] = ev[j];
+        eg[t * M + j] = ev[j];
+        if (save_en) eng[t * M + j] = ev[j];
       }
     }
     if (owns_n) {
-      gmem(R.e)[n] = 0.f;
-      if (save_en) gmem(R.en)[n] = 0.f;
+      eg[n] = 0.f;
+      if (save_en) eng[n] = 0.f;
     }
   }
-  // --- clear the next deposit buffer and, at a burst start, the snapshot bins
-  {
-    const auto other = gmem(reinterpret_cast<long long*>(R.q[qsel ^ 1]));
-    for (int k = t; k < R.n_nodes; k += blockDim.x) other[k] = 0;
-    if (zero_bins) {
-      const int nb = (R.burst_steps + 1) * 2 * R.n_coarse;
-      const auto rb = gmem(reinterpret_cast<long long*>(R.rbins));
-      for (int k = t; k < nb; k += blockDim.x) rb[k] = 0;
-    }
+  // --- clear the next deposit buffer (n_nodes = M T + 1 <= M THREADS + 1: at
+  // most M + 1 stores per thread) and, at a burst start, the snapshot bins
+#pragma unroll
+  for (int j = 0; j <= M; ++j) {
+    const int k = t + j * THREADS;
+    if (k < n_nodes) other[k] = 0;
   }
-  if (t == 0 && R.closure != 2) {
+  for (int k = t; k < n_bins; k += THREADS) bins[k] = 0;
+  if (t == 0 && !no_field) {
     double md = 0.0;
     int nan = 0;
     for (int k = 0; k < nw; ++k) {

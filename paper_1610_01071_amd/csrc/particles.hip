@@ -24,23 +24,7 @@
 namespace efpi {
 namespace {
 
-// Pointers read from the replica descriptor are generic; casting them to the
-// global address space lets the compiler use global (not flat) memory
-// instructions, which do not couple the LDS and memory wait counters.
-#define EFPI_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ EFPI_GLOBAL T* gptr(T* p) {
-  return (EFPI_GLOBAL T*)p;
-}
 typedef EFPI_GLOBAL unsigned long long gu64;
-
-// Element i of a tile array, addressed as a 32-bit byte offset from the tile's
-// base address (uniform, in scalar registers): one vector add per access instead
-// of 64-bit address arithmetic.  Tiles hold at most 65536 ions.
-template <typename T>
-__device__ __forceinline__ EFPI_GLOBAL T* at(EFPI_GLOBAL T* base, unsigned i) {
-  return (EFPI_GLOBAL T*)((EFPI_GLOBAL const char*)base + i * (unsigned)sizeof(T));
-}
 
 // A value that is the same in every lane, read so that the compiler knows it is
 // uniform (scalar registers, uniform control flow).
@@ -303,12 +287,12 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
       // p < 0: plain restriction of the current state (tau = 0, snapshot slot 0)
       const float tau = p < 0 ? 0.f : (float)(R.macro_dt - (double)p * R.dt);
       const bool coev = R.coevolving != 0 && p >= 0;
-      const EFPI_GLOBAL float* __restrict__ e = gptr(R.e);
-      const EFPI_GLOBAL float* __restrict__ en = gptr(R.en);
-      EFPI_GLOBAL int16_t* __restrict__ cellp = gptr(R.cell + i0);
-      EFPI_GLOBAL float* __restrict__ fracp = gptr(R.frac + i0);
-      EFPI_GLOBAL float* __restrict__ vp_ = gptr(R.v + i0);
-      const EFPI_GLOBAL float* __restrict__ wp = gptr(R.w + i0);
+      const EFPI_GLOBAL float* __restrict__ e = gmem(R.e);
+      const EFPI_GLOBAL float* __restrict__ en = gmem(R.en);
+      EFPI_GLOBAL int16_t* __restrict__ cellp = gmem(R.cell + i0);
+      EFPI_GLOBAL float* __restrict__ fracp = gmem(R.frac + i0);
+      EFPI_GLOBAL float* __restrict__ vp_ = gmem(R.v + i0);
+      const EFPI_GLOBAL float* __restrict__ wp = gmem(R.w + i0);
       const float half_dt = 0.5f * dt;
       const float dt_inv_h = dt * inv_h;
       const float tau_inv_h = coev ? tau * inv_h : 0.f;
