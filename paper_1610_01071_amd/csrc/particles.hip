@@ -252,7 +252,8 @@ __device__ __forceinline__ void merge_moments(int (&key)[kBatch], const float (&
 template <int MODE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ item_prefix,
-                 int n_reps, int64_t total_items, int tile, int p, int fresh_flag, int qsel) {
+                 int n_reps, int64_t total_items, int tile, int p, double pd, int fresh_flag,
+                 int qsel) {
   __shared__ long long lds_q[kQWin];
   __shared__ long long lds_qs[kWaves][kWave];
   __shared__ long long lds_r[kWaves][2][kRWin];
@@ -285,7 +286,9 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
       const int levels = R.levels;
       const int nc = R.n_coarse;
       // p < 0: plain restriction of the current state (tau = 0, snapshot slot 0)
-      const float tau = p < 0 ? 0.f : (float)(R.macro_dt - (double)p * R.dt);
+      // (pd = p as binary64, a kernel argument: converting p here would give a
+      // value the compiler keeps in a vector register across the whole kernel)
+      const float tau = p < 0 ? 0.f : (float)(R.macro_dt - pd * R.dt);
       const bool coev = R.coevolving != 0 && p >= 0;
       const EFPI_GLOBAL float* __restrict__ e = gmem(R.e);
       const EFPI_GLOBAL float* __restrict__ en = gmem(R.en);
@@ -543,10 +546,10 @@ void launch_mode(dim3 grid, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1,
                  int64_t total_items, int tile, int p, int fresh, int qsel) {
   if (ev0 && ev1)
     hipExtLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, ev0, ev1, 0, d_reps,
-                          d_item_prefix, n_reps, total_items, tile, p, fresh, qsel);
+                          d_item_prefix, n_reps, total_items, tile, p, (double)p, fresh, qsel);
   else
     hipLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, d_reps, d_item_prefix,
-                       n_reps, total_items, tile, p, fresh, qsel);
+                       n_reps, total_items, tile, p, (double)p, fresh, qsel);
 }
 }  // namespace
 
