@@ -202,8 +202,10 @@ def run_bench(args, np, torch, synth, E):
 
     # The same number of macro steps again with every burst-step particle launch
     # bracketed by its own start/end events (hipExtLaunchKernelGGL): the kernel's
-    # average duration for the roofline.  Those events slow the enqueue, so the
-    # headline rate above is taken without them.
+    # average duration for the roofline.  Each interval also holds the two event
+    # markers (a few microseconds above the kernel's execution in a kernel trace),
+    # and the markers slow the macro step, so the headline rate above is taken
+    # without them.
     E.efpi_timing(ctx.ctx, True)
     ms_total_ev = timed(torch, lambda: run(args.warmup + args.steps))
     kern_ms, kern_n = E.efpi_timing_read(ctx.ctx)

@@ -330,9 +330,12 @@ efpi_status efpi_rel_l2(const double* d_a, const double* d_b, int64_t n, double*
 efpi_status efpi_sync(efpi_ctx* ctx, uint32_t* h_bits);
 
 /* Measurement aid: with enable != 0, every later burst-step particle launch (the
- * pass that pushes, deposits and restricts) records the kernel's own start and
- * end timestamps in a pair of HIP events (extended launch), so the summed time
- * is kernel execution only.  Enabling resets the record. */
+ * pass that pushes, deposits and restricts) is bracketed by a pair of HIP events
+ * (extended launch), and efpi_timing_read returns their summed intervals.  The
+ * events are created without the system-scope fence (timing only: recording
+ * them writes back no caches).  Each interval also holds the processing of the
+ * two event markers around the dispatch, a few microseconds more than the
+ * kernel's execution as a kernel trace reports it.  Enabling resets the record. */
 efpi_status efpi_timing(efpi_ctx* ctx, int32_t enable);
 
 /* Synchronous: wait for the stream, then return the summed event time in ms and

@@ -363,7 +363,9 @@ efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shift
 hipEvent_t next_event(efpi_ctx* c) {
   if (c->events_used == c->events.size()) {
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // timing only: no system-scope fence (no cache writeback at the event, which
+    // would add to the measured interval and slow the following launch)
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     c->events.push_back(e);
   }
   return c->events[c->events_used++];

@@ -538,8 +538,7 @@ __global__ void k_copy_particles(const RepDev* reps, int rep, const int16_t* cel
 }  // namespace
 
 namespace {
-// With both events given, the launch records the kernel's own start and end
-// timestamps in them (the same interval a kernel trace reports).
+// With both events given, the launch is bracketed by them (extended launch).
 template <int MODE>
 void launch_mode(dim3 grid, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1,
                  const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
