@@ -502,6 +502,7 @@ void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
   hipLaunchKernelGGL((k_newton<MM, TT>), grid, dim3(threads), 0, stream, d_reps, iters,         \
                      cold, qsel, save_en, zero_bins, tol, d_status)
   if (M == 1) EFPI_NEWTON(1, 256);
+  else if (M == 8 && threads > 256) EFPI_NEWTON(8, 512);
   else if (M == 2) EFPI_NEWTON(2, 256);
   else if (M == 4) EFPI_NEWTON(4, 256);
   else if (M == 8) EFPI_NEWTON(8, 256);
