@@ -106,10 +106,7 @@ __device__ __forceinline__ long long rint_i64(double x) {
 }
 
 // rint(x) for |x| < 2^51 as a binary64 value (the same rounding as rint_i64).
-__device__ __forceinline__ double rint_d(double x) {
-  const double magic = 6755399441055744.0;
-  return (x + magic) - magic;
-}
+__device__ __forceinline__ double rint_d(double x) { return __builtin_rint(x); }
 
 // q = rint(w 2^40): the particle's charge in fixed point, as an exact binary64
 // integer value.
@@ -297,6 +294,9 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
       EFPI_GLOBAL float* __restrict__ vp_ = gmem(R.v + i0);
       const EFPI_GLOBAL float* __restrict__ wp = gmem(R.w + i0);
       const float half_dt = 0.5f * dt;
+      const float half_dt_r = fresh ? 0.f : half_dt;  // snapshot velocity v + half_dt_r E
+      const float dt_push = fresh ? half_dt : dt;     // push: v + dt_push E
+      const int lmask = (1 << levels) - 1;
       const float dt_inv_h = dt * inv_h;
       const float tau_inv_h = coev ? tau * inv_h : 0.f;
       const float tau_e = coev ? tau : 0.f;
@@ -399,27 +399,30 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
             const float ep = epa[j];
             // Snapshot p: time-centred velocity, then the approximate characteristic
             // over tau = Delta t - p dt (eq. B.4) and CIC at the moved position (eq. B.5).
-            const float vpc = fresh ? v : v + half_dt * ep;
+            const float vpc = v + half_dt_r * ep;  // half_dt_r = 0 on a fresh state
             const float enx = (1.f - f) * n0[j] + f * n1[j];
             const float xt = f + tau_inv_h * vpc;
             const float vt = vpc + tau_e * enx;
             const float fl = floorf(xt);
-            const bool wrap_up = (xt - fl) >= 1.f;
-            const float th = wrap_up ? 0.f : xt - fl;
+            const float fx = xt - fl;
+            const bool wrap_up = fx >= 1.f;
             const int ct0 = cs + (int)fl + (wrap_up ? 1 : 0);
             const int ct = periodic ? (ct0 & nmask) : ct0;
             const bool in = alive && (periodic || (ct >= 0 && ct < n));
-            const float wv = w * vt;
             const int bl = ct >> levels;
-            const int nr = periodic ? ((ct + 1) & nmask) : ct + 1;
-            const int br = min(nr >> levels, nc - 1);  // wall node N joins the last block
-            const bool same = br == bl;
-            const float nrs = w * th, jrs = wv * th;
+            // both nodes of cell ct in block bl: ct is not the block's last cell, or
+            // (walls) the block is the last one, which also owns wall node N, or
+            // (periodic) there is a single block
+            const bool last = (ct & lmask) == lmask;
+            const bool same = !last || (periodic ? nc == 1 : bl == nc - 1);
+            // right-node share theta, zero when both nodes are in the same block
+            const float th = (wrap_up || same) ? 0.f : fx;
+            const float wv = w * vt;
             rkey[j] = in ? bl : -1;
-            ra0[j] = same ? w : w - nrs;
-            ra1[j] = same ? wv : wv - jrs;
-            rb0[j] = same ? 0.f : nrs;
-            rb1[j] = same ? 0.f : jrs;
+            ra0[j] = w - w * th;
+            ra1[j] = wv - wv * th;
+            rb0[j] = w * th;
+            rb1[j] = wv * th;
           }
           merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, rbase, racc0, racc1, rb,
                         rb + nc);
@@ -441,7 +444,7 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
             int cn = cs;
             float fn = f, vn = v;
             if (push) {
-              vn = fresh ? v + half_dt * ep : v + dt * ep;
+              vn = v + dt_push * ep;
               const float xn = f + dt_inv_h * vn;
               const float fl = floorf(xn);
               const bool wrap_up = (xn - fl) >= 1.f;
