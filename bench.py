@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-updates/s + EFPI wall-time speedup vs full PIC at fixed moment error"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 24  # read cell(2) frac v w (4 each), write cell frac v
-TILE = 2048  # ions per work item of the particle pass
+TILE = 4096  # ions per work item of the particle pass
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_particles_hbm_traffic_iaw4096.md")

@@ -96,8 +96,8 @@ typedef struct {
   double newton_tol;                 /* status threshold on max |last Newton update|;
                                         convergence is quadratic, so the remaining
                                         error is about its square                 */
-  int32_t tile;                      /* particles per work item: 0 (default) or a
-                                        multiple of 1024 up to 65536              */
+  int32_t tile;                      /* particles per work item: 0 (default, 4096)
+                                        or a multiple of 1024 up to 65536         */
   int32_t grid_blocks;               /* persistent grid size, 0 = default         */
   uint32_t flags;                    /* EFPI_FLAG_*                               */
 } efpi_config;

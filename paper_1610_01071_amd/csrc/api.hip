@@ -33,7 +33,7 @@ int ilog2(int64_t x) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int kDefaultTile = 2048;
+constexpr int kDefaultTile = 4096;
 constexpr size_t kMaxGraphs = 8;  // captured macro steps kept per context
 constexpr int kDefaultGrid = 2048;
 
