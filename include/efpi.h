@@ -119,7 +119,8 @@ efpi_status efpi_workspace_size(const efpi_config* cfg, size_t* h_bytes);
 efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes,
                       void* hip_stream, efpi_ctx** out);
 
-/* Release the host context (the workspace stays the caller's). */
+/* Wait for the work the context queued on its stream, then release the host
+ * context (the workspace stays the caller's and may be freed afterwards). */
 void efpi_destroy(efpi_ctx* ctx);
 
 /* Change the stream later calls enqueue on. */

@@ -119,6 +119,8 @@ struct efpi_ctx {
   };
   std::vector<MacroGraph> graphs;
   ~efpi_ctx() {
+    // work still queued may use the events, the captured graphs and the workspace
+    note(hipStreamSynchronize(stream));
     for (hipEvent_t e : events) note(hipEventDestroy(e));
     for (MacroGraph& g : graphs) note(hipGraphExecDestroy(g.exec));
   }
