@@ -313,6 +313,22 @@ __global__ void k_restrict(const RepDev* __restrict__ reps, int steps, double* _
     out[k] = (double)gmem(R.rbins)[k] * scale;
 }
 
+// LS slope (eq. 3.18) and projective step (eq. 3.17) for one coefficient, from its
+// snapshot values v(p), p = 0..ne.  Products and sums are never fused into FMAs
+// here, so every kernel that calls it gives the same bits for the same snapshots.
+template <class V>
+__device__ __forceinline__ double project_value(V v, int ne, double dt, double macro_dt) {
+#pragma clang fp contract(off)
+  const double den = (double)ne * (ne + 1) * (ne + 2) * dt;
+  const double leap = macro_dt - ne * dt;
+  double slope = 0.0;
+  for (int p = 0; p <= ne / 2; ++p) {
+    const double coef = 6.0 * (double)(ne - 2 * p) / den;
+    slope += coef * (v(ne - p) - v(p));
+  }
+  return v(ne) + leap * slope;
+}
+
 __global__ void k_project(const RepDev* __restrict__ reps, const double* __restrict__ snap,
                           const int64_t* __restrict__ soff, double* __restrict__ out,
                           const int64_t* __restrict__ coff, uint32_t* __restrict__ status) {
@@ -321,15 +337,9 @@ __global__ void k_project(const RepDev* __restrict__ reps, const double* __restr
   const int ne = R.burst_steps;
   const double* s = snap + soff[blockIdx.y];
   double* o = out + coff[blockIdx.y];
-  const double den = (double)ne * (ne + 1) * (ne + 2) * R.dt;
-  const double leap = R.macro_dt - ne * R.dt;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
-    double slope = 0.0;
-    for (int p = 0; p <= ne / 2; ++p) {
-      const double coef = 6.0 * (double)(ne - 2 * p) / den;
-      slope += coef * (s[(int64_t)(ne - p) * 2 * nc + k] - s[(int64_t)p * 2 * nc + k]);
-    }
-    const double val = s[(int64_t)ne * 2 * nc + k] + leap * slope;
+    auto snapshot = [&](int p) { return s[(int64_t)p * 2 * nc + k]; };
+    const double val = project_value(snapshot, ne, R.dt, R.macro_dt);
     o[k] = val;
     if (!(fabs(val) < 1e300)) atomicOr(status, 2u);
     if (k < nc && val < 0.0) atomicOr(status, 8u);
@@ -352,17 +362,11 @@ __global__ void k_restrict_project(const RepDev* __restrict__ reps, double* __re
   const auto rb = gmem(R.rbins);
   double* s = snap + soff[blockIdx.y];
   double* o = out + coff[blockIdx.y];
-  const double den = (double)ne * (ne + 1) * (ne + 2) * R.dt;
-  const double leap = R.macro_dt - ne * R.dt;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
-    auto val = [&](int p) { return (double)rb[(int64_t)p * 2 * nc + k] * scale; };
-    for (int p = 0; p <= ne; ++p) s[(int64_t)p * 2 * nc + k] = val(p);
-    double slope = 0.0;
-    for (int p = 0; p <= ne / 2; ++p) {
-      const double coef = 6.0 * (double)(ne - 2 * p) / den;
-      slope += coef * (val(ne - p) - val(p));
-    }
-    const double v = val(ne) + leap * slope;
+    // the snapshot value as k_restrict stores it (one rounded product)
+    auto snapshot = [&](int p) { return (double)rb[(int64_t)p * 2 * nc + k] * scale; };
+    for (int p = 0; p <= ne; ++p) s[(int64_t)p * 2 * nc + k] = snapshot(p);
+    const double v = project_value(snapshot, ne, R.dt, R.macro_dt);
     o[k] = v;
     if (!(fabs(v) < 1e300)) atomicOr(status, 2u);
     if (k < nc && v < 0.0) atomicOr(status, 8u);

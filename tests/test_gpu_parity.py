@@ -289,6 +289,36 @@ def test_macro_step_matches_oracle():
     assert torch.equal(cout, cout2)
 
 
+@pytest.mark.parametrize("bc", [0, 1])
+def test_macro_step_equals_composed_calls(bc):
+    """efpi_macro_step (fused lift preparation, fused restriction and projection)
+    gives the same bits as the single-step calls lift, burst, restrict, project,
+    each path in a fresh context."""
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, bc=bc, ppc=64, haar_levels=3, burst_steps=10,
+                         macro_dt=6.0, vth=0.316 if bc == 0 else 0.1)
+    parts = iaw_particles(spec, 21) if bc == 0 else slab_particles(spec, 21)
+    first = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    set_particles(first, 0, *parts)
+    cin = first.new_coarse()
+    E.efpi_restrict_state(first.ctx, cin)
+    E.efpi_sync(first.ctx)
+    shift = synth.lift_shift(22)
+    a = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    out_a = a.new_coarse()
+    E.efpi_macro_step(a.ctx, cin, out_a, [shift])
+    b = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    E.efpi_lift(b.ctx, cin, [shift])
+    E.efpi_pic_burst(b.ctx, spec.burst_steps, True)
+    snap = b.new_snap()
+    E.efpi_restrict(b.ctx, snap)
+    out_b = b.new_coarse()
+    E.efpi_project(b.ctx, snap, out_b)
+    E.efpi_sync(a.ctx, raise_on_error=False)
+    E.efpi_sync(b.ctx, raise_on_error=False)
+    assert torch.equal(out_a, out_b)
+
+
 # -------------------------------------------------------------- status/error --
 
 def test_invalid_config_rejected():
