@@ -431,7 +431,8 @@ def slab_leg(E, torch, np, synth, args):
     E.efpi_restrict_state(pctx.ctx, cp)
     pic_bits = E.efpi_sync(pctx.ctx, raise_on_error=False)
     pctx.close()
-    ref = cp.view(2, -1)[0].cpu().numpy()
+    ref_both = cp.view(2, -1).cpu().numpy()
+    ref = ref_both[0]
     steps = int(round(horizon / spec.macro_dt))
     a, b = ctx.new_coarse(), ctx.new_coarse()
     a.copy_(c0)
@@ -445,8 +446,11 @@ def slab_leg(E, torch, np, synth, args):
 
     t_efpi = timed(torch, efpi_run)
     bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
-    got = st["a"].view(2, -1)[0].cpu().numpy()
+    got_both = st["a"].view(2, -1).cpu().numpy()
+    got = got_both[0]
     eps = float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(got * got + ref * ref)))
+    gm, rm = got_both[1], ref_both[1]
+    eps_mom = float(np.sqrt(np.sum((gm - rm) ** 2) / np.sum(gm * gm + rm * rm)))
     ctx.close()
     return {
         "n_cells": n_cells, "ppc": ppc, "n_ions_t0": n_ions, "horizon": horizon,
@@ -454,7 +458,8 @@ def slab_leg(E, torch, np, synth, args):
         "pic_particle_updates_per_s": n_ions * fine / (t_pic * 1e-3),
         "efpi_macro_dt_over_dt": mult, "efpi_macro_steps": steps, "efpi_ms": t_efpi,
         "efpi_ms_per_macro_step": t_efpi / steps, "speedup": t_pic / t_efpi,
-        "eps_density": eps, "device_status_pic": pic_bits, "device_status_efpi": bits,
+        "eps_density": eps, "eps_momentum": eps_mom,
+        "device_status_pic": pic_bits, "device_status_efpi": bits,
     }
 
 
@@ -559,12 +564,14 @@ def learned_slab_leg(E, torch, np, synth, args):
     torch.cuda.synchronize()
     wall_plain = (time.perf_counter() - t0) * 1e3
     b = ref[-1].cpu().numpy().reshape(2, -1)
+    o = L.plain_run(ctx, c0, steps, seed=78)[-1].cpu().numpy().reshape(2, -1)
 
     def eps(u, w):
         return float(np.sqrt(np.sum((u - w) ** 2) / np.sum(u * u + w * w)))
 
     out = {"macro_dt_over_dt": 50, "macro_steps": steps, "threshold": 2e-3, "train_noise": 1.0,
-           "plain_ms": wall_plain, "datagen_s": t_gen, "train_s": t_train, "train_iters": 10_000}
+           "plain_ms": wall_plain, "datagen_s": t_gen, "train_s": t_train, "train_iters": 10_000,
+           "plain_spread_density": eps(o[0], b[0]), "plain_spread_momentum": eps(o[1], b[1])}
     for jp in (2, 4):
         run = L.run_learned(ctx, tr, norm, c0, steps, seed=77, judge_period=jp, threshold=2e-3)
         a = run.states[-1].cpu().numpy().reshape(2, -1)
