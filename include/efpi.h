@@ -196,6 +196,29 @@ efpi_status efpi_restrict(efpi_ctx* ctx, double* d_snap);
  * efpi_restrict; snapshots of every replica must hold burst_steps + 1 entries. */
 efpi_status efpi_project(efpi_ctx* ctx, const double* d_snap, double* d_coarse_next);
 
+/* Variable projective step: set Delta t of every replica to macro_dt (>= burst_steps
+ * dt of each; EFPI_EINVAL otherwise, nothing changed).  Later bursts use it in the
+ * co-evolving restriction (tau = Delta t - p dt, App. B) and later projections over
+ * Delta t - N_e dt (eq. 3.17), eager or replayed from captured graphs.  Copies the
+ * descriptors to the device on the context's stream and waits for the copy. */
+efpi_status efpi_set_macro_dt(efpi_ctx* ctx, double macro_dt);
+
+/* Second-order projective step (the higher-order projection the paper mentions
+ * after eq. 3.17, read as Adams-Bashforth 2 on the burst slopes).  From the
+ * snapshots d_snap[r][0..N_e][2][N_c] (as efpi_project):
+ *   d_slope[r][2][N_c]   <- f, the LS slope of eq. 3.18 (keep it for the next step);
+ *   d_euler[r][2][N_c]   <- c^{N_e} + (Delta t - N_e dt) f, eq. 3.17 (NULL: skipped;
+ *                           the same bits as efpi_project);
+ *   d_coarse_next[r][2][N_c] <- c^{N_e} + (Delta t - N_e dt) f*, with
+ *     f* = f + (f - f_prev) Delta t / (2 gap)
+ *   where f_prev = d_slope_prev (the previous step's d_slope) and gap the previous
+ *   step's Delta t: f and f_prev estimate the derivative at the centres of two
+ *   bursts gap apart, and f* extrapolates them to the middle of the projection leap.
+ *   With d_slope_prev == NULL, f* = f (the forward-Euler step).  gap must be finite
+ *   and > 0 when d_slope_prev is given. */
+efpi_status efpi_project2(efpi_ctx* ctx, const double* d_snap, const double* d_slope_prev,
+                          double gap, double* d_slope, double* d_euler, double* d_coarse_next);
+
 /* One whole macro step for every replica: lift(d_coarse_in) -> restricting burst
  * of burst_steps -> restrict -> project -> d_coarse_out.  d_coarse_in and
  * d_coarse_out may alias. */

@@ -133,6 +133,42 @@ def project(snaps, dt: float, macro_dt: float):
     return snaps[ne] + (macro_dt - ne * dt) * ls_slope(snaps, dt)
 
 
+def project2(snaps, dt: float, macro_dt: float, slope_prev=None, gap=None):
+    """Second-order projective step (the higher-order projection mentioned after
+    eq. 3.17), read as Adams-Bashforth 2 on the burst slopes.
+
+    The LS slope f of this burst (eq. 3.18) estimates the derivative at the
+    burst's centre; slope_prev estimates it at the previous burst's centre, gap
+    (the previous Delta t) earlier.  Their linear extrapolation to the middle of
+    the leap [N_e dt, Delta t] is f* = f + (f - f_prev) Delta t / (2 gap), and the
+    state advances from the last snapshot by (Delta t - N_e dt) f*.  Returns
+    (f, forward-Euler projection of eq. 3.17, second-order projection); without
+    slope_prev the second-order step is the Euler step.
+    """
+    snaps = np.asarray(snaps, dtype=np.float64)
+    ne = snaps.shape[0] - 1
+    f = ls_slope(snaps, dt)
+    leap = macro_dt - ne * dt
+    euler = snaps[ne] + leap * f
+    if slope_prev is None:
+        return f, euler, euler.copy()
+    fstar = f + (f - np.asarray(slope_prev, dtype=np.float64)) * (macro_dt / (2.0 * gap))
+    return f, euler, snaps[ne] + leap * fstar
+
+
+def next_macro_dt(macro_dt: float, err: float, tol: float, dt_min: float, dt_max: float,
+                  safety: float = 0.9) -> float:
+    """Step-size rule of the adaptive projective integrator.
+
+    err (eq. 4.2 between the second-order and the Euler projections of the
+    coarse density) estimates the local error of a first-order step, which grows
+    as Delta t^2, so the next step is Delta t (tol / err)^{1/2} times a safety
+    factor, changed by at most a factor 2 either way and kept in [dt_min, dt_max].
+    """
+    factor = 2.0 if err <= 0.0 else min(2.0, max(0.5, safety * np.sqrt(tol / err)))
+    return float(min(dt_max, max(dt_min, macro_dt * factor)))
+
+
 # ----------------------------------------------------------------------------
 # Lifting: coarse coefficients -> fine profile -> quiet-start particles (App. C)
 # ----------------------------------------------------------------------------

@@ -738,6 +738,41 @@ efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {
   return hip_check("restrict_state");
 }
 
+efpi_status efpi_set_macro_dt(efpi_ctx* ctx, double macro_dt) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!std::isfinite(macro_dt)) return fail(EFPI_EINVAL, "macro_dt must be finite");
+  for (int r = 0; r < ctx->R; ++r) {
+    const efpi_replica& p = ctx->reps[r];
+    if (!(macro_dt >= p.burst_steps * p.dt * (1.0 - 1e-12)))
+      return fail(EFPI_EINVAL, "macro_dt must be >= burst_steps * dt of every replica");
+  }
+  for (int r = 0; r < ctx->R; ++r) {
+    ctx->reps[r].macro_dt = macro_dt;
+    ctx->h_reps[r].macro_dt = macro_dt;
+  }
+  for (RepDev& d : ctx->h_newton_reps) d.macro_dt = macro_dt;
+  // kernels (and captured graphs) read the descriptors on the device when they run,
+  // so the new step takes effect for the work enqueued after this call
+  note(hipMemcpyAsync(ctx->d_reps, ctx->h_reps.data(), sizeof(RepDev) * ctx->R,
+                      hipMemcpyHostToDevice, ctx->stream));
+  note(hipMemcpyAsync(ctx->d_newton_reps, ctx->h_newton_reps.data(), sizeof(RepDev) * ctx->R,
+                      hipMemcpyHostToDevice, ctx->stream));
+  // the host copies must outlive the asynchronous copies above
+  note(hipStreamSynchronize(ctx->stream));
+  return hip_check("set_macro_dt");
+}
+
+efpi_status efpi_project2(efpi_ctx* ctx, const double* d_snap, const double* d_slope_prev,
+                          double gap, double* d_slope, double* d_euler, double* d_coarse_next) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_snap || !d_slope || !d_coarse_next) return fail(EFPI_EINVAL, "NULL array");
+  if (d_slope_prev && !(gap > 0.0 && std::isfinite(gap)))
+    return fail(EFPI_EINVAL, "gap must be finite and > 0 with a previous slope");
+  launch_project2(ctx->d_reps, ctx->R, d_snap, ctx->d_snap_off, d_slope_prev, gap, d_slope,
+                  d_euler, d_coarse_next, ctx->d_coarse_off, ctx->d_status, ctx->stream);
+  return hip_check("project2");
+}
+
 efpi_status efpi_ensemble_mean(efpi_ctx* ctx, double* d_coarse) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   if (!d_coarse) return fail(EFPI_EINVAL, "d_coarse is NULL");

@@ -313,20 +313,27 @@ __global__ void k_restrict(const RepDev* __restrict__ reps, int steps, double* _
     out[k] = (double)gmem(R.rbins)[k] * scale;
 }
 
-// LS slope (eq. 3.18) and projective step (eq. 3.17) for one coefficient, from its
-// snapshot values v(p), p = 0..ne.  Products and sums are never fused into FMAs
-// here, so every kernel that calls it gives the same bits for the same snapshots.
+// LS slope (eq. 3.18) of one coefficient from its snapshot values v(p), p = 0..ne,
+// and the forward-Euler projective step (eq. 3.17).  Products and sums are never
+// fused into FMAs here, so every kernel that calls these gives the same bits for
+// the same snapshots.
 template <class V>
-__device__ __forceinline__ double project_value(V v, int ne, double dt, double macro_dt) {
+__device__ __forceinline__ double ls_slope_value(V v, int ne, double dt) {
 #pragma clang fp contract(off)
   const double den = (double)ne * (ne + 1) * (ne + 2) * dt;
-  const double leap = macro_dt - ne * dt;
   double slope = 0.0;
   for (int p = 0; p <= ne / 2; ++p) {
     const double coef = 6.0 * (double)(ne - 2 * p) / den;
     slope += coef * (v(ne - p) - v(p));
   }
-  return v(ne) + leap * slope;
+  return slope;
+}
+
+template <class V>
+__device__ __forceinline__ double project_value(V v, int ne, double dt, double macro_dt) {
+#pragma clang fp contract(off)
+  const double leap = macro_dt - ne * dt;
+  return v(ne) + leap * ls_slope_value(v, ne, dt);
 }
 
 __global__ void k_project(const RepDev* __restrict__ reps, const double* __restrict__ snap,
@@ -370,6 +377,42 @@ __global__ void k_restrict_project(const RepDev* __restrict__ reps, double* __re
     o[k] = v;
     if (!(fabs(v) < 1e300)) atomicOr(status, 2u);
     if (k < nc && v < 0.0) atomicOr(status, 8u);
+  }
+}
+
+// Second-order projective step.  The LS slope f of this burst estimates the time
+// derivative at the burst's centre, and f_prev (the previous burst's) at the centre
+// one macro step of length `gap` earlier; their linear extrapolation to the middle
+// of the projection leap [t + N_e dt, t + Delta t] is f + (f - f_prev) Delta t /
+// (2 gap) (Adams-Bashforth 2 for equal steps: 3/2 f - 1/2 f_prev), and the state
+// advances from the last snapshot over the leap with it.  Writes the slope, the
+// forward-Euler projection (eq. 3.17, as k_project) and the second-order one
+// (equal to Euler when f_prev is absent).
+__global__ void k_project2(const RepDev* __restrict__ reps, const double* __restrict__ snap,
+                           const int64_t* __restrict__ soff, const double* __restrict__ slope_prev,
+                           double gap, double* __restrict__ slope_out,
+                           double* __restrict__ euler_out, double* __restrict__ out,
+                           const int64_t* __restrict__ coff, uint32_t* __restrict__ status) {
+#pragma clang fp contract(off)
+  const RepDev& R = reps[blockIdx.y];
+  const int nc = R.n_coarse;
+  const int ne = R.burst_steps;
+  const double* s = snap + soff[blockIdx.y];
+  const int64_t co = coff[blockIdx.y];
+  const double leap = R.macro_dt - ne * R.dt;
+  const double w = slope_prev ? R.macro_dt / (2.0 * gap) : 0.0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
+    auto snapshot = [&](int p) { return s[(int64_t)p * 2 * nc + k]; };
+    const double f = ls_slope_value(snapshot, ne, R.dt);
+    const double last = snapshot(ne);
+    const double euler = last + leap * f;
+    const double fm = slope_prev ? f + (f - slope_prev[co + k]) * w : f;
+    const double val = last + leap * fm;
+    slope_out[co + k] = f;
+    if (euler_out) euler_out[co + k] = euler;
+    out[co + k] = val;
+    if (!(fabs(val) < 1e300)) atomicOr(status, 2u);
+    if (k < nc && val < 0.0) atomicOr(status, 8u);
   }
 }
 
@@ -466,6 +509,14 @@ void launch_restrict_project(const RepDev* d_reps, int n_reps, double* d_snap,
                              uint32_t* d_status, hipStream_t stream) {
   hipLaunchKernelGGL(k_restrict_project, dim3(4, n_reps), dim3(256), 0, stream, d_reps, d_snap,
                      d_soff, d_out, d_coff, d_status);
+}
+
+void launch_project2(const RepDev* d_reps, int n_reps, const double* d_snap,
+                     const int64_t* d_soff, const double* d_slope_prev, double gap,
+                     double* d_slope, double* d_euler, double* d_out, const int64_t* d_coff,
+                     uint32_t* d_status, hipStream_t stream) {
+  hipLaunchKernelGGL(k_project2, dim3(4, n_reps), dim3(256), 0, stream, d_reps, d_snap, d_soff,
+                     d_slope_prev, gap, d_slope, d_euler, d_out, d_coff, d_status);
 }
 
 void launch_ensemble_mean(const RepDev* d_reps, int n_reps, const int32_t* d_group,

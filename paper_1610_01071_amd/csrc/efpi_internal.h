@@ -118,6 +118,11 @@ void launch_project(const RepDev* d_reps, int n_reps, const double* d_snap,
 void launch_restrict_project(const RepDev* d_reps, int n_reps, double* d_snap,
                              const int64_t* d_soff, double* d_out, const int64_t* d_coff,
                              uint32_t* d_status, hipStream_t stream);
+// Slope, forward-Euler and second-order projections (d_slope_prev may be NULL).
+void launch_project2(const RepDev* d_reps, int n_reps, const double* d_snap,
+                     const int64_t* d_soff, const double* d_slope_prev, double gap,
+                     double* d_slope, double* d_euler, double* d_out, const int64_t* d_coff,
+                     uint32_t* d_status, hipStream_t stream);
 void launch_ensemble_mean(const RepDev* d_reps, int n_reps, const int32_t* d_group,
                           double* d_coarse, const int64_t* d_coff, hipStream_t stream);
 void launch_fill_u8(void* d_ptr, size_t bytes, hipStream_t stream);

@@ -97,6 +97,8 @@ def _load():
         "efpi_pic_burst": [P, I32, I32],
         "efpi_restrict": [P, P],
         "efpi_project": [P, P, P],
+        "efpi_set_macro_dt": [P, ctypes.c_double],
+        "efpi_project2": [P, P, P, ctypes.c_double, P, P, P],
         "efpi_macro_step": [P, P, P, ctypes.POINTER(U32)],
         "efpi_macro_step_graph": [P, P, P, ctypes.POINTER(U32)],
         "efpi_ensemble_mean": [P, P],
@@ -135,7 +137,8 @@ LIB = _load()
 EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream", "efpi_n_coarse",
             "efpi_set_particles", "efpi_get_particles", "efpi_get_grid", "efpi_set_potential",
             "efpi_load_profile", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
-            "efpi_restrict", "efpi_project", "efpi_macro_step", "efpi_macro_step_graph",
+            "efpi_restrict", "efpi_project", "efpi_set_macro_dt", "efpi_project2",
+            "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
             "efpi_restrict_state",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error",
@@ -297,6 +300,16 @@ def efpi_restrict(ctx, snap):
 
 def efpi_project(ctx, snap, coarse_next):
     _check(LIB.efpi_project(ctx, _dev(snap, torch.float64), _dev(coarse_next, torch.float64)))
+
+
+def efpi_set_macro_dt(ctx, macro_dt):
+    _check(LIB.efpi_set_macro_dt(ctx, float(macro_dt)))
+
+
+def efpi_project2(ctx, snap, slope_prev, gap, slope, euler, coarse_next):
+    _check(LIB.efpi_project2(ctx, _dev(snap, torch.float64), _dev(slope_prev, torch.float64),
+                             float(gap), _dev(slope, torch.float64), _dev(euler, torch.float64),
+                             _dev(coarse_next, torch.float64)))
 
 
 def efpi_macro_step(ctx, coarse_in, coarse_out, shifts):

@@ -88,6 +88,74 @@ def test_projection_conserves_charge():
     assert efpi.project(snaps, 0.1, 20.0)[0].sum() == pytest.approx(16.0, rel=1e-13)
 
 
+# ------------------------------------------ second-order projective step ---
+
+def _quadratic_bursts(ne, dt, gap, macro_dt, seed):
+    """Snapshots of c(t) = a + b t + q t^2 for the previous burst (starting at
+    -gap) and the current one (starting at 0), and c at t = macro_dt."""
+    g = np.random.default_rng(seed)
+    a, b, q = (g.standard_normal((2, 8)) for _ in range(3))
+    c = lambda t: a + b * t + q * t * t
+    prev = np.array([c(-gap + p * dt) for p in range(ne + 1)])
+    cur = np.array([c(p * dt) for p in range(ne + 1)])
+    return prev, cur, c(macro_dt), q
+
+
+@pytest.mark.parametrize("ne,gap,macro_dt", [(20, 7.5, 7.5), (10, 5.0, 6.0), (6, 8.0, 4.0)])
+def test_project2_exact_on_quadratic_trajectories(ne, gap, macro_dt):
+    # For a quadratic trajectory the LS slope of a burst is the derivative at its
+    # centre, the derivative is linear, and its value at the middle of the leap
+    # integrates it exactly: the second-order step lands on c(Delta t); the
+    # forward-Euler step misses by the curvature term.
+    dt = 0.1
+    prev, cur, exact, q = _quadratic_bursts(ne, dt, gap, macro_dt, ne)
+    f_prev = efpi.ls_slope(prev, dt)
+    f, euler, second = efpi.project2(cur, dt, macro_dt, f_prev, gap)
+    assert np.allclose(f, efpi.ls_slope(cur, dt))
+    assert np.max(np.abs(second - exact)) < 1e-10 * np.max(np.abs(exact))
+    leap = macro_dt - ne * dt
+    # Euler: c(t_e) + leap c'(centre) differs from c(Delta t) by q leap Delta t
+    assert np.allclose(exact - euler, q * leap * macro_dt, atol=1e-9)
+
+
+def test_project2_reduces_to_euler():
+    g = np.random.default_rng(5)
+    snaps = g.standard_normal((21, 2, 16))
+    f, euler, second = efpi.project2(snaps, 0.1, 7.5)
+    assert np.array_equal(euler, second)
+    assert np.allclose(euler, efpi.project(snaps, 0.1, 7.5), rtol=0, atol=1e-14)
+    _, euler2, second2 = efpi.project2(snaps, 0.1, 7.5, f, 7.5)
+    assert np.array_equal(euler2, second2)
+
+
+def test_project2_conserves_charge():
+    # Equal totals in every snapshot of both bursts -> both slopes sum to zero,
+    # so the second-order step keeps the total charge (as eq. 3.17 does).
+    g = np.random.default_rng(6)
+    def burst():
+        sn = g.standard_normal((21, 2, 16))
+        sn -= sn.sum(axis=2, keepdims=True) / 16
+        return sn + 1.0
+    f_prev = efpi.ls_slope(burst(), 0.1)
+    _, _, second = efpi.project2(burst(), 0.1, 7.5, f_prev, 6.0)
+    assert second[0].sum() == pytest.approx(16.0, rel=1e-13)
+
+
+def test_step_rule_meets_tolerance_under_its_error_model():
+    # If the Euler-step error is C Delta t^2, the next step's error is safety^2 tol
+    # (inside the factor-2 and [dt_min, dt_max] limits), and the rule is monotone.
+    tol, safety = 1e-3, 0.9
+    for C, dt in ((2e-5, 6.0), (1e-4, 4.0), (4e-5, 5.0)):
+        err = C * dt * dt
+        nxt = efpi.next_macro_dt(dt, err, tol, 0.1, 100.0, safety)
+        if 0.5 * dt < nxt < 2.0 * dt:
+            assert C * nxt * nxt == pytest.approx(safety ** 2 * tol, rel=1e-12)
+    steps = [efpi.next_macro_dt(5.0, e, tol, 2.0, 7.5) for e in (0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1.0)]
+    assert steps == sorted(steps, reverse=True)
+    assert steps[0] == 7.5 and steps[-1] == 2.5
+    assert efpi.next_macro_dt(2.1, 1.0, tol, 2.0, 7.5) == 2.0
+
+
 # ------------------------------------------------------ co-evolving frame ---
 
 def test_coevolving_frame_exact_in_free_streaming():
