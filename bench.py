@@ -14,7 +14,8 @@ Printed: one JSON line with particle-updates/s (K x ions per macro step over
 the macro-step wall time, lift included), the roofline of the dominant kernel
 (the fused push/deposit/restrict particle pass, timed by HIP events inside the
 timed region), the EFPI speedup over full PIC for the same physical time with
-the coarse-density error between them (eq. 4.2), the learned projection
+the coarse-density error between them (eq. 4.2), forward-Euler, second-order
+and adaptive projective runs against the same full-PIC reference, the learned projection
 against plain EFPI (wall time and error at the same physical time), and the
 CPU oracle timed on a bounded sample of the same workload on this host.
 """
@@ -154,6 +155,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-slab", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the Euler / second-order / adaptive projective runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB three times (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -373,7 +376,12 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
         cx.close()
     ok = [r for r in rows if r["eps_density"] <= args.eps_max]
     best = max(ok, key=lambda r: r["macro_dt_over_dt"]) if ok else None
+    extra = {}
+    if not args.no_adaptive:
+        extra["projective_vs_pic"] = projective_leg(E, torch, np, synth, spec, c0, ref, t_pic,
+                                                    shift0, args)
     return {
+        **extra,
         "efpi_speedup_vs_pic": best["speedup"] if best else None,
         "efpi_vs_pic": {
             "horizon": args.horizon,
@@ -385,6 +393,66 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
             "fixed_error_macro_dt_over_dt": best["macro_dt_over_dt"] if best else None,
             "sweep": rows,
         },
+    }
+
+
+def projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args):
+    """Forward-Euler, second-order and adaptive projective runs against the same
+    full-PIC reference as the fixed-step sweep (same start, lift rotations and
+    horizon).  Each run goes through set_macro_dt / lift / restricting burst /
+    restrict / project2 with the Euler-vs-second-order density difference read
+    back every step (the adaptive controller's error estimate), so its wall time
+    includes one host round trip per macro step that the fused chains above do
+    not pay."""
+    from paper_1610_01071_amd.projective import run_projective
+
+    def shift_of(i):
+        return shift0 if i == 0 else synth.lift_shift(20_000 + i)
+
+    runs = [dict(order=o, macro_dt_over_dt=m) for o in (1, 2) for m in (75, 100, 150, 200)]
+    runs += [dict(order=2, tol=tol, dt_min_over_dt=50, dt_max_over_dt=400, macro_dt_over_dt=75)
+             for tol in (1e-4, 3e-4, 1e-3)]
+    rows = []
+    for r in runs:
+        sp = workload_spec(E)
+        sp.macro_dt = r["macro_dt_over_dt"] * spec.dt
+        cx = E.Context(E.ConfigSpec([sp], newton_iters=2, newton_iters_start=4, tile=TILE))
+        kw = {}
+        if "tol" in r:
+            kw = dict(tol=r["tol"], dt_min=r["dt_min_over_dt"] * spec.dt,
+                      dt_max=r["dt_max_over_dt"] * spec.dt)
+        box = {}
+
+        def go():
+            box["run"] = run_projective(cx, c0, args.horizon, sp.macro_dt, 0, order=r["order"],
+                                        shift_of=shift_of, **kw)
+
+        ms = timed(torch, go)
+        bits = E.efpi_sync(cx.ctx, raise_on_error=False)
+        run = box["run"]
+        got = run.states[-1].view(2, -1)[0].cpu().numpy()
+        eps = float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(got * got + ref * ref)))
+        row = dict(r, macro_steps=len(run.steps), efpi_ms=ms, speedup=t_pic / ms,
+                   eps_density=eps, device_status=bits)
+        if "tol" in r:
+            row["macro_dt_over_dt_range"] = [min(run.steps) / spec.dt, max(run.steps) / spec.dt]
+        rows.append(row)
+        cx.close()
+
+    def best(sel):
+        ok = [x for x in rows if sel(x) and x["eps_density"] <= args.eps_max]
+        return max(ok, key=lambda x: x["speedup"]) if ok else None
+
+    b1 = best(lambda x: x["order"] == 1 and "tol" not in x)
+    b2 = best(lambda x: x["order"] == 2 and "tol" not in x)
+    ba = best(lambda x: "tol" in x)
+    return {
+        "eps_max": args.eps_max,
+        "euler_best_speedup": b1["speedup"] if b1 else None,
+        "second_order_best_speedup": b2["speedup"] if b2 else None,
+        "second_order_best_macro_dt_over_dt": b2["macro_dt_over_dt"] if b2 else None,
+        "adaptive_best_speedup": ba["speedup"] if ba else None,
+        "runs": rows,
     }
 
 

@@ -444,7 +444,8 @@ class Context:
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         off = (-self.workspace.data_ptr()) % 256
         self.workspace = self.workspace[off: off + nbytes]
-        self.ctx = efpi_init(self.cfg, self.workspace, stream)
+        self.stream = torch.cuda.current_stream(self.workspace.device) if stream is None else stream
+        self.ctx = efpi_init(self.cfg, self.workspace, self.stream)
         self.device = self.workspace.device
         self.coarse_sizes = [r.n_coarse for r in spec.replicas]
 

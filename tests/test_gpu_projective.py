@@ -1,0 +1,225 @@
+"""Variable projective step and the second-order projection against the oracle.
+
+Bars: efpi_project2's slope and second-order projection within 1e-12 of the
+FP64 oracle on the same snapshots (the two differ only in summation order);
+its Euler output bit-equal to efpi_project; a context switched to another
+Delta t by efpi_set_macro_dt bit-equal to a fresh context built with it, eager
+and replayed from a graph captured before the switch; whole projective runs
+(Euler, second order, adaptive) within eps = 2e-3 (eq. 4.2) of oracle runs
+taking the same steps.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import efpi as oefpi
+from oracle import metrics
+from helpers import lib, oracle_grid, oracle_scheme, relmax, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def make_ctx(specs, **kw):
+    E = lib()
+    return E.Context(E.ConfigSpec(list(specs), **kw))
+
+
+def start_state(E, spec, seed):
+    """Coarse state of a quiet IAW start, restricted in a context of its own."""
+    ctx = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    n0, u0 = synth.iaw_profile(spec.n_cells, spec.length)
+    E.efpi_load_profile(ctx.ctx, 0, torch.as_tensor(n0, device="cuda"),
+                        torch.as_tensor(u0, device="cuda"), synth.lift_shift(seed))
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 20, cold=True)
+    c = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c)
+    E.efpi_sync(ctx.ctx)
+    return c
+
+
+# ------------------------------------------------------------- project2 --
+
+def test_project2_matches_oracle():
+    E = lib()
+    specs = [E.ReplicaSpec(256, 256.0, haar_levels=2, burst_steps=10, dt=0.1, macro_dt=8.0),
+             E.ReplicaSpec(512, 512.0, bc=1, haar_levels=3, burst_steps=6, dt=0.2, macro_dt=8.0)]
+    ctx = make_ctx(specs)
+    E.efpi_set_macro_dt(ctx.ctx, 6.5)
+    rng = np.random.default_rng(5)
+    snaps = [1.0 + 0.01 * rng.standard_normal((s.burst_steps + 1, 2, s.n_coarse)) for s in specs]
+    prevs = [0.002 * rng.standard_normal((2, s.n_coarse)) for s in specs]
+    gap = 5.0
+    d_snap = to_dev(np.concatenate([a.ravel() for a in snaps]), torch.float64)
+    d_prev = to_dev(np.concatenate([a.ravel() for a in prevs]), torch.float64)
+    slope, euler, second = ctx.new_coarse(), ctx.new_coarse(), ctx.new_coarse()
+    E.efpi_project2(ctx.ctx, d_snap, d_prev, gap, slope, euler, second)
+    plain = ctx.new_coarse()
+    E.efpi_project(ctx.ctx, d_snap, plain)
+    E.efpi_sync(ctx.ctx)
+    assert torch.equal(euler, plain)
+    for r, s in enumerate(specs):
+        f, eu, sec = oefpi.project2(snaps[r], s.dt, 6.5, prevs[r], gap)
+        assert relmax(ctx.split_coarse(slope)[r].cpu().numpy(), f) < 1e-12
+        assert relmax(ctx.split_coarse(euler)[r].cpu().numpy(), eu) < 1e-12
+        assert relmax(ctx.split_coarse(second)[r].cpu().numpy(), sec) < 1e-12
+    # no previous slope: the second-order output is the Euler step, bit for bit
+    E.efpi_project2(ctx.ctx, d_snap, None, 0.0, slope, None, second)
+    E.efpi_sync(ctx.ctx)
+    assert torch.equal(second, plain)
+    # a previous slope needs a positive finite gap
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(E.EfpiError):
+            E.efpi_project2(ctx.ctx, d_snap, d_prev, bad, slope, euler, second)
+
+
+# ------------------------------------------------------- set_macro_dt --
+
+def test_set_macro_dt_validates():
+    E = lib()
+    spec = E.ReplicaSpec(256, 256.0, haar_levels=2, burst_steps=10, dt=0.1, macro_dt=8.0)
+    ctx = make_ctx([spec])
+    rng = np.random.default_rng(6)
+    d_snap = to_dev(1.0 + 0.01 * rng.standard_normal(ctx.snap_numel()), torch.float64)
+    before, after = ctx.new_coarse(), ctx.new_coarse()
+    E.efpi_project(ctx.ctx, d_snap, before)
+    for bad in (0.5, 1.0 - 1e-6, float("nan"), float("inf"), -3.0):
+        with pytest.raises(E.EfpiError):
+            E.efpi_set_macro_dt(ctx.ctx, bad)
+    E.efpi_project(ctx.ctx, d_snap, after)
+    E.efpi_sync(ctx.ctx)
+    assert torch.equal(before, after)       # a rejected value changes nothing
+    E.efpi_set_macro_dt(ctx.ctx, 1.0)       # Delta t = N_e dt: projection over zero time
+    E.efpi_project(ctx.ctx, d_snap, after)
+    E.efpi_sync(ctx.ctx)
+    last = ctx.split_snap(d_snap)[0][-1].reshape(-1)
+    assert relmax(after.cpu().numpy(), last.cpu().numpy()) < 1e-15
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_set_macro_dt_equals_fresh_context(bc):
+    """Macro steps after efpi_set_macro_dt equal those of a context built with
+    that Delta t, eager and from a graph captured at the old Delta t."""
+    E = lib()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        kw = dict(bc=bc, ppc=64, haar_levels=3, burst_steps=10, vth=0.316 if bc == 0 else 0.1)
+        s8 = E.ReplicaSpec(512, 512.0, macro_dt=8.0, **kw)
+        s6 = dataclasses.replace(s8, macro_dt=6.0)
+        cin = start_state(E, s8, 31)
+        shift = [synth.lift_shift(32)]
+        ref = {}
+        for dt, spec in ((8.0, s8), (6.0, s6)):
+            fresh = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+            ref[dt] = fresh.new_coarse()
+            E.efpi_macro_step(fresh.ctx, cin, ref[dt], shift)
+            E.efpi_sync(fresh.ctx, raise_on_error=False)
+            fresh.close()
+        assert not torch.equal(ref[8.0], ref[6.0])
+        eager = make_ctx([s8], newton_iters=3, newton_iters_start=6)
+        graph = make_ctx([s8], newton_iters=3, newton_iters_start=6)
+        out_e, out_g = eager.new_coarse(), graph.new_coarse()
+        for dt in (8.0, 6.0, 8.0, 6.0):
+            E.efpi_set_macro_dt(eager.ctx, dt)
+            E.efpi_set_macro_dt(graph.ctx, dt)
+            E.efpi_macro_step(eager.ctx, cin, out_e, shift)
+            E.efpi_macro_step_graph(graph.ctx, cin, out_g, shift)   # captured at 8.0
+            side.synchronize()
+            assert torch.equal(out_e, ref[dt]), f"eager at {dt}"
+            assert torch.equal(out_g, ref[dt]), f"graph at {dt}"
+        E.efpi_sync(eager.ctx, raise_on_error=False)
+        E.efpi_sync(graph.ctx, raise_on_error=False)
+
+
+# ------------------------------------------------------ projective runs --
+
+def oracle_run(c0, spec, steps, shifts, order):
+    """Oracle projective run over the given step sizes: macro steps of the oracle
+    with Delta t per step, projected by oracle project2."""
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    c = np.asarray(c0, dtype=np.float64).reshape(2, -1)
+    out, f_prev, gap = [], None, None
+    for n, dt in enumerate(steps):
+        sn = dataclasses.replace(sch, macro_dt=dt)
+        _, snaps, _ = oefpi.macro_step(c, g, sn, shifts[n])
+        f, eu, sec = oefpi.project2(snaps, g.dt, dt, f_prev, gap)
+        c = sec if order == 2 else eu
+        out.append(c)
+        f_prev, gap = f, dt
+    return out
+
+
+def _spec(E):
+    return E.ReplicaSpec(256, 256.0, ppc=64, haar_levels=3, burst_steps=10, macro_dt=6.0)
+
+
+def test_projective_euler_equals_macro_steps():
+    """Order-1 runs through set_macro_dt/lift/burst/restrict/project2 reproduce
+    efpi_macro_step chains bit for bit."""
+    from paper_1610_01071_amd import projective
+    E = lib()
+    spec = _spec(E)
+    c0 = start_state(E, spec, 41)
+    shift_of = lambda n: synth.lift_shift(500 + n)
+    a = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    run = projective.run_projective(a, c0, 4 * 6.0, 6.0, 0, order=1, shift_of=shift_of)
+    b = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    cur = c0.clone()
+    assert run.steps == [6.0] * 4
+    for n in range(4):
+        nxt = b.new_coarse()
+        E.efpi_macro_step(b.ctx, cur, nxt, [shift_of(n)])
+        cur = nxt
+        torch.cuda.synchronize()
+        assert torch.equal(run.states[n + 1], cur), f"step {n}"
+    E.efpi_sync(a.ctx, raise_on_error=False)
+    E.efpi_sync(b.ctx, raise_on_error=False)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_projective_run_matches_oracle(order):
+    from paper_1610_01071_amd import projective
+    E = lib()
+    spec = _spec(E)
+    c0 = start_state(E, spec, 43)
+    shift_of = lambda n: synth.lift_shift(700 + n)
+    ctx = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    run = projective.run_projective(ctx, c0, 3 * 6.0, 6.0, 0, order=order, shift_of=shift_of)
+    E.efpi_sync(ctx.ctx)
+    assert run.steps == [6.0] * 3 and abs(run.times[-1] - 18.0) < 1e-12
+    ref = oracle_run(c0.cpu().numpy(), spec, run.steps, [shift_of(n) for n in range(3)], order)
+    for n in range(3):
+        got = run.states[n + 1].view(2, -1).cpu().numpy()
+        for m in range(2):
+            assert metrics.rel_l2(got[m], ref[n][m]) < 2e-3, f"step {n} moment {m}"
+
+
+def test_adaptive_run_follows_step_rule_and_oracle():
+    from paper_1610_01071_amd import projective
+    E = lib()
+    spec = _spec(E)
+    c0 = start_state(E, spec, 47)
+    shift_of = lambda n: synth.lift_shift(900 + n)
+    ctx = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    t_end, tol, lo, hi = 30.0, 1e-4, 1.0, 9.0
+    run = projective.run_projective(ctx, c0, t_end, 3.0, 0, order=2, tol=tol, dt_min=lo,
+                                    dt_max=hi, shift_of=shift_of)
+    E.efpi_sync(ctx.ctx)
+    assert abs(run.times[-1] - t_end) < 1e-9 and abs(sum(run.steps) - t_end) < 1e-9
+    assert all(lo - 1e-12 <= s <= hi + 1e-12 for s in run.steps)
+    assert run.err[0] == 0.0 and all(e > 0.0 for e in run.err[1:])
+    assert len(set(run.steps)) > 1              # the controller moved the step
+    # every step but the first and the two end-adjusted ones follows the step rule
+    assert len(run.steps) >= 5
+    for n in range(1, len(run.steps) - 3):
+        want = oefpi.next_macro_dt(run.steps[n], run.err[n], tol, lo, hi)
+        assert run.steps[n + 1] == pytest.approx(want, rel=1e-15, abs=0.0), f"step {n + 1}"
+    ref = oracle_run(c0.cpu().numpy(), spec, run.steps,
+                     [shift_of(n) for n in range(len(run.steps))], 2)
+    for n in range(len(run.steps)):
+        got = run.states[n + 1].view(2, -1).cpu().numpy()
+        for m in range(2):
+            assert metrics.rel_l2(got[m], ref[n][m]) < 2e-3, f"step {n} moment {m}"
