@@ -102,7 +102,8 @@ def run_projective(ctx: E.Context, c0: torch.Tensor, t_end: float, macro_dt: flo
         e = 0.0
         if prev is not None:
             E.efpi_rel_l2(second[:nc2 // 2], euler[:nc2 // 2], eps, ctx.stream)
-            e = float(eps.item())
+            with torch.cuda.stream(ctx.stream):      # read it back on the context's stream
+                e = float(eps.item())
         cur = second if order == 2 else euler
         t += dt
         states.append(cur)
