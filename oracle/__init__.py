@@ -17,6 +17,9 @@ efpi     coarse representation and the projective cycle: co-evolving restriction
          (App. B), Haar scaling coefficients (App. A), least-squares slope and
          projection (eqs. 3.17-3.18), quiet-start lift (App. C), the macro step
          (Sec. 3.1) and the ensemble mean.
+kinetic  fine solver with kinetic electrons (two-species leapfrog, linear
+         Poisson, eq. 2.2), Boltzmann-equilibrium electron loading at lift
+         (eqs. 3.15-3.16, App. C) and the macro step with kinetic electrons.
 nn       1D-convolution surrogate for the coarse time derivative: forward,
          hand-derived backward and Adam, FP64.
 metrics  the relative L2 error of eq. 4.2.
