@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define EFPI_ABI_VERSION 1u
+#define EFPI_ABI_VERSION 2u
 
 typedef enum {
   EFPI_OK = 0,
@@ -67,6 +67,10 @@ typedef enum {
 #define EFPI_BC_PERIODIC 0
 #define EFPI_BC_WALLS 1      /* absorbing walls, Neumann potential (phi' = 0)    */
 #define EFPI_CLOSURE_BOLTZMANN 0 /* Newton solve of eq. 3.15                      */
+#define EFPI_CLOSURE_KINETIC 1   /* kinetic electrons (particles, eq. 2.5) and the
+                                    linear Poisson equation -phi'' = n_i - n_e
+                                    (eq. 2.2); periodic only, n_cells <= 8192, and
+                                    every replica of the context kinetic          */
 #define EFPI_CLOSURE_NOFIELD 2   /* E = 0 (free streaming; test closure)          */
 
 /* One replica (an independent plasma).  Ensembles pass several. */
@@ -85,6 +89,15 @@ typedef struct {
   double macro_dt;      /* projective step Delta t >= N_e dt (eq. 3.17)           */
   double n_floor;       /* density below which a cell is empty at lift (> 0)     */
   int64_t capacity;     /* particle slots reserved for this replica               */
+  /* kinetic electrons (EFPI_CLOSURE_KINETIC only; ignored otherwise).  Units are
+   * the ions' (length lambda_D, time 1/omega_pi, potential T_e/e): with
+   * mu = m_i/m_e the electrons have q/m = -mu, omega_pe = sqrt(mu) and thermal
+   * speed sqrt(mu) at T_e0. */
+  double qm_e;          /* electron charge-to-mass ratio, < 0 (-m_i/m_e)         */
+  double vth_e;         /* electron thermal speed at loading, >= 0               */
+  int32_t ppc_e;        /* electrons per occupied cell at loading, >= 1          */
+  int32_t pad_e;        /* must be 0                                              */
+  int64_t capacity_e;   /* electron slots reserved for this replica               */
 } efpi_replica;
 
 typedef struct {
@@ -170,13 +183,55 @@ efpi_status efpi_load_profile(efpi_ctx* ctx, int32_t replica, const double* d_n,
  * the block momentum.  d_coarse must stay valid until the work has run. */
 efpi_status efpi_lift(efpi_ctx* ctx, const double* d_coarse, const uint32_t* h_shifts);
 
-/* Deposit the fixed-point CIC charge of the current particles (Sec. 2.2). */
+/* Deposit the fixed-point CIC charge of the current particles (Sec. 2.2): ion
+ * charge, minus the electron charge in kinetic contexts (each electron deposits
+ * -q_L, -q_R with the ions' fixed-point split). */
 efpi_status efpi_deposit(efpi_ctx* ctx);
 
 /* Solve -phi'' + exp(phi) = rho (eq. 3.15) by `iters` Newton iterations from the
  * current potential (cold != 0: from ln max(rho, 1e-8)), then set the node field
- * E_k = -(phi_{k+1} - phi_{k-1}) / 2h.  Requires a deposit since the last state change. */
+ * E_k = -(phi_{k+1} - phi_{k-1}) / 2h.  Requires a deposit since the last state change.
+ * Kinetic contexts instead solve the periodic linear Poisson equation
+ * -phi'' = rho - mean(rho) (eq. 2.2) exactly, with mean(phi) = 0 (iters and cold
+ * are checked but not used). */
 efpi_status efpi_solve_field(efpi_ctx* ctx, int32_t iters, int32_t cold);
+
+/* ---------------------------------------------------- kinetic electrons -- */
+/* Contexts whose replicas use EFPI_CLOSURE_KINETIC hold a second particle store
+ * per replica for the electrons (same SoA layout as the ions).  Every burst
+ * step pushes both species with the same field (electrons with q/m = qm_e,
+ * time step dt) and deposits both charges; the field is the linear Poisson
+ * solution.  Lifts (efpi_lift, efpi_macro_step, captured graphs) load the
+ * electrons in Boltzmann equilibrium with the lifted ions, as
+ * efpi_boltzmann_electrons.  All four calls return EFPI_ESTATE in contexts
+ * without kinetic electrons. */
+
+/* Copy n electrons into replica r's electron store (layout of efpi_set_particles;
+ * n <= capacity_e).  Marks both species as freshly loaded (integer-time velocities). */
+efpi_status efpi_set_electrons(efpi_ctx* ctx, int32_t replica, const int16_t* d_cell,
+                               const float* d_frac, const float* d_v, const float* d_w,
+                               int64_t n);
+
+/* Copy replica r's electrons out (as efpi_get_particles; synchronous). */
+efpi_status efpi_get_electrons(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, float* d_frac,
+                               float* d_v, float* d_w, int64_t* h_n);
+
+/* Quiet-start electrons of replica r from node profiles d_n (density) and d_u
+ * (mean velocity), FP64, N nodes: the loading of efpi_load_profile (App. C) with
+ * ppc_e electrons per occupied cell and thermal speed vth_e, rotation `shift`.
+ * The ions must be at an integer time level (loaded, lifted or set since the
+ * last burst); EFPI_ESTATE otherwise. */
+efpi_status efpi_load_electrons(efpi_ctx* ctx, int32_t replica, const double* d_n,
+                                const double* d_u, uint32_t shift);
+
+/* Electrons in Boltzmann equilibrium with the current ions of every replica
+ * (the passive electron variables of Sec. 3.3, eqs. 3.15-3.16): deposit the ion
+ * charge, solve -phi'' + exp(phi) = n_i by newton_iters_start Newton iterations
+ * from ln max(n_i, 1e-8), and load electrons with density exp(phi), mean velocity
+ * the ions' fine velocity profile of their last lift or load, thermal speed
+ * vth_e and Hammersley rotation h_shifts[r] XOR 0x9E3779B9.  The ions must be at
+ * an integer time level (EFPI_ESTATE otherwise). */
+efpi_status efpi_boltzmann_electrons(efpi_ctx* ctx, const uint32_t* h_shifts);
 
 /* Fine burst on every replica: `steps` leapfrog steps (gather, push, boundary,
  * fixed-point deposit, Newton solve).  With restrict != 0 the burst starts by

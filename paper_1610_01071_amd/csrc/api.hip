@@ -72,6 +72,10 @@ struct efpi_ctx {
   int64_t* d_coarse_off = nullptr;
   int32_t* d_group = nullptr;
   RepDev* d_newton_reps = nullptr;  // descriptors in Newton launch order
+  bool kinetic = false;             // kinetic electrons (every replica)
+  int max_nodes = 0;                // largest node count of the replicas
+  std::vector<RepDev> h_ereps;      // electron descriptors (kinetic contexts)
+  RepDev* d_ereps = nullptr;
   double* d_snap = nullptr;
   double* d_coarse = nullptr;
   int32_t* d_sort_hist = nullptr;
@@ -150,8 +154,23 @@ efpi_status check_config(const efpi_config* cfg) {
     if (!is_pow2(p.n_cells) || p.n_cells < 8 || p.n_cells > 16384)
       return bad("n_cells must be a power of two in [8, 16384]");
     if (p.bc != EFPI_BC_PERIODIC && p.bc != EFPI_BC_WALLS) return bad("unknown bc");
-    if (p.closure != EFPI_CLOSURE_BOLTZMANN && p.closure != EFPI_CLOSURE_NOFIELD)
+    if (p.closure != EFPI_CLOSURE_BOLTZMANN && p.closure != EFPI_CLOSURE_NOFIELD &&
+        p.closure != EFPI_CLOSURE_KINETIC)
       return bad("unsupported closure");
+    if ((p.closure == EFPI_CLOSURE_KINETIC) != (cfg->replicas[0].closure == EFPI_CLOSURE_KINETIC))
+      return bad("kinetic electrons must be used by every replica of a context or by none");
+    if (p.closure == EFPI_CLOSURE_KINETIC) {
+      if (p.bc != EFPI_BC_PERIODIC) return bad("kinetic electrons need a periodic domain");
+      if (p.n_cells > 8192) return bad("kinetic electrons need n_cells <= 8192");
+      if (!(p.qm_e < 0.0) || !std::isfinite(p.qm_e)) return bad("qm_e must be finite and < 0");
+      if (!(p.vth_e >= 0.0) || !std::isfinite(p.vth_e)) return bad("vth_e must be >= 0");
+      if (p.ppc_e < 1) return bad("ppc_e must be >= 1");
+      if ((int64_t)p.n_cells * p.ppc_e > (int64_t(1) << 32))
+        return bad("n_cells * ppc_e must fit in 32 bits (Hammersley index)");
+      if (p.pad_e != 0) return bad("pad_e must be 0");
+      if (p.capacity_e < 1 || p.capacity_e >= (int64_t(1) << 31))
+        return bad("capacity_e must be in [1, 2^31 - 1]");
+    }
     if (p.ppc < 1) return bad("ppc must be >= 1");
     if ((int64_t)p.n_cells * p.ppc > (int64_t(1) << 32))
       return bad("n_cells * ppc must fit in 32 bits (Hammersley index)");
@@ -185,6 +204,8 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
   uint8_t* p_coff = take(sizeof(int64_t) * R);
   uint8_t* p_group = take(sizeof(int32_t) * R);
   uint8_t* p_nreps = take(sizeof(RepDev) * R);
+  const bool kinetic = cfg->replicas[0].closure == EFPI_CLOSURE_KINETIC;
+  uint8_t* p_ereps = kinetic ? take(sizeof(RepDev) * R) : nullptr;
   int64_t snap_total = 0, coarse_total = 0;
   for (int r = 0; r < R; ++r) {
     const efpi_replica& p = cfg->replicas[r];
@@ -219,6 +240,9 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     ctx->snap_total = snap_total;
     ctx->coarse_total = coarse_total;
     ctx->h_reps.assign(R, RepDev{});
+    ctx->kinetic = kinetic;
+    ctx->d_ereps = reinterpret_cast<RepDev*>(p_ereps);
+    if (kinetic) ctx->h_ereps.assign(R, RepDev{});
   }
   int64_t soff = 0, coff = 0;
   const bool sortbuf = (cfg->flags & EFPI_FLAG_SORT_BUFFER) != 0;
@@ -251,6 +275,22 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     uint8_t* cor = take(sizeof(int32_t) * n);
     uint8_t* br = take(sizeof(int32_t) * (nc + 1));
     uint8_t* aux = take(sizeof(int64_t) * 4);
+    // electron store and loading arrays of a kinetic replica
+    uint8_t *ecell = nullptr, *efrac = nullptr, *ev = nullptr, *ew = nullptr, *enp = nullptr;
+    uint8_t *epn = nullptr, *epu = nullptr, *ecor = nullptr, *ebr = nullptr, *eaux = nullptr;
+    if (kinetic) {
+      const int64_t cap_e = p.capacity_e;
+      ecell = take(sizeof(int16_t) * cap_e);
+      efrac = take(sizeof(float) * cap_e);
+      ev = take(sizeof(float) * cap_e);
+      ew = take(sizeof(float) * cap_e);
+      enp = take(sizeof(int64_t));
+      epn = take(sizeof(double) * (nn + 1));
+      epu = take(sizeof(double) * (nn + 1));
+      ecor = take(sizeof(int32_t) * n);
+      ebr = take(sizeof(int32_t) * (nc + 1));
+      eaux = take(sizeof(int64_t) * 4);
+    }
     if (ctx) {
       RepDev& d = ctx->h_reps[r];
       d.n_cells = n;
@@ -294,6 +334,29 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
       d.cell_of_rank = reinterpret_cast<int32_t*>(cor);
       d.block_rank = reinterpret_cast<int32_t*>(br);
       d.aux = reinterpret_cast<int64_t*>(aux);
+      d.qm = 1.0;
+      if (kinetic) {
+        RepDev& el = ctx->h_ereps[r];
+        el = d;
+        el.ppc = p.ppc_e;
+        el.vth = p.vth_e;
+        el.capacity = p.capacity_e;
+        el.qm = p.qm_e;
+        el.cell = reinterpret_cast<int16_t*>(ecell);
+        el.frac = reinterpret_cast<float*>(efrac);
+        el.v = reinterpret_cast<float*>(ev);
+        el.w = reinterpret_cast<float*>(ew);
+        el.cell2 = nullptr;
+        el.frac2 = nullptr;
+        el.v2 = nullptr;
+        el.w2 = nullptr;
+        el.np = reinterpret_cast<int64_t*>(enp);
+        el.prof_n = reinterpret_cast<double*>(epn);
+        el.prof_u = reinterpret_cast<double*>(epu);
+        el.cell_of_rank = reinterpret_cast<int32_t*>(ecor);
+        el.block_rank = reinterpret_cast<int32_t*>(ebr);
+        el.aux = reinterpret_cast<int64_t*>(eaux);
+      }
     }
     soff += (int64_t)(p.burst_steps + 1) * 2 * nc;
     coff += 2 * nc;
@@ -337,6 +400,43 @@ void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
   c->field_valid = true;
 }
 
+// Field of the current deposit: linear Poisson with kinetic electrons, else Newton.
+void run_field(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
+  if (c->kinetic) {
+    launch_poisson(c->d_reps, c->R, c->cur, save_en, zero_bins, c->d_status, c->stream);
+    c->other_zero = true;
+    c->field_valid = true;
+  } else {
+    run_newton(c, iters, cold, save_en, zero_bins);
+  }
+}
+
+// Charge of the current particles (both species in kinetic contexts) into the
+// next buffer, which becomes the current one.
+void deposit_all(efpi_ctx* c, bool electrons) {
+  deposit_into_next(c);
+  launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, 0,
+                   kDepositOnly, c->cur ^ 1, c->stream);
+  if (electrons && c->kinetic)
+    launch_electrons(c->d_ereps, c->R, 0, 0, c->cur ^ 1, c->max_nodes, c->stream);
+  c->cur ^= 1;
+  c->other_zero = false;
+  c->deposited = true;
+}
+
+// Electrons in Boltzmann equilibrium with the current ions: ion charge, Newton
+// solve of eq. 3.15, density exp(phi) with the ions' fine velocity profile, and
+// the quiet start with the electron rotation derived on the device from the
+// ions' stored rotation.
+void load_boltzmann_electrons(efpi_ctx* c) {
+  deposit_all(c, false);
+  run_newton(c, c->cfg.newton_iters_start, 1, 0, 0);
+  launch_electron_profile(c->d_reps, c->d_ereps, c->R, c->stream);
+  launch_occupancy(c->d_ereps, c->R, -1, c->d_status, c->stream);
+  launch_lift_particles(c->d_ereps, c->d_block_prefix, c->R, c->total_blocks, -1, nullptr,
+                        c->d_coarse_off, nullptr, c->grid_blocks, c->stream);
+}
+
 void mark_new_particles(efpi_ctx* c) {
   c->fresh = true;
   c->field_valid = false;
@@ -358,6 +458,7 @@ efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shift
                    h_shifts ? &sh : nullptr, c->stream);
   launch_lift_particles(c->d_reps, c->d_block_prefix, c->R, c->total_blocks, -1, d_coarse,
                         c->d_coarse_off, nullptr, c->grid_blocks, c->stream);
+  if (c->kinetic) load_boltzmann_electrons(c);
   mark_new_particles(c);
   return hip_check("lift");
 }
@@ -375,15 +476,8 @@ hipEvent_t next_event(efpi_ctx* c) {
 
 efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
   if (!c->field_valid) {
-    if (!c->deposited) {
-      deposit_into_next(c);
-      launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks,
-                       0, kDepositOnly, c->cur ^ 1, c->stream);
-      c->cur ^= 1;
-      c->other_zero = false;
-      c->deposited = true;
-    }
-    run_newton(c, c->cfg.newton_iters_start, 0, restrict_ ? 1 : 0, restrict_ ? 1 : 0);
+    if (!c->deposited) deposit_all(c, true);
+    run_field(c, c->cfg.newton_iters_start, 0, restrict_ ? 1 : 0, restrict_ ? 1 : 0);
   } else if (restrict_) {
     launch_prep_burst(c->d_reps, c->R, c->stream);
   }
@@ -405,10 +499,13 @@ efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
     launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, p,
                      flags, c->cur ^ 1, c->stream, e0, e1);
     if (push) {
+      if (c->kinetic)
+        launch_electrons(c->d_ereps, c->R, 1, (flags & kFresh) ? 1 : 0, c->cur ^ 1, c->max_nodes,
+                         c->stream);
       c->cur ^= 1;
       c->other_zero = false;
       c->fresh = false;
-      run_newton(c, c->cfg.newton_iters, 0, 0, 0);
+      run_field(c, c->cfg.newton_iters, 0, 0, 0);
     }
   }
   if (steps > 0) c->fresh = false;
@@ -514,6 +611,10 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
                  hipMemcpyHostToDevice, c->stream));
   note(hipMemcpyAsync(c->d_group, c->h_group.data(), sizeof(int32_t) * c->R, hipMemcpyHostToDevice,
                  c->stream));
+  for (int r = 0; r < c->R; ++r) c->max_nodes = std::max(c->max_nodes, c->h_reps[r].n_nodes);
+  if (c->kinetic)
+    note(hipMemcpyAsync(c->d_ereps, c->h_ereps.data(), sizeof(RepDev) * c->R,
+                        hipMemcpyHostToDevice, c->stream));
   c->h_newton_reps.clear();
   for (int32_t r : c->h_newton_list) c->h_newton_reps.push_back(c->h_reps[r]);
   note(hipMemcpyAsync(c->d_newton_reps, c->h_newton_reps.data(), sizeof(RepDev) * c->R,
@@ -605,6 +706,64 @@ efpi_status efpi_load_profile(efpi_ctx* ctx, int32_t replica, const double* d_n,
   return hip_check("load_profile");
 }
 
+efpi_status efpi_set_electrons(efpi_ctx* ctx, int32_t replica, const int16_t* d_cell,
+                               const float* d_frac, const float* d_v, const float* d_w,
+                               int64_t n) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (!ctx->kinetic) return fail(EFPI_ESTATE, "the context has no kinetic electrons");
+  if (!d_cell || !d_frac || !d_v || !d_w) return fail(EFPI_EINVAL, "NULL array");
+  if (n < 0 || n > ctx->h_ereps[replica].capacity) return fail(EFPI_EINVAL, "n out of [0, capacity_e]");
+  launch_copy_particles(ctx->d_ereps, replica, d_cell, d_frac, d_v, d_w, n, 1, nullptr, nullptr,
+                        nullptr, nullptr, ctx->stream);
+  mark_new_particles(ctx);
+  return hip_check("set_electrons");
+}
+
+efpi_status efpi_get_electrons(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, float* d_frac,
+                               float* d_v, float* d_w, int64_t* h_n) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (!ctx->kinetic) return fail(EFPI_ESTATE, "the context has no kinetic electrons");
+  const RepDev& d = ctx->h_ereps[replica];
+  launch_copy_particles(ctx->d_ereps, replica, nullptr, nullptr, nullptr, nullptr, d.capacity, 0,
+                        d_cell, d_frac, d_v, d_w, ctx->stream);
+  int64_t n = 0;
+  note(hipMemcpyAsync(&n, d.np, sizeof n, hipMemcpyDeviceToHost, ctx->stream));
+  const hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(EFPI_EHIP, std::string("get_electrons: ") + hipGetErrorString(e));
+  if (h_n) *h_n = n;
+  return hip_check("get_electrons");
+}
+
+efpi_status efpi_load_electrons(efpi_ctx* ctx, int32_t replica, const double* d_n,
+                                const double* d_u, uint32_t shift) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (!ctx->kinetic) return fail(EFPI_ESTATE, "the context has no kinetic electrons");
+  if (!d_n || !d_u) return fail(EFPI_EINVAL, "NULL profile");
+  if (!ctx->fresh) return fail(EFPI_ESTATE, "load electrons with the ions at an integer time level");
+  launch_set_profile(ctx->d_ereps, replica, d_n, d_u, ctx->stream);
+  launch_occupancy(ctx->d_ereps, ctx->R, replica, ctx->d_status, ctx->stream);
+  ShiftArg s;
+  std::memset(&s, 0, sizeof s);
+  s.s[replica] = shift;
+  launch_lift_particles(ctx->d_ereps, ctx->d_block_prefix, ctx->R,
+                        ctx->h_reps[replica].n_coarse, replica, nullptr, ctx->d_coarse_off, &s,
+                        ctx->grid_blocks, ctx->stream);
+  mark_new_particles(ctx);
+  return hip_check("load_electrons");
+}
+
+efpi_status efpi_boltzmann_electrons(efpi_ctx* ctx, const uint32_t* h_shifts) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!ctx->kinetic) return fail(EFPI_ESTATE, "the context has no kinetic electrons");
+  if (!h_shifts) return fail(EFPI_EINVAL, "h_shifts is NULL");
+  if (!ctx->fresh) return fail(EFPI_ESTATE, "load electrons with the ions at an integer time level");
+  // the ions' rotation slot carries the rotation the electron profile derives from
+  launch_set_shifts(ctx->d_reps, ctx->R, -1, shifts_of(ctx, h_shifts), ctx->stream);
+  load_boltzmann_electrons(ctx);
+  mark_new_particles(ctx);
+  return hip_check("boltzmann_electrons");
+}
+
 efpi_status efpi_lift(efpi_ctx* ctx, const double* d_coarse, const uint32_t* h_shifts) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   if (!d_coarse) return fail(EFPI_EINVAL, "d_coarse is NULL");
@@ -614,12 +773,7 @@ efpi_status efpi_lift(efpi_ctx* ctx, const double* d_coarse, const uint32_t* h_s
 
 efpi_status efpi_deposit(efpi_ctx* ctx) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
-  deposit_into_next(ctx);
-  launch_particles(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
-                   ctx->grid_blocks, 0, kDepositOnly, ctx->cur ^ 1, ctx->stream);
-  ctx->cur ^= 1;
-  ctx->other_zero = false;
-  ctx->deposited = true;
+  deposit_all(ctx, true);
   return hip_check("deposit");
 }
 
@@ -627,7 +781,7 @@ efpi_status efpi_solve_field(efpi_ctx* ctx, int32_t iters, int32_t cold) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   if (iters < 1 || iters > 1000) return fail(EFPI_EINVAL, "iters must be in [1, 1000]");
   if (!ctx->deposited) return fail(EFPI_ESTATE, "solve_field needs a deposit of the current particles");
-  run_newton(ctx, iters, cold ? 1 : 0, 0, 0);
+  run_field(ctx, iters, cold ? 1 : 0, 0, 0);
   return hip_check("solve_field");
 }
 
@@ -751,6 +905,10 @@ efpi_status efpi_set_macro_dt(efpi_ctx* ctx, double macro_dt) {
     ctx->h_reps[r].macro_dt = macro_dt;
   }
   for (RepDev& d : ctx->h_newton_reps) d.macro_dt = macro_dt;
+  for (RepDev& d : ctx->h_ereps) d.macro_dt = macro_dt;
+  if (ctx->kinetic)
+    note(hipMemcpyAsync(ctx->d_ereps, ctx->h_ereps.data(), sizeof(RepDev) * ctx->R,
+                        hipMemcpyHostToDevice, ctx->stream));
   // kernels (and captured graphs) read the descriptors on the device when they run,
   // so the new step takes effect for the work enqueued after this call
   note(hipMemcpyAsync(ctx->d_reps, ctx->h_reps.data(), sizeof(RepDev) * ctx->R,

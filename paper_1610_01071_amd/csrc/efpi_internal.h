@@ -67,7 +67,14 @@ struct RepDev {
   int32_t* cell_of_rank; // [N] occupied cells in order
   int32_t* block_rank;   // [N_c + 1] first occupied-cell rank of every block
   int64_t* aux;          // [4] per-replica scratch: [0] absorbed ions of a sort, [1] lift rotation
+  // species of the store above: charge-to-mass ratio (1 for ions).  The
+  // electron descriptor of a kinetic replica is a copy of the ion one with the
+  // electron store, count, profile, rank arrays, aux, ppc, vth, capacity and qm.
+  double qm;
 };
+
+// Rotation of the electron quiet start relative to the ions' of the same lift.
+constexpr uint32_t kElectronShiftXor = 0x9E3779B9u;
 
 // Kernel flags of the particle pass.
 enum : int {
@@ -92,6 +99,19 @@ void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
                    int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
                    uint32_t* d_status, hipStream_t stream);
 void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream);
+// Kinetic electrons (electrons.hip, field.hip).  d_ereps: electron descriptors.
+// Push (gather, leapfrog with R.qm, periodic wrap) and deposit -charge into
+// R.q[qsel]; with push == 0 only the deposit of the current positions.
+void launch_electrons(const RepDev* d_ereps, int n_reps, int push, int fresh, int qsel,
+                      int max_nodes, hipStream_t stream);
+// Linear periodic Poisson solve of every replica from R.q[qsel]: phi, E (and E_n
+// with save_en), the other charge buffer cleared, the snapshot bins with zero_bins.
+void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
+                    uint32_t* d_status, hipStream_t stream);
+// Electron loading profile of every replica: density exp(phi), mean velocity the
+// ions' fine profile u, and the rotation (ion rotation XOR kElectronShiftXor).
+void launch_electron_profile(const RepDev* d_reps, const RepDev* d_ereps, int n_reps,
+                             hipStream_t stream);
 void launch_set_profile(const RepDev* d_reps, int rep, const double* d_n, const double* d_u,
                         hipStream_t stream);
 // Fine profile and occupied-cell ranks of every replica before a lift; with

@@ -491,7 +491,160 @@ __global__ void k_prep_burst(const RepDev* __restrict__ reps) {
   for (int k = threadIdx.x; k < nb; k += blockDim.x) rb[k] = 0;
 }
 
+// ---------------------------------------------------------- linear Poisson --
+// Periodic -phi'' = rho - mean(rho) (eq. 2.2) for the kinetic-electron closure,
+// solved exactly by two prefix sums: with S_k = sum_{j<=k} (rho_j - mean) and
+// g_k = phi_{k+1} - phi_k, the second difference gives g_k = c - h^2 S_k, where
+// periodicity (sum_k g_k = 0) fixes c = h^2 mean(S); phi_k = sum_{j<k} g_j, then
+// the mean of phi is removed.  One workgroup per replica, each thread owning M
+// consecutive nodes; every sum runs in a fixed order (reproducible bits).
+constexpr int kPThreads = 1024;
+constexpr int kPMaxM = 8;  // n_cells <= 8192
+
+// Exclusive scan of x over the workgroup (thread order) and the total.
+__device__ double block_excl_scan(double x, double* s_w, double& total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  double inc = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  double ex = __shfl_up(inc, 1, kWave);
+  if (lane == 0) ex = 0.0;
+  if (lane == kWave - 1) s_w[wid] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int k = 0; k < kPThreads / kWave; ++k) {
+      const double t = s_w[k];
+      s_w[k] = run;
+      run += t;
+    }
+    s_w[kPThreads / kWave] = run;
+  }
+  __syncthreads();
+  const double out = s_w[wid] + ex;
+  total = s_w[kPThreads / kWave];
+  __syncthreads();  // s_w is reused by the next scan
+  return out;
+}
+
+__global__ __launch_bounds__(kPThreads) void k_poisson(const RepDev* __restrict__ reps, int qsel,
+                                                      int save_en, int zero_bins,
+                                                      uint32_t* __restrict__ status) {
+  __shared__ double s_w[kPThreads / kWave + 1];
+  __shared__ double s_first[kPThreads], s_last[kPThreads];
+  __shared__ int s_bad;
+  const RepDev& R = reps[blockIdx.x];
+  const int n = R.n_cells;
+  const int M = n > kPThreads ? n / kPThreads : 1;
+  const int T = n / M;
+  const int t = threadIdx.x;
+  const bool act = t < T;
+  const double h = R.h;
+  const double h2 = h * h;
+  const double qscale = kFxInv / h;
+  const auto Q = gmem(reinterpret_cast<const long long*>(R.q[qsel]));
+  if (t == 0) s_bad = 0;
+  double r[kPMaxM];
+  double loc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPMaxM; ++j) {
+    r[j] = (act && j < M) ? (double)Q[t * M + j] * qscale : 0.0;
+    loc += r[j];
+  }
+  double tot;
+  block_excl_scan(loc, s_w, tot);
+  const double mean = tot / n;
+  loc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPMaxM; ++j) {
+    r[j] = (act && j < M) ? r[j] - mean : 0.0;
+    loc += r[j];
+  }
+  double run = block_excl_scan(loc, s_w, tot);
+  double ssum = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPMaxM; ++j) {
+    run += r[j];
+    r[j] = run;  // S_k
+    if (j < M) ssum += run;
+  }
+  if (!act) ssum = 0.0;
+  double stot;
+  block_excl_scan(ssum, s_w, stot);
+  const double c = h2 * (stot / n);
+  loc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPMaxM; ++j) {
+    r[j] = (act && j < M) ? c - h2 * r[j] : 0.0;  // g_k
+    loc += r[j];
+  }
+  run = block_excl_scan(loc, s_w, tot);
+  double psum = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPMaxM; ++j) {
+    const double g = r[j];
+    r[j] = run;  // phi_k = sum_{j<k} g_j
+    run += g;
+    if (j < M) psum += r[j];
+  }
+  if (!act) psum = 0.0;
+  double ptot;
+  block_excl_scan(psum, s_w, ptot);
+  const double pmean = ptot / n;
+#pragma unroll
+  for (int j = 0; j < kPMaxM; ++j) r[j] -= pmean;
+  if (act) {
+    s_first[t] = r[0];
+    s_last[t] = r[M - 1];
+  }
+  __syncthreads();
+  const auto phig = gmem(R.phi);
+  const auto eg = gmem(R.e);
+  const auto eng = gmem(R.en);
+  if (act) {
+    const double pl = s_last[t > 0 ? t - 1 : T - 1];
+    const double pr = s_first[t < T - 1 ? t + 1 : 0];
+    const double inv2h = 0.5 / h;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < kPMaxM; ++j) {
+      if (j < M) {
+        const int k = t * M + j;
+        const double left = j > 0 ? r[j - 1] : pl;
+        const double right = j < M - 1 ? r[j + 1] : pr;
+        const float ev = (float)(-(right - left) * inv2h);
+        phig[k] = r[j];
+        eg[k] = ev;
+        if (save_en) eng[k] = ev;
+        bad |= !(fabs(r[j]) < 1e300);
+      }
+    }
+    if (bad) s_bad = 1;
+  }
+  // clear the next deposit buffer and, at a burst start, the snapshot bins
+  const auto other = gmem(reinterpret_cast<long long*>(R.q[qsel ^ 1]));
+  for (int k = t; k < R.n_nodes; k += kPThreads) other[k] = 0;
+  if (zero_bins) {
+    const int nb = (R.burst_steps + 1) * 2 * R.n_coarse;
+    const auto bins = gmem(reinterpret_cast<long long*>(R.rbins));
+    for (int k = t; k < nb; k += kPThreads) bins[k] = 0;
+  }
+  __syncthreads();
+  if (t == 0 && s_bad) atomicOr(status, 2u);
+}
+
 }  // namespace
+
+void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
+                    uint32_t* d_status, hipStream_t stream) {
+  if (n_reps <= 0) return;
+  hipLaunchKernelGGL(k_poisson, dim3(n_reps), dim3(kPThreads), 0, stream, d_reps, qsel, save_en,
+                     zero_bins, d_status);
+}
 
 void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
                    int iters, int cold, int qsel, int save_en, int zero_bins, double tol,

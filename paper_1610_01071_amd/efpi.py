@@ -17,9 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # EFPI_LIBRARY may name another build of the same library (e.g. to compare builds).
 LIB_PATH = os.environ.get("EFPI_LIBRARY") or os.path.join(HERE, "libefpi.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 BC_PERIODIC, BC_WALLS = 0, 1
-CLOSURE_BOLTZMANN, CLOSURE_NOFIELD = 0, 2
+CLOSURE_BOLTZMANN, CLOSURE_KINETIC, CLOSURE_NOFIELD = 0, 1, 2
 FLAG_SORT_BUFFER = 1
 DEV_NEWTON, DEV_NAN, DEV_OVERFLOW, DEV_NEGMASS = 1, 2, 4, 8
 
@@ -49,6 +49,11 @@ class Replica(ctypes.Structure):
         ("macro_dt", ctypes.c_double),
         ("n_floor", ctypes.c_double),
         ("capacity", ctypes.c_int64),
+        ("qm_e", ctypes.c_double),
+        ("vth_e", ctypes.c_double),
+        ("ppc_e", ctypes.c_int32),
+        ("pad_e", ctypes.c_int32),
+        ("capacity_e", ctypes.c_int64),
     ]
 
 
@@ -91,6 +96,10 @@ def _load():
         "efpi_get_grid": [P, I32, P, P, P],
         "efpi_set_potential": [P, I32, P],
         "efpi_load_profile": [P, I32, P, P, U32],
+        "efpi_set_electrons": [P, I32, P, P, P, P, I64],
+        "efpi_get_electrons": [P, I32, P, P, P, P, ctypes.POINTER(I64)],
+        "efpi_load_electrons": [P, I32, P, P, U32],
+        "efpi_boltzmann_electrons": [P, ctypes.POINTER(U32)],
         "efpi_lift": [P, P, ctypes.POINTER(U32)],
         "efpi_deposit": [P],
         "efpi_solve_field": [P, I32, I32],
@@ -136,7 +145,8 @@ LIB = _load()
 
 EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream", "efpi_n_coarse",
             "efpi_set_particles", "efpi_get_particles", "efpi_get_grid", "efpi_set_potential",
-            "efpi_load_profile", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
+            "efpi_load_profile", "efpi_set_electrons", "efpi_get_electrons",
+            "efpi_load_electrons", "efpi_boltzmann_electrons", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
             "efpi_restrict", "efpi_project", "efpi_set_macro_dt", "efpi_project2",
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
@@ -183,12 +193,20 @@ class ReplicaSpec:
     macro_dt: float = 20.0
     n_floor: float = 1e-6
     capacity: int = 0
+    # kinetic electrons (closure CLOSURE_KINETIC): q/m = -m_i/m_e, thermal speed,
+    # electrons per occupied cell and slots (0: n_cells * ppc_e)
+    qm_e: float = -1836.0
+    vth_e: float = 42.8485705712571
+    ppc_e: int = 100
+    capacity_e: int = 0
 
     def to_c(self) -> Replica:
         cap = self.capacity if self.capacity > 0 else self.n_cells * self.ppc
+        cap_e = self.capacity_e if self.capacity_e > 0 else self.n_cells * self.ppc_e
         return Replica(self.n_cells, self.bc, self.closure, self.ppc, self.haar_levels,
                        self.burst_steps, self.coevolving, self.lift_linear, self.length, self.vth,
-                       self.dt, self.macro_dt, self.n_floor, cap)
+                       self.dt, self.macro_dt, self.n_floor, cap, self.qm_e, self.vth_e,
+                       self.ppc_e, 0, cap_e)
 
     @property
     def n_coarse(self) -> int:
@@ -258,6 +276,28 @@ def efpi_get_particles(ctx, replica, cell=None, frac=None, v=None, w=None) -> in
     _check(LIB.efpi_get_particles(ctx, replica, _dev(cell, torch.int16), _dev(frac, torch.float32),
                                   _dev(v, torch.float32), _dev(w, torch.float32), ctypes.byref(n)))
     return n.value
+
+
+def efpi_set_electrons(ctx, replica, cell, frac, v, w):
+    n = cell.numel()
+    _check(LIB.efpi_set_electrons(ctx, replica, _dev(cell, torch.int16), _dev(frac, torch.float32),
+                                  _dev(v, torch.float32), _dev(w, torch.float32), n))
+
+
+def efpi_get_electrons(ctx, replica, cell=None, frac=None, v=None, w=None) -> int:
+    n = ctypes.c_int64(0)
+    _check(LIB.efpi_get_electrons(ctx, replica, _dev(cell, torch.int16), _dev(frac, torch.float32),
+                                  _dev(v, torch.float32), _dev(w, torch.float32), ctypes.byref(n)))
+    return n.value
+
+
+def efpi_load_electrons(ctx, replica, n, u, shift: int):
+    _check(LIB.efpi_load_electrons(ctx, replica, _dev(n, torch.float64), _dev(u, torch.float64),
+                                   int(shift) & 0xFFFFFFFF))
+
+
+def efpi_boltzmann_electrons(ctx, shifts):
+    _check(LIB.efpi_boltzmann_electrons(ctx, _shift_array(shifts)))
 
 
 def efpi_get_grid(ctx, replica, q=None, phi=None, e=None):
@@ -495,6 +535,15 @@ class Context:
         v = torch.empty(cap, dtype=torch.float32, device=self.device)
         w = torch.empty(cap, dtype=torch.float32, device=self.device)
         n = efpi_get_particles(self.ctx, replica, cell, frac, v, w)
+        return cell[:n], frac[:n], v[:n], w[:n]
+
+    def electrons(self, replica=0):
+        cap = self.cfg.replicas[replica].capacity_e
+        cell = torch.empty(cap, dtype=torch.int16, device=self.device)
+        frac = torch.empty(cap, dtype=torch.float32, device=self.device)
+        v = torch.empty(cap, dtype=torch.float32, device=self.device)
+        w = torch.empty(cap, dtype=torch.float32, device=self.device)
+        n = efpi_get_electrons(self.ctx, replica, cell, frac, v, w)
         return cell[:n], frac[:n], v[:n], w[:n]
 
     def grid(self, replica=0):

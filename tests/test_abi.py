@@ -26,9 +26,12 @@ def test_library_exports_every_declared_symbol():
 def test_binding_struct_layout_matches_header():
     import ctypes
     import paper_1610_01071_amd.efpi as E
-    # efpi_replica: 8 int32, 5 double, 1 int64 -> 8*4 + 5*8 + 8 = 80 bytes
-    assert ctypes.sizeof(E.Replica) == 80
+    # efpi_replica: 8 int32, 5 double, 1 int64, then the electron fields
+    # 2 double, 2 int32, 1 int64 -> 80 + 32 = 112 bytes
+    assert ctypes.sizeof(E.Replica) == 112
     assert E.Replica.length.offset == 32 and E.Replica.capacity.offset == 72
+    assert E.Replica.qm_e.offset == 80 and E.Replica.ppc_e.offset == 96
+    assert E.Replica.capacity_e.offset == 104
     # efpi_config: 2 uint32, pointer, 2 int32, double, 2 int32, uint32 (+ padding)
     assert E.Config.replicas.offset == 8 and E.Config.newton_tol.offset == 24
 
@@ -40,7 +43,7 @@ def test_binding_struct_layout_matches_header():
     ("dt", 0.0, "dt"),
     ("macro_dt", 0.5, "macro_dt"),
     ("ppc", 0, "ppc"),
-    ("closure", 1, "closure"),
+    ("closure", 3, "closure"),
     ("capacity", -5, "capacity"),
 ])
 def test_config_validation(field, value, msg):
@@ -51,6 +54,44 @@ def test_config_validation(field, value, msg):
     with pytest.raises(E.EfpiError) as ei:
         E.efpi_workspace_size(cfg)
     assert ei.value.status == -1 and msg in str(ei.value)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("bc", 1, "periodic"),
+    ("n_cells", 16384, "8192"),
+    ("qm_e", 1.0, "qm_e"),
+    ("vth_e", -1.0, "vth_e"),
+    ("ppc_e", 0, "ppc_e"),
+    ("pad_e", 3, "pad_e"),
+    ("capacity_e", 0, "capacity_e"),
+])
+def test_kinetic_config_validation(field, value, msg):
+    import paper_1610_01071_amd.efpi as E
+    spec = E.ReplicaSpec(1024, 1024.0, ppc=10, closure=E.CLOSURE_KINETIC, ppc_e=10)
+    cfg = E.ConfigSpec([spec]).to_c()
+    E.efpi_workspace_size(cfg)
+    setattr(cfg.replicas[0], field, value)
+    with pytest.raises(E.EfpiError) as ei:
+        E.efpi_workspace_size(cfg)
+    assert ei.value.status == -1 and msg in str(ei.value)
+
+
+def test_kinetic_replicas_not_mixed():
+    import paper_1610_01071_amd.efpi as E
+    specs = [E.ReplicaSpec(256, 256.0, ppc=10, closure=E.CLOSURE_KINETIC, ppc_e=10),
+             E.ReplicaSpec(256, 256.0, ppc=10)]
+    with pytest.raises(E.EfpiError) as ei:
+        E.efpi_workspace_size(E.ConfigSpec(specs).to_c())
+    assert "every replica" in str(ei.value)
+
+
+def test_kinetic_workspace_holds_the_electron_store():
+    import paper_1610_01071_amd.efpi as E
+    a = E.efpi_workspace_size(E.ConfigSpec([E.ReplicaSpec(4096, 4096.0, ppc=100)]).to_c())
+    b = E.efpi_workspace_size(E.ConfigSpec([E.ReplicaSpec(
+        4096, 4096.0, ppc=100, closure=E.CLOSURE_KINETIC, ppc_e=300)]).to_c())
+    # 14 bytes per electron slot plus the electron loading arrays (< 200 KB here)
+    assert 14 * 4096 * 300 < b - a < 14 * 4096 * 300 + 200_000
 
 
 def test_workspace_size_scales_with_capacity():
