@@ -15,7 +15,8 @@ the macro-step wall time, lift included), the roofline of the dominant kernel
 (the fused push/deposit/restrict particle pass, timed by HIP events inside the
 timed region), the EFPI speedup over full PIC for the same physical time with
 the coarse-density error between them (eq. 4.2), forward-Euler, second-order
-and adaptive projective runs against the same full-PIC reference, the learned projection
+and adaptive projective runs against the same full-PIC reference, the same wave
+with kinetic electrons (full two-species PIC against EFPI), the learned projection
 against plain EFPI (wall time and error at the same physical time), and the
 CPU oracle timed on a bounded sample of the same workload on this host.
 """
@@ -155,6 +156,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-slab", action="store_true")
+    ap.add_argument("--no-kinetic", action="store_true",
+                    help="skip the kinetic-electron fine solver and its EFPI runs")
+    ap.add_argument("--kinetic-horizon", type=float, default=60.0,
+                    help="physical time of the kinetic-electron comparison")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the Euler / second-order / adaptive projective runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -307,6 +312,8 @@ def run_bench(args, np, torch, synth, E):
 
     if not args.no_speedup:
         out.update(speedup_sweep(E, torch, np, synth, ctx, spec, c0, args))
+    if not args.no_kinetic:
+        out["kinetic"] = kinetic_leg(E, torch, np, synth, c0, args)
     if not args.no_slab:
         out["slab"] = slab_leg(E, torch, np, synth, args)
     if not args.no_ensemble:
@@ -464,6 +471,84 @@ def projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args):
         "adaptive_best": ({k: ba[k] for k in ("order", "tol", "macro_steps", "eps_density")}
                           if ba else None),
         "runs": rows,
+    }
+
+
+def kinetic_spec(E, macro_dt=7.5, burst=60):
+    """The benchmark IAW with kinetic electrons: m_i / m_e = 1836, T_e = 1 (thermal
+    speed sqrt(1836)), 1000 electrons per cell, dt = 0.25 / omega_pe."""
+    mu = 1836.0
+    return E.ReplicaSpec(n_cells=4096, length=4096.0, ppc=1000, haar_levels=4, burst_steps=burst,
+                         macro_dt=macro_dt, dt=0.25 / math.sqrt(mu), vth=math.sqrt(0.1),
+                         coevolving=1, lift_linear=1, closure=E.CLOSURE_KINETIC, qm_e=-mu,
+                         vth_e=math.sqrt(mu), ppc_e=1000)
+
+
+def kinetic_leg(E, torch, np, synth, c0, args):
+    """The ion-acoustic wave with kinetic electrons (the two-species fine solver
+    of Sec. 2 and 4.1): 4,096,000 ions and 4,096,000 electrons, linear Poisson.
+    Full PIC (both species sorted by cell every 200 steps: at dt = 0.25 / omega_pe a
+    thermal electron crosses a quarter cell per step, and an unsorted electron store
+    spreads every workgroup's deposit over the whole grid) over the horizon from the lifted start
+    (ions and Boltzmann electrons) against EFPI macro steps of N_e = 60 fine
+    steps and Delta t in {2, 4, 5, 7.5, 10}, eps (eq. 4.2) on the coarse ion density."""
+    sp = kinetic_spec(E)
+    n_ions = sp.n_cells * sp.ppc
+    n_el = sp.n_cells * sp.ppc_e
+    fine = int(round(args.kinetic_horizon / sp.dt))
+    shift0 = synth.lift_shift(30_000)
+    pctx = E.Context(E.ConfigSpec([sp], newton_iters=2, newton_iters_start=8, tile=PIC_TILE,
+                                  flags=E.FLAG_SORT_BUFFER))
+
+    def pic_run():
+        E.efpi_lift(pctx.ctx, c0, [shift0])
+        done = 0
+        while done < fine:
+            k = min(200, fine - done)
+            E.efpi_pic_burst(pctx.ctx, k, False)
+            done += k
+            if done < fine:
+                E.efpi_sort(pctx.ctx)
+
+    t_pic = timed(torch, pic_run)
+    c_pic = pctx.new_coarse()
+    E.efpi_restrict_state(pctx.ctx, c_pic)
+    pic_bits = E.efpi_sync(pctx.ctx, raise_on_error=False)
+    pctx.close()
+    ref = c_pic.view(2, -1)[0].cpu().numpy()
+    rows = []
+    for macro_dt in (2.0, 4.0, 5.0, 7.5, 10.0):
+        spm = kinetic_spec(E, macro_dt=macro_dt)
+        cx = E.Context(E.ConfigSpec([spm], newton_iters=2, newton_iters_start=8, tile=TILE))
+        m = int(round(args.kinetic_horizon / macro_dt))
+        a, b = cx.new_coarse(), cx.new_coarse()
+        a.copy_(c0)
+        state = {"a": a, "b": b}
+
+        def efpi_run():
+            for i in range(m):
+                sh = shift0 if i == 0 else synth.lift_shift(30_000 + i)
+                E.efpi_macro_step(cx.ctx, state["a"], state["b"], [sh])
+                state["a"], state["b"] = state["b"], state["a"]
+
+        t_efpi = timed(torch, efpi_run)
+        bits = E.efpi_sync(cx.ctx, raise_on_error=False)
+        got = state["a"].view(2, -1)[0].cpu().numpy()
+        eps = float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(got * got + ref * ref)))
+        rows.append({"macro_dt": macro_dt, "macro_dt_over_dt": round(macro_dt / sp.dt, 1),
+                     "macro_steps": m, "time": m * macro_dt, "efpi_ms": t_efpi,
+                     "speedup": t_pic / t_efpi, "eps_density": eps, "device_status": bits})
+        cx.close()
+    ok = [r for r in rows if r["eps_density"] <= args.eps_max]
+    best = max(ok, key=lambda r: r["speedup"]) if ok else None
+    return {
+        "ions": n_ions, "electrons": n_el, "mass_ratio": -sp.qm_e, "dt": sp.dt,
+        "burst_steps": sp.burst_steps, "horizon": args.kinetic_horizon, "pic_fine_steps": fine,
+        "pic_ms": t_pic, "pic_ms_per_step": t_pic / fine,
+        "pic_particle_updates_per_s": (n_ions + n_el) * fine / (t_pic * 1e-3),
+        "pic_device_status": pic_bits,
+        "efpi_speedup_vs_pic": best["speedup"] if best else None,
+        "sweep": rows,
     }
 
 

@@ -76,6 +76,9 @@ struct efpi_ctx {
   int max_nodes = 0;                // largest node count of the replicas
   std::vector<RepDev> h_ereps;      // electron descriptors (kinetic contexts)
   RepDev* d_ereps = nullptr;
+  int64_t* d_eitem_prefix = nullptr;  // electron work items (sort) per replica
+  std::vector<int64_t> h_eitem_prefix;
+  int64_t total_eitems = 0;
   double* d_snap = nullptr;
   double* d_coarse = nullptr;
   int32_t* d_sort_hist = nullptr;
@@ -206,6 +209,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
   uint8_t* p_nreps = take(sizeof(RepDev) * R);
   const bool kinetic = cfg->replicas[0].closure == EFPI_CLOSURE_KINETIC;
   uint8_t* p_ereps = kinetic ? take(sizeof(RepDev) * R) : nullptr;
+  uint8_t* p_eitems = kinetic ? take(sizeof(int64_t) * (R + 1)) : nullptr;
   int64_t snap_total = 0, coarse_total = 0;
   for (int r = 0; r < R; ++r) {
     const efpi_replica& p = cfg->replicas[r];
@@ -220,8 +224,13 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
   if (cfg->flags & EFPI_FLAG_SORT_BUFFER) {
     const int tile = cfg->tile > 0 ? cfg->tile : kDefaultTile;
     int64_t items = 0;
-    for (int r = 0; r < R; ++r) items += (cfg->replicas[r].capacity + tile - 1) / tile;
-    p_hist = take(sizeof(int32_t) * 256 * items);
+    int64_t eitems = 0;
+    for (int r = 0; r < R; ++r) {
+      items += (cfg->replicas[r].capacity + tile - 1) / tile;
+      if (kinetic) eitems += (cfg->replicas[r].capacity_e + tile - 1) / tile;
+    }
+    // the electron sort runs after the ion sort and reuses the histograms
+    p_hist = take(sizeof(int32_t) * 256 * std::max(items, eitems));
     p_base = take(sizeof(int64_t) * 256 * R);
   }
   if (ctx) {
@@ -242,6 +251,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     ctx->h_reps.assign(R, RepDev{});
     ctx->kinetic = kinetic;
     ctx->d_ereps = reinterpret_cast<RepDev*>(p_ereps);
+    ctx->d_eitem_prefix = reinterpret_cast<int64_t*>(p_eitems);
     if (kinetic) ctx->h_ereps.assign(R, RepDev{});
   }
   int64_t soff = 0, coff = 0;
@@ -278,12 +288,19 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     // electron store and loading arrays of a kinetic replica
     uint8_t *ecell = nullptr, *efrac = nullptr, *ev = nullptr, *ew = nullptr, *enp = nullptr;
     uint8_t *epn = nullptr, *epu = nullptr, *ecor = nullptr, *ebr = nullptr, *eaux = nullptr;
+    uint8_t *ecell2 = nullptr, *efrac2 = nullptr, *ev2 = nullptr, *ew2 = nullptr;
     if (kinetic) {
       const int64_t cap_e = p.capacity_e;
       ecell = take(sizeof(int16_t) * cap_e);
       efrac = take(sizeof(float) * cap_e);
       ev = take(sizeof(float) * cap_e);
       ew = take(sizeof(float) * cap_e);
+      if (sortbuf) {
+        ecell2 = take(sizeof(int16_t) * cap_e);
+        efrac2 = take(sizeof(float) * cap_e);
+        ev2 = take(sizeof(float) * cap_e);
+        ew2 = take(sizeof(float) * cap_e);
+      }
       enp = take(sizeof(int64_t));
       epn = take(sizeof(double) * (nn + 1));
       epu = take(sizeof(double) * (nn + 1));
@@ -346,10 +363,10 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
         el.frac = reinterpret_cast<float*>(efrac);
         el.v = reinterpret_cast<float*>(ev);
         el.w = reinterpret_cast<float*>(ew);
-        el.cell2 = nullptr;
-        el.frac2 = nullptr;
-        el.v2 = nullptr;
-        el.w2 = nullptr;
+        el.cell2 = reinterpret_cast<int16_t*>(ecell2);
+        el.frac2 = reinterpret_cast<float*>(efrac2);
+        el.v2 = reinterpret_cast<float*>(ev2);
+        el.w2 = reinterpret_cast<float*>(ew2);
         el.np = reinterpret_cast<int64_t*>(enp);
         el.prof_n = reinterpret_cast<double*>(epn);
         el.prof_u = reinterpret_cast<double*>(epu);
@@ -563,6 +580,17 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
     co += 2 * d.n_coarse;
   }
   c->total_items = c->h_item_prefix[c->R];
+  if (c->kinetic) {
+    c->h_eitem_prefix.assign(c->R + 1, 0);
+    for (int r = 0; r < c->R; ++r) {
+      RepDev& el = c->h_ereps[r];
+      // the lift finds a replica's coarse blocks by the ions' block numbering
+      el.block_begin = c->h_reps[r].block_begin;
+      el.item_begin = c->h_eitem_prefix[r];
+      c->h_eitem_prefix[r + 1] = c->h_eitem_prefix[r] + (el.capacity + c->tile - 1) / c->tile;
+    }
+    c->total_eitems = c->h_eitem_prefix[c->R];
+  }
   c->total_blocks = c->h_block_prefix[c->R];
   c->grid_blocks = cfg->grid_blocks > 0 ? cfg->grid_blocks : kDefaultGrid;
   // ensemble groups: replicas with equal (n_cells, length) share the first one's index
@@ -612,9 +640,12 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
   note(hipMemcpyAsync(c->d_group, c->h_group.data(), sizeof(int32_t) * c->R, hipMemcpyHostToDevice,
                  c->stream));
   for (int r = 0; r < c->R; ++r) c->max_nodes = std::max(c->max_nodes, c->h_reps[r].n_nodes);
-  if (c->kinetic)
+  if (c->kinetic) {
     note(hipMemcpyAsync(c->d_ereps, c->h_ereps.data(), sizeof(RepDev) * c->R,
                         hipMemcpyHostToDevice, c->stream));
+    note(hipMemcpyAsync(c->d_eitem_prefix, c->h_eitem_prefix.data(), sizeof(int64_t) * (c->R + 1),
+                        hipMemcpyHostToDevice, c->stream));
+  }
   c->h_newton_reps.clear();
   for (int32_t r : c->h_newton_list) c->h_newton_reps.push_back(c->h_reps[r]);
   note(hipMemcpyAsync(c->d_newton_reps, c->h_newton_reps.data(), sizeof(RepDev) * c->R,
@@ -944,6 +975,9 @@ efpi_status efpi_sort(efpi_ctx* ctx) {
     return fail(EFPI_ESTATE, "efpi_sort needs EFPI_FLAG_SORT_BUFFER at init");
   launch_sort(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
               ctx->d_sort_hist, ctx->d_sort_base, ctx->grid_blocks, ctx->stream);
+  if (ctx->kinetic)
+    launch_sort(ctx->d_ereps, ctx->d_eitem_prefix, ctx->R, ctx->total_eitems, ctx->tile,
+                ctx->d_sort_hist, ctx->d_sort_base, ctx->grid_blocks, ctx->stream);
   return hip_check("sort");
 }
 

@@ -268,3 +268,50 @@ def test_kinetic_graph_replays_equal_eager():
             ae, be = be, ae
             ag, bg = bg, ag
         assert E.efpi_sync(cg.ctx, raise_on_error=False) == E.efpi_sync(ce.ctx, raise_on_error=False)
+
+
+def test_two_replica_context_equals_single_contexts():
+    """Replicas of different sizes in one kinetic context (shared launches) give
+    the same bits as each replica alone."""
+    E = lib()
+    specs = [kspec(E, 256, 32, 24, burst_steps=10, macro_dt=1.0, vth=0.316),
+             kspec(E, 512, 20, 16, burst_steps=10, macro_dt=1.0, vth=0.316)]
+    both = make_ctx(specs)
+    starts = [_kinetic_start(E, s, 100 + i) for i, s in enumerate(specs)]
+    cin = to_dev(np.concatenate([c.ravel() for c in starts]), torch.float64)
+    out = both.new_coarse()
+    shifts = [synth.lift_shift(110), synth.lift_shift(111)]
+    E.efpi_macro_step(both.ctx, cin, out, shifts)
+    E.efpi_sync(both.ctx, raise_on_error=False)
+    for r, s in enumerate(specs):
+        one = make_ctx([s])
+        o1 = one.new_coarse()
+        E.efpi_macro_step(one.ctx, to_dev(starts[r].ravel(), torch.float64), o1, [shifts[r]])
+        E.efpi_sync(one.ctx, raise_on_error=False)
+        assert torch.equal(both.split_coarse(out)[r].reshape(-1), o1), f"replica {r}"
+
+
+def test_sort_orders_electrons_and_keeps_the_dynamics():
+    E = lib()
+    n, ppc = 256, 24
+    spec = kspec(E, n, ppc, ppc, haar_levels=2)
+    ctxs = [make_ctx([spec], flags=E.FLAG_SORT_BUFFER) for _ in range(2)]
+    ions, elec = random_pair(n, ppc, 33)
+    for c in ctxs:
+        set_particles(c, 0, *ions)
+        set_electrons(c, 0, *elec)
+        E.efpi_pic_burst(c.ctx, 30, False)
+    before = electrons_np(ctxs[0])
+    E.efpi_sort(ctxs[0].ctx)
+    after = electrons_np(ctxs[0])
+    assert np.all(np.diff(after[0].astype(np.int64)) >= 0)
+    key = lambda s: np.lexsort((s[3], s[2], s[1], s[0]))
+    for a, b in zip((x[key(before)] for x in before), (x[key(after)] for x in after)):
+        assert np.array_equal(a, b)
+    for c in ctxs:
+        E.efpi_pic_burst(c.ctx, 5, False)
+    qa, pa, _ = grid_np(ctxs[0])
+    qb, pb, _ = grid_np(ctxs[1])
+    assert np.array_equal(qa, qb)
+    for c in ctxs:
+        E.efpi_sync(c.ctx)
