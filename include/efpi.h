@@ -207,7 +207,8 @@ efpi_status efpi_solve_field(efpi_ctx* ctx, int32_t iters, int32_t cold);
  * without kinetic electrons. */
 
 /* Copy n electrons into replica r's electron store (layout of efpi_set_particles;
- * n <= capacity_e).  Marks both species as freshly loaded (integer-time velocities). */
+ * n <= capacity_e).  Their velocities are taken at the current integer time level
+ * (their next push is a half step); the ions are left as they are. */
 efpi_status efpi_set_electrons(efpi_ctx* ctx, int32_t replica, const int16_t* d_cell,
                                const float* d_frac, const float* d_v, const float* d_w,
                                int64_t n);
@@ -218,9 +219,8 @@ efpi_status efpi_get_electrons(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, 
 
 /* Quiet-start electrons of replica r from node profiles d_n (density) and d_u
  * (mean velocity), FP64, N nodes: the loading of efpi_load_profile (App. C) with
- * ppc_e electrons per occupied cell and thermal speed vth_e, rotation `shift`.
- * The ions must be at an integer time level (loaded, lifted or set since the
- * last burst); EFPI_ESTATE otherwise. */
+ * ppc_e electrons per occupied cell and thermal speed vth_e, rotation `shift`,
+ * at the current time level (as efpi_set_electrons). */
 efpi_status efpi_load_electrons(efpi_ctx* ctx, int32_t replica, const double* d_n,
                                 const double* d_u, uint32_t shift);
 
@@ -232,6 +232,18 @@ efpi_status efpi_load_electrons(efpi_ctx* ctx, int32_t replica, const double* d_
  * vth_e and Hammersley rotation h_shifts[r] XOR 0x9E3779B9.  The ions must be at
  * an integer time level (EFPI_ESTATE otherwise). */
 efpi_status efpi_boltzmann_electrons(efpi_ctx* ctx, const uint32_t* h_shifts);
+
+/* Reset the electrons of every replica to the Boltzmann equilibrium of the
+ * current ions, at any point of a run (the control run of Sec. 4.1 that resets
+ * the electrons periodically from the ion density): deposit the ion charge n_i
+ * and the ion momentum with time-centred velocities (v + dt/2 E at the ions
+ * after a burst), solve eq. 3.15 as efpi_boltzmann_electrons, and load
+ * electrons with density exp(phi), mean velocity the ion node momentum over the
+ * ion node charge (0 where the ion density is below n_floor), thermal speed
+ * vth_e and rotation h_shifts[r] XOR 0x9E3779B9.  The ions are not changed; the
+ * electrons start at the current time level (their next push is a half step).
+ * After a burst the field must be current (it is after efpi_pic_burst). */
+efpi_status efpi_reset_electrons(efpi_ctx* ctx, const uint32_t* h_shifts);
 
 /* Fine burst on every replica: `steps` leapfrog steps (gather, push, boundary,
  * fixed-point deposit, Newton solve).  With restrict != 0 the burst starts by

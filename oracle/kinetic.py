@@ -135,6 +135,19 @@ def boltzmann_electrons(x_i, w_i, u_nodes, grid: Grid, el: Electrons, shift: int
     return c, f, v, w, phi
 
 
+def reset_electrons(x_i, vc_i, w_i, grid: Grid, el: Electrons, shift: int, n_floor=1e-6):
+    """Electrons reset to the Boltzmann equilibrium of the current ions (the
+    control run of Sec. 4.1): ion node density and momentum by CIC, mean velocity
+    u = j / n where n > n_floor (else 0), then boltzmann_electrons with that u.
+    vc_i are the ions' time-centred velocities.  Returns (cell, frac, v, w, phi)."""
+    n = pic.deposit_density(x_i, w_i, grid)
+    j = pic.deposit_mass(x_i, w_i * vc_i, grid) / grid.node_volume()
+    u = np.zeros_like(n)
+    ok = n > n_floor
+    u[ok] = j[ok] / n[ok]
+    return boltzmann_electrons(x_i, w_i, u, grid, el, shift, n_floor)
+
+
 # ----------------------------------------------------------------------------
 # The projective cycle with kinetic electrons (Sec. 3.1, App. B)
 # ----------------------------------------------------------------------------

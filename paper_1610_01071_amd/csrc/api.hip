@@ -93,7 +93,8 @@ struct efpi_ctx {
   bool other_zero = true;  // q[cur ^ 1] is known to be zero
   bool deposited = false;  // charge matches the current particles
   bool field_valid = false;
-  bool fresh = true;       // velocities at an integer time level
+  bool fresh = true;       // ion velocities at an integer time level
+  bool fresh_e = true;     // electron velocities at an integer time level (kinetic)
   int last_burst_steps = -1;
   // optional event timing of the burst-step particle launches
   bool timing = false;
@@ -102,11 +103,11 @@ struct efpi_ctx {
   // captured macro steps, keyed by their arguments and the state they start from
   struct HostState {
     int cur;
-    bool other_zero, deposited, field_valid, fresh;
+    bool other_zero, deposited, field_valid, fresh, fresh_e;
     int last_burst_steps;
   };
   HostState state() const {
-    return {cur, other_zero, deposited, field_valid, fresh, last_burst_steps};
+    return {cur, other_zero, deposited, field_valid, fresh, fresh_e, last_burst_steps};
   }
   void set_state(const HostState& s) {
     cur = s.cur;
@@ -114,6 +115,7 @@ struct efpi_ctx {
     deposited = s.deposited;
     field_valid = s.field_valid;
     fresh = s.fresh;
+    fresh_e = s.fresh_e;
     last_burst_steps = s.last_burst_steps;
   }
   struct MacroGraph {
@@ -289,6 +291,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     uint8_t *ecell = nullptr, *efrac = nullptr, *ev = nullptr, *ew = nullptr, *enp = nullptr;
     uint8_t *epn = nullptr, *epu = nullptr, *ecor = nullptr, *ebr = nullptr, *eaux = nullptr;
     uint8_t *ecell2 = nullptr, *efrac2 = nullptr, *ev2 = nullptr, *ew2 = nullptr;
+    uint8_t* jfx = nullptr;
     if (kinetic) {
       const int64_t cap_e = p.capacity_e;
       ecell = take(sizeof(int16_t) * cap_e);
@@ -303,6 +306,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
       }
       enp = take(sizeof(int64_t));
       epn = take(sizeof(double) * (nn + 1));
+      jfx = take(sizeof(int64_t) * (nn + 1));
       epu = take(sizeof(double) * (nn + 1));
       ecor = take(sizeof(int32_t) * n);
       ebr = take(sizeof(int32_t) * (nc + 1));
@@ -352,6 +356,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
       d.block_rank = reinterpret_cast<int32_t*>(br);
       d.aux = reinterpret_cast<int64_t*>(aux);
       d.qm = 1.0;
+      d.jfx = reinterpret_cast<int64_t*>(jfx);
       if (kinetic) {
         RepDev& el = ctx->h_ereps[r];
         el = d;
@@ -448,10 +453,17 @@ void deposit_all(efpi_ctx* c, bool electrons) {
 void load_boltzmann_electrons(efpi_ctx* c) {
   deposit_all(c, false);
   run_newton(c, c->cfg.newton_iters_start, 1, 0, 0);
-  launch_electron_profile(c->d_reps, c->d_ereps, c->R, c->stream);
+  launch_electron_profile(c->d_reps, c->d_ereps, c->R, 0, c->cur, c->stream);
   launch_occupancy(c->d_ereps, c->R, -1, c->d_status, c->stream);
   launch_lift_particles(c->d_ereps, c->d_block_prefix, c->R, c->total_blocks, -1, nullptr,
                         c->d_coarse_off, nullptr, c->grid_blocks, c->stream);
+}
+
+// New electrons (kinetic contexts): their first push is a half step.
+void mark_new_electrons(efpi_ctx* c) {
+  c->fresh_e = true;
+  c->field_valid = false;
+  c->deposited = false;
 }
 
 void mark_new_particles(efpi_ctx* c) {
@@ -475,7 +487,10 @@ efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shift
                    h_shifts ? &sh : nullptr, c->stream);
   launch_lift_particles(c->d_reps, c->d_block_prefix, c->R, c->total_blocks, -1, d_coarse,
                         c->d_coarse_off, nullptr, c->grid_blocks, c->stream);
-  if (c->kinetic) load_boltzmann_electrons(c);
+  if (c->kinetic) {
+    load_boltzmann_electrons(c);
+    mark_new_electrons(c);
+  }
   mark_new_particles(c);
   return hip_check("lift");
 }
@@ -517,15 +532,19 @@ efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
                      flags, c->cur ^ 1, c->stream, e0, e1);
     if (push) {
       if (c->kinetic)
-        launch_electrons(c->d_ereps, c->R, 1, (flags & kFresh) ? 1 : 0, c->cur ^ 1, c->max_nodes,
-                         c->stream);
+        launch_electrons(c->d_ereps, c->R, 1, (p == 0 && c->fresh_e) ? 1 : 0, c->cur ^ 1,
+                         c->max_nodes, c->stream);
       c->cur ^= 1;
       c->other_zero = false;
       c->fresh = false;
+      c->fresh_e = false;
       run_field(c, c->cfg.newton_iters, 0, 0, 0);
     }
   }
-  if (steps > 0) c->fresh = false;
+  if (steps > 0) {
+    c->fresh = false;
+    c->fresh_e = false;
+  }
   if (restrict_) c->last_burst_steps = steps;
   return hip_check("pic_burst");
 }
@@ -746,7 +765,7 @@ efpi_status efpi_set_electrons(efpi_ctx* ctx, int32_t replica, const int16_t* d_
   if (n < 0 || n > ctx->h_ereps[replica].capacity) return fail(EFPI_EINVAL, "n out of [0, capacity_e]");
   launch_copy_particles(ctx->d_ereps, replica, d_cell, d_frac, d_v, d_w, n, 1, nullptr, nullptr,
                         nullptr, nullptr, ctx->stream);
-  mark_new_particles(ctx);
+  mark_new_electrons(ctx);
   return hip_check("set_electrons");
 }
 
@@ -770,7 +789,6 @@ efpi_status efpi_load_electrons(efpi_ctx* ctx, int32_t replica, const double* d_
   if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
   if (!ctx->kinetic) return fail(EFPI_ESTATE, "the context has no kinetic electrons");
   if (!d_n || !d_u) return fail(EFPI_EINVAL, "NULL profile");
-  if (!ctx->fresh) return fail(EFPI_ESTATE, "load electrons with the ions at an integer time level");
   launch_set_profile(ctx->d_ereps, replica, d_n, d_u, ctx->stream);
   launch_occupancy(ctx->d_ereps, ctx->R, replica, ctx->d_status, ctx->stream);
   ShiftArg s;
@@ -779,7 +797,7 @@ efpi_status efpi_load_electrons(efpi_ctx* ctx, int32_t replica, const double* d_
   launch_lift_particles(ctx->d_ereps, ctx->d_block_prefix, ctx->R,
                         ctx->h_reps[replica].n_coarse, replica, nullptr, ctx->d_coarse_off, &s,
                         ctx->grid_blocks, ctx->stream);
-  mark_new_particles(ctx);
+  mark_new_electrons(ctx);
   return hip_check("load_electrons");
 }
 
@@ -791,8 +809,30 @@ efpi_status efpi_boltzmann_electrons(efpi_ctx* ctx, const uint32_t* h_shifts) {
   // the ions' rotation slot carries the rotation the electron profile derives from
   launch_set_shifts(ctx->d_reps, ctx->R, -1, shifts_of(ctx, h_shifts), ctx->stream);
   load_boltzmann_electrons(ctx);
-  mark_new_particles(ctx);
+  mark_new_electrons(ctx);
   return hip_check("boltzmann_electrons");
+}
+
+efpi_status efpi_reset_electrons(efpi_ctx* ctx, const uint32_t* h_shifts) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!ctx->kinetic) return fail(EFPI_ESTATE, "the context has no kinetic electrons");
+  if (!h_shifts) return fail(EFPI_EINVAL, "h_shifts is NULL");
+  if (!ctx->fresh && !ctx->field_valid)
+    return fail(EFPI_ESTATE, "reset_electrons after a burst needs the current field");
+  launch_set_shifts(ctx->d_reps, ctx->R, -1, shifts_of(ctx, h_shifts), ctx->stream);
+  // ion momentum with time-centred velocities, from the current field
+  for (int r = 0; r < ctx->R; ++r)
+    launch_fill_u8(ctx->h_reps[r].jfx, sizeof(int64_t) * ctx->h_reps[r].n_nodes, ctx->stream);
+  launch_ion_momentum(ctx->d_reps, ctx->R, ctx->fresh ? 0 : 1, ctx->max_nodes, ctx->stream);
+  // ion charge (kept in q[cur] through the Newton solve), eq. 3.15, profile, load
+  deposit_all(ctx, false);
+  run_newton(ctx, ctx->cfg.newton_iters_start, 1, 0, 0);
+  launch_electron_profile(ctx->d_reps, ctx->d_ereps, ctx->R, 1, ctx->cur, ctx->stream);
+  launch_occupancy(ctx->d_ereps, ctx->R, -1, ctx->d_status, ctx->stream);
+  launch_lift_particles(ctx->d_ereps, ctx->d_block_prefix, ctx->R, ctx->total_blocks, -1, nullptr,
+                        ctx->d_coarse_off, nullptr, ctx->grid_blocks, ctx->stream);
+  mark_new_electrons(ctx);
+  return hip_check("reset_electrons");
 }
 
 efpi_status efpi_lift(efpi_ctx* ctx, const double* d_coarse, const uint32_t* h_shifts) {

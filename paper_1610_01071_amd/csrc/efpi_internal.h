@@ -71,6 +71,7 @@ struct RepDev {
   // electron descriptor of a kinetic replica is a copy of the ion one with the
   // electron store, count, profile, rank arrays, aux, ppc, vth, capacity and qm.
   double qm;
+  int64_t* jfx;          // kinetic ions: fixed-point node momentum of an electron reset
 };
 
 // Rotation of the electron quiet start relative to the ions' of the same lift.
@@ -109,9 +110,15 @@ void launch_electrons(const RepDev* d_ereps, int n_reps, int push, int fresh, in
 void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
                     uint32_t* d_status, hipStream_t stream);
 // Electron loading profile of every replica: density exp(phi), mean velocity the
-// ions' fine profile u, and the rotation (ion rotation XOR kElectronShiftXor).
+// ions' fine profile u (from_moments == 0) or the ion node momentum R.jfx over the
+// ion node charge R.q[qsel] (from_moments != 0), and the rotation (ion rotation
+// XOR kElectronShiftXor).
 void launch_electron_profile(const RepDev* d_reps, const RepDev* d_ereps, int n_reps,
-                             hipStream_t stream);
+                             int from_moments, int qsel, hipStream_t stream);
+// Fixed-point CIC momentum of the ions into R.jfx (cleared first), with
+// velocities v + half_kick dt E at the ion (time-centred after a burst).
+void launch_ion_momentum(const RepDev* d_reps, int n_reps, int half_kick, int max_nodes,
+                         hipStream_t stream);
 void launch_set_profile(const RepDev* d_reps, int rep, const double* d_n, const double* d_u,
                         hipStream_t stream);
 // Fine profile and occupied-cell ranks of every replica before a lift; with

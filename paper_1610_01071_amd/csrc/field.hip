@@ -493,13 +493,15 @@ __global__ void k_prep_burst(const RepDev* __restrict__ reps) {
 
 // ---------------------------------------------------------- linear Poisson --
 // Periodic -phi'' = rho - mean(rho) (eq. 2.2) for the kinetic-electron closure,
-// solved exactly by two prefix sums: with S_k = sum_{j<=k} (rho_j - mean) and
-// g_k = phi_{k+1} - phi_k, the second difference gives g_k = c - h^2 S_k, where
-// periodicity (sum_k g_k = 0) fixes c = h^2 mean(S); phi_k = sum_{j<k} g_j, then
-// the mean of phi is removed.  One workgroup per replica, each thread owning M
-// consecutive nodes; every sum runs in a fixed order (reproducible bits).
-constexpr int kPThreads = 1024;
-constexpr int kPMaxM = 8;  // n_cells <= 8192
+// solved exactly by prefix sums.  With S_k = sum_{j<=k} (rho_j - mean) and
+// g_k = phi_{k+1} - phi_k, the second difference gives g_k = c - h^2 S_k, and
+// periodicity (sum_k g_k = 0) fixes c = h^2 Q_N / N with Q_k = sum_{j<k} S_j.  So
+// phi_k = sum_{j<k} g_j = h^2 (k Q_N / N - Q_k), and the mean of phi is removed.
+// One workgroup per replica, each thread owning M consecutive nodes: two scans
+// (of rho, then of S) and one sum, each in a fixed order (reproducible bits).
+constexpr int kPThreads = 256;
+constexpr int kPWaves = kPThreads / kWave;
+constexpr int kPMaxM = 32;  // n_cells <= 8192
 
 // Exclusive scan of x over the workgroup (thread order) and the total.
 __device__ double block_excl_scan(double x, double* s_w, double& total) {
@@ -515,26 +517,22 @@ __device__ double block_excl_scan(double x, double* s_w, double& total) {
   if (lane == 0) ex = 0.0;
   if (lane == kWave - 1) s_w[wid] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    for (int k = 0; k < kPThreads / kWave; ++k) {
-      const double t = s_w[k];
-      s_w[k] = run;
-      run += t;
-    }
-    s_w[kPThreads / kWave] = run;
+  double before = 0.0, all = 0.0;
+#pragma unroll
+  for (int k = 0; k < kPWaves; ++k) {
+    const double t = s_w[k];
+    if (k < wid) before += t;
+    all += t;
   }
-  __syncthreads();
-  const double out = s_w[wid] + ex;
-  total = s_w[kPThreads / kWave];
+  total = all;
   __syncthreads();  // s_w is reused by the next scan
-  return out;
+  return before + ex;
 }
 
 __global__ __launch_bounds__(kPThreads) void k_poisson(const RepDev* __restrict__ reps, int qsel,
                                                       int save_en, int zero_bins,
                                                       uint32_t* __restrict__ status) {
-  __shared__ double s_w[kPThreads / kWave + 1];
+  __shared__ double s_w[kPWaves];
   __shared__ double s_first[kPThreads], s_last[kPThreads];
   __shared__ int s_bad;
   const RepDev& R = reps[blockIdx.x];
@@ -556,50 +554,40 @@ __global__ __launch_bounds__(kPThreads) void k_poisson(const RepDev* __restrict_
     loc += r[j];
   }
   double tot;
-  block_excl_scan(loc, s_w, tot);
-  const double mean = tot / n;
-  loc = 0.0;
-#pragma unroll
-  for (int j = 0; j < kPMaxM; ++j) {
-    r[j] = (act && j < M) ? r[j] - mean : 0.0;
-    loc += r[j];
-  }
   double run = block_excl_scan(loc, s_w, tot);
-  double ssum = 0.0;
+  const double mean = tot / n;
+  // S_k = (sum_{j<=k} rho_j) - (k + 1) mean
+  loc = 0.0;
 #pragma unroll
   for (int j = 0; j < kPMaxM; ++j) {
     run += r[j];
-    r[j] = run;  // S_k
-    if (j < M) ssum += run;
+    r[j] = (act && j < M) ? run - (double)(t * M + j + 1) * mean : 0.0;
+    loc += r[j];
   }
-  if (!act) ssum = 0.0;
-  double stot;
-  block_excl_scan(ssum, s_w, stot);
-  const double c = h2 * (stot / n);
+  double qn;
+  run = block_excl_scan(loc, s_w, qn);
+  const double cq = qn / n;
+  // phi_k = h^2 (k Q_N / N - Q_k), Q_k the exclusive running sum of S
   loc = 0.0;
 #pragma unroll
   for (int j = 0; j < kPMaxM; ++j) {
-    r[j] = (act && j < M) ? c - h2 * r[j] : 0.0;  // g_k
+    const double sk = r[j];
+    r[j] = (act && j < M) ? h2 * ((double)(t * M + j) * cq - run) : 0.0;
+    run += sk;
     loc += r[j];
   }
-  run = block_excl_scan(loc, s_w, tot);
-  double psum = 0.0;
+  double ptot;
+  block_excl_scan(loc, s_w, ptot);
+  const double pmean = ptot / n;
+  double last = 0.0;
 #pragma unroll
   for (int j = 0; j < kPMaxM; ++j) {
-    const double g = r[j];
-    r[j] = run;  // phi_k = sum_{j<k} g_j
-    run += g;
-    if (j < M) psum += r[j];
+    r[j] -= pmean;
+    if (j == M - 1) last = r[j];  // no dynamic index into r (keeps it in registers)
   }
-  if (!act) psum = 0.0;
-  double ptot;
-  block_excl_scan(psum, s_w, ptot);
-  const double pmean = ptot / n;
-#pragma unroll
-  for (int j = 0; j < kPMaxM; ++j) r[j] -= pmean;
   if (act) {
     s_first[t] = r[0];
-    s_last[t] = r[M - 1];
+    s_last[t] = last;
   }
   __syncthreads();
   const auto phig = gmem(R.phi);

@@ -100,6 +100,7 @@ def _load():
         "efpi_get_electrons": [P, I32, P, P, P, P, ctypes.POINTER(I64)],
         "efpi_load_electrons": [P, I32, P, P, U32],
         "efpi_boltzmann_electrons": [P, ctypes.POINTER(U32)],
+        "efpi_reset_electrons": [P, ctypes.POINTER(U32)],
         "efpi_lift": [P, P, ctypes.POINTER(U32)],
         "efpi_deposit": [P],
         "efpi_solve_field": [P, I32, I32],
@@ -146,7 +147,8 @@ LIB = _load()
 EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream", "efpi_n_coarse",
             "efpi_set_particles", "efpi_get_particles", "efpi_get_grid", "efpi_set_potential",
             "efpi_load_profile", "efpi_set_electrons", "efpi_get_electrons",
-            "efpi_load_electrons", "efpi_boltzmann_electrons", "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
+            "efpi_load_electrons", "efpi_boltzmann_electrons", "efpi_reset_electrons",
+            "efpi_lift", "efpi_deposit", "efpi_solve_field", "efpi_pic_burst",
             "efpi_restrict", "efpi_project", "efpi_set_macro_dt", "efpi_project2",
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
@@ -298,6 +300,10 @@ def efpi_load_electrons(ctx, replica, n, u, shift: int):
 
 def efpi_boltzmann_electrons(ctx, shifts):
     _check(LIB.efpi_boltzmann_electrons(ctx, _shift_array(shifts)))
+
+
+def efpi_reset_electrons(ctx, shifts):
+    _check(LIB.efpi_reset_electrons(ctx, _shift_array(shifts)))
 
 
 def efpi_get_grid(ctx, replica, q=None, phi=None, e=None):

@@ -216,8 +216,11 @@ def test_electron_calls_check_state():
     E.efpi_load_profile(ctx.ctx, 0, ones, z, 3)
     E.efpi_load_electrons(ctx.ctx, 0, ones, z, 4)
     E.efpi_pic_burst(ctx.ctx, 2, False)
-    with pytest.raises(E.EfpiError):      # ions at a half step now
-        E.efpi_load_electrons(ctx.ctx, 0, ones, z, 5)
+    with pytest.raises(E.EfpiError):      # ions at a half step: their lift profile is stale
+        E.efpi_boltzmann_electrons(ctx.ctx, [5])
+    with pytest.raises(E.EfpiError):
+        E.efpi_reset_electrons(plain.ctx, [5])
+    E.efpi_load_electrons(ctx.ctx, 0, ones, z, 5)   # electrons may be replaced at any time
     E.efpi_sync(ctx.ctx)
 
 
@@ -315,3 +318,49 @@ def test_sort_orders_electrons_and_keeps_the_dynamics():
     assert np.array_equal(qa, qb)
     for c in ctxs:
         E.efpi_sync(c.ctx)
+
+
+def test_reset_electrons_matches_oracle_and_restarts_the_leapfrog():
+    """Reset in the middle of a run (the control run of Sec. 4.1): the electrons
+    equal the oracle's reset of the GPU's current ions, the ions are untouched,
+    and the next step kicks the electrons by half a step and the ions by a full one."""
+    E = lib()
+    n, ppc, ppc_e = 256, 48, 40
+    spec = kspec(E, n, ppc, ppc_e)
+    ctx = make_ctx([spec])
+    dens, u = synth.iaw_profile(n, float(n))
+    E.efpi_load_profile(ctx.ctx, 0, to_dev(dens, torch.float64), to_dev(u, torch.float64), 3)
+    E.efpi_boltzmann_electrons(ctx.ctx, [4])
+    E.efpi_pic_burst(ctx.ctx, 7, False)
+    ions = particles_np(ctx)
+    _, _, e_now = grid_np(ctx)
+    E.efpi_reset_electrons(ctx.ctx, [77])
+    E.efpi_sync(ctx.ctx)
+    g = oracle_grid(spec)
+    ci, fi, vi, wi = ions
+    xi = x_of(ci, fi, g.h)
+    vc = vi.astype(np.float64) + 0.5 * g.dt * opic.gather(e_now.astype(np.float64), xi, g)
+    rc, rf, rv, rw, _ = okin.reset_electrons(xi, vc, wi.astype(np.float64), g, el_params(ppc_e),
+                                             okin.electron_shift(77))
+    c, f, v, w = electrons_np(ctx)
+    assert np.array_equal(c, rc) and np.array_equal(f.astype(np.float64), rf)
+    assert relmax(v, rv) < 1e-6 and relmax(w, rw) < 1e-6
+    after = particles_np(ctx)
+    for a, b in zip(ions, after):
+        assert np.array_equal(a, b)
+    # one more step: field of both species at the current positions, ions a full
+    # kick from their half-step velocities, electrons a half kick from integer time
+    E.efpi_pic_burst(ctx.ctx, 1, False)
+    xe = x_of(c, f, g.h)
+    al_i = np.ones(xi.size, bool)
+    al_e = np.ones(xe.size, bool)
+    _, _, e0 = okin.kinetic_field(xi, wi.astype(np.float64), al_i, xe, w.astype(np.float64),
+                                  al_e, g)
+    xi1, vi1, _ = okin.species_step(xi, vi.astype(np.float64), al_i, 1.0, e0, g)
+    xe1, ve1, _ = okin.species_step(xe, v.astype(np.float64), al_e, -MU / 2.0, e0, g)
+    gc, gf, gv, _ = particles_np(ctx)
+    assert relmax(gv, vi1) < 1e-5
+    ec, ef, ev, _ = electrons_np(ctx)
+    assert relmax(ev, ve1) < 1e-5
+    assert np.max(np.abs(periodic_dx(x_of(ec, ef, g.h), xe1, g.length))) < 1e-4
+    E.efpi_sync(ctx.ctx)

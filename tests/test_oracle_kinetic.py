@@ -135,3 +135,27 @@ def test_kinetic_burst_snapshots_are_restrictions_of_the_plain_run():
         vc = vh + 0.5 * g.dt * pic.gather(pic.field(phi, g), xi, g)
         ref = efpi.restrict_state(xi, vc, ions[2], np.ones(xi.size, bool), g, sch)
         assert np.max(np.abs(snaps[p] - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_reset_velocity_profile_is_the_ion_mean_velocity():
+    # Ions drifting as a block at velocity U: the node momentum over the node
+    # density is U exactly wherever there are ions, so the reset electrons carry
+    # mean velocity U (their quiet-start deviates have zero mean per cell pair).
+    n, ppc = 64, 40
+    g = Grid(n, float(n))
+    rng = np.random.default_rng(3)
+    xi = rng.uniform(0, n, n * ppc)
+    wi = rng.uniform(0.5, 1.5, xi.size) / ppc
+    U = 0.37
+    el = Electrons(mu=100.0, vth=10.0, ppc=32)
+    c, f, v, w, phi = kinetic.reset_electrons(xi, np.full(xi.size, U), wi, g, el, 5)
+    right = (c + 1) % n
+    rho = pic.deposit_density(xi, wi, g)
+    j = pic.deposit_mass(xi, wi * U, g) / g.node_volume()
+    assert np.max(np.abs(j / rho - U)) < 1e-14
+    z = (v - U) / el.vth
+    assert abs(np.mean(z)) < 0.01 and abs(np.std(z) - 1.0) < 0.02
+    # electron weights are exp(phi) at the electron, phi solving eq. 3.15 for the ions
+    assert np.max(np.abs(pic.neg_laplacian(g) @ phi + np.exp(phi) - rho)) < 1e-10
+    want = ((1 - f) * np.exp(phi[c]) + f * np.exp(phi[right])) * g.h / el.ppc
+    assert np.max(np.abs(w - want)) < 1e-14
