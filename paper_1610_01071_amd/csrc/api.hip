@@ -425,7 +425,9 @@ void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
 // Field of the current deposit: linear Poisson with kinetic electrons, else Newton.
 void run_field(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
   if (c->kinetic) {
-    launch_poisson(c->d_reps, c->R, c->cur, save_en, zero_bins, c->d_status, c->stream);
+    for (const NewtonGroup& g : c->ngroups)
+      launch_poisson(c->d_newton_reps + g.first, g.count, g.M, g.threads, c->cur, save_en,
+                     zero_bins, c->d_status, c->stream);
     c->other_zero = true;
     c->field_valid = true;
   } else {

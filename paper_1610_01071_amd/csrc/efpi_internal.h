@@ -105,10 +105,12 @@ void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream);
 // R.q[qsel]; with push == 0 only the deposit of the current positions.
 void launch_electrons(const RepDev* d_ereps, int n_reps, int push, int fresh, int qsel,
                       int max_nodes, hipStream_t stream);
-// Linear periodic Poisson solve of every replica from R.q[qsel]: phi, E (and E_n
-// with save_en), the other charge buffer cleared, the snapshot bins with zero_bins.
-void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
-                    uint32_t* d_status, hipStream_t stream);
+// Linear periodic Poisson solve from R.q[qsel] of the replicas in d_reps (one
+// launch group of Newton's shape: M rows per thread, `threads` threads): phi, E
+// (and E_n with save_en), the other charge buffer cleared, the snapshot bins with
+// zero_bins.
+void launch_poisson(const RepDev* d_reps, int n_list, int M, int threads, int qsel, int save_en,
+                    int zero_bins, uint32_t* d_status, hipStream_t stream);
 // Electron loading profile of every replica: density exp(phi), mean velocity the
 // ions' fine profile u (from_moments == 0) or the ion node momentum R.jfx over the
 // ion node charge R.q[qsel] (from_moments != 0), and the rotation (ion rotation

@@ -497,14 +497,15 @@ __global__ void k_prep_burst(const RepDev* __restrict__ reps) {
 // g_k = phi_{k+1} - phi_k, the second difference gives g_k = c - h^2 S_k, and
 // periodicity (sum_k g_k = 0) fixes c = h^2 Q_N / N with Q_k = sum_{j<k} S_j.  So
 // phi_k = sum_{j<k} g_j = h^2 (k Q_N / N - Q_k), and the mean of phi is removed.
-// One workgroup per replica, each thread owning M consecutive nodes: two scans
-// (of rho, then of S) and one sum, each in a fixed order (reproducible bits).
-constexpr int kPThreads = 256;
-constexpr int kPWaves = kPThreads / kWave;
-constexpr int kPMaxM = 32;  // n_cells <= 8192
+// One workgroup per replica, each thread owning M consecutive nodes (M and the
+// workgroup size fixed at compile time, as for Newton, so that a thread's loads
+// are issued together): two scans (of rho, then of S) and one sum, each in a
+// fixed order (reproducible bits).
 
 // Exclusive scan of x over the workgroup (thread order) and the total.
+template <int THREADS>
 __device__ double block_excl_scan(double x, double* s_w, double& total) {
+  constexpr int kW = THREADS / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   double inc = x;
@@ -519,7 +520,7 @@ __device__ double block_excl_scan(double x, double* s_w, double& total) {
   __syncthreads();
   double before = 0.0, all = 0.0;
 #pragma unroll
-  for (int k = 0; k < kPWaves; ++k) {
+  for (int k = 0; k < kW; ++k) {
     const double t = s_w[k];
     if (k < wid) before += t;
     all += t;
@@ -529,97 +530,120 @@ __device__ double block_excl_scan(double x, double* s_w, double& total) {
   return before + ex;
 }
 
-__global__ __launch_bounds__(kPThreads) void k_poisson(const RepDev* __restrict__ reps, int qsel,
-                                                      int save_en, int zero_bins,
-                                                      uint32_t* __restrict__ status) {
-  __shared__ double s_w[kPWaves];
-  __shared__ double s_first[kPThreads], s_last[kPThreads];
+template <int M, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_poisson(const RepDev* __restrict__ reps, int qsel,
+                                                    int save_en, int zero_bins,
+                                                    uint32_t* __restrict__ status) {
+  __shared__ double s_w[THREADS / kWave];
+  __shared__ double s_first[THREADS], s_last[THREADS];
   __shared__ int s_bad;
   const RepDev& R = reps[blockIdx.x];
   const int n = R.n_cells;
-  const int M = n > kPThreads ? n / kPThreads : 1;
   const int T = n / M;
   const int t = threadIdx.x;
   const bool act = t < T;
   const double h = R.h;
   const double h2 = h * h;
   const double qscale = kFxInv / h;
-  const auto Q = gmem(reinterpret_cast<const long long*>(R.q[qsel]));
   if (t == 0) s_bad = 0;
-  double r[kPMaxM];
+  double r[M];
   double loc = 0.0;
+  if (act) {
+    if constexpr (M >= 2) {
+      const auto q2 = gmem(reinterpret_cast<const i64x2*>(R.q[qsel])) + t * (M / 2);
 #pragma unroll
-  for (int j = 0; j < kPMaxM; ++j) {
-    r[j] = (act && j < M) ? (double)Q[t * M + j] * qscale : 0.0;
-    loc += r[j];
+      for (int j = 0; j < M / 2; ++j) {
+        const i64x2 v = q2[j];
+        r[2 * j] = (double)v.x * qscale;
+        r[2 * j + 1] = (double)v.y * qscale;
+      }
+    } else {
+      r[0] = (double)gmem(reinterpret_cast<const long long*>(R.q[qsel]))[t] * qscale;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) r[j] = 0.0;
   }
+#pragma unroll
+  for (int j = 0; j < M; ++j) loc += r[j];
   double tot;
-  double run = block_excl_scan(loc, s_w, tot);
+  double run = block_excl_scan<THREADS>(loc, s_w, tot);
   const double mean = tot / n;
   // S_k = (sum_{j<=k} rho_j) - (k + 1) mean
   loc = 0.0;
 #pragma unroll
-  for (int j = 0; j < kPMaxM; ++j) {
+  for (int j = 0; j < M; ++j) {
     run += r[j];
-    r[j] = (act && j < M) ? run - (double)(t * M + j + 1) * mean : 0.0;
+    r[j] = act ? run - (double)(t * M + j + 1) * mean : 0.0;
     loc += r[j];
   }
   double qn;
-  run = block_excl_scan(loc, s_w, qn);
+  run = block_excl_scan<THREADS>(loc, s_w, qn);
   const double cq = qn / n;
   // phi_k = h^2 (k Q_N / N - Q_k), Q_k the exclusive running sum of S
   loc = 0.0;
 #pragma unroll
-  for (int j = 0; j < kPMaxM; ++j) {
+  for (int j = 0; j < M; ++j) {
     const double sk = r[j];
-    r[j] = (act && j < M) ? h2 * ((double)(t * M + j) * cq - run) : 0.0;
+    r[j] = act ? h2 * ((double)(t * M + j) * cq - run) : 0.0;
     run += sk;
     loc += r[j];
   }
   double ptot;
-  block_excl_scan(loc, s_w, ptot);
+  block_excl_scan<THREADS>(loc, s_w, ptot);
   const double pmean = ptot / n;
-  double last = 0.0;
 #pragma unroll
-  for (int j = 0; j < kPMaxM; ++j) {
-    r[j] -= pmean;
-    if (j == M - 1) last = r[j];  // no dynamic index into r (keeps it in registers)
-  }
+  for (int j = 0; j < M; ++j) r[j] -= pmean;
   if (act) {
     s_first[t] = r[0];
-    s_last[t] = last;
+    s_last[t] = r[M - 1];
   }
   __syncthreads();
-  const auto phig = gmem(R.phi);
-  const auto eg = gmem(R.e);
-  const auto eng = gmem(R.en);
   if (act) {
     const double pl = s_last[t > 0 ? t - 1 : T - 1];
     const double pr = s_first[t < T - 1 ? t + 1 : 0];
     const double inv2h = 0.5 / h;
     bool bad = false;
+    float ev[M];
 #pragma unroll
-    for (int j = 0; j < kPMaxM; ++j) {
-      if (j < M) {
-        const int k = t * M + j;
-        const double left = j > 0 ? r[j - 1] : pl;
-        const double right = j < M - 1 ? r[j + 1] : pr;
-        const float ev = (float)(-(right - left) * inv2h);
-        phig[k] = r[j];
-        eg[k] = ev;
-        if (save_en) eng[k] = ev;
-        bad |= !(fabs(r[j]) < 1e300);
+    for (int j = 0; j < M; ++j) {
+      const double left = j > 0 ? r[j - 1] : pl;
+      const double right = j < M - 1 ? r[j + 1] : pr;
+      ev[j] = (float)(-(right - left) * inv2h);
+      bad |= !(fabs(r[j]) < 1e300);
+    }
+    const auto phig = gmem(R.phi);
+    const auto eg = gmem(R.e);
+    const auto eng = gmem(R.en);
+    if constexpr (M >= 4) {
+      const auto p2 = reinterpret_cast<EFPI_GLOBAL f64x2*>(phig) + t * (M / 2);
+#pragma unroll
+      for (int j = 0; j < M / 2; ++j) p2[j] = f64x2{r[2 * j], r[2 * j + 1]};
+      const auto e4 = reinterpret_cast<EFPI_GLOBAL f32x4*>(eg) + t * (M / 4);
+      const auto n4 = reinterpret_cast<EFPI_GLOBAL f32x4*>(eng) + t * (M / 4);
+#pragma unroll
+      for (int j = 0; j < M / 4; ++j) {
+        const f32x4 v = {ev[4 * j], ev[4 * j + 1], ev[4 * j + 2], ev[4 * j + 3]};
+        e4[j] = v;
+        if (save_en) n4[j] = v;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        phig[t * M + j] = r[j];
+        eg[t * M + j] = ev[j];
+        if (save_en) eng[t * M + j] = ev[j];
       }
     }
     if (bad) s_bad = 1;
   }
   // clear the next deposit buffer and, at a burst start, the snapshot bins
   const auto other = gmem(reinterpret_cast<long long*>(R.q[qsel ^ 1]));
-  for (int k = t; k < R.n_nodes; k += kPThreads) other[k] = 0;
+  for (int k = t; k < R.n_nodes; k += THREADS) other[k] = 0;
   if (zero_bins) {
     const int nb = (R.burst_steps + 1) * 2 * R.n_coarse;
     const auto bins = gmem(reinterpret_cast<long long*>(R.rbins));
-    for (int k = t; k < nb; k += kPThreads) bins[k] = 0;
+    for (int k = t; k < nb; k += THREADS) bins[k] = 0;
   }
   __syncthreads();
   if (t == 0 && s_bad) atomicOr(status, 2u);
@@ -627,11 +651,20 @@ __global__ __launch_bounds__(kPThreads) void k_poisson(const RepDev* __restrict_
 
 }  // namespace
 
-void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
-                    uint32_t* d_status, hipStream_t stream) {
-  if (n_reps <= 0) return;
-  hipLaunchKernelGGL(k_poisson, dim3(n_reps), dim3(kPThreads), 0, stream, d_reps, qsel, save_en,
-                     zero_bins, d_status);
+void launch_poisson(const RepDev* d_reps, int n_list, int M, int threads, int qsel, int save_en,
+                    int zero_bins, uint32_t* d_status, hipStream_t stream) {
+  if (n_list <= 0) return;
+  const dim3 grid(n_list);
+#define EFPI_POISSON(MM, TT)                                                                  \
+  hipLaunchKernelGGL((k_poisson<MM, TT>), grid, dim3(TT), 0, stream, d_reps, qsel, save_en,       \
+                     zero_bins, d_status)
+  if (M == 1) EFPI_POISSON(1, 256);
+  else if (M == 8 && threads > 256) EFPI_POISSON(8, 512);
+  else if (M == 2) EFPI_POISSON(2, 256);
+  else if (M == 4) EFPI_POISSON(4, 256);
+  else if (M == 8) EFPI_POISSON(8, 256);
+  else EFPI_POISSON(16, 512);
+#undef EFPI_POISSON
 }
 
 void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
