@@ -518,6 +518,22 @@ def kinetic_leg(E, torch, np, synth, c0, args):
     pic_bits = E.efpi_sync(pctx.ctx, raise_on_error=False)
     ref = c_pic.view(2, -1)[0].cpu().numpy()
 
+    # live roofline of the electron pass: 200 further steps with every ion and
+    # electron launch bracketed by events (outside the timed comparison above)
+    E.efpi_sort(pctx.ctx)
+    E.efpi_timing(pctx.ctx, True)
+    E.efpi_pic_burst(pctx.ctx, 200, False)
+    el_ms, el_n = E.efpi_timing_read_electrons(pctx.ctx)
+    io_ms, io_n = E.efpi_timing_read(pctx.ctx)
+    E.efpi_timing(pctx.ctx, False)
+    el_us = el_ms * 1e3 / max(el_n, 1)
+    el_bytes = BYTES_PER_UPDATE * n_el
+    el_roofline = {"bound": "hbm", "kernel": "k_electrons (push + deposit)",
+                   "achieved": el_bytes / (el_us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": el_bytes / (el_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                   "bytes_per_launch": el_bytes, "avg_launch_us": el_us, "launches": el_n,
+                   "ion_pass_avg_launch_us": io_ms * 1e3 / max(io_n, 1)}
+
     # the control run of Sec. 4.1: full PIC with the electrons reset to the
     # Boltzmann equilibrium of the ions every 150 steps (the reset loads them in
     # cell order); both species are sorted every 600 steps, as the ions drift out
@@ -603,6 +619,7 @@ def kinetic_leg(E, torch, np, synth, c0, args):
         "pic_ms": t_pic, "pic_ms_per_step": t_pic / fine,
         "pic_particle_updates_per_s": (n_ions + n_el) * fine / (t_pic * 1e-3),
         "pic_device_status": pic_bits,
+        "roofline_electrons": el_roofline,
         "reset_pic_ms": t_reset, "reset_pic_device_status": reset_bits,
         "eps_density_reset_pic_vs_pic": eps_of(ref_reset, ref),
         "efpi_speedup_vs_pic": best["speedup"] if best else None,

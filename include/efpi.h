@@ -433,6 +433,11 @@ efpi_status efpi_timing(efpi_ctx* ctx, int32_t enable);
  * the number of timed launches since the last read or enable, and reset them. */
 efpi_status efpi_timing_read(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launches);
 
+/* As efpi_timing_read for the electron pass of kinetic contexts: with timing
+ * enabled every burst-step electron launch (push and deposit) is bracketed by
+ * its own pair of events as well.  EFPI_ESTATE without kinetic electrons. */
+efpi_status efpi_timing_read_electrons(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launches);
+
 /* Message for the last failed call on this thread ("" when none). */
 const char* efpi_last_error(void);
 

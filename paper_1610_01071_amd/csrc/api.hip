@@ -100,6 +100,8 @@ struct efpi_ctx {
   bool timing = false;
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
+  // event pairs (indices into events) around the timed ion and electron launches
+  std::vector<std::pair<size_t, size_t>> ion_pairs, el_pairs;
   // captured macro steps, keyed by their arguments and the state they start from
   struct HostState {
     int cur;
@@ -529,13 +531,21 @@ efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
     if (c->timing && push) {
       e0 = next_event(c);
       e1 = next_event(c);
+      if (e0 && e1) c->ion_pairs.push_back({c->events_used - 2, c->events_used - 1});
     }
     launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, p,
                      flags, c->cur ^ 1, c->stream, e0, e1);
     if (push) {
-      if (c->kinetic)
+      if (c->kinetic) {
+        hipEvent_t f0 = nullptr, f1 = nullptr;
+        if (c->timing) {
+          f0 = next_event(c);
+          f1 = next_event(c);
+          if (f0 && f1) c->el_pairs.push_back({c->events_used - 2, c->events_used - 1});
+        }
         launch_electrons(c->d_ereps, c->R, 1, (p == 0 && c->fresh_e) ? 1 : 0, c->cur ^ 1,
-                         c->max_nodes, c->stream);
+                         c->max_nodes, c->stream, f0, f1);
+      }
       c->cur ^= 1;
       c->other_zero = false;
       c->fresh = false;
@@ -1044,26 +1054,43 @@ efpi_status efpi_timing(efpi_ctx* ctx, int32_t enable) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   ctx->timing = enable != 0;
   ctx->events_used = 0;
+  ctx->ion_pairs.clear();
+  ctx->el_pairs.clear();
   return EFPI_OK;
 }
 
-efpi_status efpi_timing_read(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launches) {
-  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+namespace {
+// Sum the intervals of the given event pairs and forget them; the event pool is
+// reused once neither list holds pairs.
+efpi_status read_pairs(efpi_ctx* ctx, std::vector<std::pair<size_t, size_t>>& pairs,
+                       double* h_total_ms, int64_t* h_launches) {
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(EFPI_EHIP, std::string("timing_read: ") + hipGetErrorString(e));
   double total = 0.0;
-  int64_t n = 0;
-  for (size_t k = 0; k + 1 < ctx->events_used; k += 2) {
+  for (const auto& pr : pairs) {
     float ms = 0.f;
-    e = hipEventElapsedTime(&ms, ctx->events[k], ctx->events[k + 1]);
+    e = hipEventElapsedTime(&ms, ctx->events[pr.first], ctx->events[pr.second]);
     if (e != hipSuccess) return fail(EFPI_EHIP, std::string("timing_read: ") + hipGetErrorString(e));
     total += ms;
-    ++n;
   }
-  ctx->events_used = 0;
+  const int64_t n = (int64_t)pairs.size();
+  pairs.clear();
+  if (ctx->ion_pairs.empty() && ctx->el_pairs.empty()) ctx->events_used = 0;
   if (h_total_ms) *h_total_ms = total;
   if (h_launches) *h_launches = n;
   return EFPI_OK;
+}
+}  // namespace
+
+efpi_status efpi_timing_read(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launches) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  return read_pairs(ctx, ctx->ion_pairs, h_total_ms, h_launches);
+}
+
+efpi_status efpi_timing_read_electrons(efpi_ctx* ctx, double* h_total_ms, int64_t* h_launches) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!ctx->kinetic) return fail(EFPI_ESTATE, "the context has no kinetic electrons");
+  return read_pairs(ctx, ctx->el_pairs, h_total_ms, h_launches);
 }
 
 // ------------------------------------------------------ learned projection

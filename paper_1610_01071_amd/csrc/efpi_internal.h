@@ -104,7 +104,8 @@ void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream);
 // Push (gather, leapfrog with R.qm, periodic wrap) and deposit -charge into
 // R.q[qsel]; with push == 0 only the deposit of the current positions.
 void launch_electrons(const RepDev* d_ereps, int n_reps, int push, int fresh, int qsel,
-                      int max_nodes, hipStream_t stream);
+                      int max_nodes, hipStream_t stream, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 // Linear periodic Poisson solve from R.q[qsel] of the replicas in d_reps (one
 // launch group of Newton's shape: M rows per thread, `threads` threads): phi, E
 // (and E_n with save_en), the other charge buffer cleared, the snapshot bins with

@@ -8,6 +8,8 @@
 // within a burst.  Every workgroup therefore deposits into a whole-grid LDS
 // histogram of int64 fixed-point charge (LDS atomics are exact and
 // order-independent) and adds its non-zero entries to the global charge once.
+#include <hip/hip_ext.h>
+
 #include "efpi_internal.h"
 
 namespace efpi {
@@ -160,13 +162,16 @@ __global__ void k_electron_profile(const RepDev* __restrict__ reps,
 }  // namespace
 
 void launch_electrons(const RepDev* d_ereps, int n_reps, int push, int fresh, int qsel,
-                      int max_nodes, hipStream_t stream) {
+                      int max_nodes, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
   if (n_reps <= 0 || max_nodes > kEMaxNodes) return;
   // enough workgroups for every chunk of the largest store the host allows;
   // the surplus of a smaller store leaves at once
   const dim3 grid(1024, (unsigned)n_reps);
   const size_t lds = sizeof(long long) * (size_t)max_nodes;
-  if (push)
+  if (push && ev0 && ev1)  // bracketed by the timing events (extended launch)
+    hipExtLaunchKernelGGL(k_electrons<true>, grid, dim3(kEThreads), lds, stream, ev0, ev1, 0,
+                          d_ereps, fresh, qsel);
+  else if (push)
     hipLaunchKernelGGL(k_electrons<true>, grid, dim3(kEThreads), lds, stream, d_ereps, fresh, qsel);
   else
     hipLaunchKernelGGL(k_electrons<false>, grid, dim3(kEThreads), lds, stream, d_ereps, fresh,

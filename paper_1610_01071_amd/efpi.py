@@ -117,6 +117,7 @@ def _load():
         "efpi_sync": [P, ctypes.POINTER(U32)],
         "efpi_timing": [P, I32],
         "efpi_timing_read": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)],
+        "efpi_timing_read_electrons": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)],
         "efpi_nn_workspace_size": [I32, I32, ctypes.POINTER(ctypes.c_size_t)],
         "efpi_nn_pack": [P, P, P],
         "efpi_nn_forward": [P, P, P, P, I32, I32, I32, P, ctypes.c_size_t, P],
@@ -153,7 +154,8 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
             "efpi_restrict_state",
-            "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_last_error",
+            "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_timing_read_electrons",
+            "efpi_last_error",
             "efpi_nn_workspace_size", "efpi_nn_pack", "efpi_nn_forward", "efpi_nn_backward",
             "efpi_nn_mse", "efpi_nn_adam", "efpi_nn_features", "efpi_nn_step", "efpi_rel_l2",
             "efpi_nn_predict_step"]
@@ -396,6 +398,13 @@ def efpi_timing_read(ctx):
     ms = ctypes.c_double(0.0)
     n = ctypes.c_int64(0)
     _check(LIB.efpi_timing_read(ctx, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def efpi_timing_read_electrons(ctx):
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(LIB.efpi_timing_read_electrons(ctx, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
 
 

@@ -364,3 +364,22 @@ def test_reset_electrons_matches_oracle_and_restarts_the_leapfrog():
     assert relmax(ev, ve1) < 1e-5
     assert np.max(np.abs(periodic_dx(x_of(ec, ef, g.h), xe1, g.length))) < 1e-4
     E.efpi_sync(ctx.ctx)
+
+
+def test_timing_counts_ion_and_electron_launches():
+    E = lib()
+    spec = kspec(E, 256, 16, 16, haar_levels=2)
+    ctx = make_ctx([spec])
+    ions, elec = random_pair(256, 16, 12)
+    set_particles(ctx, 0, *ions)
+    set_electrons(ctx, 0, *elec)
+    E.efpi_timing(ctx.ctx, True)
+    E.efpi_pic_burst(ctx.ctx, 5, False)
+    ms_e, n_e = E.efpi_timing_read_electrons(ctx.ctx)
+    ms_i, n_i = E.efpi_timing_read(ctx.ctx)
+    E.efpi_timing(ctx.ctx, False)
+    assert n_e == 5 and n_i == 5 and ms_e > 0.0 and ms_i > 0.0
+    plain = make_ctx([E.ReplicaSpec(64, 64.0, ppc=4)])
+    with pytest.raises(E.EfpiError):
+        E.efpi_timing_read_electrons(plain.ctx)
+    E.efpi_sync(ctx.ctx)
