@@ -320,6 +320,8 @@ def run_bench(args, np, torch, synth, E):
         out["ensemble"] = ensemble_leg(E, torch, np, synth, args)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_leg(E, torch, np, synth, args)
+        if not args.no_kinetic:
+            out["learned_kinetic"] = learned_leg(E, torch, np, synth, args, kinetic=True)
         if not args.no_slab:
             out["learned_slab"] = learned_slab_leg(E, torch, np, synth, args)
     if not args.no_cpu:
@@ -823,8 +825,12 @@ def learned_slab_leg(E, torch, np, synth, args):
     return out
 
 
-def learned_leg(E, torch, np, synth, args):
+def learned_leg(E, torch, np, synth, args, kinetic=False):
     """Learned projection against plain EFPI on the benchmark grid.
+
+    With kinetic=True the same comparison runs on the kinetic-electron workload
+    (kinetic_spec, Delta t = 7.5 = 1286 fine steps, 27 macro steps to t = 202.5),
+    where every fine burst costs 60 two-species steps.
 
     Training data: plain EFPI trajectories (27 macro steps of Delta t = 75 dt,
     the largest stable step of the sweep, t = 202.5) of the ion-acoustic wave at
@@ -835,10 +841,18 @@ def learned_leg(E, torch, np, synth, args):
     over the same time from the same lifted start.
     """
     import paper_1610_01071_amd.learned as L
-    mult = 75
-    spec = workload_spec(E)
-    spec.macro_dt = mult * spec.dt
-    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4, tile=TILE,
+    if kinetic:
+        spec = kinetic_spec(E, macro_dt=7.5)
+        mult = spec.macro_dt / spec.dt
+        sort_period = 200
+        start_iters = 8
+    else:
+        mult = 75
+        spec = workload_spec(E)
+        spec.macro_dt = mult * spec.dt
+        sort_period = args.sort_period
+        start_iters = 4
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=start_iters, tile=TILE,
                                  flags=E.FLAG_SORT_BUFFER))
     steps = 27
 
@@ -883,15 +897,15 @@ def learned_leg(E, torch, np, synth, args):
     o = other[-1].cpu().numpy().reshape(2, -1)
 
     # full PIC over the same time from the same lifted start
-    fine = steps * mult
+    fine = int(round(steps * mult))
 
-    pctx = pic_context(E, spec, 2, 4)
+    pctx = pic_context(E, spec, 2, start_iters)
 
     def pic_run():
         E.efpi_lift(pctx.ctx, c0, [L.lift_shift(77, 0)])
         done = 0
         while done < fine:
-            k = min(args.sort_period, fine - done)
+            k = min(sort_period, fine - done)
             E.efpi_pic_burst(pctx.ctx, k, False)
             done += k
             if done < fine:
@@ -909,6 +923,8 @@ def learned_leg(E, torch, np, synth, args):
 
     ctx.close()
     return {
+        "workload": "ion-acoustic wave, kinetic electrons" if kinetic else
+                    "ion-acoustic wave, Boltzmann electrons",
         "macro_dt_over_dt": mult, "macro_steps": steps, "judge_period": 4, "threshold": 2e-3,
         "plain_ms": wall_plain, "learned_ms": run.wall_ms, "speedup": wall_plain / run.wall_ms,
         "pic_ms": t_pic, "learned_speedup_vs_pic": t_pic / run.wall_ms,
