@@ -20,6 +20,11 @@ efpi     coarse representation and the projective cycle: co-evolving restriction
 kinetic  fine solver with kinetic electrons (two-species leapfrog, linear
          Poisson, eq. 2.2), Boltzmann-equilibrium electron loading at lift
          (eqs. 3.15-3.16, App. C) and the macro step with kinetic electrons.
+phase    phase-space coarse variables (Sec. 3.3, App. A, App. C): phase-space
+         histogram, full weighting and midpoint interpolation (eqs. 3.7-3.8), the
+         order-4 Coiflet filter from its defining conditions, the periodized
+         wavelet transform, the CDF repair and inverse-CDF quiet start, and the
+         macro step on phase-space coefficients.
 nn       1D-convolution surrogate for the coarse time derivative: forward,
          hand-derived backward and Adam, FP64.
 metrics  the relative L2 error of eq. 4.2.

@@ -1,0 +1,171 @@
+"""Pins of the phase-space coarse-variable oracle (Sec. 3.3, App. A, App. C).
+
+Each check uses a property fixed by the mathematics: the Coiflet conditions
+themselves, perfect reconstruction and Parseval for the periodized transform,
+preservation of the first four moments by the scaling coefficients, mass
+conservation of the full-weighting restriction, exact interpolation of linear
+data, the histogram's mass, and the repaired CDF's monotonicity and
+conservation of M_0 and M_1 (the lemma of App. C).
+"""
+import numpy as np
+import pytest
+
+from oracle import phase
+from oracle.phase import PhaseScheme
+from oracle.pic import Grid
+
+
+@pytest.fixture(scope="module")
+def h():
+    return phase.coiflet_filter()
+
+
+def test_coiflet_conditions(h):
+    assert h.size == 12
+    assert np.max(np.abs(phase.coiflet_conditions(h))) < 1e-12
+    g = phase.highpass(h)
+    assert abs(np.dot(h, g)) < 1e-14                      # low and high pass orthogonal
+    k = np.arange(12, dtype=float)
+    assert max(abs(np.sum(g * k ** p)) for p in range(4)) < 1e-10
+
+
+def test_dwt_perfect_reconstruction_and_parseval(h):
+    x = np.random.default_rng(1).standard_normal((4, 128))
+    a, d = phase.dwt_level(x, h)
+    assert np.max(np.abs(phase.idwt_level(a, d, h) - x)) < 1e-13
+    assert np.allclose(np.sum(x * x, axis=-1), np.sum(a * a, axis=-1) + np.sum(d * d, axis=-1),
+                       rtol=1e-13)
+
+
+def test_scaling_coefficients_keep_the_first_four_moments(h):
+    # A sharp column well inside the periodic window: dropping the details of
+    # three levels leaves its moments of order 0..3 unchanged (four vanishing
+    # moments of the wavelet), while order 4 changes.
+    n = 256
+    k = np.arange(n, dtype=float)
+    x = np.exp(-0.5 * ((k - 128.0) / 2.5) ** 2) + 0.5 * (np.abs(k - 110.0) < 3.0)
+    y = phase.from_scaling_coefficients(phase.scaling_coefficients(x, h, 3), h, 3)
+    mom = lambda z, p: np.sum(z * k ** p)
+    for p in range(4):
+        assert abs(mom(y, p) - mom(x, p)) < 1e-9 * abs(mom(x, p)) + 1e-9
+    assert abs(mom(y, 4) - mom(x, 4)) > 1e-8 * abs(mom(x, 4))
+
+
+def test_full_weighting_and_interpolation():
+    f = np.random.default_rng(2).uniform(0.5, 1.5, (64, 3))
+    c = phase.full_weighting(f)
+    assert np.allclose(2.0 * c.sum(axis=0), f.sum(axis=0), rtol=1e-14)   # spacing doubles
+    const = np.full((16, 2), 0.7)
+    assert np.array_equal(phase.midpoint_interpolation(const), np.full((32, 2), 0.7))
+    lin = np.arange(16, dtype=float)[:, None] * np.ones((1, 2))
+    fine = phase.midpoint_interpolation(lin)
+    assert np.allclose(fine[:-1], (np.arange(31) / 2.0)[:, None])        # interior: linear
+    # restriction of the interpolant of a constant is that constant
+    assert np.allclose(phase.full_weighting(phase.midpoint_interpolation(const)), const)
+
+
+def test_histogram_mass_and_momentum():
+    g = Grid(32, 32.0)
+    ps = PhaseScheme(v_min=-2.0, v_max=2.0, jf=6)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 32, 5000)
+    v = rng.uniform(-1.9, 1.9, 5000)
+    w = rng.uniform(0.5, 1.5, 5000) / 100
+    f = phase.phase_histogram(x, v, w, g, ps)
+    assert np.sum(f) * g.h * ps.dv == pytest.approx(np.sum(w), rel=1e-13)
+    centres = ps.v_min + (np.arange(ps.n_vf) + 0.5) * ps.dv
+    kv = np.floor((v - ps.v_min) / ps.dv).astype(int)
+    assert np.sum(f * centres[None, :]) * g.h * ps.dv == \
+        pytest.approx(np.sum(w * centres[kv]), rel=1e-12)
+    # coarsening conserves mass: one coarse node stands for 2^l fine ones, and the
+    # column's scaling coefficients sum to 2^{(J_f - J_c)/2} times the fine ones
+    h = phase.coiflet_filter()
+    ps2 = PhaseScheme(levels=2, v_min=-2.0, v_max=2.0, jf=6, jc=4)
+    c = phase.coarsen(f, ps2, h)
+    mass = np.sum(c) * 2 ** ((ps2.jf - ps2.jc) / 2.0) * 2 ** (ps2.jf / 2.0) / (4.0) \
+        * (4 * g.h) * ps2.dv
+    assert mass == pytest.approx(np.sum(w), rel=1e-12)
+
+
+def _bad_cdf(seed, n=64, noise=0.08):
+    rng = np.random.default_rng(seed)
+    dens = np.exp(-0.5 * ((np.arange(n) - 30.0) / 6.0) ** 2) + noise * rng.standard_normal(n)
+    dens[:3] = -0.05                       # a negative edge
+    F = np.concatenate([[0.0], np.cumsum(dens)])
+    return F / F[-1]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_repaired_cdf_is_monotone_and_keeps_m0_m1(seed):
+    F = _bad_cdf(seed)
+    assert np.any(np.diff(F) < 0) or np.any(F < 0)
+    R = phase.repair_cdf(F)
+    assert R[0] == 0.0 and R[-1] == 1.0
+    assert np.all(np.diff(R) >= -1e-15) and np.all(R >= -1e-15) and np.all(R <= 1 + 1e-15)
+    # M_1 = n - sum_{k<n} F[k] (M_0 = 1 by construction): kept by every ramp
+    assert np.sum(R) == pytest.approx(np.sum(F), rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_repair_is_monotone_under_heavy_noise(seed):
+    # large oscillations can leave no momentum-conserving ramp below F[n] (the
+    # paper's pathological case); the result is still a valid CDF
+    R = phase.repair_cdf(_bad_cdf(seed, noise=0.3))
+    assert R[0] == 0.0 and R[-1] == 1.0 and np.all(np.diff(R) >= -1e-15)
+
+
+def test_repair_keeps_a_monotone_cdf():
+    F = np.concatenate([[0.0], np.cumsum(np.linspace(0.1, 1.0, 40))])
+    F /= F[-1]
+    assert np.max(np.abs(phase.repair_cdf(F) - F)) < 1e-15   # up to the reflection's rounding
+
+
+def test_repair_of_a_single_dip_by_hand():
+    # F = [0, .3, .2, .6, 1]: one drop after index 1.  k0 = 1, k1 = 3, k+ = 2,
+    # k- = 0; slope 2/(2-0-1) * ((0 + .3)/2 - 0) = .3 fits under F[2] = .2? no:
+    # 0 + 1 * .3 > .2, so k+ = 3: slope 2/2 * ((0 + .3 + .2)/3 - 0) = 1/6, F[1] = 1/6,
+    # F[2] = 1/3 <= .6.  The backward pass gives the same here.
+    F = np.array([0.0, 0.3, 0.2, 0.6, 1.0])
+    fwd = phase._interior_forward(F)
+    assert np.allclose(fwd, [0.0, 1 / 6, 1 / 3, 0.6, 1.0])
+    assert np.sum(fwd) == pytest.approx(np.sum(F))
+
+
+def test_inverse_cdf_of_a_uniform_column():
+    ps = PhaseScheme(v_min=-1.0, v_max=3.0, jf=5)
+    F = np.arange(ps.n_vf + 1) / ps.n_vf
+    b = np.linspace(0.01, 0.99, 17)
+    assert np.allclose(phase.inverse_cdf(F, b, ps), ps.v_min + b * (ps.v_max - ps.v_min))
+
+
+def test_lift_restores_density_and_mean_velocity(h):
+    # A drifting Maxwellian column everywhere, coarsened and lifted: the loaded ions
+    # carry the density and mean velocity (quiet start, so to sampling accuracy).
+    g = Grid(64, 64.0)
+    ps = PhaseScheme(levels=2, v_min=-2.0, v_max=2.0, jf=7, jc=5, ppc=400)
+    centres = ps.v_min + (np.arange(ps.n_vf) + 0.5) * ps.dv
+    col = np.exp(-0.5 * ((centres - 0.3) / 0.32) ** 2)
+    col /= np.sum(col) * ps.dv
+    f = np.tile(col, (64, 1))
+    cell, frac, v, w = phase.lift_phase(phase.coarsen(f, ps, h), g, ps, h, 12345)
+    assert np.sum(w) == pytest.approx(64.0, rel=1e-3)
+    assert np.sum(w * v) / np.sum(w) == pytest.approx(0.3, abs=2e-3)
+    assert np.sqrt(np.sum(w * (v - 0.3) ** 2) / np.sum(w)) == pytest.approx(0.32, rel=2e-2)
+
+
+def test_free_streaming_burst_snapshots_are_the_state_at_t_plus_dt(h):
+    # Without a field the co-evolving map X + (Dt - p dt) v sends every snapshot to
+    # the particles advanced by the whole macro step, so all snapshots agree and
+    # equal the restriction of x + Dt v (the exactness of App. B for free streaming).
+    from oracle.pic import NOFIELD
+    g = Grid(32, 32.0, closure=NOFIELD, dt=0.1)
+    ps = PhaseScheme(levels=1, v_min=-2.0, v_max=2.0, jf=6, jc=4, burst_steps=5, macro_dt=2.0)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 32, 4000)
+    v = rng.uniform(-1.5, 1.5, 4000)
+    w = np.full(4000, 0.01)
+    snaps = phase.phase_burst(x, v, w, g, ps, h)
+    want = phase.coarsen(phase.phase_histogram(np.mod(x + ps.macro_dt * v, 32.0), v, w, g, ps),
+                         ps, h)
+    for p in range(ps.burst_steps + 1):
+        assert np.max(np.abs(snaps[p] - want)) < 1e-10 * np.max(np.abs(want))
