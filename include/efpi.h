@@ -305,6 +305,43 @@ efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_
 efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in,
                                   double* d_coarse_out, const uint32_t* h_shifts);
 
+/* ------------------------------------------------- phase-space restriction -- */
+/* Phase-space coarse variables of the wavelet-based scheme (Sec. 3.3): the ion
+ * distribution on nodes x_k (CIC) times 2^jf velocity bins over [v_min, v_max)
+ * (nearest bin; ions outside are not counted), l = levels steps of the
+ * full-weighting restriction in x (eq. 3.8), then per coarse x node the
+ * periodized discrete wavelet transform of the velocity column down to 2^jc
+ * scaling coefficients (App. A) with the caller's orthonormal low-pass filter
+ * (for the paper's scheme, the 12-tap order-4 Coiflet). */
+typedef struct {
+  double v_min, v_max;   /* velocity window                                          */
+  int32_t jf;            /* 2^jf fine velocity bins, 4 <= jf <= 10                    */
+  int32_t jc;            /* 2^jc coarse coefficients per x node, jc <= jf, 2^jc >= n_taps */
+  int32_t levels;        /* full-weighting levels in x, n_cells >> levels >= 1        */
+  int32_t n_taps;        /* filter length, even, 2 <= n_taps <= 16                    */
+  double taps[16];       /* low-pass filter h_0..h_{n_taps-1} (host copy)            */
+} efpi_phase;
+
+/* Bytes of the caller-owned work buffer of efpi_phase_restrict for replica r:
+ * the int64 intermediate histogram [n_cells >> levels][2^jf]. */
+efpi_status efpi_phase_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                 size_t* h_bytes);
+
+/* Phase-space coarse coefficients of replica r's current ions:
+ * d_out[n_cells >> levels][2^jc] (FP64).  Each ion enters at X + tau v,
+ * V = v + tau E(X) (the co-evolving frame of App. B with the current field; tau = 0:
+ * plain), with time-centred velocities after a burst (v + dt/2 E).  Its charge is
+ * quantised as in the deposit, q = rint(w 2^40) split rint(theta q) / rest over the
+ * two nodes of X, and node i = 2^l K + d adds (2^l - d) and d times its share to
+ * coarse nodes K and K + 1 (the composed full-weighting weights, denominator 4^l):
+ * the histogram d_work[K][k_v] is exact int64 and order-free.  The column values
+ * are H 2^-40 / (4^l h dv) (a phase-space density) times 2^{-jf/2} (v_max - v_min)
+ * (App. A's finest scaling coefficients of the velocity rescaled to [0, 1)), then
+ * jf - jc levels a_k = sum_m h_m x_{(2k + m) mod N}.  d_work: efpi_phase_work_size
+ * bytes, 256-byte aligned.  EFPI_EINVAL on bad parameters. */
+efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                double tau, void* d_work, double* d_out);
+
 /* Plain restriction (no co-evolving frame) of the current particles of every
  * replica: d_coarse[r][2][N_c] = coarse (density, momentum) coefficients at the
  * current time, with time-centred velocities after a burst.  Overwrites the

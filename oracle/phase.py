@@ -183,6 +183,45 @@ def phase_histogram(x, v, w, grid: Grid, ps: PhaseScheme):
     return f / (grid.h * ps.dv)
 
 
+def restricted_histogram_fx(cell, frac, v, w, n_cells: int, ps: PhaseScheme):
+    """The histogram after l full-weighting levels, in exact integer arithmetic
+    (the form the GPU accumulates): the charge q = rint(w 2^40) of each ion is
+    split as in the deposit, q_R = rint(theta q), q_L = q - q_R, and fine node
+    i = 2^l K + d adds (2^l - d) and d times its share to coarse nodes K and
+    K + 1 (the composed weights of eq. 3.8, with denominator 4^l).  Ions in cell
+    c at offset theta (FP32), velocities v; bin floor((v - v_min) / dv).
+    Returns int64 H[n_cells >> l][n_vf]; H 2^-40 / (4^l h dv) equals l levels of
+    full_weighting applied to phase_histogram."""
+    cell = np.asarray(cell).astype(np.int64)
+    frac = np.asarray(frac, dtype=np.float32).astype(np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float32).astype(np.float64)
+    kv = np.floor((v - ps.v_min) / ps.dv).astype(np.int64)
+    ok = (cell >= 0) & (kv >= 0) & (kv < ps.n_vf)
+    cell, frac, kv, w = cell[ok], frac[ok], kv[ok], w[ok]
+    q = np.rint(w * pic.FX_SCALE).astype(np.int64)
+    qr = np.rint(frac * q.astype(np.float64)).astype(np.int64)
+    ql = q - qr
+    nxc = n_cells >> ps.levels
+    span = 1 << ps.levels
+    H = np.zeros((nxc, ps.n_vf), dtype=np.int64)
+    for node, share in ((cell, ql), ((cell + 1) % n_cells, qr)):
+        K = node >> ps.levels
+        d = node & (span - 1)
+        np.add.at(H, (K, kv), share * (span - d))
+        np.add.at(H, ((K + 1) % nxc, kv), share * d)
+    return H
+
+
+def coarse_from_histogram_fx(H, ps: PhaseScheme, h_grid: float, h):
+    """Coarse coefficients from restricted_histogram_fx: the phase-space density
+    H 2^-40 / (4^l h dv), scaled to App. A's finest coefficients, then the wavelet
+    transform of each column down to J_c."""
+    dens = np.asarray(H, dtype=np.float64) / pic.FX_SCALE / (4.0 ** ps.levels * h_grid * ps.dv)
+    scale = 2.0 ** (-ps.jf / 2.0) * (ps.v_max - ps.v_min)
+    return scaling_coefficients(scale * dens, h, ps.jf - ps.jc)
+
+
 def coarsen(f, ps: PhaseScheme, h):
     """l levels of full weighting in x, then per coarse x node the scaling
     coefficients at J_c of the column, whose finest-level coefficients are

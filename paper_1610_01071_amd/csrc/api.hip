@@ -961,6 +961,56 @@ efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in, doub
   return hip_check("macro_step_graph");
 }
 
+namespace {
+efpi_status check_phase(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph) {
+  if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
+  if (!ph) return fail(EFPI_EINVAL, "phase parameters are NULL");
+  const RepDev& d = ctx->h_reps[replica];
+  if (d.bc != EFPI_BC_PERIODIC) return fail(EFPI_EINVAL, "phase restriction needs a periodic replica");
+  if (!(ph->v_max > ph->v_min) || !std::isfinite(ph->v_min) || !std::isfinite(ph->v_max))
+    return fail(EFPI_EINVAL, "need finite v_min < v_max");
+  if (ph->jf < 4 || ph->jf > 10) return fail(EFPI_EINVAL, "jf must be in [4, 10]");
+  if (ph->jc < 1 || ph->jc > ph->jf) return fail(EFPI_EINVAL, "jc must be in [1, jf]");
+  if (ph->n_taps < 2 || ph->n_taps > 16 || (ph->n_taps & 1))
+    return fail(EFPI_EINVAL, "n_taps must be even in [2, 16]");
+  if ((1 << ph->jc) < ph->n_taps) return fail(EFPI_EINVAL, "2^jc must be >= n_taps");
+  if (ph->levels < 0 || (d.n_cells >> ph->levels) < 1)
+    return fail(EFPI_EINVAL, "levels out of range");
+  for (int m = 0; m < ph->n_taps; ++m)
+    if (!std::isfinite(ph->taps[m])) return fail(EFPI_EINVAL, "non-finite filter tap");
+  return EFPI_OK;
+}
+}  // namespace
+
+efpi_status efpi_phase_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                 size_t* h_bytes) {
+  const efpi_status st = check_phase(ctx, replica, ph);
+  if (st != EFPI_OK) return st;
+  if (!h_bytes) return fail(EFPI_EINVAL, "h_bytes is NULL");
+  *h_bytes = sizeof(int64_t) * (size_t)(ctx->h_reps[replica].n_cells >> ph->levels) *
+             ((size_t)1 << ph->jf);
+  return EFPI_OK;
+}
+
+efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                double tau, void* d_work, double* d_out) {
+  const efpi_status st = check_phase(ctx, replica, ph);
+  if (st != EFPI_OK) return st;
+  if (!d_work || !d_out) return fail(EFPI_EINVAL, "NULL array");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
+    return fail(EFPI_EINVAL, "d_work must be 256-byte aligned");
+  if (!std::isfinite(tau)) return fail(EFPI_EINVAL, "tau must be finite");
+  if (!ctx->fresh && !ctx->field_valid)
+    return fail(EFPI_ESTATE, "phase restriction after a burst needs the current field");
+  if (tau != 0.0 && !ctx->field_valid)
+    return fail(EFPI_ESTATE, "the co-evolving frame (tau != 0) needs the current field");
+  const RepDev& d = ctx->h_reps[replica];
+  launch_phase_restrict(ctx->d_reps, replica, d.n_cells, ph->levels, ph->v_min, ph->v_max, ph->jf,
+                        ph->jc, ph->taps, ph->n_taps, tau, ctx->fresh ? 1 : 0, d.h,
+                        static_cast<long long*>(d_work), d_out, ctx->stream);
+  return hip_check("phase_restrict");
+}
+
 efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   if (!d_coarse) return fail(EFPI_EINVAL, "d_coarse is NULL");

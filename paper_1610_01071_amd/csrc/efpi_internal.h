@@ -156,6 +156,13 @@ void launch_project2(const RepDev* d_reps, int n_reps, const double* d_snap,
 void launch_ensemble_mean(const RepDev* d_reps, int n_reps, const int32_t* d_group,
                           double* d_coarse, const int64_t* d_coff, hipStream_t stream);
 void launch_fill_u8(void* d_ptr, size_t bytes, hipStream_t stream);
+// Phase-space coarse coefficients of replica rep's ions (phase.hip): the int64
+// restricted histogram into d_hist [n_cells >> levels_x][2^jf], then the column
+// transforms into d_out [n_cells >> levels_x][2^jc].
+void launch_phase_restrict(const RepDev* d_reps, int rep, int n_cells, int levels_x, double v_min,
+                           double v_max, int jf, int jc, const double* h_taps, int n_taps,
+                           double tau, int fresh, double h, long long* d_hist, double* d_out,
+                           hipStream_t stream);
 void launch_copy_particles(const RepDev* d_reps, int rep, const int16_t* cell, const float* frac,
                            const float* v, const float* w, int64_t n, int to_store,
                            int16_t* ocell, float* ofrac, float* ov, float* ow,

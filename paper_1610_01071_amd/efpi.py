@@ -71,6 +71,18 @@ class Config(ctypes.Structure):
     ]
 
 
+class Phase(ctypes.Structure):
+    _fields_ = [
+        ("v_min", ctypes.c_double),
+        ("v_max", ctypes.c_double),
+        ("jf", ctypes.c_int32),
+        ("jc", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("n_taps", ctypes.c_int32),
+        ("taps", ctypes.c_double * 16),
+    ]
+
+
 class NnNorm(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_float * 2), ("sigma", ctypes.c_float * 2),
                 ("delta", ctypes.c_float * 2)]
@@ -113,6 +125,8 @@ def _load():
         "efpi_macro_step_graph": [P, P, P, ctypes.POINTER(U32)],
         "efpi_ensemble_mean": [P, P],
         "efpi_restrict_state": [P, P],
+        "efpi_phase_work_size": [P, I32, ctypes.POINTER(Phase), ctypes.POINTER(ctypes.c_size_t)],
+        "efpi_phase_restrict": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, P, P],
         "efpi_sort": [P],
         "efpi_sync": [P, ctypes.POINTER(U32)],
         "efpi_timing": [P, I32],
@@ -153,7 +167,7 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_restrict", "efpi_project", "efpi_set_macro_dt", "efpi_project2",
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
-            "efpi_restrict_state",
+            "efpi_restrict_state", "efpi_phase_work_size", "efpi_phase_restrict",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_timing_read_electrons",
             "efpi_last_error",
             "efpi_nn_workspace_size", "efpi_nn_pack", "efpi_nn_forward", "efpi_nn_backward",
@@ -372,6 +386,28 @@ def efpi_macro_step_graph(ctx, coarse_in, coarse_out, shifts):
 
 def efpi_restrict_state(ctx, coarse):
     _check(LIB.efpi_restrict_state(ctx, _dev(coarse, torch.float64)))
+
+
+def phase(v_min, v_max, jf, jc, levels, taps) -> Phase:
+    """Phase-space restriction parameters (efpi_phase) with the given low-pass filter."""
+    taps = [float(t) for t in taps]
+    if len(taps) > 16:
+        raise ValueError("at most 16 filter taps")
+    arr = (ctypes.c_double * 16)(*(taps + [0.0] * (16 - len(taps))))
+    return Phase(float(v_min), float(v_max), int(jf), int(jc), int(levels), len(taps), arr)
+
+
+def efpi_phase_work_size(ctx, replica, ph: Phase) -> int:
+    out = ctypes.c_size_t(0)
+    _check(LIB.efpi_phase_work_size(ctx, replica, ctypes.byref(ph), ctypes.byref(out)))
+    return out.value
+
+
+def efpi_phase_restrict(ctx, replica, ph: Phase, tau, work, out):
+    if work.data_ptr() % 256:
+        raise ValueError("the work buffer must be 256-byte aligned")
+    _check(LIB.efpi_phase_restrict(ctx, replica, ctypes.byref(ph), float(tau),
+                                   ctypes.c_void_p(work.data_ptr()), _dev(out, torch.float64)))
 
 
 def efpi_ensemble_mean(ctx, coarse):

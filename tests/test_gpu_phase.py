@@ -1,0 +1,94 @@
+"""Phase-space restriction on the GPU (efpi_phase_restrict) against the oracle.
+
+Bars: the int64 restricted histogram bit-exact against the oracle's integer
+form (same quantisation, fresh ions, tau = 0, power-of-two bin widths); the
+coarse coefficients within 1e-13 of the oracle's transform of that histogram,
+for the closed-form 4-tap Daubechies filter and for 12 seeded taps; after a
+burst, along the co-evolving frame, within eps = 1e-4 (eq. 4.2) of the FP64
+oracle (FP32 positions and velocities move a few ions across bin edges).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import phase as ophase
+from oracle import pic as opic
+from oracle import metrics
+from helpers import lib, oracle_grid, set_particles, particles_np, grid_np, x_of
+
+pytestmark = pytest.mark.gpu
+
+S3 = math.sqrt(3.0)
+D4 = [(1 + S3) / (4 * math.sqrt(2)), (3 + S3) / (4 * math.sqrt(2)),
+      (3 - S3) / (4 * math.sqrt(2)), (1 - S3) / (4 * math.sqrt(2))]
+
+
+def run(E, ctx, ph, tau=0.0, replica=0):
+    nbytes = E.efpi_phase_work_size(ctx.ctx, replica, ph)
+    work = torch.empty(nbytes // 8 + 32, dtype=torch.int64, device="cuda")
+    off = (-work.data_ptr()) % 256 // 8
+    work = work[off: off + nbytes // 8]
+    nxc = ctx.spec.replicas[replica].n_cells >> ph.levels
+    out = torch.empty(nxc * (1 << ph.jc), dtype=torch.float64, device="cuda")
+    E.efpi_phase_restrict(ctx.ctx, replica, ph, tau, work, out)
+    torch.cuda.synchronize()
+    return work.view(nxc, 1 << ph.jf).cpu().numpy(), out.view(nxc, 1 << ph.jc).cpu().numpy()
+
+
+@pytest.mark.parametrize("n_cells,levels,jf,jc,taps", [
+    (256, 2, 6, 4, "d4"), (1024, 4, 8, 5, "taps12"), (64, 0, 5, 4, "d4"), (4096, 4, 10, 6, "d4")])
+def test_histogram_bitexact_and_coefficients(n_cells, levels, jf, jc, taps):
+    E = lib()
+    spec = E.ReplicaSpec(n_cells, float(n_cells), ppc=30, haar_levels=2)
+    ctx = E.Context(E.ConfigSpec([spec]))
+    parts = synth.random_particles(n_cells * 30, n_cells, seed=n_cells + jf, vth=0.7,
+                                   w_mean=1.0 / 30)
+    set_particles(ctx, 0, *parts)
+    # the transform is linear in the filter: any 12 taps exercise the 12-tap path
+    h = D4 if taps == "d4" else list(np.random.default_rng(5).normal(0.0, 0.3, 12))
+    ph = E.phase(-2.0, 2.0, jf, jc, levels, h)
+    ps = ophase.PhaseScheme(levels=levels, v_min=-2.0, v_max=2.0, jf=jf, jc=jc)
+    H, coarse = run(E, ctx, ph)
+    ref_H = ophase.restricted_histogram_fx(parts[0], parts[1], parts[2], parts[3], n_cells, ps)
+    assert np.array_equal(H, ref_H)
+    ref = ophase.coarse_from_histogram_fx(ref_H, ps, spec.length / n_cells, np.array(h))
+    assert np.max(np.abs(coarse - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_coevolving_frame_after_a_burst():
+    E = lib()
+    n = 512
+    spec = E.ReplicaSpec(n, float(n), ppc=60, haar_levels=3, vth=0.316)
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters_start=10))
+    dens, u = synth.iaw_profile(n, float(n))
+    E.efpi_load_profile(ctx.ctx, 0, torch.as_tensor(dens, device="cuda"),
+                        torch.as_tensor(u, device="cuda"), 7)
+    E.efpi_pic_burst(ctx.ctx, 5, False)
+    ph = E.phase(-2.0, 2.0, 7, 5, 3, D4)
+    _, coarse = run(E, ctx, ph, tau=4.0)
+    c, f, v, w = particles_np(ctx)
+    _, _, e = grid_np(ctx)
+    g = oracle_grid(spec)
+    x = x_of(c, f, g.h)
+    ex = opic.gather(e.astype(np.float64), x, g)
+    vc = v.astype(np.float64) + 0.5 * g.dt * ex
+    ps = ophase.PhaseScheme(levels=3, v_min=-2.0, v_max=2.0, jf=7, jc=5)
+    ref = ophase.restrict_phase(x, vc, ex, w.astype(np.float64), 4.0, g, ps, np.array(D4))
+    assert metrics.rel_l2(coarse, ref) < 1e-4
+    E.efpi_sync(ctx.ctx)
+
+
+def test_phase_parameters_checked():
+    E = lib()
+    walls = E.Context(E.ConfigSpec([E.ReplicaSpec(64, 64.0, bc=1, ppc=4)]))
+    with pytest.raises(E.EfpiError):
+        E.efpi_phase_work_size(walls.ctx, 0, E.phase(-1, 1, 6, 4, 1, D4))
+    per = E.Context(E.ConfigSpec([E.ReplicaSpec(64, 64.0, ppc=4)]))
+    for bad in (E.phase(-1, 1, 3, 2, 1, D4), E.phase(1, -1, 6, 4, 1, D4),
+                E.phase(-1, 1, 6, 7, 1, D4), E.phase(-1, 1, 6, 1, 1, D4),
+                E.phase(-1, 1, 6, 4, 7, D4), E.phase(-1, 1, 6, 4, 1, D4[:3])):
+        with pytest.raises(E.EfpiError):
+            E.efpi_phase_work_size(per.ctx, 0, bad)

@@ -169,3 +169,26 @@ def test_free_streaming_burst_snapshots_are_the_state_at_t_plus_dt(h):
                          ps, h)
     for p in range(ps.burst_steps + 1):
         assert np.max(np.abs(snaps[p] - want)) < 1e-10 * np.max(np.abs(want))
+
+
+def test_fixed_point_restricted_histogram_equals_full_weighting_of_the_histogram(h):
+    # the integer form with the composed hat weights is l levels of eq. 3.8 applied
+    # to the CIC x NGP histogram, up to the 2^-40 quantisation of the charge
+    g = Grid(64, 64.0)
+    ps = PhaseScheme(levels=3, v_min=-2.0, v_max=2.0, jf=6, jc=4)
+    rng = np.random.default_rng(8)
+    n = 20000
+    cell = rng.integers(0, 64, n).astype(np.int16)
+    frac = rng.random(n, dtype=np.float32)
+    v = rng.uniform(-2.2, 2.2, n).astype(np.float32)
+    w = (rng.uniform(0.5, 1.5, n) / 300).astype(np.float32)
+    H = phase.restricted_histogram_fx(cell, frac, v, w, 64, ps)
+    x = (cell.astype(np.float64) + frac.astype(np.float64)) * g.h
+    f = phase.phase_histogram(x, v.astype(np.float64), w.astype(np.float64), g, ps)
+    for _ in range(ps.levels):
+        f = phase.full_weighting(f)
+    dens = H.astype(np.float64) / 2.0 ** 40 / (4.0 ** ps.levels * g.h * ps.dv)
+    assert np.max(np.abs(dens - f)) < 1e-9 * np.max(np.abs(f))
+    c = phase.coarse_from_histogram_fx(H, ps, g.h, h)
+    assert np.max(np.abs(c - phase.coarsen(phase.phase_histogram(
+        x, v.astype(np.float64), w.astype(np.float64), g, ps), ps, h))) < 1e-9 * np.max(np.abs(c))
