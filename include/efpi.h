@@ -340,7 +340,40 @@ efpi_status efpi_phase_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phas
  * jf - jc levels a_k = sum_m h_m x_{(2k + m) mod N}.  d_work: efpi_phase_work_size
  * bytes, 256-byte aligned.  EFPI_EINVAL on bad parameters. */
 efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
-                                double tau, void* d_work, double* d_out);
+                                double tau, int32_t stored_field, void* d_work, double* d_out);
+
+/* Bytes of the caller-owned work buffer of efpi_phase_lift for replica r: the
+ * refined columns [n_cells >> levels][2^jf] and three CDF planes [2^jf + 1][n_cells]
+ * (FP64). */
+efpi_status efpi_phase_lift_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                      size_t* h_bytes);
+
+/* Lifting from phase-space coefficients d_coarse[n_cells >> levels][2^jc] (App. C):
+ * each column back to 2^jf values with zero details (inverse of the transform
+ * above) and scaled to the phase-space density, l levels of midpoint interpolation
+ * in x (eq. 3.7), per fine node the density n = (sum f) dv and the conditional CDF
+ * at the bin edges (sums in index order), the CDF repair of App. C (edges below 0
+ * and, reflected, above 1; interior ramps from the lower indexes and, reflected,
+ * from the upper ones, averaged; a ramp is accepted when its last value stays at
+ * or below F[k+]; where none fits below F[n] a straight line joins F[k-] to F[n]);
+ * then ppc ions per occupied cell (a node density above n_floor) at offsets
+ * (m + 1/2)/ppc with velocity the two nodes' inverse CDFs (lookup, linear within
+ * the bin) at the Hammersley b with rotation `shift`, interpolated in x, and weight
+ * n(X) h / ppc.  Not in kinetic contexts (EFPI_ESTATE).  d_work:
+ * efpi_phase_lift_work_size bytes, 256-byte aligned. */
+efpi_status efpi_phase_lift(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                            const double* d_coarse, uint32_t shift, void* d_work);
+
+/* Least-squares slope (eq. 3.18) of `snapshots` equally spaced (dt) snapshots
+ * d_snap[snapshots][count] and forward-Euler projection over
+ * macro_dt - (snapshots - 1) dt from the last one (eq. 3.17) -> d_out[count]. */
+efpi_status efpi_phase_project(efpi_ctx* ctx, const double* d_snap, int64_t count,
+                               int32_t snapshots, double dt, double macro_dt, double* d_out);
+
+/* Make the field current (deposit and solve if needed) and store it as E_n, the
+ * field of the burst start that the co-evolving frame uses (App. B); clears the
+ * Haar snapshot bins. */
+efpi_status efpi_store_field(efpi_ctx* ctx);
 
 /* Plain restriction (no co-evolving frame) of the current particles of every
  * replica: d_coarse[r][2][N_c] = coarse (density, momentum) coefficients at the

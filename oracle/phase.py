@@ -255,12 +255,20 @@ def refine(coarse, ps: PhaseScheme, h):
     return g
 
 
+def _seqsum(a):
+    """Sum in index order (the repair's decisions compare such sums, so the order
+    is part of the definition here)."""
+    a = np.asarray(a, dtype=np.float64)
+    return float(np.cumsum(a)[-1]) if a.size else 0.0
+
+
 def column_cdf(col, dv):
-    """Node density n = sum f dv and the conditional CDF at the bin edges,
-    F[k] = (1/n) sum_{j<k} f_j dv (F[0] = 0, F[n_vf] = 1)."""
+    """Node density n = (sum f) dv and the conditional CDF at the bin edges,
+    F[k] = ((sum_{j<k} f_j) dv) / n (F[0] = 0, F[n_vf] = 1); sums in index order."""
     col = np.asarray(col, dtype=np.float64)
-    n = np.sum(col) * dv
-    F = np.concatenate([[0.0], np.cumsum(col) * dv / n])
+    run = np.cumsum(col)
+    n = float(run[-1]) * dv
+    F = np.concatenate([[0.0], (run * dv) / n])
     F[-1] = 1.0
     return n, F
 
@@ -277,7 +285,7 @@ def _edge_low(F):
     km, kp = k0 - 1, k0 + 1
     while True:
         span = kp - km
-        dF = 2.0 * np.sum(F[1:kp]) / (span * (span - 1))
+        dF = 2.0 * _seqsum(F[1:kp]) / (span * (span - 1))
         if 0.0 <= (span - 1) * dF <= F[kp] or kp >= nf:
             break
         if km > 0:
@@ -319,7 +327,7 @@ def _interior_forward(F):
         km = int(below[-1]) if below.size else 0
         while True:
             span = kp - km
-            dF = 2.0 / (span - 1) * (np.sum(F[km:kp]) / span - F[km])
+            dF = 2.0 / (span - 1) * (_seqsum(F[km:kp]) / span - F[km])
             if 0.0 <= (span - 1) * dF and F[km] + (span - 1) * dF <= F[kp]:
                 break
             if kp >= nf:

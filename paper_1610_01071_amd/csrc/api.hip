@@ -993,7 +993,7 @@ efpi_status efpi_phase_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phas
 }
 
 efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
-                                double tau, void* d_work, double* d_out) {
+                                double tau, int32_t stored_field, void* d_work, double* d_out) {
   const efpi_status st = check_phase(ctx, replica, ph);
   if (st != EFPI_OK) return st;
   if (!d_work || !d_out) return fail(EFPI_EINVAL, "NULL array");
@@ -1002,13 +1002,74 @@ efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase
   if (!std::isfinite(tau)) return fail(EFPI_EINVAL, "tau must be finite");
   if (!ctx->fresh && !ctx->field_valid)
     return fail(EFPI_ESTATE, "phase restriction after a burst needs the current field");
-  if (tau != 0.0 && !ctx->field_valid)
+  if (tau != 0.0 && !stored_field && !ctx->field_valid)
     return fail(EFPI_ESTATE, "the co-evolving frame (tau != 0) needs the current field");
   const RepDev& d = ctx->h_reps[replica];
   launch_phase_restrict(ctx->d_reps, replica, d.n_cells, ph->levels, ph->v_min, ph->v_max, ph->jf,
-                        ph->jc, ph->taps, ph->n_taps, tau, ctx->fresh ? 1 : 0, d.h,
-                        static_cast<long long*>(d_work), d_out, ctx->stream);
+                        ph->jc, ph->taps, ph->n_taps, tau, ctx->fresh ? 1 : 0,
+                        stored_field ? 1 : 0, d.h, static_cast<long long*>(d_work), d_out,
+                        ctx->stream);
   return hip_check("phase_restrict");
+}
+
+namespace {
+size_t phase_lift_cols_bytes(const RepDev& d, const efpi_phase* ph) {
+  return align256(sizeof(double) * (size_t)(d.n_cells >> ph->levels) * ((size_t)1 << ph->jf));
+}
+size_t phase_lift_cdf_bytes(const RepDev& d, const efpi_phase* ph) {
+  return align256(sizeof(double) * 3 * (((size_t)1 << ph->jf) + 1) * (size_t)d.n_cells);
+}
+}  // namespace
+
+efpi_status efpi_phase_lift_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                      size_t* h_bytes) {
+  const efpi_status st = check_phase(ctx, replica, ph);
+  if (st != EFPI_OK) return st;
+  if (!h_bytes) return fail(EFPI_EINVAL, "h_bytes is NULL");
+  const RepDev& d = ctx->h_reps[replica];
+  *h_bytes = phase_lift_cols_bytes(d, ph) + phase_lift_cdf_bytes(d, ph);
+  return EFPI_OK;
+}
+
+efpi_status efpi_phase_lift(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                            const double* d_coarse, uint32_t shift, void* d_work) {
+  const efpi_status st = check_phase(ctx, replica, ph);
+  if (st != EFPI_OK) return st;
+  if (ctx->kinetic) return fail(EFPI_ESTATE, "the phase-space lift loads no electrons");
+  if (!d_coarse || !d_work) return fail(EFPI_EINVAL, "NULL array");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
+    return fail(EFPI_EINVAL, "d_work must be 256-byte aligned");
+  const RepDev& d = ctx->h_reps[replica];
+  uint8_t* w = static_cast<uint8_t*>(d_work);
+  double* cols = reinterpret_cast<double*>(w);
+  double* cdf = reinterpret_cast<double*>(w + phase_lift_cols_bytes(d, ph));
+  launch_phase_lift(ctx->d_reps, replica, d.n_cells, ph->levels, ph->v_min, ph->v_max, ph->jf,
+                    ph->jc, ph->taps, ph->n_taps, d_coarse, cols, cdf, ctx->d_status, shift,
+                    ctx->stream);
+  mark_new_particles(ctx);
+  return hip_check("phase_lift");
+}
+
+efpi_status efpi_phase_project(efpi_ctx* ctx, const double* d_snap, int64_t count,
+                               int32_t snapshots, double dt, double macro_dt, double* d_out) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!d_snap || !d_out) return fail(EFPI_EINVAL, "NULL array");
+  if (count < 1 || snapshots < 2) return fail(EFPI_EINVAL, "need count >= 1 and snapshots >= 2");
+  if (!(dt > 0.0) || !(macro_dt >= (snapshots - 1) * dt * (1.0 - 1e-12)))
+    return fail(EFPI_EINVAL, "need dt > 0 and macro_dt >= (snapshots - 1) dt");
+  launch_phase_project(d_snap, count, snapshots - 1, dt, macro_dt, d_out, ctx->stream);
+  return hip_check("phase_project");
+}
+
+efpi_status efpi_store_field(efpi_ctx* ctx) {
+  if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
+  if (!ctx->field_valid) {
+    if (!ctx->deposited) deposit_all(ctx, true);
+    run_field(ctx, ctx->cfg.newton_iters_start, 0, 1, 0);
+  } else {
+    launch_prep_burst(ctx->d_reps, ctx->R, ctx->stream);
+  }
+  return hip_check("store_field");
 }
 
 efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {

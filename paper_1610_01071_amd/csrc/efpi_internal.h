@@ -161,8 +161,17 @@ void launch_fill_u8(void* d_ptr, size_t bytes, hipStream_t stream);
 // transforms into d_out [n_cells >> levels_x][2^jc].
 void launch_phase_restrict(const RepDev* d_reps, int rep, int n_cells, int levels_x, double v_min,
                            double v_max, int jf, int jc, const double* h_taps, int n_taps,
-                           double tau, int fresh, double h, long long* d_hist, double* d_out,
-                           hipStream_t stream);
+                           double tau, int fresh, int stored_field, double h, long long* d_hist,
+                           double* d_out, hipStream_t stream);
+// Ions of replica rep lifted from phase-space coefficients d_coarse [nxc][2^jc]:
+// columns refined into d_cols [nxc][2^jf], CDFs repaired in d_cdf (3 planes of
+// [2^jf + 1][n_cells]), node densities in R.prof_n, ranks by the occupancy, load.
+void launch_phase_lift(const RepDev* d_reps, int rep, int n_cells, int levels_x, double v_min,
+                       double v_max, int jf, int jc, const double* h_taps, int n_taps,
+                       const double* d_coarse, double* d_cols, double* d_cdf,
+                       uint32_t* d_status, uint32_t shift, hipStream_t stream);
+void launch_phase_project(const double* d_snap, int64_t count, int ne, double dt, double macro_dt,
+                          double* d_out, hipStream_t stream);
 void launch_copy_particles(const RepDev* d_reps, int rep, const int16_t* cell, const float* frac,
                            const float* v, const float* w, int64_t n, int to_store,
                            int16_t* ocell, float* ofrac, float* ov, float* ow,

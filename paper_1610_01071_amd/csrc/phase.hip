@@ -25,7 +25,7 @@ constexpr int kPhWin = 8;      // coarse x nodes of a work item's LDS window
 struct PhaseHistArg {
   double v_min, inv_dv;
   float tau;
-  int levels, n_vf, win, fresh;
+  int levels, n_vf, win, fresh, stored_field;
 };
 
 __global__ __launch_bounds__(kPhThreads) void k_phase_hist(const RepDev* __restrict__ reps,
@@ -40,6 +40,7 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_hist(const RepDev* __restr
   const int64_t np = *gmem(R.np);
   const int64_t items = (np + kPhTile - 1) / kPhTile;
   const EFPI_GLOBAL float* __restrict__ e = gmem(R.e);
+  const EFPI_GLOBAL float* __restrict__ en_ = gmem(R.en);
   const EFPI_GLOBAL int16_t* __restrict__ cellp = gmem(R.cell);
   const EFPI_GLOBAL float* __restrict__ fracp = gmem(R.frac);
   const EFPI_GLOBAL float* __restrict__ velp = gmem(R.v);
@@ -78,13 +79,15 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_hist(const RepDev* __restr
       float ep = 0.f;
       if (!a.fresh || a.tau != 0.f) ep = (1.f - f) * e[c] + f * e[(c + 1) & nmask];
       if (!a.fresh) v += half_dt * ep;  // time-centred velocity after a burst
-      // co-evolving frame: X + tau v, V = v + tau E(X) (App. B)
+      // co-evolving frame: X + tau v, V = v + tau E_n(X) (App. B), E_n the field
+      // stored at the burst start or the current one
+      const float en = a.stored_field ? (1.f - f) * en_[c] + f * en_[(c + 1) & nmask] : ep;
       const float xs = f + tau_inv_h * v;
       const float fl = floorf(xs);
       const bool wrap_up = (xs - fl) >= 1.f;
       const float fn = wrap_up ? 0.f : xs - fl;
       const int cn = (c + (int)fl + (wrap_up ? 1 : 0)) & nmask;
-      const float vt = v + a.tau * ep;
+      const float vt = v + a.tau * en;
       const double bin = floor(((double)vt - a.v_min) * a.inv_dv);
       if (!(bin >= 0.0 && bin < (double)a.n_vf)) continue;
       const int kv = (int)bin;
@@ -141,12 +144,294 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_dwt(const long long* __res
   for (int k = threadIdx.x; k < len; k += kPhThreads) out[(int64_t)K * len + k] = cur[k];
 }
 
+// ------------------------------------------------------------------ lift --
+// The lift repeats the oracle's arithmetic operation by operation (the CDF
+// repair takes decisions on compared sums), so nothing here is contracted into
+// fused multiply-adds.
+#pragma clang fp contract(off)
+// Columns of the coarse nodes back at J_f with zero details: level by level,
+// x_t = sum over taps m = t (mod 2), in ascending m, of h_m a_{((t - m) / 2) mod N/2},
+// then scaled to the phase-space density.
+__global__ __launch_bounds__(kPhThreads) void k_phase_refine(const double* __restrict__ coarse,
+                                                            PhaseDwtArg a, double up_scale,
+                                                            double* __restrict__ cols) {
+  extern __shared__ double s_col[];  // [2][n_vf]
+  const int K = blockIdx.x;
+  double* cur = s_col;
+  double* nxt = s_col + a.n_vf;
+  int len = a.n_vf >> a.levels_v;
+  for (int k = threadIdx.x; k < len; k += kPhThreads) cur[k] = coarse[(int64_t)K * len + k];
+  __syncthreads();
+  for (int lev = 0; lev < a.levels_v; ++lev) {
+    const int n2 = 2 * len;
+    for (int t = threadIdx.x; t < n2; t += kPhThreads) {
+      double acc = 0.0;
+      for (int m = 0; m < a.n_taps; ++m) {
+        const int r = t - m;
+        if (r & 1) continue;
+        const int k = ((r % n2 + n2) % n2) >> 1;
+        acc = acc + a.taps[m] * cur[k];
+      }
+      nxt[t] = acc;
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    len = n2;
+  }
+  for (int k = threadIdx.x; k < a.n_vf; k += kPhThreads)
+    cols[(int64_t)K * a.n_vf + k] = up_scale * cur[k];
+}
+
+// The CDF work arrays of the repair, [n_vf + 1][n] (node index fastest).
+struct CdfArrays {
+  double* E;  // after the edge reconstruction; at the end the repaired CDF
+  double* P;  // forward interior reconstruction
+  double* M;  // reflected copy for the backward one
+  int n;
+  __device__ double& at(double* A, int k, int i) const { return A[(int64_t)k * n + i]; }
+};
+
+// Edge reconstruction of App. C for entries below 0, on column i of A.
+__device__ void edge_low(const CdfArrays& W, double* A, int i, int nf) {
+  int k0 = -1;
+  for (int k = nf; k >= 0; --k)
+    if (W.at(A, k, i) < 0.0) {
+      k0 = k;
+      break;
+    }
+  if (k0 < 0) return;
+  int km = k0 - 1, kp = k0 + 1;
+  double dF = 0.0;
+  while (true) {
+    const int span = kp - km;
+    double sum = 0.0;
+    for (int k = 1; k < kp; ++k) sum = sum + W.at(A, k, i);
+    dF = 2.0 * sum / (double)(span * (span - 1));
+    if ((0.0 <= (span - 1) * dF && (span - 1) * dF <= W.at(A, kp, i)) || kp >= nf) break;
+    if (km > 0) {
+      --km;
+    } else {
+      ++kp;
+      km = k0 - 1;
+    }
+  }
+  const int k_lo = km > 0 ? km : 0;
+  for (int k = 0; k < k_lo; ++k) W.at(A, k, i) = 0.0;
+  for (int k = k_lo; k < kp; ++k) W.at(A, k, i) = (k - km) * dF;
+}
+
+// Interior reconstruction of App. C from the lower indexes, on column i of A.
+__device__ void interior_forward(const CdfArrays& W, double* A, int i, int nf) {
+  int k0 = 0;
+  while (true) {
+    int j = -1;
+    for (int k = k0; k < nf; ++k)
+      if (W.at(A, k, i) > W.at(A, k + 1, i)) {
+        j = k;
+        break;
+      }
+    if (j < 0) return;
+    k0 = j;
+    const double fk0 = W.at(A, k0, i);
+    int k1 = nf;
+    for (int k = k0 + 1; k <= nf; ++k)
+      if (W.at(A, k, i) >= fk0) {
+        k1 = k;
+        break;
+      }
+    int kp = k0 + 1;
+    for (int k = k0 + 2; k <= k1; ++k)
+      if (W.at(A, k, i) < W.at(A, kp, i)) kp = k;
+    int km = 0;
+    for (int k = k0 - 1; k >= 0; --k)
+      if (W.at(A, k, i) <= W.at(A, kp, i)) {
+        km = k;
+        break;
+      }
+    double dF;
+    while (true) {
+      const int span = kp - km;
+      double sum = 0.0;
+      for (int k = km; k < kp; ++k) sum = sum + W.at(A, k, i);
+      dF = 2.0 / (span - 1) * (sum / span - W.at(A, km, i));
+      if (0.0 <= (span - 1) * dF && W.at(A, km, i) + (span - 1) * dF <= W.at(A, kp, i)) break;
+      if (kp >= nf) {
+        dF = (W.at(A, nf, i) - W.at(A, km, i)) / (nf - km);
+        kp = nf;
+        break;
+      }
+      ++kp;
+    }
+    const double base = W.at(A, km, i);
+    for (int k = km + 1; k < kp; ++k) W.at(A, k, i) = base + (k - km) * dF;
+    k0 = kp;
+  }
+}
+
+// One thread per fine node: the node's column from its two coarse columns by l
+// levels of midpoint interpolation (eq. 3.7), density and CDF (sums in index
+// order), then the repair of App. C: edges, forward and backward interior
+// passes, averaged.  Writes the node density to R.prof_n.
+__global__ __launch_bounds__(kPhThreads) void k_phase_cdf(const RepDev* __restrict__ reps, int rep,
+                                                         const double* __restrict__ cols,
+                                                         int levels, int n_vf, double dv,
+                                                         CdfArrays W) {
+  const RepDev& R = reps[rep];
+  const int n = R.n_cells;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int nxc = n >> levels;
+  const int K = i >> levels;
+  const int K1 = K + 1 == nxc ? 0 : K + 1;
+  double run = 0.0;
+  for (int k = 0; k < n_vf; ++k) {
+    double A = cols[(int64_t)K * n_vf + k];
+    double B = cols[(int64_t)K1 * n_vf + k];
+    for (int j = levels - 1; j >= 0; --j) {  // bits of i below the coarse node, top first
+      const double mid = 0.5 * (A + B);
+      if ((i >> j) & 1) A = mid;
+      else B = mid;
+    }
+    run = run + A;
+    W.at(W.E, k + 1, i) = run;
+  }
+  const double dens = run * dv;
+  gmem(R.prof_n)[i] = dens;
+  if (!(dens > R.n_floor)) return;
+  W.at(W.E, 0, i) = 0.0;
+  for (int k = 1; k < n_vf; ++k) W.at(W.E, k, i) = (W.at(W.E, k, i) * dv) / dens;
+  W.at(W.E, n_vf, i) = 1.0;
+  // edges: below 0 directly, above 1 on the reflected array (always reflected)
+  edge_low(W, W.E, i, n_vf);
+  for (int k = 0; k <= n_vf; ++k) W.at(W.M, k, i) = 1.0 - W.at(W.E, n_vf - k, i);
+  edge_low(W, W.M, i, n_vf);
+  for (int k = 0; k <= n_vf; ++k) W.at(W.E, k, i) = 1.0 - W.at(W.M, n_vf - k, i);
+  // forward pass on a copy, backward pass on the reflection
+  for (int k = 0; k <= n_vf; ++k) {
+    W.at(W.P, k, i) = W.at(W.E, k, i);
+    W.at(W.M, k, i) = 1.0 - W.at(W.E, n_vf - k, i);
+  }
+  interior_forward(W, W.P, i, n_vf);
+  interior_forward(W, W.M, i, n_vf);
+  for (int k = 0; k <= n_vf; ++k)
+    W.at(W.E, k, i) = 0.5 * (W.at(W.P, k, i) + (1.0 - W.at(W.M, n_vf - k, i)));
+}
+
+// v with RF(v) = b in node i's repaired CDF: the last bin k with RF[k] <= b
+// (binary search), linear inside it.
+__device__ double inverse_cdf(const CdfArrays& W, int i, int nf, double b, double v_min,
+                              double dv) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (W.at(W.E, mid, i) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const double f0 = W.at(W.E, lo, i), f1 = W.at(W.E, lo + 1, i);
+  const double t = f1 > f0 ? (b - f0) / (f1 - f0) : 0.5;
+  return v_min + (lo + t) * dv;
+}
+
+// Quiet start from the repaired CDFs: ion m of occupied cell c (rank order) at
+// offset (m + 1/2)/ppc, velocity the inverse CDFs of the cell's two nodes at the
+// Hammersley b, interpolated in x, weight n(X) h / ppc.
+__global__ __launch_bounds__(kPhThreads) void k_phase_load(const RepDev* __restrict__ reps,
+                                                          int rep, CdfArrays W, int n_vf,
+                                                          double v_min, double dv,
+                                                          uint32_t shift) {
+  const RepDev& R = reps[rep];
+  const int n = R.n_cells;
+  const int ppc = R.ppc;
+  const int64_t total = *gmem(R.np);
+  const auto prof_n = gmem(R.prof_n);
+  const auto cell_of_rank = gmem(R.cell_of_rank);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(j / ppc);
+    const int m = (int)(j - (int64_t)r * ppc);
+    const int c = cell_of_rank[r];
+    const int cr = (c + 1) & (n - 1);
+    const float frac = (float)(((double)m + 0.5) / (double)ppc);
+    const double th = (double)frac;
+    const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
+    const uint32_t u = __brev(idx) + shift;
+    const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
+    const double nl = prof_n[c], nr = prof_n[cr];
+    const bool okl = nl > R.n_floor, okr = nr > R.n_floor;
+    double vl = okl ? inverse_cdf(W, c, n_vf, b, v_min, dv) : 0.0;
+    double vr = okr ? inverse_cdf(W, cr, n_vf, b, v_min, dv) : vl;
+    if (!okl) vl = vr;
+    const double v = (1.0 - th) * vl + th * vr;
+    const double nx = (1.0 - th) * fmax(nl, 0.0) + th * fmax(nr, 0.0);
+    gmem(R.cell)[j] = (int16_t)c;
+    gmem(R.frac)[j] = frac;
+    gmem(R.v)[j] = (float)v;
+    gmem(R.w)[j] = (float)(nx * R.h / ppc);
+  }
+}
+
+// Least squares over the snapshots (eq. 3.18) and forward-Euler projection
+// (eq. 3.17) of arbitrary coefficient arrays snap[0..ne][count].
+__global__ void k_phase_project(const double* __restrict__ snap, int64_t count, int ne, double dt,
+                                double macro_dt, double* __restrict__ out) {
+#pragma clang fp contract(off)
+  const double den = (double)ne * (ne + 1) * (ne + 2) * dt;
+  const double leap = macro_dt - ne * dt;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double slope = 0.0;
+    for (int p = 0; p <= ne / 2; ++p) {
+      const double coef = 6.0 * (double)(ne - 2 * p) / den;
+      slope += coef * (snap[(int64_t)(ne - p) * count + k] - snap[(int64_t)p * count + k]);
+    }
+    out[k] = snap[(int64_t)ne * count + k] + leap * slope;
+  }
+}
+
 }  // namespace
+
+void launch_phase_lift(const RepDev* d_reps, int rep, int n_cells, int levels_x, double v_min,
+                       double v_max, int jf, int jc, const double* h_taps, int n_taps,
+                       const double* d_coarse, double* d_cols, double* d_cdf,
+                       uint32_t* d_status, uint32_t shift, hipStream_t stream) {
+  const int n_vf = 1 << jf;
+  const int nxc = n_cells >> levels_x;
+  const double dv = (v_max - v_min) / n_vf;
+  PhaseDwtArg da;
+  da.scale = 0.0;
+  da.n_vf = n_vf;
+  da.levels_v = jf - jc;
+  da.n_taps = n_taps;
+  for (int m = 0; m < 16; ++m) da.taps[m] = m < n_taps ? h_taps[m] : 0.0;
+  const double up_scale = std::pow(2.0, 0.5 * jf) / (v_max - v_min);
+  hipLaunchKernelGGL(k_phase_refine, dim3(nxc), dim3(kPhThreads), sizeof(double) * 2 * n_vf,
+                     stream, d_coarse, da, up_scale, d_cols);
+  CdfArrays W;
+  const size_t plane = (size_t)(n_vf + 1) * n_cells;
+  W.E = d_cdf;
+  W.P = d_cdf + plane;
+  W.M = d_cdf + 2 * plane;
+  W.n = n_cells;
+  hipLaunchKernelGGL(k_phase_cdf, dim3((n_cells + kPhThreads - 1) / kPhThreads), dim3(kPhThreads),
+                     0, stream, d_reps, rep, d_cols, levels_x, n_vf, dv, W);
+  launch_occupancy(d_reps, 0, rep, d_status, stream);
+  hipLaunchKernelGGL(k_phase_load, dim3(2048), dim3(kPhThreads), 0, stream, d_reps, rep, W, n_vf,
+                     v_min, dv, shift);
+}
+
+void launch_phase_project(const double* d_snap, int64_t count, int ne, double dt, double macro_dt,
+                          double* d_out, hipStream_t stream) {
+  const int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(k_phase_project, dim3((unsigned)(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024)),
+                     dim3(256), 0, stream, d_snap, count, ne, dt, macro_dt, d_out);
+}
 
 void launch_phase_restrict(const RepDev* d_reps, int rep, int n_cells, int levels_x, double v_min,
                            double v_max, int jf, int jc, const double* h_taps, int n_taps,
-                           double tau, int fresh, double h, long long* d_hist, double* d_out,
-                           hipStream_t stream) {
+                           double tau, int fresh, int stored_field, double h, long long* d_hist,
+                           double* d_out, hipStream_t stream) {
   const int n_vf = 1 << jf;
   const int nxc = n_cells >> levels_x;
   PhaseHistArg ha;
@@ -157,6 +442,7 @@ void launch_phase_restrict(const RepDev* d_reps, int rep, int n_cells, int level
   ha.n_vf = n_vf;
   ha.win = nxc < kPhWin ? nxc : kPhWin;
   ha.fresh = fresh;
+  ha.stored_field = stored_field;
   launch_fill_u8(d_hist, sizeof(long long) * (size_t)nxc * n_vf, stream);
   const size_t lds = sizeof(long long) * (size_t)ha.win * n_vf;
   hipLaunchKernelGGL(k_phase_hist, dim3(2048), dim3(kPhThreads), lds, stream, d_reps, rep, ha,

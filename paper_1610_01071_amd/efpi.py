@@ -126,7 +126,12 @@ def _load():
         "efpi_ensemble_mean": [P, P],
         "efpi_restrict_state": [P, P],
         "efpi_phase_work_size": [P, I32, ctypes.POINTER(Phase), ctypes.POINTER(ctypes.c_size_t)],
-        "efpi_phase_restrict": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, P, P],
+        "efpi_phase_restrict": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, I32, P, P],
+        "efpi_phase_lift_work_size": [P, I32, ctypes.POINTER(Phase),
+                                      ctypes.POINTER(ctypes.c_size_t)],
+        "efpi_phase_lift": [P, I32, ctypes.POINTER(Phase), P, U32, P],
+        "efpi_phase_project": [P, P, I64, I32, ctypes.c_double, ctypes.c_double, P],
+        "efpi_store_field": [P],
         "efpi_sort": [P],
         "efpi_sync": [P, ctypes.POINTER(U32)],
         "efpi_timing": [P, I32],
@@ -168,6 +173,8 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
             "efpi_restrict_state", "efpi_phase_work_size", "efpi_phase_restrict",
+            "efpi_phase_lift_work_size", "efpi_phase_lift", "efpi_phase_project",
+            "efpi_store_field",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_timing_read_electrons",
             "efpi_last_error",
             "efpi_nn_workspace_size", "efpi_nn_pack", "efpi_nn_forward", "efpi_nn_backward",
@@ -403,11 +410,37 @@ def efpi_phase_work_size(ctx, replica, ph: Phase) -> int:
     return out.value
 
 
-def efpi_phase_restrict(ctx, replica, ph: Phase, tau, work, out):
+def efpi_phase_restrict(ctx, replica, ph: Phase, tau, work, out, stored_field=False):
     if work.data_ptr() % 256:
         raise ValueError("the work buffer must be 256-byte aligned")
     _check(LIB.efpi_phase_restrict(ctx, replica, ctypes.byref(ph), float(tau),
-                                   ctypes.c_void_p(work.data_ptr()), _dev(out, torch.float64)))
+                                   1 if stored_field else 0, ctypes.c_void_p(work.data_ptr()),
+                                   _dev(out, torch.float64)))
+
+
+def efpi_phase_lift_work_size(ctx, replica, ph: Phase) -> int:
+    out = ctypes.c_size_t(0)
+    _check(LIB.efpi_phase_lift_work_size(ctx, replica, ctypes.byref(ph), ctypes.byref(out)))
+    return out.value
+
+
+def efpi_phase_lift(ctx, replica, ph: Phase, coarse, shift: int, work):
+    if work.data_ptr() % 256:
+        raise ValueError("the work buffer must be 256-byte aligned")
+    _check(LIB.efpi_phase_lift(ctx, replica, ctypes.byref(ph), _dev(coarse, torch.float64),
+                               int(shift) & 0xFFFFFFFF, ctypes.c_void_p(work.data_ptr())))
+
+
+def efpi_phase_project(ctx, snap, snapshots, dt, macro_dt, out):
+    count = out.numel()
+    if snap.numel() != count * snapshots:
+        raise ValueError("snap must hold snapshots x out.numel() values")
+    _check(LIB.efpi_phase_project(ctx, _dev(snap, torch.float64), count, snapshots, float(dt),
+                                  float(macro_dt), _dev(out, torch.float64)))
+
+
+def efpi_store_field(ctx):
+    _check(LIB.efpi_store_field(ctx))
 
 
 def efpi_ensemble_mean(ctx, coarse):

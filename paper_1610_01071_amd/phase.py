@@ -1,0 +1,84 @@
+"""Projective integration on phase-space coarse variables (the wavelet-based
+scheme of Sec. 3.3), driven through the C ABI.
+
+A macro step is: efpi_phase_lift (columns back to the fine velocity grid,
+midpoint interpolation in x, CDF repair of App. C, inverse-CDF quiet start),
+efpi_store_field (E_n of the burst start), then for p = 0..N_e the phase-space
+restriction along the co-evolving frame with tau = Delta t - p dt (App. B)
+after p fine steps, and efpi_phase_project (eqs. 3.17-3.18) over the
+snapshots.  Python only sequences the calls and owns the buffers.
+
+The order-4 Coiflet filter the paper uses is not tabulated here: coiflet_taps
+solves its defining conditions (twelve taps, orthonormal, four vanishing
+wavelet moments, scaling-function moments 1..3 vanishing about its centre) by
+least squares.  Those conditions leave the taps ill-conditioned, so another
+solver may land on a slightly different filter with the same properties.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+from scipy.optimize import least_squares
+
+from . import efpi as E
+
+
+def _filter_residuals(h):
+    n = h.size
+    idx = np.arange(n, dtype=np.float64)
+    res = [np.sum(h) - np.sqrt(2.0), np.sum(h * h) - 1.0]
+    res += [np.sum(h[:n - 2 * s] * h[2 * s:]) for s in range(1, n // 2)]
+    hp = np.where(idx % 2 == 0, 1.0, -1.0) * h[::-1]
+    res += [np.sum(hp * idx ** q) for q in range(4)]
+    centre = np.sum(idx * h) / np.sqrt(2.0)
+    res += [np.sum(h * (idx - centre) ** q) for q in (2, 3)]
+    return np.array(res)
+
+
+def coiflet_taps(seed: int = 0) -> np.ndarray:
+    """Twelve low-pass taps satisfying the order-4 Coiflet conditions to 1e-13."""
+    rng = np.random.default_rng(seed)
+    for _ in range(500):
+        fit = least_squares(_filter_residuals, rng.normal(0.0, 0.3, 12), xtol=1e-15, ftol=1e-15,
+                            gtol=1e-15, max_nfev=20000)
+        if np.max(np.abs(_filter_residuals(fit.x))) < 1e-13:
+            return fit.x
+    raise RuntimeError("no filter satisfies the Coiflet conditions")
+
+
+def _aligned(nbytes: int, device) -> torch.Tensor:
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off: off + nbytes]
+
+
+class PhaseStepper:
+    """Buffers and calls of phase-space macro steps for replica 0 of a context."""
+
+    def __init__(self, ctx: E.Context, ph: E.Phase, replica: int = 0):
+        spec = ctx.spec.replicas[replica]
+        self.ctx, self.ph, self.replica, self.spec = ctx, ph, replica, spec
+        dev = ctx.device
+        self.n_coef = (spec.n_cells >> ph.levels) << ph.jc
+        self.hist = _aligned(E.efpi_phase_work_size(ctx.ctx, replica, ph), dev)
+        self.lift_work = _aligned(E.efpi_phase_lift_work_size(ctx.ctx, replica, ph), dev)
+        self.snaps = torch.empty((spec.burst_steps + 1, self.n_coef), dtype=torch.float64,
+                                 device=dev)
+
+    def new_coarse(self) -> torch.Tensor:
+        return torch.zeros(self.n_coef, dtype=torch.float64, device=self.ctx.device)
+
+    def restrict(self, out: torch.Tensor, tau: float = 0.0, stored_field: bool = False):
+        E.efpi_phase_restrict(self.ctx.ctx, self.replica, self.ph, tau, self.hist, out,
+                              stored_field)
+
+    def macro_step(self, coarse_in: torch.Tensor, coarse_out: torch.Tensor, shift: int):
+        s = self.spec
+        E.efpi_phase_lift(self.ctx.ctx, self.replica, self.ph, coarse_in, shift, self.lift_work)
+        E.efpi_store_field(self.ctx.ctx)
+        for p in range(s.burst_steps + 1):
+            if p > 0:
+                E.efpi_pic_burst(self.ctx.ctx, 1, False)
+            self.restrict(self.snaps[p], s.macro_dt - p * s.dt, True)
+        E.efpi_phase_project(self.ctx.ctx, self.snaps, s.burst_steps + 1, s.dt, s.macro_dt,
+                             coarse_out)

@@ -92,3 +92,57 @@ def test_phase_parameters_checked():
                 E.phase(-1, 1, 6, 4, 7, D4), E.phase(-1, 1, 6, 4, 1, D4[:3])):
         with pytest.raises(E.EfpiError):
             E.efpi_phase_work_size(per.ctx, 0, bad)
+
+
+def _phase_state(n, ppc, seed, ps, h):
+    """Coarse phase-space coefficients of a quiet IAW start (oracle load and coarsening)."""
+    from oracle import efpi as oefpi
+    g = opic.Grid(n, float(n))
+    sch = oefpi.Scheme(ppc=ppc, vth=0.316)
+    dens, u = synth.iaw_profile(n, float(n))
+    c, f, v, w = oefpi.load_particles(dens, u, g, sch, synth.lift_shift(seed))
+    x = oefpi.particles_to_x(c, f, g)
+    return ophase.coarsen(ophase.phase_histogram(x, v, w, g, ps), ps, h)
+
+
+@pytest.mark.parametrize("n,levels,jf,jc,ppc", [(128, 2, 6, 4, 40), (256, 3, 7, 5, 24)])
+def test_phase_lift_matches_oracle(n, levels, jf, jc, ppc):
+    E = lib()
+    spec = E.ReplicaSpec(n, float(n), ppc=ppc, haar_levels=2)
+    ctx = E.Context(E.ConfigSpec([spec]))
+    ps = ophase.PhaseScheme(levels=levels, v_min=-2.0, v_max=2.0, jf=jf, jc=jc, ppc=ppc)
+    h = np.array(D4)
+    coarse = _phase_state(n, 50, 3, ps, h)
+    # the D4 reconstruction of a sharp Maxwellian has negative wiggles: the repair runs
+    refined = ophase.refine(coarse, ps, h)
+    assert np.min(refined) < 0.0
+    ph = E.phase(-2.0, 2.0, jf, jc, levels, D4)
+    work = torch.empty(E.efpi_phase_lift_work_size(ctx.ctx, 0, ph) + 256, dtype=torch.uint8,
+                       device="cuda")
+    work = work[(-work.data_ptr()) % 256:]
+    E.efpi_phase_lift(ctx.ctx, 0, ph, torch.as_tensor(coarse.ravel(), device="cuda"), 4242, work)
+    E.efpi_sync(ctx.ctx)
+    gc, gf, gv, gw = particles_np(ctx)
+    rc, rf, rv, rw = ophase.lift_phase(coarse, opic.Grid(n, float(n)), ps, h, 4242)
+    assert np.array_equal(gc, rc) and np.array_equal(gf.astype(np.float64), rf)
+    assert np.max(np.abs(gv - rv)) <= 1e-6 * np.max(np.abs(rv))     # FP32 store
+    assert np.max(np.abs(gw - rw)) <= 1e-6 * np.max(np.abs(rw))
+
+
+def test_phase_macro_step_matches_oracle():
+    from paper_1610_01071_amd.phase import PhaseStepper
+    E = lib()
+    n, ppc = 128, 48
+    spec = E.ReplicaSpec(n, float(n), ppc=ppc, haar_levels=2, burst_steps=6, macro_dt=3.0,
+                         vth=0.316)
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters_start=12))
+    ps = ophase.PhaseScheme(levels=2, v_min=-2.0, v_max=2.0, jf=6, jc=4, burst_steps=6,
+                            macro_dt=3.0, ppc=ppc)
+    h = np.array(D4)
+    coarse = _phase_state(n, 50, 5, ps, h)
+    stepper = PhaseStepper(ctx, E.phase(-2.0, 2.0, 6, 4, 2, D4))
+    out = stepper.new_coarse()
+    stepper.macro_step(torch.as_tensor(coarse.ravel(), device="cuda"), out, 777)
+    E.efpi_sync(ctx.ctx)
+    ref, _ = ophase.phase_macro_step(coarse, opic.Grid(n, float(n)), ps, h, 777)
+    assert metrics.rel_l2(out.view(ref.shape).cpu().numpy(), ref) < 1e-3

@@ -192,3 +192,11 @@ def test_fixed_point_restricted_histogram_equals_full_weighting_of_the_histogram
     c = phase.coarse_from_histogram_fx(H, ps, g.h, h)
     assert np.max(np.abs(c - phase.coarsen(phase.phase_histogram(
         x, v.astype(np.float64), w.astype(np.float64), g, ps), ps, h))) < 1e-9 * np.max(np.abs(c))
+
+
+def test_product_coiflet_taps_satisfy_the_conditions():
+    # the product derives its own filter; any solution of the conditions serves
+    from paper_1610_01071_amd.phase import coiflet_taps
+    taps = coiflet_taps()
+    assert taps.size == 12
+    assert np.max(np.abs(phase.coiflet_conditions(taps))) < 1e-12
