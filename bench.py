@@ -16,7 +16,8 @@ the macro-step wall time, lift included), the roofline of the dominant kernel
 timed region), the EFPI speedup over full PIC for the same physical time with
 the coarse-density error between them (eq. 4.2), forward-Euler, second-order
 and adaptive projective runs against the same full-PIC reference, the same wave
-with kinetic electrons (full two-species PIC against EFPI), the learned projection
+with kinetic electrons (full two-species PIC against EFPI), EFPI on the paper's
+phase-space wavelet coarse variables, the learned projection
 against plain EFPI (wall time and error at the same physical time), and the
 CPU oracle timed on a bounded sample of the same workload on this host.
 """
@@ -156,6 +157,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-slab", action="store_true")
+    ap.add_argument("--no-phase", action="store_true",
+                    help="skip the phase-space (wavelet) coarse-variable runs")
     ap.add_argument("--no-kinetic", action="store_true",
                     help="skip the kinetic-electron fine solver and its EFPI runs")
     ap.add_argument("--kinetic-horizon", type=float, default=60.0,
@@ -312,6 +315,10 @@ def run_bench(args, np, torch, synth, E):
 
     if not args.no_speedup:
         out.update(speedup_sweep(E, torch, np, synth, ctx, spec, c0, args))
+    if not args.no_phase:
+        out["phase_space"] = phase_leg(E, torch, np, synth, c0, args)
+        if not args.no_kinetic:
+            out["phase_space_kinetic"] = phase_leg(E, torch, np, synth, c0, args, kinetic=True)
     if not args.no_kinetic:
         out["kinetic"] = kinetic_leg(E, torch, np, synth, c0, args)
     if not args.no_slab:
@@ -626,6 +633,92 @@ def kinetic_leg(E, torch, np, synth, c0, args):
         "eps_density_reset_pic_vs_pic": eps_of(ref_reset, ref),
         "efpi_speedup_vs_pic": best["speedup"] if best else None,
         "sweep": rows,
+    }
+
+
+def phase_leg(E, torch, np, synth, c0, args, kinetic=False):
+    """Projective integration on phase-space coarse variables (Sec. 3.3): the
+    benchmark wave, 4096 cells and 1000 ions per cell, l = 4 full-weighting levels
+    (256 coarse x nodes), 2^8 velocity bins over [-2, 2) reduced to 2^5 order-4
+    Coiflet scaling coefficients per node (8192 coarse variables), N_e = 20,
+    Delta t = 75 dt, 27 macro steps to t = 202.5.  The start is the phase-space
+    restriction of the lifted benchmark state; full PIC runs from that lifted
+    state.  The error compares the coarse density of the final state (its ions
+    restricted onto the Haar blocks of the benchmark) with full PIC's (eq. 4.2).
+    Also timed: one phase-space restriction of the 4,096,000 ions (histogram,
+    transform) and one phase-space lift."""
+    from paper_1610_01071_amd.phase import PhaseStepper, coiflet_taps
+    steps = 27
+    if kinetic:
+        spec = kinetic_spec(E, macro_dt=7.5)
+        mult = spec.macro_dt / spec.dt
+        start_iters, sort_period = 8, 200
+    else:
+        mult = 75
+        spec = workload_spec(E)
+        spec.macro_dt = mult * spec.dt
+        start_iters, sort_period = 4, args.sort_period
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=start_iters,
+                                 tile=TILE))
+    taps = coiflet_taps()
+    ph = E.phase(-2.0, 2.0, 8, 5, 4, taps)
+    st = PhaseStepper(ctx, ph)
+    shift0 = synth.lift_shift(40_000)
+    E.efpi_lift(ctx.ctx, c0, [shift0])
+    a, b = st.new_coarse(), st.new_coarse()
+    st.restrict(a)
+    # restriction and lift timings
+    reps = 20
+    t_r = timed(torch, lambda: [st.restrict(b) for _ in range(reps)]) / reps
+    t_l = timed(torch, lambda: E.efpi_phase_lift(ctx.ctx, 0, ph, a, 5, st.lift_work))
+    E.efpi_lift(ctx.ctx, c0, [shift0])
+    st.restrict(a)
+    n_ions = spec.n_cells * spec.ppc
+    state = {"a": a, "b": b}
+
+    def run():
+        for i in range(steps):
+            st.macro_step(state["a"], state["b"], synth.lift_shift(40_000 + i))
+            state["a"], state["b"] = state["b"], state["a"]
+
+    t_run = timed(torch, run)
+    bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    # density of the final state through a lift and the Haar restriction
+    E.efpi_phase_lift(ctx.ctx, 0, ph, state["a"], 99, st.lift_work)
+    cfin = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, cfin)
+    got = cfin.view(2, -1)[0].cpu().numpy()
+
+    fine = int(round(steps * mult))
+    pctx = pic_context(E, spec, 2, start_iters)
+
+    def pic_run():
+        E.efpi_lift(pctx.ctx, c0, [shift0])
+        done = 0
+        while done < fine:
+            k = min(sort_period, fine - done)
+            E.efpi_pic_burst(pctx.ctx, k, False)
+            done += k
+            if done < fine:
+                E.efpi_sort(pctx.ctx)
+
+    t_pic = timed(torch, pic_run)
+    cp = pctx.new_coarse()
+    E.efpi_restrict_state(pctx.ctx, cp)
+    E.efpi_sync(pctx.ctx, raise_on_error=False)
+    pctx.close()
+    ctx.close()
+    ref = cp.view(2, -1)[0].cpu().numpy()
+    eps = float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(got * got + ref * ref)))
+    return {
+        "workload": "ion-acoustic wave, kinetic electrons" if kinetic else
+                    "ion-acoustic wave, Boltzmann electrons",
+        "coarse_variables": st.n_coef, "velocity_bins": 256, "scaling_coefficients_per_node": 32,
+        "x_levels": 4, "macro_dt_over_dt": mult, "macro_steps": steps,
+        "ms_per_macro_step": t_run / steps, "efpi_ms": t_run, "pic_ms": t_pic,
+        "speedup_vs_pic": t_pic / t_run, "eps_density_vs_pic": eps,
+        "restrict_us": t_r * 1e3, "restrict_ion_gbs": 14 * n_ions / (t_r * 1e-3) / 1e9,
+        "lift_ms": t_l, "device_status": bits,
     }
 
 

@@ -343,8 +343,8 @@ efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase
                                 double tau, int32_t stored_field, void* d_work, double* d_out);
 
 /* Bytes of the caller-owned work buffer of efpi_phase_lift for replica r: the
- * refined columns [n_cells >> levels][2^jf] and three CDF planes [2^jf + 1][n_cells]
- * (FP64). */
+ * refined columns [n_cells >> levels][2^jf] and the repaired CDFs
+ * [n_cells][2^jf + 1] (FP64). */
 efpi_status efpi_phase_lift_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
                                       size_t* h_bytes);
 
@@ -359,7 +359,8 @@ efpi_status efpi_phase_lift_work_size(efpi_ctx* ctx, int32_t replica, const efpi
  * then ppc ions per occupied cell (a node density above n_floor) at offsets
  * (m + 1/2)/ppc with velocity the two nodes' inverse CDFs (lookup, linear within
  * the bin) at the Hammersley b with rotation `shift`, interpolated in x, and weight
- * n(X) h / ppc.  Not in kinetic contexts (EFPI_ESTATE).  d_work:
+ * n(X) h / ppc.  Kinetic electrons are left as they are: efpi_reset_electrons
+ * then loads them in Boltzmann equilibrium with the lifted ions.  d_work:
  * efpi_phase_lift_work_size bytes, 256-byte aligned. */
 efpi_status efpi_phase_lift(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
                             const double* d_coarse, uint32_t shift, void* d_work);

@@ -1017,7 +1017,7 @@ size_t phase_lift_cols_bytes(const RepDev& d, const efpi_phase* ph) {
   return align256(sizeof(double) * (size_t)(d.n_cells >> ph->levels) * ((size_t)1 << ph->jf));
 }
 size_t phase_lift_cdf_bytes(const RepDev& d, const efpi_phase* ph) {
-  return align256(sizeof(double) * 3 * (((size_t)1 << ph->jf) + 1) * (size_t)d.n_cells);
+  return align256(sizeof(double) * (((size_t)1 << ph->jf) + 1) * (size_t)d.n_cells);
 }
 }  // namespace
 
@@ -1035,7 +1035,6 @@ efpi_status efpi_phase_lift(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph
                             const double* d_coarse, uint32_t shift, void* d_work) {
   const efpi_status st = check_phase(ctx, replica, ph);
   if (st != EFPI_OK) return st;
-  if (ctx->kinetic) return fail(EFPI_ESTATE, "the phase-space lift loads no electrons");
   if (!d_coarse || !d_work) return fail(EFPI_EINVAL, "NULL array");
   if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
     return fail(EFPI_EINVAL, "d_work must be 256-byte aligned");

@@ -164,8 +164,8 @@ void launch_phase_restrict(const RepDev* d_reps, int rep, int n_cells, int level
                            double tau, int fresh, int stored_field, double h, long long* d_hist,
                            double* d_out, hipStream_t stream);
 // Ions of replica rep lifted from phase-space coefficients d_coarse [nxc][2^jc]:
-// columns refined into d_cols [nxc][2^jf], CDFs repaired in d_cdf (3 planes of
-// [2^jf + 1][n_cells]), node densities in R.prof_n, ranks by the occupancy, load.
+// columns refined into d_cols [nxc][2^jf], CDFs repaired into d_cdf
+// [n_cells][2^jf + 1], node densities in R.prof_n, ranks by the occupancy, load.
 void launch_phase_lift(const RepDev* d_reps, int rep, int n_cells, int levels_x, double v_min,
                        double v_max, int jf, int jc, const double* h_taps, int n_taps,
                        const double* d_coarse, double* d_cols, double* d_cdf,

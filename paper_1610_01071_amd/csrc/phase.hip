@@ -184,20 +184,11 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_refine(const double* __res
     cols[(int64_t)K * a.n_vf + k] = up_scale * cur[k];
 }
 
-// The CDF work arrays of the repair, [n_vf + 1][n] (node index fastest).
-struct CdfArrays {
-  double* E;  // after the edge reconstruction; at the end the repaired CDF
-  double* P;  // forward interior reconstruction
-  double* M;  // reflected copy for the backward one
-  int n;
-  __device__ double& at(double* A, int k, int i) const { return A[(int64_t)k * n + i]; }
-};
-
-// Edge reconstruction of App. C for entries below 0, on column i of A.
-__device__ void edge_low(const CdfArrays& W, double* A, int i, int nf) {
+// Edge reconstruction of App. C for entries below 0 of the array A[0..nf].
+__device__ void edge_low(double* A, int nf) {
   int k0 = -1;
   for (int k = nf; k >= 0; --k)
-    if (W.at(A, k, i) < 0.0) {
+    if (A[k] < 0.0) {
       k0 = k;
       break;
     }
@@ -207,9 +198,9 @@ __device__ void edge_low(const CdfArrays& W, double* A, int i, int nf) {
   while (true) {
     const int span = kp - km;
     double sum = 0.0;
-    for (int k = 1; k < kp; ++k) sum = sum + W.at(A, k, i);
+    for (int k = 1; k < kp; ++k) sum = sum + A[k];
     dF = 2.0 * sum / (double)(span * (span - 1));
-    if ((0.0 <= (span - 1) * dF && (span - 1) * dF <= W.at(A, kp, i)) || kp >= nf) break;
+    if ((0.0 <= (span - 1) * dF && (span - 1) * dF <= A[kp]) || kp >= nf) break;
     if (km > 0) {
       --km;
     } else {
@@ -218,35 +209,35 @@ __device__ void edge_low(const CdfArrays& W, double* A, int i, int nf) {
     }
   }
   const int k_lo = km > 0 ? km : 0;
-  for (int k = 0; k < k_lo; ++k) W.at(A, k, i) = 0.0;
-  for (int k = k_lo; k < kp; ++k) W.at(A, k, i) = (k - km) * dF;
+  for (int k = 0; k < k_lo; ++k) A[k] = 0.0;
+  for (int k = k_lo; k < kp; ++k) A[k] = (k - km) * dF;
 }
 
-// Interior reconstruction of App. C from the lower indexes, on column i of A.
-__device__ void interior_forward(const CdfArrays& W, double* A, int i, int nf) {
+// Interior reconstruction of App. C from the lower indexes on A[0..nf].
+__device__ void interior_forward(double* A, int nf) {
   int k0 = 0;
   while (true) {
     int j = -1;
     for (int k = k0; k < nf; ++k)
-      if (W.at(A, k, i) > W.at(A, k + 1, i)) {
+      if (A[k] > A[k + 1]) {
         j = k;
         break;
       }
     if (j < 0) return;
     k0 = j;
-    const double fk0 = W.at(A, k0, i);
+    const double fk0 = A[k0];
     int k1 = nf;
     for (int k = k0 + 1; k <= nf; ++k)
-      if (W.at(A, k, i) >= fk0) {
+      if (A[k] >= fk0) {
         k1 = k;
         break;
       }
     int kp = k0 + 1;
     for (int k = k0 + 2; k <= k1; ++k)
-      if (W.at(A, k, i) < W.at(A, kp, i)) kp = k;
+      if (A[k] < A[kp]) kp = k;
     int km = 0;
     for (int k = k0 - 1; k >= 0; --k)
-      if (W.at(A, k, i) <= W.at(A, kp, i)) {
+      if (A[k] <= A[kp]) {
         km = k;
         break;
       }
@@ -254,82 +245,100 @@ __device__ void interior_forward(const CdfArrays& W, double* A, int i, int nf) {
     while (true) {
       const int span = kp - km;
       double sum = 0.0;
-      for (int k = km; k < kp; ++k) sum = sum + W.at(A, k, i);
-      dF = 2.0 / (span - 1) * (sum / span - W.at(A, km, i));
-      if (0.0 <= (span - 1) * dF && W.at(A, km, i) + (span - 1) * dF <= W.at(A, kp, i)) break;
+      for (int k = km; k < kp; ++k) sum = sum + A[k];
+      dF = 2.0 / (span - 1) * (sum / span - A[km]);
+      if (0.0 <= (span - 1) * dF && A[km] + (span - 1) * dF <= A[kp]) break;
       if (kp >= nf) {
-        dF = (W.at(A, nf, i) - W.at(A, km, i)) / (nf - km);
+        dF = (A[nf] - A[km]) / (nf - km);
         kp = nf;
         break;
       }
       ++kp;
     }
-    const double base = W.at(A, km, i);
-    for (int k = km + 1; k < kp; ++k) W.at(A, k, i) = base + (k - km) * dF;
+    const double base = A[km];
+    for (int k = km + 1; k < kp; ++k) A[k] = base + (k - km) * dF;
     k0 = kp;
   }
 }
 
-// One thread per fine node: the node's column from its two coarse columns by l
-// levels of midpoint interpolation (eq. 3.7), density and CDF (sums in index
-// order), then the repair of App. C: edges, forward and backward interior
-// passes, averaged.  Writes the node density to R.prof_n.
-__global__ __launch_bounds__(kPhThreads) void k_phase_cdf(const RepDev* __restrict__ reps, int rep,
-                                                         const double* __restrict__ cols,
-                                                         int levels, int n_vf, double dv,
-                                                         CdfArrays W) {
+// One wave per fine node, the node's arrays in LDS: the lanes build the column
+// from its two coarse columns by l levels of midpoint interpolation (eq. 3.7);
+// lane 0 takes the density and CDF (sums in index order) and runs the repair of
+// App. C (edges, forward and backward interior passes, averaged) on LDS; the
+// lanes write the repaired CDF rf[i][0..n_vf] and the density to R.prof_n.
+__global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ reps, int rep,
+                                                    const double* __restrict__ cols, int levels,
+                                                    int n_vf, double dv,
+                                                    double* __restrict__ rf) {
+  extern __shared__ double s_cdf[];  // E, P, M: 3 x (n_vf + 1)
   const RepDev& R = reps[rep];
   const int n = R.n_cells;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int nf = n_vf;
+  double* sE = s_cdf;
+  double* sP = s_cdf + (nf + 1);
+  double* sM = s_cdf + 2 * (nf + 1);
   const int nxc = n >> levels;
   const int K = i >> levels;
   const int K1 = K + 1 == nxc ? 0 : K + 1;
-  double run = 0.0;
-  for (int k = 0; k < n_vf; ++k) {
-    double A = cols[(int64_t)K * n_vf + k];
-    double B = cols[(int64_t)K1 * n_vf + k];
+  for (int k = lane; k < nf; k += kWave) {
+    double A = cols[(int64_t)K * nf + k];
+    double B = cols[(int64_t)K1 * nf + k];
     for (int j = levels - 1; j >= 0; --j) {  // bits of i below the coarse node, top first
       const double mid = 0.5 * (A + B);
       if ((i >> j) & 1) A = mid;
       else B = mid;
     }
-    run = run + A;
-    W.at(W.E, k + 1, i) = run;
+    sP[k] = A;
   }
-  const double dens = run * dv;
-  gmem(R.prof_n)[i] = dens;
-  if (!(dens > R.n_floor)) return;
-  W.at(W.E, 0, i) = 0.0;
-  for (int k = 1; k < n_vf; ++k) W.at(W.E, k, i) = (W.at(W.E, k, i) * dv) / dens;
-  W.at(W.E, n_vf, i) = 1.0;
-  // edges: below 0 directly, above 1 on the reflected array (always reflected)
-  edge_low(W, W.E, i, n_vf);
-  for (int k = 0; k <= n_vf; ++k) W.at(W.M, k, i) = 1.0 - W.at(W.E, n_vf - k, i);
-  edge_low(W, W.M, i, n_vf);
-  for (int k = 0; k <= n_vf; ++k) W.at(W.E, k, i) = 1.0 - W.at(W.M, n_vf - k, i);
-  // forward pass on a copy, backward pass on the reflection
-  for (int k = 0; k <= n_vf; ++k) {
-    W.at(W.P, k, i) = W.at(W.E, k, i);
-    W.at(W.M, k, i) = 1.0 - W.at(W.E, n_vf - k, i);
+  __syncthreads();
+  __shared__ double s_dens;
+  if (lane == 0) {
+    double run = 0.0;
+    for (int k = 0; k < nf; ++k) {
+      run = run + sP[k];
+      sE[k + 1] = run;
+    }
+    const double dens = run * dv;
+    s_dens = dens;
+    gmem(R.prof_n)[i] = dens;
+    if (dens > R.n_floor) {
+      sE[0] = 0.0;
+      for (int k = 1; k < nf; ++k) sE[k] = (sE[k] * dv) / dens;
+      sE[nf] = 1.0;
+      // edges: below 0 directly, above 1 on the reflected array (always reflected)
+      edge_low(sE, nf);
+      for (int k = 0; k <= nf; ++k) sM[k] = 1.0 - sE[nf - k];
+      edge_low(sM, nf);
+      for (int k = 0; k <= nf; ++k) sE[k] = 1.0 - sM[nf - k];
+      // forward pass on a copy, backward pass on the reflection
+      for (int k = 0; k <= nf; ++k) {
+        sP[k] = sE[k];
+        sM[k] = 1.0 - sE[nf - k];
+      }
+      interior_forward(sP, nf);
+      interior_forward(sM, nf);
+      for (int k = 0; k <= nf; ++k) sE[k] = 0.5 * (sP[k] + (1.0 - sM[nf - k]));
+    }
   }
-  interior_forward(W, W.P, i, n_vf);
-  interior_forward(W, W.M, i, n_vf);
-  for (int k = 0; k <= n_vf; ++k)
-    W.at(W.E, k, i) = 0.5 * (W.at(W.P, k, i) + (1.0 - W.at(W.M, n_vf - k, i)));
+  __syncthreads();
+  if (!(s_dens > R.n_floor)) return;
+  for (int k = lane; k <= nf; k += kWave) rf[(int64_t)i * (nf + 1) + k] = sE[k];
 }
 
-// v with RF(v) = b in node i's repaired CDF: the last bin k with RF[k] <= b
-// (binary search), linear inside it.
-__device__ double inverse_cdf(const CdfArrays& W, int i, int nf, double b, double v_min,
-                              double dv) {
+// v with RF(v) = b in node i's repaired CDF rf[i][0..nf]: the last bin k with
+// RF[k] <= b (binary search), linear inside it.
+__device__ double inverse_cdf(const double* __restrict__ rf, int i, int nf, double b,
+                              double v_min, double dv) {
+  const double* F = rf + (int64_t)i * (nf + 1);
   int lo = 0, hi = nf - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (W.at(W.E, mid, i) <= b) lo = mid;
+    if (F[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
-  const double f0 = W.at(W.E, lo, i), f1 = W.at(W.E, lo + 1, i);
+  const double f0 = F[lo], f1 = F[lo + 1];
   const double t = f1 > f0 ? (b - f0) / (f1 - f0) : 0.5;
   return v_min + (lo + t) * dv;
 }
@@ -338,8 +347,8 @@ __device__ double inverse_cdf(const CdfArrays& W, int i, int nf, double b, doubl
 // offset (m + 1/2)/ppc, velocity the inverse CDFs of the cell's two nodes at the
 // Hammersley b, interpolated in x, weight n(X) h / ppc.
 __global__ __launch_bounds__(kPhThreads) void k_phase_load(const RepDev* __restrict__ reps,
-                                                          int rep, CdfArrays W, int n_vf,
-                                                          double v_min, double dv,
+                                                          int rep, const double* __restrict__ rf,
+                                                          int n_vf, double v_min, double dv,
                                                           uint32_t shift) {
   const RepDev& R = reps[rep];
   const int n = R.n_cells;
@@ -360,8 +369,8 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_load(const RepDev* __restr
     const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
     const double nl = prof_n[c], nr = prof_n[cr];
     const bool okl = nl > R.n_floor, okr = nr > R.n_floor;
-    double vl = okl ? inverse_cdf(W, c, n_vf, b, v_min, dv) : 0.0;
-    double vr = okr ? inverse_cdf(W, cr, n_vf, b, v_min, dv) : vl;
+    double vl = okl ? inverse_cdf(rf, c, n_vf, b, v_min, dv) : 0.0;
+    double vr = okr ? inverse_cdf(rf, cr, n_vf, b, v_min, dv) : vl;
     if (!okl) vl = vr;
     const double v = (1.0 - th) * vl + th * vr;
     const double nx = (1.0 - th) * fmax(nl, 0.0) + th * fmax(nr, 0.0);
@@ -408,17 +417,11 @@ void launch_phase_lift(const RepDev* d_reps, int rep, int n_cells, int levels_x,
   const double up_scale = std::pow(2.0, 0.5 * jf) / (v_max - v_min);
   hipLaunchKernelGGL(k_phase_refine, dim3(nxc), dim3(kPhThreads), sizeof(double) * 2 * n_vf,
                      stream, d_coarse, da, up_scale, d_cols);
-  CdfArrays W;
-  const size_t plane = (size_t)(n_vf + 1) * n_cells;
-  W.E = d_cdf;
-  W.P = d_cdf + plane;
-  W.M = d_cdf + 2 * plane;
-  W.n = n_cells;
-  hipLaunchKernelGGL(k_phase_cdf, dim3((n_cells + kPhThreads - 1) / kPhThreads), dim3(kPhThreads),
-                     0, stream, d_reps, rep, d_cols, levels_x, n_vf, dv, W);
+  hipLaunchKernelGGL(k_phase_cdf, dim3(n_cells), dim3(kWave), sizeof(double) * 3 * (n_vf + 1),
+                     stream, d_reps, rep, d_cols, levels_x, n_vf, dv, d_cdf);
   launch_occupancy(d_reps, 0, rep, d_status, stream);
-  hipLaunchKernelGGL(k_phase_load, dim3(2048), dim3(kPhThreads), 0, stream, d_reps, rep, W, n_vf,
-                     v_min, dv, shift);
+  hipLaunchKernelGGL(k_phase_load, dim3(2048), dim3(kPhThreads), 0, stream, d_reps, rep, d_cdf,
+                     n_vf, v_min, dv, shift);
 }
 
 void launch_phase_project(const double* d_snap, int64_t count, int ne, double dt, double macro_dt,

@@ -3,7 +3,8 @@ scheme of Sec. 3.3), driven through the C ABI.
 
 A macro step is: efpi_phase_lift (columns back to the fine velocity grid,
 midpoint interpolation in x, CDF repair of App. C, inverse-CDF quiet start),
-efpi_store_field (E_n of the burst start), then for p = 0..N_e the phase-space
+with kinetic electrons efpi_reset_electrons (Boltzmann electrons for the lifted
+ions), efpi_store_field (E_n of the burst start), then for p = 0..N_e the phase-space
 restriction along the co-evolving frame with tau = Delta t - p dt (App. B)
 after p fine steps, and efpi_phase_project (eqs. 3.17-3.18) over the
 snapshots.  Python only sequences the calls and owns the buffers.
@@ -75,6 +76,10 @@ class PhaseStepper:
     def macro_step(self, coarse_in: torch.Tensor, coarse_out: torch.Tensor, shift: int):
         s = self.spec
         E.efpi_phase_lift(self.ctx.ctx, self.replica, self.ph, coarse_in, shift, self.lift_work)
+        if s.closure == E.CLOSURE_KINETIC:
+            # electrons in Boltzmann equilibrium with the lifted ions (their density
+            # and mean velocity), as at every kinetic lift
+            E.efpi_reset_electrons(self.ctx.ctx, [shift] * len(self.ctx.spec.replicas))
         E.efpi_store_field(self.ctx.ctx)
         for p in range(s.burst_steps + 1):
             if p > 0:
