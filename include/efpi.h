@@ -315,7 +315,7 @@ efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in,
  * (for the paper's scheme, the 12-tap order-4 Coiflet). */
 typedef struct {
   double v_min, v_max;   /* velocity window                                          */
-  int32_t jf;            /* 2^jf fine velocity bins, 4 <= jf <= 10                    */
+  int32_t jf;            /* 2^jf fine velocity bins, 4 <= jf <= 11                    */
   int32_t jc;            /* 2^jc coarse coefficients per x node, jc <= jf, 2^jc >= n_taps */
   int32_t levels;        /* full-weighting levels in x, n_cells >> levels >= 1        */
   int32_t n_taps;        /* filter length, even, 2 <= n_taps <= 16                    */

@@ -969,7 +969,8 @@ efpi_status check_phase(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph) {
   if (d.bc != EFPI_BC_PERIODIC) return fail(EFPI_EINVAL, "phase restriction needs a periodic replica");
   if (!(ph->v_max > ph->v_min) || !std::isfinite(ph->v_min) || !std::isfinite(ph->v_max))
     return fail(EFPI_EINVAL, "need finite v_min < v_max");
-  if (ph->jf < 4 || ph->jf > 10) return fail(EFPI_EINVAL, "jf must be in [4, 10]");
+  // jf = 11 fills 64 KB of LDS with the histogram window (four x nodes x 2^11 int64)
+  if (ph->jf < 4 || ph->jf > 11) return fail(EFPI_EINVAL, "jf must be in [4, 11]");
   if (ph->jc < 1 || ph->jc > ph->jf) return fail(EFPI_EINVAL, "jc must be in [1, jf]");
   if (ph->n_taps < 2 || ph->n_taps > 16 || (ph->n_taps & 1))
     return fail(EFPI_EINVAL, "n_taps must be even in [2, 16]");

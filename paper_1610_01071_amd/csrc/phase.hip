@@ -25,6 +25,7 @@ constexpr int kPhThreads = 256;
 constexpr int kPhTile = 2048;  // ions per work item
 constexpr int kPhWin = 4;      // coarse x nodes of a work item's LDS window
 constexpr int kPhGrid = 8192;  // workgroups, striding over the work items
+static_assert(kPhWin * 2048 * sizeof(long long) <= 65536, "window of 2^11 bins over 64 KB");
 
 struct PhaseHistArg {
   double v_min, inv_dv;
@@ -188,68 +189,126 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_refine(const double* __res
     cols[(int64_t)K * a.n_vf + k] = up_scale * cur[k];
 }
 
-// Edge reconstruction of App. C for entries below 0 of the array A[0..nf].
-__device__ void edge_low(double* A, int nf) {
+// The repair of App. C below runs on a whole wave over one node's LDS arrays.
+// Every search that the method defines as "the first index in a given order with
+// a property" tests 64 candidates at once and takes the first set lane of the
+// ballot; each candidate is computed with the same operations as in a sequential
+// scan, so the chosen index and every stored value are those of the sequential
+// method.  Sums over the array stay sequential in index order (the same on all
+// lanes, from broadcast LDS reads), since the method's decisions compare them.
+
+// Index of the first set lane of a ballot (m != 0).
+__device__ __forceinline__ int first_lane(unsigned long long m) { return __ffsll(m) - 1; }
+
+// Edge reconstruction of App. C for entries below 0 of the array A[0..nf]: k0 is
+// the last negative entry; for each right end kp rising from k0 + 1 the first left
+// end km (falling from k0 - 1 to 0) whose momentum-conserving ramp from 0 stays in
+// [0, A[kp]] is taken; the right end nf is taken unconditionally.
+__device__ void edge_low(double* A, int nf, int lane) {
   int k0 = -1;
-  for (int k = nf; k >= 0; --k)
-    if (A[k] < 0.0) {
-      k0 = k;
+  for (int top = nf; top >= 0; top -= kWave) {
+    const int k = top - lane;
+    const unsigned long long m = __ballot(k >= 0 && A[k] < 0.0);
+    if (m) {
+      k0 = top - first_lane(m);
       break;
     }
+  }
   if (k0 < 0) return;
-  // for each right end kp (rising from k0 + 1) the left end km falls from k0 - 1 to 0;
-  // the sum A[1] + ... + A[kp - 1] (index order) depends on kp only and grows by
-  // one term as kp moves right
+  // A[1] + ... + A[kp - 1] in index order, one term more per step of kp
+  double sum = 0.0;
+  for (int k = 1; k <= k0; ++k) sum = sum + A[k];
+  const int n_cand = k0 >= 1 ? k0 : 1;  // km = k0 - 1 - j, j < n_cand (km = -1 if k0 = 0)
   int km = k0 - 1, kp = k0 + 1;
-  double dF = 0.0, sum = 0.0;
-  for (int k = 1; k < kp; ++k) sum = sum + A[k];
   for (;; ++kp) {
-    bool done = false;
-    for (km = k0 - 1;; --km) {
-      const int span = kp - km;
-      dF = 2.0 * sum / (double)(span * (span - 1));
-      if ((0.0 <= (span - 1) * dF && (span - 1) * dF <= A[kp]) || kp >= nf) {
-        done = true;
+    if (kp >= nf) {
+      km = k0 - 1;
+      break;
+    }
+    bool found = false;
+    for (int j0 = 0; j0 < n_cand; j0 += kWave) {
+      const int j = j0 + lane;
+      bool ok = false;
+      if (j < n_cand) {
+        const int span = kp - (k0 - 1 - j);
+        const double d = 2.0 * sum / (double)(span * (span - 1));
+        ok = 0.0 <= (span - 1) * d && (span - 1) * d <= A[kp];
+      }
+      const unsigned long long m = __ballot(ok);
+      if (m) {
+        km = k0 - 1 - (j0 + first_lane(m));
+        found = true;
         break;
       }
-      if (km <= 0) break;
     }
-    if (done) break;
+    if (found) break;
     sum = sum + A[kp];
   }
+  const int span = kp - km;
+  const double dF = 2.0 * sum / (double)(span * (span - 1));
   const int k_lo = km > 0 ? km : 0;
-  for (int k = 0; k < k_lo; ++k) A[k] = 0.0;
-  for (int k = k_lo; k < kp; ++k) A[k] = (k - km) * dF;
+  __syncthreads();  // every lane has read A before any lane writes the ramp
+  for (int k = lane; k < kp; k += kWave) A[k] = k < k_lo ? 0.0 : (k - km) * dF;
+  __syncthreads();
 }
 
-// Interior reconstruction of App. C from the lower indexes on A[0..nf].
-__device__ void interior_forward(double* A, int nf) {
+// Interior reconstruction of App. C from the lower indexes on A[0..nf]: at each
+// first decrease k0 the ramp starts at k_- (the last earlier entry not above
+// A[k_+]) and ends at k_+ (the first minimum before the array climbs back to
+// A[k0]), and k_+ moves right until the momentum-conserving ramp is monotone.
+__device__ void interior_forward(double* A, int nf, int lane) {
   int k0 = 0;
   while (true) {
     int j = -1;
-    for (int k = k0; k < nf; ++k)
-      if (A[k] > A[k + 1]) {
-        j = k;
+    for (int b = k0; b < nf; b += kWave) {
+      const int k = b + lane;
+      const unsigned long long m = __ballot(k < nf && A[k] > A[k + 1]);
+      if (m) {
+        j = b + first_lane(m);
         break;
       }
+    }
     if (j < 0) return;
     k0 = j;
     const double fk0 = A[k0];
     int k1 = nf;
-    for (int k = k0 + 1; k <= nf; ++k)
-      if (A[k] >= fk0) {
-        k1 = k;
+    for (int b = k0 + 1; b <= nf; b += kWave) {
+      const int k = b + lane;
+      const unsigned long long m = __ballot(k <= nf && A[k] >= fk0);
+      if (m) {
+        k1 = b + first_lane(m);
         break;
       }
-    int kp = k0 + 1;
-    for (int k = k0 + 2; k <= k1; ++k)
-      if (A[k] < A[kp]) kp = k;
+    }
+    // first index of the minimum over [k0 + 1, k1]: (value, index) reduced over the wave
+    double best = A[k0 + 1];
+    int at = k0 + 1;
+    for (int k = k0 + 1 + lane; k <= k1; k += kWave) {
+      const double a = A[k];
+      if (a < best || (a == best && k < at)) {
+        best = a;
+        at = k;
+      }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oa = __shfl_xor(at, off);
+      if (ob < best || (ob == best && oa < at)) {
+        best = ob;
+        at = oa;
+      }
+    }
+    int kp = at;
+    const double fkp = A[kp];
     int km = 0;
-    for (int k = k0 - 1; k >= 0; --k)
-      if (A[k] <= A[kp]) {
-        km = k;
+    for (int top = k0 - 1; top >= 0; top -= kWave) {
+      const int k = top - lane;
+      const unsigned long long m = __ballot(k >= 0 && A[k] <= fkp);
+      if (m) {
+        km = top - first_lane(m);
         break;
       }
+    }
     // sum of A[km .. kp - 1] in index order, extended by one term as kp moves right
     double dF, sum = 0.0;
     for (int k = km; k < kp; ++k) sum = sum + A[k];
@@ -266,7 +325,9 @@ __device__ void interior_forward(double* A, int nf) {
       ++kp;
     }
     const double base = A[km];
-    for (int k = km + 1; k < kp; ++k) A[k] = base + (k - km) * dF;
+    __syncthreads();
+    for (int k = km + 1 + lane; k < kp; k += kWave) A[k] = base + (k - km) * dF;
+    __syncthreads();
     k0 = kp;
   }
 }
@@ -274,9 +335,8 @@ __device__ void interior_forward(double* A, int nf) {
 // One wave per fine node, the node's arrays in LDS: the lanes build the column
 // from its two coarse columns by l levels of midpoint interpolation (eq. 3.7);
 // lane 0 takes the density and CDF sums in index order; the repair of App. C
-// follows (edges, forward and backward interior passes, averaged), its searches
-// on lane 0 (the two interior passes side by side on lanes 0 and 1) and its
-// elementwise steps on all lanes.  The lanes write the repaired CDF
+// follows (edges, forward and backward interior passes, averaged) on the whole
+// wave.  The lanes write the repaired CDF
 // rf[i][0..n_vf] and lane 0 the density to R.prof_n.
 __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ reps, int rep,
                                                     const double* __restrict__ cols, int levels,
@@ -319,30 +379,28 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
   __syncthreads();
   const double dens = s_dens;
   if (!(dens > R.n_floor)) return;  // the same for every lane of the workgroup
-  // the elementwise steps run on all lanes, the sequential searches on lane 0
+  // normalisation on all lanes; the repair below runs on the whole wave
   for (int k = 1 + lane; k < nf; k += kWave) sE[k] = (sE[k] * dv) / dens;
-  __syncthreads();
   if (lane == 0) {
     sE[0] = 0.0;
     sE[nf] = 1.0;
-    edge_low(sE, nf);  // entries below 0
   }
   __syncthreads();
+  edge_low(sE, nf, lane);  // entries below 0
   // entries above 1: the same rule on the reflected array
   for (int k = lane; k <= nf; k += kWave) sM[k] = 1.0 - sE[nf - k];
   __syncthreads();
-  if (lane == 0) edge_low(sM, nf);
-  __syncthreads();
+  edge_low(sM, nf, lane);
   for (int k = lane; k <= nf; k += kWave) sE[k] = 1.0 - sM[nf - k];
   __syncthreads();
-  // forward pass on a copy (lane 0), backward pass on the reflection (lane 1)
+  // forward pass on a copy, backward pass on the reflection
   for (int k = lane; k <= nf; k += kWave) {
     sP[k] = sE[k];
     sM[k] = 1.0 - sE[nf - k];
   }
   __syncthreads();
-  if (lane < 2) interior_forward(lane == 0 ? sP : sM, nf);
-  __syncthreads();
+  interior_forward(sP, nf, lane);
+  interior_forward(sM, nf, lane);
   for (int k = lane; k <= nf; k += kWave)
     rf[(int64_t)i * (nf + 1) + k] = 0.5 * (sP[k] + (1.0 - sM[nf - k]));
 }

@@ -1,7 +1,8 @@
 """Phase-space restriction on the GPU (efpi_phase_restrict) against the oracle.
 
 Bars: the int64 restricted histogram bit-exact against the oracle's integer
-form (same quantisation, fresh ions, tau = 0, power-of-two bin widths); the
+form (same quantisation, fresh ions, tau = 0, power-of-two bin widths, 2^5 to
+2^11 bins); the
 coarse coefficients within 1e-13 of the oracle's transform of that histogram,
 for the closed-form 4-tap Daubechies filter and for 12 seeded taps; after a
 burst, along the co-evolving frame, within eps = 1e-4 (eq. 4.2) of the FP64
@@ -39,7 +40,8 @@ def run(E, ctx, ph, tau=0.0, replica=0):
 
 
 @pytest.mark.parametrize("n_cells,levels,jf,jc,taps", [
-    (256, 2, 6, 4, "d4"), (1024, 4, 8, 5, "taps12"), (64, 0, 5, 4, "d4"), (4096, 4, 10, 6, "d4")])
+    (256, 2, 6, 4, "d4"), (1024, 4, 8, 5, "taps12"), (64, 0, 5, 4, "d4"), (4096, 4, 10, 6, "d4"),
+    (512, 2, 11, 6, "taps12")])
 def test_histogram_bitexact_and_coefficients(n_cells, levels, jf, jc, taps):
     E = lib()
     spec = E.ReplicaSpec(n_cells, float(n_cells), ppc=30, haar_levels=2)
@@ -89,7 +91,8 @@ def test_phase_parameters_checked():
     per = E.Context(E.ConfigSpec([E.ReplicaSpec(64, 64.0, ppc=4)]))
     for bad in (E.phase(-1, 1, 3, 2, 1, D4), E.phase(1, -1, 6, 4, 1, D4),
                 E.phase(-1, 1, 6, 7, 1, D4), E.phase(-1, 1, 6, 1, 1, D4),
-                E.phase(-1, 1, 6, 4, 7, D4), E.phase(-1, 1, 6, 4, 1, D4[:3])):
+                E.phase(-1, 1, 6, 4, 7, D4), E.phase(-1, 1, 6, 4, 1, D4[:3]),
+                E.phase(-1, 1, 12, 6, 1, D4)):
         with pytest.raises(E.EfpiError):
             E.efpi_phase_work_size(per.ctx, 0, bad)
 
@@ -105,7 +108,8 @@ def _phase_state(n, ppc, seed, ps, h):
     return ophase.coarsen(ophase.phase_histogram(x, v, w, g, ps), ps, h)
 
 
-@pytest.mark.parametrize("n,levels,jf,jc,ppc", [(128, 2, 6, 4, 40), (256, 3, 7, 5, 24)])
+@pytest.mark.parametrize("n,levels,jf,jc,ppc", [(128, 2, 6, 4, 40), (256, 3, 7, 5, 24),
+                                                 (128, 2, 11, 6, 24)])
 def test_phase_lift_matches_oracle(n, levels, jf, jc, ppc):
     E = lib()
     spec = E.ReplicaSpec(n, float(n), ppc=ppc, haar_levels=2)
