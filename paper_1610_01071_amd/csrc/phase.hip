@@ -19,11 +19,11 @@ namespace efpi {
 namespace {
 
 constexpr int kPhThreads = 256;
-// 2048 ions per work item and a window of 4 coarse nodes: 34 us per restriction of
-// 4,096,000 ions against 41 us at 4096 ions and 8 nodes (the result is the same
-// integer histogram for any tile and window)
-constexpr int kPhTile = 2048;  // ions per work item
-constexpr int kPhWin = 4;      // coarse x nodes of a work item's LDS window
+// At 2^8 bins, 2048 ions per work item and a window of 4 coarse nodes: 34 us per
+// restriction of 4,096,000 ions against 41 us at 4096 ions and 8 nodes (the result
+// is the same integer histogram for any tile and window)
+constexpr int kPhTile = 2048;  // ions per work item (at least)
+constexpr int kPhWin = 4;      // coarse x nodes of a work item's LDS window (at most)
 constexpr int kPhGrid = 8192;  // workgroups, striding over the work items
 static_assert(kPhWin * 2048 * sizeof(long long) <= 65536, "window of 2^11 bins over 64 KB");
 
@@ -197,6 +197,21 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_refine(const double* __res
 // method.  Sums over the array stay sequential in index order (the same on all
 // lanes, from broadcast LDS reads), since the method's decisions compare them.
 
+// s + A[lo] + A[lo + 1] + ... + A[hi - 1], added in index order; the loads are
+// issued eight at a time ahead of the additions.
+__device__ double seq_sum(const double* A, int lo, int hi, double s) {
+  int k = lo;
+  for (; k + 8 <= hi; k += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = A[k + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = s + v[u];
+  }
+  for (; k < hi; ++k) s = s + A[k];
+  return s;
+}
+
 // Index of the first set lane of a ballot (m != 0).
 __device__ __forceinline__ int first_lane(unsigned long long m) { return __ffsll(m) - 1; }
 
@@ -216,8 +231,7 @@ __device__ void edge_low(double* A, int nf, int lane) {
   }
   if (k0 < 0) return;
   // A[1] + ... + A[kp - 1] in index order, one term more per step of kp
-  double sum = 0.0;
-  for (int k = 1; k <= k0; ++k) sum = sum + A[k];
+  double sum = seq_sum(A, 1, k0 + 1, 0.0);
   const int n_cand = k0 >= 1 ? k0 : 1;  // km = k0 - 1 - j, j < n_cand (km = -1 if k0 = 0)
   int km = k0 - 1, kp = k0 + 1;
   for (;; ++kp) {
@@ -310,8 +324,7 @@ __device__ void interior_forward(double* A, int nf, int lane) {
       }
     }
     // sum of A[km .. kp - 1] in index order, extended by one term as kp moves right
-    double dF, sum = 0.0;
-    for (int k = km; k < kp; ++k) sum = sum + A[k];
+    double dF, sum = seq_sum(A, km, kp, 0.0);
     while (true) {
       const int span = kp - km;
       dF = 2.0 / (span - 1) * (sum / span - A[km]);
@@ -368,9 +381,15 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
   __shared__ double s_dens;
   if (lane == 0) {
     double run = 0.0;
-    for (int k = 0; k < nf; ++k) {
-      run = run + sP[k];
-      sE[k + 1] = run;
+    for (int k = 0; k < nf; k += 8) {  // nf is a power of two >= 16
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = sP[k + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        run = run + v[u];
+        sE[k + u + 1] = run;
+      }
     }
     const double dens = run * dv;
     s_dens = dens;
@@ -521,8 +540,13 @@ void launch_phase_restrict(const RepDev* d_reps, int rep, int n_cells, int level
   ha.tau = (float)tau;
   ha.levels = levels_x;
   ha.n_vf = n_vf;
-  ha.win = nxc < kPhWin ? nxc : kPhWin;
-  ha.tile = kPhTile;
+  // the window's clear and flush grow with 2^jf, so wider columns take longer work
+  // items: 4 x 2^jf ions, at least kPhTile (at 2^11 bins: 68 us per restriction with
+  // 8192 ions and a 3-node window, against 88 us with 2048 ions)
+  const int tile = 4 * n_vf > kPhTile ? 4 * n_vf : kPhTile;
+  const int win = n_vf > 1024 ? 3 : kPhWin;
+  ha.win = nxc < win ? nxc : win;
+  ha.tile = tile;
   ha.fresh = fresh;
   ha.stored_field = stored_field;
   launch_fill_u8(d_hist, sizeof(long long) * (size_t)nxc * n_vf, stream);
