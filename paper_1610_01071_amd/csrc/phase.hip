@@ -355,15 +355,14 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
                                                     const double* __restrict__ cols, int levels,
                                                     int n_vf, double dv,
                                                     double* __restrict__ rf) {
-  extern __shared__ double s_cdf[];  // E, P, M: 3 x (n_vf + 1)
+  extern __shared__ double s_cdf[];  // E, M: 2 x (n_vf + 1)
   const RepDev& R = reps[rep];
   const int n = R.n_cells;
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   const int nf = n_vf;
-  double* sE = s_cdf;
-  double* sP = s_cdf + (nf + 1);
-  double* sM = s_cdf + 2 * (nf + 1);
+  double* sE = s_cdf;            // the CDF, later the forward pass
+  double* sM = s_cdf + (nf + 1);  // the column, later the reflected arrays
   const int nxc = n >> levels;
   const int K = i >> levels;
   const int K1 = K + 1 == nxc ? 0 : K + 1;
@@ -375,7 +374,7 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
       if ((i >> j) & 1) A = mid;
       else B = mid;
     }
-    sP[k] = A;
+    sM[k] = A;
   }
   __syncthreads();
   __shared__ double s_dens;
@@ -384,7 +383,7 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
     for (int k = 0; k < nf; k += 8) {  // nf is a power of two >= 16
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = sP[k + u];
+      for (int u = 0; u < 8; ++u) v[u] = sM[k + u];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         run = run + v[u];
@@ -412,16 +411,13 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
   edge_low(sM, nf, lane);
   for (int k = lane; k <= nf; k += kWave) sE[k] = 1.0 - sM[nf - k];
   __syncthreads();
-  // forward pass on a copy, backward pass on the reflection
-  for (int k = lane; k <= nf; k += kWave) {
-    sP[k] = sE[k];
-    sM[k] = 1.0 - sE[nf - k];
-  }
+  // forward pass in place, backward pass on the reflection
+  for (int k = lane; k <= nf; k += kWave) sM[k] = 1.0 - sE[nf - k];
   __syncthreads();
-  interior_forward(sP, nf, lane);
+  interior_forward(sE, nf, lane);
   interior_forward(sM, nf, lane);
   for (int k = lane; k <= nf; k += kWave)
-    rf[(int64_t)i * (nf + 1) + k] = 0.5 * (sP[k] + (1.0 - sM[nf - k]));
+    rf[(int64_t)i * (nf + 1) + k] = 0.5 * (sE[k] + (1.0 - sM[nf - k]));
 }
 
 // v with RF(v) = b in node i's repaired CDF rf[i][0..nf]: the last bin k with
@@ -514,7 +510,7 @@ void launch_phase_lift(const RepDev* d_reps, int rep, int n_cells, int levels_x,
   const double up_scale = std::pow(2.0, 0.5 * jf) / (v_max - v_min);
   hipLaunchKernelGGL(k_phase_refine, dim3(nxc), dim3(kPhThreads), sizeof(double) * 2 * n_vf,
                      stream, d_coarse, da, up_scale, d_cols);
-  hipLaunchKernelGGL(k_phase_cdf, dim3(n_cells), dim3(kWave), sizeof(double) * 3 * (n_vf + 1),
+  hipLaunchKernelGGL(k_phase_cdf, dim3(n_cells), dim3(kWave), sizeof(double) * 2 * (n_vf + 1),
                      stream, d_reps, rep, d_cols, levels_x, n_vf, dv, d_cdf);
   launch_occupancy(d_reps, 0, rep, d_status, stream);
   hipLaunchKernelGGL(k_phase_load, dim3(2048), dim3(kPhThreads), 0, stream, d_reps, rep, d_cdf,
