@@ -422,9 +422,7 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
 
 // v with RF(v) = b in node i's repaired CDF rf[i][0..nf]: the last bin k with
 // RF[k] <= b (binary search), linear inside it.
-__device__ double inverse_cdf(const double* __restrict__ rf, int i, int nf, double b,
-                              double v_min, double dv) {
-  const double* F = rf + (int64_t)i * (nf + 1);
+__device__ double inverse_cdf(const double* F, int nf, double b, double v_min, double dv) {
   int lo = 0, hi = nf - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -438,39 +436,52 @@ __device__ double inverse_cdf(const double* __restrict__ rf, int i, int nf, doub
 
 // Quiet start from the repaired CDFs: ion m of occupied cell c (rank order) at
 // offset (m + 1/2)/ppc, velocity the inverse CDFs of the cell's two nodes at the
-// Hammersley b, interpolated in x, weight n(X) h / ppc.
+// Hammersley b, interpolated in x, weight n(X) h / ppc.  One workgroup per
+// occupied cell stages the two nodes' CDFs in LDS for its ions' binary searches.
 __global__ __launch_bounds__(kPhThreads) void k_phase_load(const RepDev* __restrict__ reps,
                                                           int rep, const double* __restrict__ rf,
                                                           int n_vf, double v_min, double dv,
                                                           uint32_t shift) {
+  extern __shared__ double s_rf[];  // CDFs of the cell's left and right node: 2 x (n_vf + 1)
   const RepDev& R = reps[rep];
   const int n = R.n_cells;
+  const int nf = n_vf;
   const int ppc = R.ppc;
   const int64_t total = *gmem(R.np);
+  const int64_t ranks = (total + ppc - 1) / ppc;
   const auto prof_n = gmem(R.prof_n);
   const auto cell_of_rank = gmem(R.cell_of_rank);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(j / ppc);
-    const int m = (int)(j - (int64_t)r * ppc);
+  double* FL = s_rf;
+  double* FR = s_rf + (nf + 1);
+  for (int64_t r = blockIdx.x; r < ranks; r += gridDim.x) {
     const int c = cell_of_rank[r];
     const int cr = (c + 1) & (n - 1);
-    const float frac = (float)(((double)m + 0.5) / (double)ppc);
-    const double th = (double)frac;
-    const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
-    const uint32_t u = __brev(idx) + shift;
-    const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
     const double nl = prof_n[c], nr = prof_n[cr];
     const bool okl = nl > R.n_floor, okr = nr > R.n_floor;
-    double vl = okl ? inverse_cdf(rf, c, n_vf, b, v_min, dv) : 0.0;
-    double vr = okr ? inverse_cdf(rf, cr, n_vf, b, v_min, dv) : vl;
-    if (!okl) vl = vr;
-    const double v = (1.0 - th) * vl + th * vr;
-    const double nx = (1.0 - th) * fmax(nl, 0.0) + th * fmax(nr, 0.0);
-    gmem(R.cell)[j] = (int16_t)c;
-    gmem(R.frac)[j] = frac;
-    gmem(R.v)[j] = (float)v;
-    gmem(R.w)[j] = (float)(nx * R.h / ppc);
+    __syncthreads();  // the previous cell's rows are no longer read
+    for (int k = threadIdx.x; k <= nf; k += kPhThreads) {
+      if (okl) FL[k] = rf[(int64_t)c * (nf + 1) + k];
+      if (okr) FR[k] = rf[(int64_t)cr * (nf + 1) + k];
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < ppc; m += kPhThreads) {
+      const int64_t j = r * ppc + m;
+      if (j >= total) break;
+      const float frac = (float)(((double)m + 0.5) / (double)ppc);
+      const double th = (double)frac;
+      const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
+      const uint32_t u = __brev(idx) + shift;
+      const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
+      double vl = okl ? inverse_cdf(FL, nf, b, v_min, dv) : 0.0;
+      double vr = okr ? inverse_cdf(FR, nf, b, v_min, dv) : vl;
+      if (!okl) vl = vr;
+      const double v = (1.0 - th) * vl + th * vr;
+      const double nx = (1.0 - th) * fmax(nl, 0.0) + th * fmax(nr, 0.0);
+      gmem(R.cell)[j] = (int16_t)c;
+      gmem(R.frac)[j] = frac;
+      gmem(R.v)[j] = (float)v;
+      gmem(R.w)[j] = (float)(nx * R.h / ppc);
+    }
   }
 }
 
@@ -513,8 +524,8 @@ void launch_phase_lift(const RepDev* d_reps, int rep, int n_cells, int levels_x,
   hipLaunchKernelGGL(k_phase_cdf, dim3(n_cells), dim3(kWave), sizeof(double) * 2 * (n_vf + 1),
                      stream, d_reps, rep, d_cols, levels_x, n_vf, dv, d_cdf);
   launch_occupancy(d_reps, 0, rep, d_status, stream);
-  hipLaunchKernelGGL(k_phase_load, dim3(2048), dim3(kPhThreads), 0, stream, d_reps, rep, d_cdf,
-                     n_vf, v_min, dv, shift);
+  hipLaunchKernelGGL(k_phase_load, dim3(4096), dim3(kPhThreads), sizeof(double) * 2 * (n_vf + 1),
+                     stream, d_reps, rep, d_cdf, n_vf, v_min, dv, shift);
 }
 
 void launch_phase_project(const double* d_snap, int64_t count, int ne, double dt, double macro_dt,
