@@ -62,6 +62,8 @@ typedef enum {
 #define EFPI_DEV_NAN 2u      /* non-finite potential or coarse value             */
 #define EFPI_DEV_OVERFLOW 4u /* lift wanted more particles than capacity         */
 #define EFPI_DEV_NEGMASS 8u  /* projected block mass below zero (clipped at lift) */
+#define EFPI_DEV_WEIGHT 16u  /* an ion weight |w| >= 32: the exact per-lane charge
+                                sums of the particle pass need |w| < 32           */
 
 /* Boundary conditions and closures. */
 #define EFPI_BC_PERIODIC 0
@@ -110,7 +112,7 @@ typedef struct {
                                         convergence is quadratic, so the remaining
                                         error is about its square                 */
   int32_t tile;                      /* particles per work item: 0 (default, 4096)
-                                        or a multiple of 1024 up to 65536         */
+                                        or a multiple of 1024 up to 16384         */
   int32_t grid_blocks;               /* persistent grid size, 0 = default         */
   uint32_t flags;                    /* EFPI_FLAG_*                               */
 } efpi_config;

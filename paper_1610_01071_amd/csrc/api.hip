@@ -148,8 +148,8 @@ efpi_status check_config(const efpi_config* cfg) {
   if (cfg->newton_iters < 1 || cfg->newton_iters_start < 1)
     return fail(EFPI_EINVAL, "newton iteration counts must be >= 1");
   if (!(cfg->newton_tol > 0.0)) return fail(EFPI_EINVAL, "newton_tol must be > 0");
-  if (cfg->tile != 0 && (cfg->tile % 1024 != 0 || cfg->tile < 1024 || cfg->tile > 65536))
-    return fail(EFPI_EINVAL, "tile must be 0 or a multiple of 1024 in [1024, 65536]");
+  if (cfg->tile != 0 && (cfg->tile % 1024 != 0 || cfg->tile < 1024 || cfg->tile > 16384))
+    return fail(EFPI_EINVAL, "tile must be 0 or a multiple of 1024 in [1024, 16384]");
   if (cfg->grid_blocks < 0) return fail(EFPI_EINVAL, "grid_blocks must be >= 0");
   for (uint32_t r = 0; r < cfg->n_replicas; ++r) {
     const efpi_replica& p = cfg->replicas[r];
@@ -442,7 +442,7 @@ void run_field(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
 void deposit_all(efpi_ctx* c, bool electrons) {
   deposit_into_next(c);
   launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, 0,
-                   kDepositOnly, c->cur ^ 1, c->stream);
+                   kDepositOnly, c->cur ^ 1, c->d_status, c->stream);
   if (electrons && c->kinetic)
     launch_electrons(c->d_ereps, c->R, 0, 0, c->cur ^ 1, c->max_nodes, c->stream);
   c->cur ^= 1;
@@ -534,7 +534,7 @@ efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
       if (e0 && e1) c->ion_pairs.push_back({c->events_used - 2, c->events_used - 1});
     }
     launch_particles(c->d_reps, c->d_item_prefix, c->R, c->total_items, c->tile, c->grid_blocks, p,
-                     flags, c->cur ^ 1, c->stream, e0, e1);
+                     flags, c->cur ^ 1, c->d_status, c->stream, e0, e1);
     if (push) {
       if (c->kinetic) {
         hipEvent_t f0 = nullptr, f1 = nullptr;
@@ -1080,7 +1080,7 @@ efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {
   launch_prep_burst(ctx->d_reps, ctx->R, ctx->stream);
   launch_particles(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
                    ctx->grid_blocks, -1, kRestrict | (ctx->fresh ? kFresh : 0), ctx->cur ^ 1,
-                   ctx->stream);
+                   ctx->d_status, ctx->stream);
   launch_restrict(ctx->d_reps, ctx->R, 0, d_coarse, ctx->d_coarse_off, ctx->stream);
   ctx->last_burst_steps = -1;
   return hip_check("restrict_state");

@@ -91,9 +91,11 @@ struct ShiftArg {
   uint32_t s[kMaxShiftReplicas];
 };
 
+// d_status receives EFPI_DEV_WEIGHT when an ion's |w| reaches the bound that
+// keeps the exact charge sums exact.
 void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
                       int64_t total_items, int tile, int grid_blocks, int p, int flags,
-                      int qsel, hipStream_t stream, hipEvent_t ev0 = nullptr,
+                      int qsel, uint32_t* d_status, hipStream_t stream, hipEvent_t ev0 = nullptr,
                       hipEvent_t ev1 = nullptr);
 // d_reps: the descriptors of the replicas solved by this launch, one workgroup each.
 void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,

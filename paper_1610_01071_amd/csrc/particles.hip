@@ -4,17 +4,27 @@
 // one streaming pass over the structure-of-arrays ion store.
 //
 // Work decomposition: every replica's particle slots are cut into tiles of
-// `tile` consecutive particles; a persistent grid walks the (replica, tile)
-// items.  The node field around the tile is staged in LDS.  Inside a tile, each
-// wave takes runs of 512 consecutive ions (8 per lane), so that in a cell-sorted
-// store its ions touch few distinct nodes.  It merges all of its ions that hit
-// the same node (deposit) or coarse block (restriction) with fixed-order wave
-// reductions, and adds the merged value to a register owned by one lane (lane s
-// holds node or block base + s).  At the end of the tile the four waves' registers are summed
-// through LDS and flushed with one 64-bit integer atomic per non-zero target.
-// Rare targets outside a wave's 64 slots go to an LDS window (deposit) or to
-// global atomics.  Every sum that reaches memory is an integer sum, so the
-// result does not depend on scheduling order.
+// `tile` consecutive ions; a persistent grid of 256-thread workgroups walks the
+// (replica, tile) items, and wave w of a workgroup takes the w-th quarter of the
+// tile.  Waves never wait for each other: each has its own field window and
+// accumulators in LDS.  A wave reads its ions in batches of 512, lane l holding
+// the groups of four consecutive ions 4l .. 4l + 3 and 256 + 4l .. 256 + 4l + 3,
+// so that every load and store is a 16-byte (8-byte for the cells) access and
+// the wave's accesses cover contiguous memory.
+//
+// Accumulation without merges: a cell-sorted store keeps a wave's ions within a
+// few cells and coarse blocks of one another over a burst.  Each wave owns a
+// window of 16 nodes and of 16 coarse blocks around the cells of its range;
+// every lane adds its ions' shares into bins of its own in that window with
+// LDS atomics that return nothing (ds_add_f64), so no lane waits and no
+// cross-lane merge runs per ion.  Every share is first put in fixed point (unit
+// 2^-40: the charge and the snapshot mass split as rint(theta q), q - rint(theta
+// q); the momentum likewise) and held as an integer-valued binary64, so every
+// bin sum is exact and independent of order; lanes l and l + 32 share a bin.
+// At the end of the wave's range the bins are summed across lanes and added to
+// global memory with 64-bit integer atomics, so the grid charge and the
+// snapshots do not depend on scheduling.  Ions whose target lies outside the
+// window add their fixed-point shares with global atomics directly.
 #include "efpi_internal.h"
 
 #include <hip/hip_ext.h>
@@ -39,64 +49,45 @@ __device__ __forceinline__ void gatomic_add(long long* p, long long v) {
                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Accumulation into a lane's LDS bin (no value returned: ds_add_f64).  The FP32
+// form of this atomic is two orders of magnitude slower on this hardware, so all
+// bins hold fixed-point values as integer-valued binary64.
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Orders a wave's LDS accesses around a hand-over between its lanes (the LDS
+// executes one wave's instructions in issue order; this keeps the compiler's
+// order too).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kBatch = 8;       // particles per thread loaded ahead of use
-constexpr int kQWin = 256;      // node window (int64 bins)
-constexpr int kQMargin = 16;
-constexpr int kQSlotMargin = 4;  // node slots per wave start this far below the tile
-constexpr int kRWin = kWave;    // coarse block slots per wave (one per lane)
-constexpr int kRMargin = 8;
-constexpr int kEWin = 128;      // node field window staged in LDS (cells)
-constexpr int kEMargin = 32;
+constexpr int kGroup = 4;                      // consecutive ions per vector access
+constexpr int kPer = 2 * kGroup;               // ions per lane per batch
+constexpr int kBatch = kPer * kWave;           // ions per wave per batch
+constexpr int kQBins = 16;                     // node bins of a wave's charge window
+constexpr int kQSlots = 32;                    // lanes l and l + 32 share a slot
+constexpr int kQBelow = 7;                     // window starts below the reference cell
+#ifndef EFPI_PASS_RBINS
+#define EFPI_PASS_RBINS 16
+#endif
+constexpr int kRBins = EFPI_PASS_RBINS;        // coarse-block bins of a wave's window
+constexpr int kRBelow = 7;
+constexpr int kENodes = 64;                    // field window: cells (64 + 1 nodes)
+constexpr int kEBelow = 32;
+// Weights (and momenta w V) above this bound could carry a binary64 bin past 2^53
+// (at most 16384 / 4 / 32 = 128 ions share a slot at the largest tile): flagged.
+constexpr float kWeightBound = 32.f;
 
-// Wave-wide sums with a fixed pattern: inside each 16-lane row an inclusive scan
-// by row shifts 1, 2, 3 of the input, then 4 and 8 (lanes shifted in from
-// outside the row read 0), which leaves each row's total in its lane 15; the
-// four row totals are read into scalar registers and added as (r3 + r2) + (r1 +
-// r0).  The order of every addition is fixed, so FP32 sums are reproducible bit
-// for bit.  All 64 lanes must be active.
-template <int CTRL>
-__device__ __forceinline__ int dpp_shr(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, true);
-}
-
-__device__ __forceinline__ int row_scan_i32(int x) {
-  int t = x + dpp_shr<0x111>(x);
-  t += dpp_shr<0x112>(x);
-  t += dpp_shr<0x113>(x);
-  t += dpp_shr<0x114>(t);
-  t += dpp_shr<0x118>(t);
-  return t;
-}
-
-__device__ __forceinline__ int wave_sum_i32(int x) {
-  const int t = row_scan_i32(x);
-  const int r0 = __builtin_amdgcn_readlane(t, 15), r1 = __builtin_amdgcn_readlane(t, 31);
-  const int r2 = __builtin_amdgcn_readlane(t, 47), r3 = __builtin_amdgcn_readlane(t, 63);
-  return (r3 + r2) + (r1 + r0);
-}
-
-__device__ __forceinline__ float wave_sum_f32(float x) {
-  float t = x + __int_as_float(dpp_shr<0x111>(__float_as_int(x)));
-  t += __int_as_float(dpp_shr<0x112>(__float_as_int(x)));
-  t += __int_as_float(dpp_shr<0x113>(__float_as_int(x)));
-  t += __int_as_float(dpp_shr<0x114>(__float_as_int(t)));
-  t += __int_as_float(dpp_shr<0x118>(__float_as_int(t)));
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 15));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 31));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 47));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 63));
-  return (r3 + r2) + (r1 + r0);
-}
-
-// Exact wave sum of int64 values with |v| < 2^49: the low 24 bits and the rest
-// are summed separately as int32 (64 * 2^24 and 64 * 2^25 both fit) and recombined.
-__device__ __forceinline__ long long wave_sum_i64(long long v) {
-  const int lo = (int)(v & 0xFFFFFF);
-  const int hi = (int)(v >> 24);
-  return (long long)wave_sum_i32(hi) * (1ll << 24) + (long long)wave_sum_i32(lo);
-}
+struct WaveLds {
+  float2 e[kENodes + 2];          // (E^p, E_n) at the window's nodes (one spare entry)
+  double q[kQBins][kQSlots];      // fixed-point charge shares (integer-valued binary64)
+  double r[2][kRBins][kQSlots];   // fixed-point (density, momentum) shares per coarse block
+};
 
 // rint(x) as int64 for |x| < 2^51: adding 1.5 * 2^52 leaves the integer part
 // rounded to nearest (ties to even, the IEEE default) in the low mantissa bits.
@@ -105,18 +96,14 @@ __device__ __forceinline__ long long rint_i64(double x) {
   return (long long)(__double_as_longlong(x + magic) - __double_as_longlong(magic));
 }
 
-// rint(x) for |x| < 2^51 as a binary64 value (the same rounding as rint_i64).
-__device__ __forceinline__ double rint_d(double x) { return __builtin_rint(x); }
-
-// q = rint(w 2^40): the particle's charge in fixed point, as an exact binary64
-// integer value.
-__device__ __forceinline__ double fx_charge(float w) { return rint_d((double)w * kFxScale); }
+// q = rint(w 2^40): the ion's charge in fixed point, as an exact binary64 integer.
+__device__ __forceinline__ double fx_charge(float w) {
+  return __builtin_rint((double)w * kFxScale);
+}
 // Right-node share rint(theta q) in binary64 (one rounded product, then ties-to-even).
 __device__ __forceinline__ double fx_share(float theta, double q) {
-  return rint_d((double)theta * q);
+  return __builtin_rint((double)theta * q);
 }
-// Fixed-point value of an FP32 partial sum.
-__device__ __forceinline__ long long fx_of(float x) { return rint_i64((double)x * kFxScale); }
 
 __device__ __forceinline__ int find_replica(const int64_t* prefix, int n, int64_t item) {
   int lo = 0, hi = n - 1;
@@ -127,379 +114,354 @@ __device__ __forceinline__ int find_replica(const int64_t* prefix, int n, int64_
   return lo;
 }
 
-struct Window {
-  long long* lds;
-  int base;
-  int size;
-  long long* glob;
-};
+// 8- and 16-byte accesses at a byte offset from a uniform base (native vector
+// types, so that the global address space carries through the copy)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ T ldv(const EFPI_GLOBAL void* base, unsigned byte_off) {
+  return *(const EFPI_GLOBAL T*)((const EFPI_GLOBAL char*)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void stv(EFPI_GLOBAL void* base, unsigned byte_off, T v) {
+  *(EFPI_GLOBAL T*)((EFPI_GLOBAL char*)base + byte_off) = v;
+}
 
-__device__ __forceinline__ void add_to(const Window& w, int idx, long long val) {
-  if (val == 0) return;
-  int k = idx - w.base;
-  if (k >= 0 && k < w.size)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&w.lds[k]), (unsigned long long)val);
+// The ions of one wave: `cnt` slots from `t0` of replica R.  MODE as in k_particles.
+template <int MODE, bool kPeriodic>
+__device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t t0,
+                                           unsigned cnt, int p, double pd, bool fresh, int qsel,
+                                           bool& big) {
+  constexpr bool restrict_ = (MODE & kRestrict) != 0;
+  constexpr bool push = (MODE & kPush) != 0;
+  constexpr bool deposit = push || (MODE & kDepositOnly) != 0;
+  constexpr bool field = restrict_ || push;
+  const int lane = __lane_id();
+  const int n = R.n_cells;
+  const int nmask = n - 1;
+  const float dt = (float)R.dt;
+  const float inv_h = (float)R.inv_h;
+  const int levels = R.levels;
+  const int nc = R.n_coarse;
+  const int ncmask = nc - 1;
+  // p < 0: plain restriction of the current state (tau = 0, snapshot slot 0)
+  // (pd = p as binary64, a kernel argument, so no conversion is kept live)
+  const float tau = p < 0 ? 0.f : (float)(R.macro_dt - pd * R.dt);
+  const bool coev = R.coevolving != 0 && p >= 0;
+  const EFPI_GLOBAL float* __restrict__ e = gmem(R.e);
+  const EFPI_GLOBAL float* __restrict__ en = gmem(R.en);
+  EFPI_GLOBAL int16_t* __restrict__ cellp = gmem(R.cell + t0);
+  EFPI_GLOBAL float* __restrict__ fracp = gmem(R.frac + t0);
+  EFPI_GLOBAL float* __restrict__ velp = gmem(R.v + t0);
+  const EFPI_GLOBAL float* __restrict__ wp = gmem(R.w + t0);
+  long long* qg = reinterpret_cast<long long*>(R.q[qsel]);
+  long long* rb = reinterpret_cast<long long*>(R.rbins) + (int64_t)(p < 0 ? 0 : p) * 2 * nc;
+  const float half_dt = 0.5f * dt;
+  const float half_dt_r = fresh ? 0.f : half_dt;  // snapshot velocity v + half_dt_r E
+  const float dt_push = fresh ? half_dt : dt;     // push: v + dt_push E
+  const int lmask = (1 << levels) - 1;
+  const float dt_inv_h = dt * inv_h;
+  const float tau_inv_h = coev ? tau * inv_h : 0.f;
+  const float tau_e = coev ? tau : 0.f;
+
+  // Reference cell of the range: midway between its first and last cells (a
+  // cell-sorted store), or whichever of them is live.
+  const int c_lo = __builtin_amdgcn_readfirstlane((int)*at(cellp, 0u));
+  const int c_hi = __builtin_amdgcn_readfirstlane((int)*at(cellp, cnt - 1u));
+  const bool lo_ok = (unsigned)c_lo < (unsigned)n, hi_ok = (unsigned)c_hi < (unsigned)n;
+  int cref;
+  if (lo_ok && hi_ok)
+    cref = kPeriodic ? ((c_lo + (((c_hi - c_lo) & nmask) >> 1)) & nmask) : ((c_lo + c_hi) >> 1);
   else
-    gatomic_add(&w.glob[idx], val);
-}
+    cref = lo_ok ? c_lo : (hi_ok ? c_hi : 0);
+  const int ebase = cref - kEBelow;
+  const int qbase = cref - kQBelow;
+  const int rbase = (cref >> levels) - kRBelow;
 
-// Each lane holds kBatch ions.  Every distinct target of the wave is merged:
-// the lowest active lane's target is taken, every lane sums its own ions with
-// that target, the sums are reduced across the wave and the result is added to
-// a per-lane slot register (lane s owns target base + s).  A target outside the
-// 64-slot window is added to the LDS window, else to global memory.  Per-lane
-// 64-bit LDS atomics are slow on this hardware, so the merge is never skipped.
-//
-// Charge deposit: ion j adds a[j] to node key[j] and b[j] to node key[j] + 1
-// (wrapping to 0 at `wrap`, or no wrap when wrap = -1).  Exact int64 sums.
-__device__ __forceinline__ void merge_charge(int (&key)[kBatch], const double (&a)[kBatch],
-                                             const double (&b)[kBatch], int wrap, int base,
-                                             long long& acc, const Window& win) {
-  const int lane = __lane_id();
-  while (true) {
-    int mine = key[0];  // any remaining key of the lane (-1 when none is left)
-#pragma unroll
-    for (int j = 1; j < kBatch; ++j) mine = max(mine, key[j]);
-    const unsigned long long act = __ballot(mine >= 0);
-    if (act == 0ull) break;
-    const int leader = __ffsll((unsigned long long)act) - 1;
-    const int lk = __builtin_amdgcn_readlane(mine, leader);
-    // integer-valued binary64 lane sums: exact, since every lane sum stays below 2^49
-    double sa = 0.0, sb = 0.0;
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const bool m = key[j] == lk;
-      const double one = m ? 1.0 : 0.0;
-      sa = fma(one, a[j], sa);
-      sb = fma(one, b[j], sb);
-      key[j] = m ? -1 : key[j];
-    }
-    const long long ta = wave_sum_i64(rint_i64(sa));
-    const long long tb = wave_sum_i64(rint_i64(sb));
-    int r = lk + 1;
-    if (r == wrap) r = 0;
-    const int sl = lk - base;
-    const int sr = r - base;
-    acc += lane == sl ? ta : 0ll;
-    acc += lane == sr ? tb : 0ll;
-    if ((unsigned)sl >= (unsigned)kWave && lane == 0) add_to(win, lk, ta);
-    if ((unsigned)sr >= (unsigned)kWave && lane == 0) add_to(win, r, tb);
-  }
-}
-
-// Restriction snapshot: ion j adds (a0, a1)[j] to block key[j] and (b0, b1)[j]
-// to block key[j] + 1 for the (density, momentum) moments.  Every distinct
-// block of the wave is merged (FP32 partial sums in a fixed order, converted to
-// fixed point); the merged values go to per-lane slot registers, lane s of the
-// wave owning block base + s, so that no LDS atomics are needed.  Blocks outside
-// the 64-block slot window go to global atomics.
-__device__ __forceinline__ void merge_moments(int (&key)[kBatch], const float (&a0)[kBatch],
-                                              const float (&a1)[kBatch],
-                                              const float (&b0)[kBatch],
-                                              const float (&b1)[kBatch], int wrap, int base,
-                                              long long& acc0, long long& acc1,
-                                              long long* g0, long long* g1) {
-  const int lane = __lane_id();
-  while (true) {
-    int mine = key[0];  // any remaining key of the lane (-1 when none is left)
-#pragma unroll
-    for (int j = 1; j < kBatch; ++j) mine = max(mine, key[j]);
-    const unsigned long long act = __ballot(mine >= 0);
-    if (act == 0ull) break;
-    const int leader = __ffsll((unsigned long long)act) - 1;
-    const int lk = __builtin_amdgcn_readlane(mine, leader);
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const bool m = key[j] == lk;
-      const float one = m ? 1.f : 0.f;  // 1 * x + s and 0 * x + s round as the plain sums
-      s0 = fmaf(one, a0[j], s0);
-      s1 = fmaf(one, a1[j], s1);
-      s2 = fmaf(one, b0[j], s2);
-      s3 = fmaf(one, b1[j], s3);
-      key[j] = m ? -1 : key[j];
-    }
-    const long long f0 = fx_of(wave_sum_f32(s0));
-    const long long f1 = fx_of(wave_sum_f32(s1));
-    const long long f2 = fx_of(wave_sum_f32(s2));
-    const long long f3 = fx_of(wave_sum_f32(s3));
-    int r = lk + 1;
-    if (r == wrap) r = 0;
-    const int sl = lk - base;
-    const int sr = r - base;
-    acc0 += lane == sl ? f0 : 0ll;
-    acc1 += lane == sl ? f1 : 0ll;
-    acc0 += lane == sr ? f2 : 0ll;
-    acc1 += lane == sr ? f3 : 0ll;
-    if ((unsigned)sl >= (unsigned)kWave && lane == 0) {
-      gatomic_add(g0 + lk, f0);
-      gatomic_add(g1 + lk, f1);
-    }
-    if ((unsigned)sr >= (unsigned)kWave && (f2 | f3) != 0 && lane == 0) {
-      gatomic_add(g0 + r, f2);
-      gatomic_add(g1 + r, f3);
+  // field window: node ebase + k (wrapped, or clamped to the wall nodes) at k, so
+  // that a cell c with k = c - ebase in [0, kENodes) finds both of its nodes
+  if (field) {
+    for (int k = lane; k <= kENodes; k += kWave) {
+      const int g = kPeriodic ? ((ebase + k) & nmask) : min(max(ebase + k, 0), n);
+      L.e[k] = make_float2(e[g], (restrict_ && coev) ? en[g] : 0.f);
     }
   }
+  if (deposit) {
+    uint4* z = reinterpret_cast<uint4*>(&L.q[0][0]);
+    for (int k = lane; k < (int)(sizeof L.q / sizeof(uint4)); k += kWave) z[k] = make_uint4(0, 0, 0, 0);
+  }
+  if (restrict_) {
+    uint4* z = reinterpret_cast<uint4*>(&L.r[0][0][0]);
+    for (int k = lane; k < (int)(sizeof L.r / sizeof(uint4)); k += kWave) z[k] = make_uint4(0, 0, 0, 0);
+  }
+  wave_lds_sync();
+
+  double* const qbin = &L.q[0][lane & (kQSlots - 1)];
+  double* const rbin0 = &L.r[0][0][lane & (kQSlots - 1)];
+  double* const rbin1 = &L.r[1][0][lane & (kQSlots - 1)];
+
+  for (unsigned b0 = 0; b0 < cnt; b0 += kBatch) {
+    int cl[kPer];
+    float fr[kPer], vv[kPer], ww[kPer];
+    unsigned gi[2];
+    bool gvalid[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const unsigned g = b0 + (unsigned)h * (kGroup * kWave) + (unsigned)lane * kGroup;
+      gi[h] = g;
+      gvalid[h] = g < cnt;
+      u32x2 c2 = {0xFFFFFFFFu, 0xFFFFFFFFu};
+      f32x4 f4 = {0.f, 0.f, 0.f, 0.f}, v4 = f4, w4 = f4;
+      // a group that starts inside the range is read whole: slots past the range
+      // lie inside the store's allocation (rounded up to 64 slots) and are
+      // treated as absorbed and written back unchanged
+      if (gvalid[h]) {
+        c2 = ldv<u32x2>(cellp, g * 2u);
+        f4 = ldv<f32x4>(fracp, g * 4u);
+        v4 = ldv<f32x4>(velp, g * 4u);
+        w4 = ldv<f32x4>(wp, g * 4u);
+      }
+      // slots of a group past the end of the range count as absorbed
+      if (__builtin_expect(g + kGroup > cnt, 0)) {
+        const unsigned left = cnt - g;  // 1 .. 3 when the group is valid
+        if (!gvalid[h] || left < 2) c2.x |= 0xFFFF0000u;
+        if (!gvalid[h] || left < 3) c2.y |= 0x0000FFFFu;
+        if (!gvalid[h] || left < 4) c2.y |= 0xFFFF0000u;
+      }
+      const int base = h * kGroup;
+      cl[base + 0] = (int)(short)(c2.x & 0xFFFFu);
+      cl[base + 1] = (int)(short)(c2.x >> 16);
+      cl[base + 2] = (int)(short)(c2.y & 0xFFFFu);
+      cl[base + 3] = (int)(short)(c2.y >> 16);
+      fr[base + 0] = f4.x; fr[base + 1] = f4.y; fr[base + 2] = f4.z; fr[base + 3] = f4.w;
+      vv[base + 0] = v4.x; vv[base + 1] = v4.y; vv[base + 2] = v4.z; vv[base + 3] = v4.w;
+      ww[base + 0] = w4.x; ww[base + 1] = w4.y; ww[base + 2] = w4.z; ww[base + 3] = w4.w;
+    }
+    // live ions: a cell inside [0, N)
+    bool alive[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) alive[j] = (unsigned)cl[j] < (unsigned)n;
+    // node fields at both ends of each ion's cell, from the window; ions outside
+    // it (unsorted or far-drifted stores) read global memory
+    float e0[kPer], e1[kPer], n0[kPer], n1[kPer];
+    if (field) {
+      bool outside = false;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int c = cl[j];
+        const int k = kPeriodic ? ((c - ebase) & nmask) : (c - ebase);
+        const bool inw = (unsigned)k < (unsigned)kENodes;
+        const int kk = inw ? k : 0;
+        outside |= alive[j] && !inw;
+        const float2 a = L.e[kk];
+        const float2 b = L.e[kk + 1];
+        e0[j] = a.x;
+        n0[j] = a.y;
+        e1[j] = b.x;
+        n1[j] = b.y;
+      }
+      if (__builtin_expect(__ballot(outside) != 0ull, 0)) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+          const int c = cl[j];
+          const int k = kPeriodic ? ((c - ebase) & nmask) : (c - ebase);
+          if (alive[j] && (unsigned)k >= (unsigned)kENodes) {
+            const int cr = kPeriodic ? ((c + 1) & nmask) : c + 1;
+            e0[j] = e[c];
+            e1[j] = e[cr];
+            n0[j] = (restrict_ && coev) ? en[c] : 0.f;
+            n1[j] = (restrict_ && coev) ? en[cr] : 0.f;
+          }
+        }
+      }
+    }
+    float epa[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) epa[j] = field ? fmaf(fr[j], e1[j] - e0[j], e0[j]) : 0.f;
+
+    if (restrict_) {
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const float f = fr[j];
+        const float w = ww[j];
+        const int cs = alive[j] ? cl[j] : 0;
+        // Snapshot p: time-centred velocity, then the approximate characteristic
+        // over tau = Delta t - p dt (eq. B.4) and CIC at the moved position (eq. B.5).
+        const float vpc = fmaf(half_dt_r, epa[j], vv[j]);  // half_dt_r = 0 on a fresh state
+        const float enx = fmaf(f, n1[j] - n0[j], n0[j]);
+        const float xt = fmaf(tau_inv_h, vpc, f);
+        const float vt = fmaf(tau_e, enx, vpc);
+        const float fl = floorf(xt);
+        const float fx = xt - fl;
+        const bool wrap_up = fx >= 1.f;
+        const int ct0 = cs + (int)fl + (wrap_up ? 1 : 0);
+        const int ct = kPeriodic ? (ct0 & nmask) : ct0;
+        // walls: positions moved outside [0, L) are in flight to a wall, not counted
+        const bool in = alive[j] && (kPeriodic || (unsigned)ct < (unsigned)n);
+        const int bl = ct >> levels;
+        // both nodes of cell ct in block bl: ct is not the block's last cell, or
+        // (walls) the block is the last one, which also owns wall node N, or
+        // (periodic) there is a single block
+        const bool last = (ct & lmask) == lmask;
+        const bool same = !last || (kPeriodic ? nc == 1 : bl == nc - 1);
+        // right-node share theta, zero when both nodes are in the same block
+        const float th = (wrap_up || same) ? 0.f : fx;
+        // fixed-point mass and momentum with their CIC split, as the charge
+        // deposit splits the charge: right share rint(theta q), left q - right
+        const float wv = w * vt;
+        big |= in && !(fabsf(wv) < kWeightBound);
+        const double qm = fx_charge(w);
+        const double qv = fx_charge(wv);
+        const double thd = (double)th;
+        const double qm_r = __builtin_rint(thd * qm), qv_r = __builtin_rint(thd * qv);
+        const double qm_l = qm - qm_r, qv_l = qv - qv_r;
+        const int d = kPeriodic ? ((bl - rbase) & ncmask) : (bl - rbase);
+        const bool inr = (unsigned)d < (unsigned)(kRBins - 1);
+        if (in && inr) {
+          lds_add(rbin0 + d * kQSlots, qm_l);
+          lds_add(rbin1 + d * kQSlots, qv_l);
+          if (th != 0.f) {
+            lds_add(rbin0 + (d + 1) * kQSlots, qm_r);
+            lds_add(rbin1 + (d + 1) * kQSlots, qv_r);
+          }
+        } else if (in) {
+          gatomic_add(rb + bl, rint_i64(qm_l));
+          gatomic_add(rb + nc + bl, rint_i64(qv_l));
+          if (th != 0.f) {
+            const int br = kPeriodic ? ((bl + 1) & ncmask) : bl + 1;
+            gatomic_add(rb + br, rint_i64(qm_r));
+            gatomic_add(rb + nc + br, rint_i64(qv_r));
+          }
+        }
+      }
+    }
+    if (deposit) {
+      int cn_st[kPer];
+      float fn_st[kPer], vn_st[kPer];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const float f = fr[j];
+        const float v = vv[j];
+        const float w = ww[j];
+        const int cs = alive[j] ? cl[j] : 0;
+        int cn = cs;
+        float fn = f, vn = v;
+        if (push) {
+          vn = fmaf(dt_push, epa[j], v);
+          const float xn = fmaf(dt_inv_h, vn, f);
+          const float fl = floorf(xn);
+          const bool wrap_up = (xn - fl) >= 1.f;
+          fn = wrap_up ? 0.f : xn - fl;
+          cn = cs + (int)fl + (wrap_up ? 1 : 0);
+          cn = kPeriodic ? (cn & nmask) : ((unsigned)cn < (unsigned)n ? cn : -1);  // walls absorb
+        }
+        // stored state: live ions pushed, the rest written back as read
+        cn_st[j] = alive[j] ? cn : cl[j];
+        fn_st[j] = alive[j] ? fn : f;
+        vn_st[j] = alive[j] ? vn : v;
+        const bool dep = alive[j] && cn >= 0;
+        big |= dep && !(fabsf(w) < kWeightBound);
+        const double q = fx_charge(w);
+        const double qr = fx_share(fn, q);
+        const double ql = q - qr;
+        const int d = kPeriodic ? ((cn - qbase) & nmask) : (cn - qbase);
+        const bool inq = (unsigned)d < (unsigned)(kQBins - 1);
+        if (dep && inq) {
+          lds_add(qbin + d * kQSlots, ql);
+          lds_add(qbin + (d + 1) * kQSlots, qr);
+        } else if (dep) {
+          const int cr = kPeriodic ? ((cn + 1) & nmask) : cn + 1;
+          gatomic_add(qg + cn, rint_i64(ql));
+          gatomic_add(qg + cr, rint_i64(qr));
+        }
+      }
+      if (push) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (gvalid[h]) {
+            const int b = h * kGroup;
+            const u32x2 c2 = {
+                ((unsigned)cn_st[b + 0] & 0xFFFFu) | ((unsigned)cn_st[b + 1] << 16),
+                ((unsigned)cn_st[b + 2] & 0xFFFFu) | ((unsigned)cn_st[b + 3] << 16)};
+            stv<u32x2>(cellp, gi[h] * 2u, c2);
+            const f32x4 f4 = {fn_st[b], fn_st[b + 1], fn_st[b + 2], fn_st[b + 3]};
+            const f32x4 v4 = {vn_st[b], vn_st[b + 1], vn_st[b + 2], vn_st[b + 3]};
+            stv<f32x4>(fracp, gi[h] * 4u, f4);
+            stv<f32x4>(velp, gi[h] * 4u, v4);
+          }
+        }
+      }
+    }
+  }
+
+  wave_lds_sync();
+  if (deposit) {
+    // bin d's total: lane l sums 8 of the 32 slots of bin l & 15 (rotated by d so
+    // that the reads of one pass fall in different banks), then the four partial
+    // sums of every bin are added across lanes; the sums are exact
+    const int d = lane & (kQBins - 1);
+    const int g = lane >> 4;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += L.q[d][g * 8 + ((i + d) & 7)];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (g == 0 && s != 0.0) {
+      const int node = kPeriodic ? ((qbase + d) & nmask) : (qbase + d);
+      gatomic_add(qg + node, rint_i64(s));
+    }
+  }
+  if (restrict_) {
+    // (moment, block) bin b = lane % nb: the lanes b, b + nb, ... each sum a run
+    // of its slots (rotated by b across the banks), then add their partial sums;
+    // the sums are exact
+    constexpr int nb = 2 * kRBins;
+    constexpr int ns = kQSlots * nb / kWave;  // slots summed per lane
+    const int b = lane & (nb - 1);
+    const int m = b / kRBins;
+    const int d = b % kRBins;
+    const int g = lane / nb;
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < ns; ++i) t += L.r[m][d][g * ns + ((i + b) & (ns - 1))];
+#pragma unroll
+    for (int o = nb; o < kWave; o <<= 1) t += __shfl_xor(t, o);
+    if (g == 0 && t != 0.0) {
+      const int blk = kPeriodic ? ((rbase + d) & ncmask) : (rbase + d);
+      gatomic_add(rb + (int64_t)m * nc + blk, rint_i64(t));
+    }
+  }
+  wave_lds_sync();
 }
 
 // MODE (compile time): kRestrict | kPush for a burst step, kPush for plain PIC,
 // kRestrict for the last snapshot of a burst, kDepositOnly for a charge deposit.
-// Four waves per SIMD: the register budget is held at 128 (the pass is bound by
-// vector instruction issue, so it needs the occupancy to keep every SIMD busy).
 template <int MODE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kThreads)
 void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ item_prefix,
                  int n_reps, int64_t total_items, int tile, int p, double pd, int fresh_flag,
-                 int qsel) {
-  __shared__ long long lds_q[kQWin];
-  __shared__ long long lds_qs[kWaves][kWave];
-  __shared__ long long lds_r[kWaves][2][kRWin];
-  __shared__ float lds_e[kEWin + 1];
-  __shared__ float lds_en[kEWin + 1];
-  const int tid = threadIdx.x;
-  // a batch is kThreads * kBatch consecutive ions; wave w takes the w-th run of
-  // kWave * kBatch of them, lane l its ions l, l + 64, ... (coalesced loads, and
-  // each wave's ions span as few cells as possible)
-  const unsigned toff = (unsigned)(tid / kWave) * (kWave * kBatch) + (unsigned)(tid % kWave);
+                 int qsel, uint32_t* __restrict__ status) {
+  __shared__ WaveLds lds[kWaves];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  WaveLds& L = lds[wave];
   const bool fresh = fresh_flag != 0;
-  constexpr bool restrict_ = (MODE & kRestrict) != 0;
-  constexpr bool push = (MODE & kPush) != 0;
-  constexpr bool deposit = push || (MODE & kDepositOnly) != 0;
-
+  const int64_t quarter = tile / kWaves;
+  bool big = false;
   for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
     const int r = find_replica(item_prefix, n_reps, item);
     const RepDev& R = reps[r];
     const int64_t np = uniform_i64(*gmem(R.np));
-    const int64_t i0 = (item - R.item_begin) * (int64_t)tile;
-    if (i0 >= np) continue;
-    const unsigned cnt = (unsigned)min((int64_t)tile, np - i0);
-    const int n = R.n_cells;
-    // the tile body, compiled once for periodic grids and once for walls
-    auto tile_pass = [&](auto bc_tag) {
-      constexpr bool periodic = decltype(bc_tag)::value;
-      const int nmask = n - 1;
-      const float dt = (float)R.dt;
-      const float inv_h = (float)R.inv_h;
-      const int levels = R.levels;
-      const int nc = R.n_coarse;
-      // p < 0: plain restriction of the current state (tau = 0, snapshot slot 0)
-      // (pd = p as binary64, a kernel argument: converting p here would give a
-      // value the compiler keeps in a vector register across the whole kernel)
-      const float tau = p < 0 ? 0.f : (float)(R.macro_dt - pd * R.dt);
-      const bool coev = R.coevolving != 0 && p >= 0;
-      const EFPI_GLOBAL float* __restrict__ e = gmem(R.e);
-      const EFPI_GLOBAL float* __restrict__ en = gmem(R.en);
-      EFPI_GLOBAL int16_t* __restrict__ cellp = gmem(R.cell + i0);
-      EFPI_GLOBAL float* __restrict__ fracp = gmem(R.frac + i0);
-      EFPI_GLOBAL float* __restrict__ vp_ = gmem(R.v + i0);
-      const EFPI_GLOBAL float* __restrict__ wp = gmem(R.w + i0);
-      const float half_dt = 0.5f * dt;
-      const float half_dt_r = fresh ? 0.f : half_dt;  // snapshot velocity v + half_dt_r E
-      const float dt_push = fresh ? half_dt : dt;     // push: v + dt_push E
-      const int lmask = (1 << levels) - 1;
-      const float dt_inv_h = dt * inv_h;
-      const float tau_inv_h = coev ? tau * inv_h : 0.f;
-      const float tau_e = coev ? tau : 0.f;
-
-      const int c_first = __builtin_amdgcn_readfirstlane((int)cellp[0]);
-      Window wq{lds_q, c_first - kQMargin, kQWin, reinterpret_cast<long long*>(R.q[qsel])};
-      long long* rb = reinterpret_cast<long long*>(R.rbins) + (int64_t)(p < 0 ? 0 : p) * 2 * nc;
-      const int rbase = (c_first >> levels) - kRMargin;
-      long long racc0 = 0, racc1 = 0;
-      const int qbase = c_first - kQSlotMargin;
-      long long qacc = 0;
-
-      for (int k = tid; k < kQWin; k += kThreads) lds_q[k] = 0;
-      // Field window: nodes ebase .. ebase + kEWin (wrapped, or clamped to the wall
-      // nodes), so that a cell c in [ebase, ebase + kEWin) finds E_c and E_{c+1}.
-      const int ebase = c_first - kEMargin;
-      if (restrict_ || push) {
-        for (int k = tid; k <= kEWin; k += kThreads) {
-          const int g = periodic ? ((ebase + k) & nmask) : min(max(ebase + k, 0), n);
-          lds_e[k] = e[g];
-          if (restrict_) lds_en[k] = coev ? en[g] : 0.f;
-        }
-      }
-      __syncthreads();
-
-      for (unsigned b0 = 0; b0 < cnt; b0 += kThreads * kBatch) {
-        // loads use a clamped index so that they are unconditional; slots past the
-        // end of the tile are marked dead and never stored
-        int cl[kBatch];
-        float fr[kBatch], vv[kBatch], ww[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-          const unsigned idx = b0 + j * kWave + toff;
-          const unsigned ci = min(idx, cnt - 1u);
-          __builtin_assume(ci < 65536u);  // tiles hold at most 65536 ions
-          const int c = *at(cellp, ci);
-          cl[j] = idx < cnt ? c : -1;
-          fr[j] = *at(fracp, ci);
-          vv[j] = *at(vp_, ci);
-          ww[j] = *at(wp, ci);
-        }
-        // Node fields at both ends of each ion's cell, from the LDS window; ions
-        // outside it (rare: unsorted or far-drifted stores) read global memory.
-        float e0[kBatch], e1[kBatch], n0[kBatch], n1[kBatch];
-        bool outside = false;
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-          const int c = cl[j];
-          const bool alive = c >= 0 && c < n;
-          const int k = alive ? c - ebase : 0;
-          const bool inw = (unsigned)k < (unsigned)kEWin;
-          const int kk = inw ? k : 0;
-          outside |= !inw;
-          e0[j] = e1[j] = n0[j] = n1[j] = 0.f;
-          if (restrict_ || push) {
-            e0[j] = lds_e[kk];
-            e1[j] = lds_e[kk + 1];
-          }
-          if (restrict_) {
-            n0[j] = lds_en[kk];
-            n1[j] = lds_en[kk + 1];
-          }
-        }
-        if ((restrict_ || push) && __ballot(outside) != 0ull) {
-#pragma unroll
-          for (int j = 0; j < kBatch; ++j) {
-            const int c = cl[j];
-            const bool alive = c >= 0 && c < n;
-            if (alive && (unsigned)(c - ebase) >= (unsigned)kEWin) {
-              const int cr = periodic ? ((c + 1) & nmask) : c + 1;
-              e0[j] = e[c];
-              e1[j] = e[cr];
-              if (restrict_ && coev) {
-                n0[j] = en[c];
-                n1[j] = en[cr];
-              }
-            }
-          }
-        }
-        // E^p at the ions; then the snapshot values are computed and merged, and only
-        // after that the push and the new charge (the two phases' value arrays are
-        // never live together, which keeps the kernel at 4 waves per SIMD)
-        float epa[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-          const float f = fr[j];
-          epa[j] = (restrict_ || push) ? (1.f - f) * e0[j] + f * e1[j] : 0.f;
-        }
-        if (restrict_) {
-          int rkey[kBatch];
-          float ra0[kBatch], ra1[kBatch], rb0[kBatch], rb1[kBatch];
-#pragma unroll
-          for (int j = 0; j < kBatch; ++j) {
-            const int c = cl[j];
-            const float f = fr[j];
-            const float v = vv[j];
-            const float w = ww[j];
-            const bool alive = c >= 0 && c < n;  // cells outside [0, N) are treated as absorbed
-            const int cs = alive ? c : 0;         // safe cell index
-            const float ep = epa[j];
-            // Snapshot p: time-centred velocity, then the approximate characteristic
-            // over tau = Delta t - p dt (eq. B.4) and CIC at the moved position (eq. B.5).
-            const float vpc = v + half_dt_r * ep;  // half_dt_r = 0 on a fresh state
-            const float enx = (1.f - f) * n0[j] + f * n1[j];
-            const float xt = f + tau_inv_h * vpc;
-            const float vt = vpc + tau_e * enx;
-            const float fl = floorf(xt);
-            const float fx = xt - fl;
-            const bool wrap_up = fx >= 1.f;
-            const int ct0 = cs + (int)fl + (wrap_up ? 1 : 0);
-            const int ct = periodic ? (ct0 & nmask) : ct0;
-            const bool in = alive && (periodic || (ct >= 0 && ct < n));
-            const int bl = ct >> levels;
-            // both nodes of cell ct in block bl: ct is not the block's last cell, or
-            // (walls) the block is the last one, which also owns wall node N, or
-            // (periodic) there is a single block
-            const bool last = (ct & lmask) == lmask;
-            const bool same = !last || (periodic ? nc == 1 : bl == nc - 1);
-            // right-node share theta, zero when both nodes are in the same block
-            const float th = (wrap_up || same) ? 0.f : fx;
-            const float wv = w * vt;
-            rkey[j] = in ? bl : -1;
-            ra0[j] = w - w * th;
-            ra1[j] = wv - wv * th;
-            rb0[j] = w * th;
-            rb1[j] = wv * th;
-          }
-          merge_moments(rkey, ra0, ra1, rb0, rb1, periodic ? nc : -1, rbase, racc0, racc1, rb,
-                        rb + nc);
-        }
-        if (deposit) {
-          int dkey[kBatch];
-          double da[kBatch], db[kBatch];
-#pragma unroll
-          for (int j = 0; j < kBatch; ++j) {
-            const unsigned idx = b0 + j * kWave + toff;
-            __builtin_assume(idx < 65536u + kThreads * kBatch);
-            const int c = cl[j];
-            const float f = fr[j];
-            const float v = vv[j];
-            const float w = ww[j];
-            const bool alive = c >= 0 && c < n;
-            const int cs = alive ? c : 0;
-            const float ep = epa[j];
-            int cn = cs;
-            float fn = f, vn = v;
-            if (push) {
-              vn = v + dt_push * ep;
-              const float xn = f + dt_inv_h * vn;
-              const float fl = floorf(xn);
-              const bool wrap_up = (xn - fl) >= 1.f;
-              fn = wrap_up ? 0.f : xn - fl;
-              cn = cs + (int)fl + (wrap_up ? 1 : 0);
-              cn = periodic ? (cn & nmask) : ((cn < 0 || cn >= n) ? -1 : cn);  // walls absorb
-              if (alive && idx < cnt) {
-                *at(cellp, idx) = (int16_t)cn;
-                *at(fracp, idx) = fn;
-                *at(vp_, idx) = vn;
-              }
-            }
-            const bool dep = alive && cn >= 0;
-            const double q = fx_charge(w);
-            const double qr = fx_share(fn, q);
-            dkey[j] = dep ? cn : -1;
-            da[j] = q - qr;
-            db[j] = qr;
-          }
-          merge_charge(dkey, da, db, periodic ? n : -1, qbase, qacc, wq);
-        }
-      }
-      if (deposit) lds_qs[tid / kWave][tid % kWave] = qacc;
-      if (restrict_) {
-        lds_r[tid / kWave][0][tid % kWave] = racc0;
-        lds_r[tid / kWave][1][tid % kWave] = racc1;
-      }
-      __syncthreads();
-      if (deposit) {
-        long long* gq = reinterpret_cast<long long*>(R.q[qsel]);
-        for (int k = tid; k < kQWin; k += kThreads) {
-          long long val = lds_q[k];
-          const int s = k - (kQMargin - kQSlotMargin);  // slot of node wq.base + k
-          if (s >= 0 && s < kWave) {
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) val += lds_qs[w][s];
-          }
-          if (val != 0) gatomic_add(&gq[wq.base + k], val);
-        }
-      }
-      if (restrict_) {
-        for (int k = tid; k < 2 * kRWin; k += kThreads) {
-          const int m = k / kRWin;
-          const int kk = k - m * kRWin;
-          long long val = 0;
-#pragma unroll
-          for (int w = 0; w < kWaves; ++w) val += lds_r[w][m][kk];
-          if (val != 0) gatomic_add(&rb[(int64_t)m * nc + rbase + kk], val);
-        }
-      }
-      __syncthreads();
-    };
-    if (R.bc == 0) tile_pass(std::true_type{});
-    else tile_pass(std::false_type{});
+    const int64_t t0 = (item - R.item_begin) * (int64_t)tile + wave * quarter;
+    if (t0 >= np) continue;
+    const unsigned cnt = (unsigned)min(quarter, np - t0);
+    if (R.bc == 0)
+      wave_range<MODE, true>(R, L, t0, cnt, p, pd, fresh, qsel, big);
+    else
+      wave_range<MODE, false>(R, L, t0, cnt, p, pd, fresh, qsel, big);
   }
+  if (__ballot(big) != 0ull && __lane_id() == 0)
+    __hip_atomic_fetch_or(status, (uint32_t)EFPI_DEV_WEIGHT, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_fill_u8(uint8_t* p, size_t bytes) {
@@ -545,19 +507,21 @@ namespace {
 template <int MODE>
 void launch_mode(dim3 grid, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1,
                  const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
-                 int64_t total_items, int tile, int p, int fresh, int qsel) {
+                 int64_t total_items, int tile, int p, int fresh, int qsel, uint32_t* d_status) {
   if (ev0 && ev1)
     hipExtLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, ev0, ev1, 0, d_reps,
-                          d_item_prefix, n_reps, total_items, tile, p, (double)p, fresh, qsel);
+                          d_item_prefix, n_reps, total_items, tile, p, (double)p, fresh, qsel,
+                          d_status);
   else
     hipLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, d_reps, d_item_prefix,
-                       n_reps, total_items, tile, p, (double)p, fresh, qsel);
+                       n_reps, total_items, tile, p, (double)p, fresh, qsel, d_status);
 }
 }  // namespace
 
 void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
                       int64_t total_items, int tile, int grid_blocks, int p, int flags,
-                      int qsel, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+                      int qsel, uint32_t* d_status, hipStream_t stream, hipEvent_t ev0,
+                      hipEvent_t ev1) {
   if (total_items <= 0) return;
   const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_items) : total_items;
   const int fresh = (flags & kFresh) ? 1 : 0;
@@ -566,19 +530,19 @@ void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_
   switch (mode) {
     case kRestrict | kPush:
       launch_mode<kRestrict | kPush>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps,
-                                     total_items, tile, p, fresh, qsel);
+                                     total_items, tile, p, fresh, qsel, d_status);
       break;
     case kPush:
       launch_mode<kPush>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps, total_items, tile,
-                         p, fresh, qsel);
+                         p, fresh, qsel, d_status);
       break;
     case kRestrict:
       launch_mode<kRestrict>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps, total_items,
-                             tile, p, fresh, qsel);
+                             tile, p, fresh, qsel, d_status);
       break;
     default:
       launch_mode<kDepositOnly>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps,
-                                total_items, tile, p, fresh, qsel);
+                                total_items, tile, p, fresh, qsel, d_status);
       break;
   }
 }

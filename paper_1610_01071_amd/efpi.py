@@ -21,7 +21,7 @@ ABI_VERSION = 2
 BC_PERIODIC, BC_WALLS = 0, 1
 CLOSURE_BOLTZMANN, CLOSURE_KINETIC, CLOSURE_NOFIELD = 0, 1, 2
 FLAG_SORT_BUFFER = 1
-DEV_NEWTON, DEV_NAN, DEV_OVERFLOW, DEV_NEGMASS = 1, 2, 4, 8
+DEV_NEWTON, DEV_NAN, DEV_OVERFLOW, DEV_NEGMASS, DEV_WEIGHT = 1, 2, 4, 8, 16
 
 STATUS_NAMES = {0: "EFPI_OK", -1: "EFPI_EINVAL", -2: "EFPI_ENOMEM", -3: "EFPI_EHIP",
                 -4: "EFPI_ENEWTON", -5: "EFPI_ENUMERIC", -6: "EFPI_ESTATE", -7: "EFPI_EOVERFLOW"}
