@@ -113,7 +113,9 @@ typedef struct {
                                         error is about its square                 */
   int32_t tile;                      /* particles per work item: 0 (default, 4096)
                                         or a multiple of 1024 up to 16384         */
-  int32_t grid_blocks;               /* persistent grid size, 0 = default         */
+  int32_t grid_blocks;               /* persistent grid size of the particle, lift
+                                        and sort passes; 0 = one workgroup per
+                                        work item                                 */
   uint32_t flags;                    /* EFPI_FLAG_*                               */
 } efpi_config;
 

@@ -35,14 +35,6 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kDefaultTile = 4096;
 constexpr size_t kMaxGraphs = 8;  // captured macro steps kept per context
-constexpr int kDefaultGrid = 2048;
-
-struct NewtonGroup {
-  int M = 1;
-  int threads = 64;
-  int first = 0;  // offset into the list array
-  int count = 0;
-};
 
 // First failure among the enqueue calls of the current entry point; hip_check()
 // reports it (or else the runtime's last error) and clears it.
@@ -62,7 +54,7 @@ struct efpi_ctx {
   size_t ws_bytes = 0;
   int R = 0;
   int tile = kDefaultTile;
-  int grid_blocks = kDefaultGrid;
+  int grid_blocks = 0;
   std::vector<RepDev> h_reps;
   RepDev* d_reps = nullptr;
   uint32_t* d_status = nullptr;
@@ -71,7 +63,6 @@ struct efpi_ctx {
   int64_t* d_snap_off = nullptr;
   int64_t* d_coarse_off = nullptr;
   int32_t* d_group = nullptr;
-  RepDev* d_newton_reps = nullptr;  // descriptors in Newton launch order
   bool kinetic = false;             // kinetic electrons (every replica)
   int max_nodes = 0;                // largest node count of the replicas
   std::vector<RepDev> h_ereps;      // electron descriptors (kinetic contexts)
@@ -84,9 +75,7 @@ struct efpi_ctx {
   int32_t* d_sort_hist = nullptr;
   int64_t* d_sort_base = nullptr;
   std::vector<int64_t> h_item_prefix, h_block_prefix, h_snap_off, h_coarse_off;
-  std::vector<int32_t> h_group, h_newton_list;
-  std::vector<RepDev> h_newton_reps;
-  std::vector<NewtonGroup> ngroups;
+  std::vector<int32_t> h_group;
   int64_t total_items = 0, total_blocks = 0, snap_total = 0, coarse_total = 0;
   // state
   int cur = 0;             // q buffer holding the latest deposit
@@ -210,7 +199,6 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
   uint8_t* p_soff = take(sizeof(int64_t) * R);
   uint8_t* p_coff = take(sizeof(int64_t) * R);
   uint8_t* p_group = take(sizeof(int32_t) * R);
-  uint8_t* p_nreps = take(sizeof(RepDev) * R);
   const bool kinetic = cfg->replicas[0].closure == EFPI_CLOSURE_KINETIC;
   uint8_t* p_ereps = kinetic ? take(sizeof(RepDev) * R) : nullptr;
   uint8_t* p_eitems = kinetic ? take(sizeof(int64_t) * (R + 1)) : nullptr;
@@ -245,7 +233,6 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     ctx->d_snap_off = reinterpret_cast<int64_t*>(p_soff);
     ctx->d_coarse_off = reinterpret_cast<int64_t*>(p_coff);
     ctx->d_group = reinterpret_cast<int32_t*>(p_group);
-    ctx->d_newton_reps = reinterpret_cast<RepDev*>(p_nreps);
     ctx->d_snap = reinterpret_cast<double*>(p_snap);
     ctx->d_coarse = reinterpret_cast<double*>(p_coarse);
     ctx->d_sort_hist = reinterpret_cast<int32_t*>(p_hist);
@@ -327,6 +314,11 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
       d.coevolving = p.coevolving;
       d.lift_linear = p.lift_linear;
       d.log2n = ilog2(n);
+      // field solve: N rows over at most 256 threads up to N = 2048 (M = max(1,
+      // N / 256)), then over 512 threads (M = 8 at N = 4096, 16 at 8192, 32 at
+      // 16384; at N = 4096, 512 threads of 8 rows took 13.0 us for two Newton
+      // iterations against 13.5 us for 256 threads of 16 rows)
+      d.field_m = n <= 256 ? 1 : (n <= 2048 ? n / 256 : n / 512);
       d.h = p.length / n;
       d.inv_h = n / p.length;
       d.length = p.length;
@@ -417,9 +409,8 @@ void deposit_into_next(efpi_ctx* c) {
 }
 
 void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
-  for (const NewtonGroup& g : c->ngroups)
-    launch_newton(c->d_newton_reps + g.first, g.count, g.M, g.threads, iters, cold,
-                  c->cur, save_en, zero_bins, c->cfg.newton_tol, c->d_status, c->stream);
+  launch_newton(c->d_reps, c->R, iters, cold, c->cur, save_en, zero_bins, c->cfg.newton_tol,
+                c->d_status, c->stream);
   c->other_zero = true;
   c->field_valid = true;
 }
@@ -427,9 +418,7 @@ void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
 // Field of the current deposit: linear Poisson with kinetic electrons, else Newton.
 void run_field(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
   if (c->kinetic) {
-    for (const NewtonGroup& g : c->ngroups)
-      launch_poisson(c->d_newton_reps + g.first, g.count, g.M, g.threads, c->cur, save_en,
-                     zero_bins, c->d_status, c->stream);
+    launch_poisson(c->d_reps, c->R, c->cur, save_en, zero_bins, c->d_status, c->stream);
     c->other_zero = true;
     c->field_valid = true;
   } else {
@@ -623,7 +612,7 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
     c->total_eitems = c->h_eitem_prefix[c->R];
   }
   c->total_blocks = c->h_block_prefix[c->R];
-  c->grid_blocks = cfg->grid_blocks > 0 ? cfg->grid_blocks : kDefaultGrid;
+  c->grid_blocks = cfg->grid_blocks;  // 0: one workgroup per work item
   // ensemble groups: replicas with equal (n_cells, length) share the first one's index
   c->h_group.assign(c->R, 0);
   for (int r = 0; r < c->R; ++r) {
@@ -633,29 +622,6 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
         c->h_group[r] = c->h_group[q];
         break;
       }
-  }
-  // Newton launch groups by rows per thread M: N rows over at most 256 threads
-  // up to N = 2048 (M = max(1, N / 256)), then over 512 threads (M = 8 at
-  // N = 4096, 16 at 8192, 32 at 16384; at N = 4096, 512 threads of 8 rows take
-  // 13.0 us for two iterations against 13.5 us for 256 threads of 16 rows)
-  std::vector<int> ms = {1, 2, 4, 8, 16, 32};
-  c->h_newton_list.clear();
-  for (int M : ms) {
-    NewtonGroup g;
-    g.M = M;
-    g.first = (int)c->h_newton_list.size();
-    int maxT = 0;
-    for (int r = 0; r < c->R; ++r) {
-      const int n = c->reps[r].n_cells;
-      const int m = n <= 256 ? 1 : (n <= 2048 ? n / 256 : n / 512);
-      if (m == M) {
-        c->h_newton_list.push_back(r);
-        maxT = std::max(maxT, n / m);
-      }
-    }
-    g.count = (int)c->h_newton_list.size() - g.first;
-    g.threads = std::max(64, (maxT + 63) / 64 * 64);
-    if (g.count > 0) c->ngroups.push_back(g);
   }
   // clear the workspace, then upload descriptors and tables
   launch_fill_u8(c->ws, need, c->stream);
@@ -677,10 +643,6 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
     note(hipMemcpyAsync(c->d_eitem_prefix, c->h_eitem_prefix.data(), sizeof(int64_t) * (c->R + 1),
                         hipMemcpyHostToDevice, c->stream));
   }
-  c->h_newton_reps.clear();
-  for (int32_t r : c->h_newton_list) c->h_newton_reps.push_back(c->h_reps[r]);
-  note(hipMemcpyAsync(c->d_newton_reps, c->h_newton_reps.data(), sizeof(RepDev) * c->R,
-                 hipMemcpyHostToDevice, c->stream));
   const hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;
@@ -1098,7 +1060,6 @@ efpi_status efpi_set_macro_dt(efpi_ctx* ctx, double macro_dt) {
     ctx->reps[r].macro_dt = macro_dt;
     ctx->h_reps[r].macro_dt = macro_dt;
   }
-  for (RepDev& d : ctx->h_newton_reps) d.macro_dt = macro_dt;
   for (RepDev& d : ctx->h_ereps) d.macro_dt = macro_dt;
   if (ctx->kinetic)
     note(hipMemcpyAsync(ctx->d_ereps, ctx->h_ereps.data(), sizeof(RepDev) * ctx->R,
@@ -1106,8 +1067,6 @@ efpi_status efpi_set_macro_dt(efpi_ctx* ctx, double macro_dt) {
   // kernels (and captured graphs) read the descriptors on the device when they run,
   // so the new step takes effect for the work enqueued after this call
   note(hipMemcpyAsync(ctx->d_reps, ctx->h_reps.data(), sizeof(RepDev) * ctx->R,
-                      hipMemcpyHostToDevice, ctx->stream));
-  note(hipMemcpyAsync(ctx->d_newton_reps, ctx->h_newton_reps.data(), sizeof(RepDev) * ctx->R,
                       hipMemcpyHostToDevice, ctx->stream));
   // the host copies must outlive the asynchronous copies above
   note(hipStreamSynchronize(ctx->stream));

@@ -37,7 +37,8 @@ __device__ __forceinline__ EFPI_GLOBAL T* at(EFPI_GLOBAL T* base, unsigned i) {
 struct RepDev {
   int32_t n_cells, n_nodes, bc, closure;
   int32_t ppc, levels, n_coarse, burst_steps;
-  int32_t coevolving, lift_linear, log2n, pad0;
+  int32_t coevolving, lift_linear, log2n;
+  int32_t field_m;       // rows per thread of the field solve (N / field_m <= 512 threads)
   double h, inv_h, length, vth, dt, macro_dt, n_floor;
   int64_t capacity;
   int64_t item_begin;    // first particle work item of this replica
@@ -97,10 +98,10 @@ void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_
                       int64_t total_items, int tile, int grid_blocks, int p, int flags,
                       int qsel, uint32_t* d_status, hipStream_t stream, hipEvent_t ev0 = nullptr,
                       hipEvent_t ev1 = nullptr);
-// d_reps: the descriptors of the replicas solved by this launch, one workgroup each.
-void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
-                   int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
-                   uint32_t* d_status, hipStream_t stream);
+// Newton solves of every replica in one launch, one workgroup each (R.field_m
+// rows per thread).
+void launch_newton(const RepDev* d_reps, int n_reps, int iters, int cold, int qsel, int save_en,
+                   int zero_bins, double tol, uint32_t* d_status, hipStream_t stream);
 void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream);
 // Kinetic electrons (electrons.hip, field.hip).  d_ereps: electron descriptors.
 // Push (gather, leapfrog with R.qm, periodic wrap) and deposit -charge into
@@ -108,12 +109,11 @@ void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream);
 void launch_electrons(const RepDev* d_ereps, int n_reps, int push, int fresh, int qsel,
                       int max_nodes, hipStream_t stream, hipEvent_t ev0 = nullptr,
                       hipEvent_t ev1 = nullptr);
-// Linear periodic Poisson solve from R.q[qsel] of the replicas in d_reps (one
-// launch group of Newton's shape: M rows per thread, `threads` threads): phi, E
-// (and E_n with save_en), the other charge buffer cleared, the snapshot bins with
-// zero_bins.
-void launch_poisson(const RepDev* d_reps, int n_list, int M, int threads, int qsel, int save_en,
-                    int zero_bins, uint32_t* d_status, hipStream_t stream);
+// Linear periodic Poisson solve from R.q[qsel] of every replica in one launch
+// (Newton's shape: R.field_m rows per thread): phi, E (and E_n with save_en), the
+// other charge buffer cleared, the snapshot bins with zero_bins.
+void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
+                    uint32_t* d_status, hipStream_t stream);
 // Electron loading profile of every replica: density exp(phi), mean velocity the
 // ions' fine profile u (from_moments == 0) or the ion node momentum R.jfx over the
 // ion node charge R.q[qsel] (from_moments != 0), and the rotation (ion rotation

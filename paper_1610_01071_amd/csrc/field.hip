@@ -123,21 +123,36 @@ __device__ __forceinline__ float wave_cr(int lane, int nw, bool periodic, float 
   return D * rcp(A + B + C);
 }
 
-template <int M, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ reps, int iters,
-                                                   int cold, int qsel, int save_en,
-                                                   int zero_bins, double tol,
-                                                   uint32_t* __restrict__ status) {
-  constexpr int kW = THREADS / kWave;
-  __shared__ double s_first[THREADS], s_last[THREADS];
-  __shared__ float s_row0[kW][3];  // row 0 of each wave's lane 0, in terms of (X_{t-1}, X_t)
-  __shared__ float s_sol0[kW][3];  // lane 0's X in terms of the separators around its wave
-  __shared__ float s_if[kW][4];    // separator equation of each wave
-  __shared__ double s_wmax[kW];
-  __shared__ int s_wbad[kW];
-  __shared__ double s_phin;
+// Every field solve runs one workgroup of kFieldThreads threads per replica, all
+// replicas of a context in one launch; a replica's rows per thread M (its
+// descriptor's field_m) selects the compiled body, and threads past N / M only
+// take part in the barriers.
+constexpr int kFieldThreads = 512;
+constexpr int kFieldWaves = kFieldThreads / kWave;
 
-  const RepDev& R = reps[blockIdx.x];
+struct NewtonLds {
+  double s_first[kFieldThreads], s_last[kFieldThreads];
+  float s_row0[kFieldWaves][3];  // row 0 of each wave's lane 0, in terms of (X_{t-1}, X_t)
+  float s_sol0[kFieldWaves][3];  // lane 0's X in terms of the separators around its wave
+  float s_if[kFieldWaves][4];    // separator equation of each wave
+  double s_wmax[kFieldWaves];
+  int s_wbad[kFieldWaves];
+  double s_phin;
+};
+
+template <int M>
+__device__ __forceinline__ void newton_body(const RepDev& R, NewtonLds& S, int iters, int cold,
+                                            int qsel, int save_en, int zero_bins, double tol,
+                                            uint32_t* __restrict__ status) {
+  constexpr int THREADS = kFieldThreads;
+  double* const s_first = S.s_first;
+  double* const s_last = S.s_last;
+  auto& s_row0 = S.s_row0;
+  auto& s_sol0 = S.s_sol0;
+  auto& s_if = S.s_if;
+  auto& s_wmax = S.s_wmax;
+  auto& s_wbad = S.s_wbad;
+  double& s_phin = S.s_phin;
   const int n = R.n_cells;
   const int T = n / M;
   const int t = threadIdx.x;
@@ -480,6 +495,22 @@ __global__ __launch_bounds__(THREADS) void k_newton(const RepDev* __restrict__ r
   }
 }
 
+__global__ __launch_bounds__(kFieldThreads) void k_newton(const RepDev* __restrict__ reps,
+                                                         int iters, int cold, int qsel,
+                                                         int save_en, int zero_bins, double tol,
+                                                         uint32_t* __restrict__ status) {
+  __shared__ NewtonLds S;
+  const RepDev& R = reps[blockIdx.x];
+  switch (R.field_m) {
+    case 1: newton_body<1>(R, S, iters, cold, qsel, save_en, zero_bins, tol, status); break;
+    case 2: newton_body<2>(R, S, iters, cold, qsel, save_en, zero_bins, tol, status); break;
+    case 4: newton_body<4>(R, S, iters, cold, qsel, save_en, zero_bins, tol, status); break;
+    case 8: newton_body<8>(R, S, iters, cold, qsel, save_en, zero_bins, tol, status); break;
+    case 16: newton_body<16>(R, S, iters, cold, qsel, save_en, zero_bins, tol, status); break;
+    default: newton_body<32>(R, S, iters, cold, qsel, save_en, zero_bins, tol, status); break;
+  }
+}
+
 // Burst start when the field is already current: store E_n and clear the bins.
 __global__ void k_prep_burst(const RepDev* __restrict__ reps) {
   const RepDev& R = reps[blockIdx.x];
@@ -530,14 +561,21 @@ __device__ double block_excl_scan(double x, double* s_w, double& total) {
   return before + ex;
 }
 
-template <int M, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_poisson(const RepDev* __restrict__ reps, int qsel,
-                                                    int save_en, int zero_bins,
-                                                    uint32_t* __restrict__ status) {
-  __shared__ double s_w[THREADS / kWave];
-  __shared__ double s_first[THREADS], s_last[THREADS];
-  __shared__ int s_bad;
-  const RepDev& R = reps[blockIdx.x];
+struct PoissonLds {
+  double s_w[kFieldWaves];
+  double s_first[kFieldThreads], s_last[kFieldThreads];
+  int s_bad;
+};
+
+template <int M>
+__device__ __forceinline__ void poisson_body(const RepDev& R, PoissonLds& S, int qsel,
+                                             int save_en, int zero_bins,
+                                             uint32_t* __restrict__ status) {
+  constexpr int THREADS = kFieldThreads;
+  double* const s_w = S.s_w;
+  double* const s_first = S.s_first;
+  double* const s_last = S.s_last;
+  int& s_bad = S.s_bad;
   const int n = R.n_cells;
   const int T = n / M;
   const int t = threadIdx.x;
@@ -649,41 +687,34 @@ __global__ __launch_bounds__(THREADS) void k_poisson(const RepDev* __restrict__ 
   if (t == 0 && s_bad) atomicOr(status, 2u);
 }
 
-}  // namespace
-
-void launch_poisson(const RepDev* d_reps, int n_list, int M, int threads, int qsel, int save_en,
-                    int zero_bins, uint32_t* d_status, hipStream_t stream) {
-  if (n_list <= 0) return;
-  const dim3 grid(n_list);
-#define EFPI_POISSON(MM, TT)                                                                  \
-  hipLaunchKernelGGL((k_poisson<MM, TT>), grid, dim3(TT), 0, stream, d_reps, qsel, save_en,       \
-                     zero_bins, d_status)
-  if (M == 1) EFPI_POISSON(1, 256);
-  else if (M == 8 && threads > 256) EFPI_POISSON(8, 512);
-  else if (M == 2) EFPI_POISSON(2, 256);
-  else if (M == 4) EFPI_POISSON(4, 256);
-  else if (M == 8) EFPI_POISSON(8, 256);
-  else EFPI_POISSON(16, 512);
-#undef EFPI_POISSON
+__global__ __launch_bounds__(kFieldThreads) void k_poisson(const RepDev* __restrict__ reps,
+                                                          int qsel, int save_en, int zero_bins,
+                                                          uint32_t* __restrict__ status) {
+  __shared__ PoissonLds S;
+  const RepDev& R = reps[blockIdx.x];
+  switch (R.field_m) {
+    case 1: poisson_body<1>(R, S, qsel, save_en, zero_bins, status); break;
+    case 2: poisson_body<2>(R, S, qsel, save_en, zero_bins, status); break;
+    case 4: poisson_body<4>(R, S, qsel, save_en, zero_bins, status); break;
+    case 8: poisson_body<8>(R, S, qsel, save_en, zero_bins, status); break;
+    default: poisson_body<16>(R, S, qsel, save_en, zero_bins, status); break;
+  }
 }
 
-void launch_newton(const RepDev* d_reps, int n_list, int M, int threads,
-                   int iters, int cold, int qsel, int save_en, int zero_bins, double tol,
-                   uint32_t* d_status, hipStream_t stream) {
-  if (n_list <= 0) return;
-  const dim3 grid(n_list);
-#define EFPI_NEWTON(MM, TT)                                                                   \
-  hipLaunchKernelGGL((k_newton<MM, TT>), grid, dim3(threads), 0, stream, d_reps, iters,         \
-                     cold, qsel, save_en, zero_bins, tol, d_status)
-  if (M == 1) EFPI_NEWTON(1, 256);
-  else if (M == 8 && threads > 256) EFPI_NEWTON(8, 512);
-  else if (M == 2) EFPI_NEWTON(2, 256);
-  else if (M == 4) EFPI_NEWTON(4, 256);
-  else if (M == 8) EFPI_NEWTON(8, 256);
-  else if (M == 16 && threads <= 256) EFPI_NEWTON(16, 256);
-  else if (M == 16) EFPI_NEWTON(16, 512);
-  else EFPI_NEWTON(32, 512);
-#undef EFPI_NEWTON
+}  // namespace
+
+void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
+                    uint32_t* d_status, hipStream_t stream) {
+  if (n_reps <= 0) return;
+  hipLaunchKernelGGL(k_poisson, dim3(n_reps), dim3(kFieldThreads), 0, stream, d_reps, qsel,
+                     save_en, zero_bins, d_status);
+}
+
+void launch_newton(const RepDev* d_reps, int n_reps, int iters, int cold, int qsel, int save_en,
+                   int zero_bins, double tol, uint32_t* d_status, hipStream_t stream) {
+  if (n_reps <= 0) return;
+  hipLaunchKernelGGL(k_newton, dim3(n_reps), dim3(kFieldThreads), 0, stream, d_reps, iters, cold,
+                     qsel, save_en, zero_bins, tol, d_status);
 }
 
 void launch_prep_burst(const RepDev* d_reps, int n_reps, hipStream_t stream) {
