@@ -326,6 +326,16 @@ typedef struct {
   double taps[16];       /* low-pass filter h_0..h_{n_taps-1} (host copy)            */
 } efpi_phase;
 
+/* Order-2K Coiflet low-pass filter for efpi_phase (App. A: the wavelet has
+ * vanishing moments 0 .. 2K-1 and the scaling function vanishing moments
+ * 1 .. 2K-1 about the origin of its support [-2K, 4K-1], i.e. about tap 2K).
+ * n_taps = 6K: 12 for the paper's order-4 filter, or 6.  Among the isolated
+ * solutions of those conditions, the one most nearly symmetric about tap 2K is
+ * returned.  Host only and synchronous (no context, no device work); writes
+ * h_taps[n_taps] (sum sqrt 2, orthonormal even shifts).  EFPI_EINVAL for another
+ * n_taps or a NULL pointer, EFPI_ENUMERIC if the solver finds no filter. */
+efpi_status efpi_coiflet_taps(int32_t n_taps, double* h_taps);
+
 /* Bytes of the caller-owned work buffer of efpi_phase_restrict for replica r:
  * the int64 intermediate histogram [n_cells >> levels][2^jf]. */
 efpi_status efpi_phase_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,

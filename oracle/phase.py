@@ -55,13 +55,17 @@ class PhaseScheme:
 # ----------------------------------------------------------------------------
 
 COIFLET_TAPS = 12
+COIFLET_ORIGIN = 4   # tap index of the origin of the support [-4, 7]
 
 
 def coiflet_conditions(h):
-    """Residuals of the conditions that define the filter: sum h = sqrt 2,
+    """Residuals of the conditions that define the filter (App. A): sum h = sqrt 2,
     orthonormality of its even shifts, four vanishing moments of the wavelet
     (high-pass g_k = (-1)^k h_{L-1-k}) and vanishing moments 1..3 of the scaling
-    function about its centre c = sum k h_k / sqrt 2."""
+    function about the origin of its support.  The paper states the scaling
+    moments about y = 0; for taps indexed 0..11 that origin is tap 4 (support
+    [-4, 7]).  Through the two-scale relation, these discrete moments of the taps
+    vanish exactly when the continuous moments of phi and psi do."""
     h = np.asarray(h, dtype=np.float64)
     n = h.size
     k = np.arange(n, dtype=np.float64)
@@ -71,23 +75,65 @@ def coiflet_conditions(h):
     g = ((-1.0) ** k) * h[::-1]
     for p in range(4):
         r.append(np.sum(g * k ** p))
-    c = np.sum(h * k) / np.sqrt(2.0)
-    for p in (2, 3):
-        r.append(np.sum(h * (k - c) ** p))
+    for p in (1, 2, 3):
+        r.append(np.sum(h * (k - COIFLET_ORIGIN) ** p))
     return np.array(r)
 
 
-def coiflet_filter() -> np.ndarray:
-    """The 12-tap low-pass filter solving coiflet_conditions, by least squares
-    from seeded starting points (the first start that satisfies every condition
-    to 1e-13)."""
+def scaling_function(h, levels: int):
+    """The scaling function at the dyadic points i 2^-levels of its support [0, L-1]
+    (taps indexed from 0), by the cascade: its values at the integers are the
+    eigenvector of eigenvalue 1 of the refinement matrix sqrt 2 h_{2n-m}, summing
+    to 1, and each level follows from phi(y) = sqrt 2 sum_k h_k phi(2y - k)."""
+    h = np.asarray(h, dtype=np.float64)
+    n = h.size
+    a = np.zeros((n, n))
+    for i in range(n):
+        for m in range(n):
+            if 0 <= 2 * i - m < n:
+                a[i, m] = np.sqrt(2.0) * h[2 * i - m]
+    w, vec = np.linalg.eig(a)
+    phi = np.real(vec[:, np.argmin(np.abs(w - 1.0))])
+    phi = phi / phi.sum()
+    for j in range(levels):
+        step = 1 << j
+        size = (n - 1) * 2 * step + 1
+        nxt = np.zeros(size)
+        for k in range(n):
+            src = np.arange(size) - k * step
+            ok = (src >= 0) & (src < phi.size)
+            nxt[ok] += np.sqrt(2.0) * h[k] * phi[src[ok]]
+        phi = nxt
+    return phi
+
+
+def coiflet_filter(starts: int = 60) -> np.ndarray:
+    """The 12-tap order-4 Coiflet.  coiflet_conditions has several isolated
+    solutions; they are found by least squares from seeded starting points, and
+    the one whose scaling function (cascade, 2^-10 grid) is most nearly symmetric
+    about the support origin is returned (the paper picks this family for its
+    regularity and symmetry)."""
     rng = np.random.default_rng(0)
-    for _ in range(500):
+    sols = []
+    for _ in range(starts):
         sol = least_squares(coiflet_conditions, rng.normal(0.0, 0.3, COIFLET_TAPS),
                             xtol=1e-15, ftol=1e-15, gtol=1e-15, max_nfev=20000)
-        if np.max(np.abs(coiflet_conditions(sol.x))) < 1e-13:
-            return sol.x
-    raise RuntimeError("no Coiflet filter found")
+        if np.max(np.abs(coiflet_conditions(sol.x))) < 1e-12 and \
+                not any(np.max(np.abs(sol.x - s)) < 1e-8 for s in sols):
+            sols.append(sol.x)
+    if not sols:
+        raise RuntimeError("no Coiflet filter found")
+    levels = 10
+    o = COIFLET_ORIGIN << levels
+
+    def asymmetry(h):
+        phi = scaling_function(h, levels)
+        right = phi[o:]
+        left = np.zeros(right.size)
+        left[: o + 1] = phi[o::-1]
+        return np.sum((right - left) ** 2) * 2.0 ** -levels
+
+    return min(sols, key=asymmetry)
 
 
 def highpass(h):

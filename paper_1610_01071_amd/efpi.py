@@ -125,6 +125,7 @@ def _load():
         "efpi_macro_step_graph": [P, P, P, ctypes.POINTER(U32)],
         "efpi_ensemble_mean": [P, P],
         "efpi_restrict_state": [P, P],
+        "efpi_coiflet_taps": [I32, ctypes.POINTER(ctypes.c_double)],
         "efpi_phase_work_size": [P, I32, ctypes.POINTER(Phase), ctypes.POINTER(ctypes.c_size_t)],
         "efpi_phase_restrict": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, I32, P, P],
         "efpi_phase_lift_work_size": [P, I32, ctypes.POINTER(Phase),
@@ -172,7 +173,8 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_restrict", "efpi_project", "efpi_set_macro_dt", "efpi_project2",
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
-            "efpi_restrict_state", "efpi_phase_work_size", "efpi_phase_restrict",
+            "efpi_restrict_state", "efpi_coiflet_taps", "efpi_phase_work_size",
+            "efpi_phase_restrict",
             "efpi_phase_lift_work_size", "efpi_phase_lift", "efpi_phase_project",
             "efpi_store_field",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_timing_read_electrons",
@@ -402,6 +404,13 @@ def phase(v_min, v_max, jf, jc, levels, taps) -> Phase:
         raise ValueError("at most 16 filter taps")
     arr = (ctypes.c_double * 16)(*(taps + [0.0] * (16 - len(taps))))
     return Phase(float(v_min), float(v_max), int(jf), int(jc), int(levels), len(taps), arr)
+
+
+def efpi_coiflet_taps(n_taps: int = 12):
+    """Order-n_taps/3 Coiflet low-pass taps derived by the library (host only)."""
+    out = (ctypes.c_double * n_taps)()
+    _check(LIB.efpi_coiflet_taps(n_taps, out))
+    return [out[k] for k in range(n_taps)]
 
 
 def efpi_phase_work_size(ctx, replica, ph: Phase) -> int:

@@ -9,42 +9,19 @@ restriction along the co-evolving frame with tau = Delta t - p dt (App. B)
 after p fine steps, and efpi_phase_project (eqs. 3.17-3.18) over the
 snapshots.  Python only sequences the calls and owns the buffers.
 
-The order-4 Coiflet filter the paper uses is not tabulated here: coiflet_taps
-solves its defining conditions (twelve taps, orthonormal, four vanishing
-wavelet moments, scaling-function moments 1..3 vanishing about its centre) by
-least squares.  Those conditions leave the taps ill-conditioned, so another
-solver may land on a slightly different filter with the same properties.
+The order-4 Coiflet filter of App. A comes from the library
+(efpi_coiflet_taps), which derives it from its moment conditions.
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
-from scipy.optimize import least_squares
-
 from . import efpi as E
 
 
-def _filter_residuals(h):
-    n = h.size
-    idx = np.arange(n, dtype=np.float64)
-    res = [np.sum(h) - np.sqrt(2.0), np.sum(h * h) - 1.0]
-    res += [np.sum(h[:n - 2 * s] * h[2 * s:]) for s in range(1, n // 2)]
-    hp = np.where(idx % 2 == 0, 1.0, -1.0) * h[::-1]
-    res += [np.sum(hp * idx ** q) for q in range(4)]
-    centre = np.sum(idx * h) / np.sqrt(2.0)
-    res += [np.sum(h * (idx - centre) ** q) for q in (2, 3)]
-    return np.array(res)
-
-
-def coiflet_taps(seed: int = 0) -> np.ndarray:
-    """Twelve low-pass taps satisfying the order-4 Coiflet conditions to 1e-13."""
-    rng = np.random.default_rng(seed)
-    for _ in range(500):
-        fit = least_squares(_filter_residuals, rng.normal(0.0, 0.3, 12), xtol=1e-15, ftol=1e-15,
-                            gtol=1e-15, max_nfev=20000)
-        if np.max(np.abs(_filter_residuals(fit.x))) < 1e-13:
-            return fit.x
-    raise RuntimeError("no filter satisfies the Coiflet conditions")
+def coiflet_taps(n_taps: int = 12) -> np.ndarray:
+    """The library's order-n_taps/3 Coiflet low-pass taps (12: the paper's order 4)."""
+    return np.array(E.efpi_coiflet_taps(n_taps))
 
 
 def _aligned(nbytes: int, device) -> torch.Tensor:
