@@ -315,3 +315,54 @@ def test_rel_l2_metric():
     assert metrics.rel_l2([1, 2], [1, 2]) == 0.0
     assert metrics.rel_l2([1, 0], [0, 1]) == pytest.approx(1.0)
     assert metrics.rel_l2([2.0], [1.0]) == pytest.approx(np.sqrt(1 / 5))
+
+
+# ----------------------------------------------------- in-cell interpolation --
+# Hand-worked quiet starts (App. C: density and mean velocity are interpolated
+# linearly between the two nodes of a cell).  Node values n = (1, 3, 2, 5),
+# u = (0.1, -0.2, 0.4, 0.0), h = 2, two ions per cell at offsets 1/4 and 3/4, cold
+# ions (vth = 0) so that v = u(X) exactly; w = n(X) h / ppc = n(X).
+
+HAND_N = np.array([1.0, 3.0, 2.0, 5.0])
+HAND_U = np.array([0.1, -0.2, 0.4, 0.0])
+
+
+def test_load_particles_interpolates_n_and_u_in_the_cell_periodic():
+    g = Grid(4, 8.0)
+    sch = efpi.Scheme(ppc=2, vth=0.0)
+    cell, frac, v, w = efpi.load_particles(HAND_N, HAND_U, g, sch, 12345)
+    assert list(cell) == [0, 0, 1, 1, 2, 2, 3, 3]
+    assert list(frac) == [0.25, 0.75] * 4
+    # cell 3 takes its right node from node 0 (periodic)
+    assert np.allclose(w, [1.5, 2.5, 2.75, 2.25, 2.75, 4.25, 4.0, 2.0], rtol=0, atol=1e-15)
+    assert np.allclose(v, [0.025, -0.125, -0.05, 0.25, 0.3, 0.1, 0.025, 0.075], rtol=0,
+                       atol=1e-15)
+
+
+def test_load_particles_interpolates_n_and_u_in_the_cell_walls():
+    g = Grid(4, 8.0, bc=WALLS)
+    sch = efpi.Scheme(ppc=2, vth=0.0)
+    n5 = np.append(HAND_N, 3.0)            # wall node 4
+    u5 = np.append(HAND_U, -0.4)
+    cell, frac, v, w = efpi.load_particles(n5, u5, g, sch, 12345)
+    assert np.allclose(w[6:], [4.5, 3.5], rtol=0, atol=1e-15)        # (5, 3) at 1/4, 3/4
+    assert np.allclose(v[6:], [-0.1, -0.3], rtol=0, atol=1e-15)      # (0, -0.4)
+    assert np.allclose(w[:6], [1.5, 2.5, 2.75, 2.25, 2.75, 4.25], rtol=0, atol=1e-15)
+
+
+def test_lift_profile_linear_between_block_centres():
+    # 8 cells, blocks of 4 (l = 2) with means 1 and 3 (coefficients 2^{l/2} times
+    # the means); centres at 1.5 and 5.5.  Periodic: node 0 lies 2.5 to the right
+    # of the previous period's centre 5.5 - 8, a fraction 0.625 of the way to 1.5.
+    sch = efpi.Scheme(levels=2, lift_linear=True)
+    coarse = np.array([[2.0, 6.0], [0.4, -0.2]])           # means (1, 3) and (0.2, -0.1)
+    n, j = efpi.lift_profile(coarse, Grid(8, 8.0), sch)
+    assert np.allclose(n, [1.75, 1.25, 1.25, 1.75, 2.25, 2.75, 2.75, 2.25], rtol=0, atol=1e-15)
+    assert np.allclose(j, [0.0875, 0.1625, 0.1625, 0.0875, 0.0125, -0.0625, -0.0625, 0.0125],
+                       rtol=0, atol=1e-15)
+    # walls: constant beyond the end centres, node 8 included
+    n, _ = efpi.lift_profile(coarse, Grid(8, 8.0, bc=WALLS), sch)
+    assert np.allclose(n, [1.0, 1.0, 1.25, 1.75, 2.25, 2.75, 3.0, 3.0, 3.0], rtol=0, atol=1e-15)
+    # and the piecewise-constant inverse Haar without the flag
+    n, _ = efpi.lift_profile(coarse, Grid(8, 8.0), efpi.Scheme(levels=2, lift_linear=False))
+    assert np.allclose(n, [1.0] * 4 + [3.0] * 4, rtol=0, atol=1e-15)

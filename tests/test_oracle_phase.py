@@ -288,3 +288,30 @@ def test_repair_sum_order_does_not_decide_the_gpu_cases(n, levels, jf, jc, ppc, 
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     for k in (2, 3):
         assert np.max(np.abs(a[k] - b[k])) <= 1e-12 * np.max(np.abs(a[k]))
+
+
+def _bitrev32(i):
+    return int(format(i, "032b")[::-1], 2)
+
+
+def test_lift_phase_interpolates_between_the_two_nodes(monkeypatch):
+    # Hand-worked lift (App. C: values at a particle are interpolated linearly
+    # between the two closest grid points).  Two periodic cells, h = 1, 16 bins of
+    # dv = 1/4 over [-2, 2).  Node 0 holds density 4 in bin 5 only (n = 1), node 1
+    # density 8 in bin 9 only (n = 2); both CDFs are valid, so the repair keeps them
+    # and a node's inverse CDF at b is v_min + (bin + b) dv.  Two ions per cell.
+    ps = PhaseScheme(levels=0, v_min=-2.0, v_max=2.0, jf=4, jc=4, ppc=2)
+    fine = np.zeros((2, 16))
+    fine[0, 5] = 4.0
+    fine[1, 9] = 8.0
+    monkeypatch.setattr(phase, "refine", lambda coarse, ps_, h_: fine)
+    shift = 987654321
+    cell, frac, v, w = phase.lift_phase(None, Grid(2, 2.0), ps, None, shift)
+    assert list(cell) == [0, 0, 1, 1] and list(frac) == [0.25, 0.75, 0.25, 0.75]
+    b = [((_bitrev32(i) + shift) % 2 ** 32 + 0.5) / 2.0 ** 32 for i in range(4)]
+    # cell 0: bin 5 -> 9 across the cell, i.e. 5 + 4 frac; cell 1: 9 -> 5
+    expect_v = [-2.0 + 0.25 * (5 + 1 + b[0]), -2.0 + 0.25 * (5 + 3 + b[1]),
+                -2.0 + 0.25 * (9 - 1 + b[2]), -2.0 + 0.25 * (9 - 3 + b[3])]
+    assert np.allclose(v, expect_v, rtol=0, atol=1e-14)
+    # w = n(X) h / ppc with n = 1 at node 0 and 2 at node 1
+    assert np.allclose(w, [0.625, 0.875, 0.875, 0.625], rtol=0, atol=1e-15)
