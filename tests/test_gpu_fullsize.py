@@ -1,8 +1,9 @@
 """Parity at the benchmark's full size and launch configuration.
 
 Workload: the ion-acoustic wave (eq. 4.1) on 4096 cells with 1000 ions per cell
-(4,096,000 ions), l = 4, N_e = 20, dt = 0.1, Delta t = 200 dt, the default tile
-and grid that bench.py times.  The oracle loads the ions itself (quiet start of
+(4,096,000 ions), l = 4, N_e = 20, dt = 0.1, Delta t = 200 dt, at the particle
+tile of bench.py's EFPI runs (4096, one workgroup per tile) and of its full-PIC
+references (2048).  The oracle loads the ions itself (quiet start of
 App. C from the same profile and rotation) and the GPU receives the same FP32
 state.  Bars as in the small-size tests: charge bit-exact; one step sampled
 particle by particle within 1e-5; restriction within 1e-7; the macro step's
@@ -26,12 +27,13 @@ pytestmark = pytest.mark.gpu
 N, PPC = 4096, 1000
 
 
-@pytest.fixture(scope="module")
-def full():
+@pytest.fixture(scope="module", params=[4096, 2048])
+def full(request):
     E = lib()
     spec = E.ReplicaSpec(N, float(N), ppc=PPC, haar_levels=4, burst_steps=20, macro_dt=20.0,
                          dt=0.1, vth=math.sqrt(0.1))
-    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4, tile=2048))
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4,
+                                 tile=request.param))
     g, sch = oracle_grid(spec), oracle_scheme(spec)
     n, u = synth.iaw_profile(N, float(N))
     c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(2016))

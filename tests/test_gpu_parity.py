@@ -361,3 +361,82 @@ def test_restrict_state_matches_oracle():
     ref = oefpi.restrict_state(xp, vi, parts[3].astype(np.float64), al, g, sch)
     for m in range(2):
         assert metrics.rel_l2(got[m], ref[m]) < 1e-5
+
+
+# ------------------------------------------------------------ absorbing walls --
+
+def wall_particles(n_cells, seed, n_edge=4000, n_bulk=40000):
+    """A bulk population in the middle (it makes the field) and ions in the two
+    end cells moving out at 0.5 .. 3 cells per unit time, so that a step of
+    dt = 0.1 takes a known part of them through x = 0 and x = L."""
+    g = np.random.default_rng(seed)
+    cb, fb, vb, wb = synth.random_particles(n_bulk, n_cells // 2, seed=seed, vth=0.2,
+                                            w_mean=n_cells / (2.0 * n_bulk))
+    cb = (cb + n_cells // 4).astype(np.int16)
+    left = np.zeros(n_edge, np.int16)
+    right = np.full(n_edge, n_cells - 1, np.int16)
+    fe = g.random(2 * n_edge, dtype=np.float32) * np.float32(0.999)
+    ve = g.uniform(0.5, 3.0, 2 * n_edge).astype(np.float32)
+    ve[:n_edge] *= -1.0                                          # left end: towards x = 0
+    we = (g.uniform(0.5, 1.5, 2 * n_edge) * 0.01).astype(np.float32)
+    cell = np.concatenate([left, right, cb])
+    order = np.argsort(cell, kind="stable")
+    cat = lambda a, b: np.concatenate([a, b])[order]
+    return (cell[order], cat(fe, fb), cat(ve, vb), cat(we, wb))
+
+
+def test_one_step_through_both_walls():
+    E = lib()
+    n = 256
+    spec = E.ReplicaSpec(n, float(n), bc=1, ppc=1, haar_levels=3, vth=0.1,
+                         capacity=48000)
+    ctx = make_ctx([spec])
+    cell, frac, v, w = wall_particles(n, 41)
+    set_particles(ctx, 0, cell, frac, v, w)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 80, cold=True)
+    E.efpi_pic_burst(ctx.ctx, 1, False)
+    gc, gf, gv, gw = particles_np(ctx)
+    q, _, e = grid_np(ctx)
+    g = oracle_grid(spec)
+    x0 = x_of(cell, frac, g.h)
+    alive0 = np.ones(x0.size, bool)
+    _, phi0, e0 = opic.field_from_particles(x0, w.astype(np.float64), alive0, g)
+    vh = v.astype(np.float64) + 0.5 * g.dt * opic.gather(e0, x0, g)
+    x1, alive = opic.apply_bc(x0 + g.dt * vh, alive0, g)
+    # both walls absorbed ions in this step, and exactly the oracle's ones
+    assert np.sum(~alive & (x1 < 0)) > 100 and np.sum(~alive & (x1 >= g.length)) > 100
+    assert np.array_equal(gc >= 0, alive)
+    assert relmax(gv[alive], vh[alive]) < 1e-5
+    assert np.max(np.abs(x_of(gc[alive], gf[alive], g.h) - x1[alive])) < 1e-5 * g.h
+    # charge: survivors only, bit-exact, and the fused deposit equals the oracle's
+    assert np.array_equal(q, opic.deposit_fx(gc, gf, gw, g))
+    qsurv = int(np.sum(np.rint(w[alive].astype(np.float64) * 2.0 ** 40).astype(np.int64)))
+    assert int(q.sum()) == qsurv
+
+
+def test_burst_with_positions_moved_past_the_walls():
+    # Plasma filling the box: over tau = Delta t - p dt of up to 20, the
+    # co-evolving positions X + tau V of the outer ions leave [0, L) and are left
+    # out of the snapshots (in flight to a wall), and ions reach the walls during
+    # the burst itself.
+    E = lib()
+    n = 512
+    spec = E.ReplicaSpec(n, float(n), bc=1, ppc=40, haar_levels=3, burst_steps=20,
+                         macro_dt=20.0, vth=0.8)
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    dens, u = synth.slab_profile(n, width=1.0)
+    cell, frac, v, w = oefpi.load_particles(dens, u, g, sch, synth.lift_shift(43))
+    parts = (cell.astype(np.int16), frac.astype(np.float32), v.astype(np.float32),
+             w.astype(np.float32))
+    gs, gn, os_, on = _burst_compare(spec, parts, "wide slab", newton_iters=3)
+    # the exclusion acts: the first snapshot misses mass that left the box
+    total = np.sum(w.astype(np.float64)) / g.h * 2.0 ** (-sch.levels / 2.0)
+    assert np.sum(os_[0, 0]) < 0.98 * total
+    assert abs(np.sum(gs[0, 0]) / np.sum(os_[0, 0]) - 1.0) < 2e-3
+    # and ions were absorbed during the burst on both sides
+    ctx = make_ctx([spec], newton_iters=3)
+    set_particles(ctx, 0, *parts)
+    E.efpi_pic_burst(ctx.ctx, spec.burst_steps, False)
+    gc = particles_np(ctx)[0]
+    assert np.sum(gc < 0) > 30
