@@ -166,7 +166,11 @@ efpi_status efpi_get_particles(efpi_ctx* ctx, int32_t replica, int16_t* d_cell, 
 efpi_status efpi_get_grid(efpi_ctx* ctx, int32_t replica, int64_t* d_q, double* d_phi,
                           float* d_e);
 
-/* Set replica r's potential (warm start of the next Newton solve). */
+/* Set replica r's potential (warm start of the next Newton solve).  Without it,
+ * or a solve, the first field solve of a context after a load or lift starts cold
+ * from phi = ln max(rho, 1e-8); once any replica's potential is set or solved,
+ * burst starts are warm for every replica.  A cold first solve takes
+ * max(newton_iters_start, 40) iterations. */
 efpi_status efpi_set_potential(efpi_ctx* ctx, int32_t replica, const double* d_phi);
 
 /* ------------------------------------------------------------- hot path -- */
@@ -321,7 +325,9 @@ typedef struct {
   double v_min, v_max;   /* velocity window                                          */
   int32_t jf;            /* 2^jf fine velocity bins, 4 <= jf <= 11                    */
   int32_t jc;            /* 2^jc coarse coefficients per x node, jc <= jf, 2^jc >= n_taps */
-  int32_t levels;        /* full-weighting levels in x, n_cells >> levels >= 1        */
+  int32_t levels;        /* full-weighting levels in x, n_cells >> levels >= 1, and
+                            h 4^levels < 2^18 (the int64 histogram holds node
+                            densities up to 16 n_0 at that bound)                   */
   int32_t n_taps;        /* filter length, even, 2 <= n_taps <= 16                    */
   double taps[16];       /* low-pass filter h_0..h_{n_taps-1} (host copy)            */
 } efpi_phase;

@@ -35,6 +35,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kDefaultTile = 4096;
 constexpr size_t kMaxGraphs = 8;  // captured macro steps kept per context
+constexpr int kColdIters = 40;     // Newton iterations of a context's first (cold) solve
 
 // First failure among the enqueue calls of the current entry point; hip_check()
 // reports it (or else the runtime's last error) and clears it.
@@ -82,6 +83,7 @@ struct efpi_ctx {
   bool other_zero = true;  // q[cur ^ 1] is known to be zero
   bool deposited = false;  // charge matches the current particles
   bool field_valid = false;
+  bool phi_valid = false;  // phi holds a solve of this context (a warm start)
   bool fresh = true;       // ion velocities at an integer time level
   bool fresh_e = true;     // electron velocities at an integer time level (kinetic)
   int last_burst_steps = -1;
@@ -94,17 +96,18 @@ struct efpi_ctx {
   // captured macro steps, keyed by their arguments and the state they start from
   struct HostState {
     int cur;
-    bool other_zero, deposited, field_valid, fresh, fresh_e;
+    bool other_zero, deposited, field_valid, phi_valid, fresh, fresh_e;
     int last_burst_steps;
   };
   HostState state() const {
-    return {cur, other_zero, deposited, field_valid, fresh, fresh_e, last_burst_steps};
+    return {cur, other_zero, deposited, field_valid, phi_valid, fresh, fresh_e, last_burst_steps};
   }
   void set_state(const HostState& s) {
     cur = s.cur;
     other_zero = s.other_zero;
     deposited = s.deposited;
     field_valid = s.field_valid;
+    phi_valid = s.phi_valid;
     fresh = s.fresh;
     fresh_e = s.fresh_e;
     last_burst_steps = s.last_burst_steps;
@@ -112,8 +115,9 @@ struct efpi_ctx {
   struct MacroGraph {
     const double* in;
     double* out;
-    int cur0;            // the captured launches depend only on these two fields
+    int cur0;            // the captured launches depend only on these three fields
     bool other_zero0;
+    bool phi_valid0;
     HostState after;     // state the macro step leaves
     hipGraphExec_t exec;
   };
@@ -413,6 +417,7 @@ void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {
                 c->d_status, c->stream);
   c->other_zero = true;
   c->field_valid = true;
+  c->phi_valid = true;
 }
 
 // Field of the current deposit: linear Poisson with kinetic electrons, else Newton.
@@ -502,7 +507,12 @@ hipEvent_t next_event(efpi_ctx* c) {
 efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
   if (!c->field_valid) {
     if (!c->deposited) deposit_all(c, true);
-    run_field(c, c->cfg.newton_iters_start, 0, restrict_ ? 1 : 0, restrict_ ? 1 : 0);
+    // the first solve of a context starts from phi = ln max(rho, 1e-8) (its stored
+    // phi is zero, far from the solution where the density vanishes) and takes
+    // kColdIters iterations: near a plasma edge the vacuum guess lies 10 and more
+    // below the solution, and each Newton correction is clamped to 2
+    run_field(c, c->phi_valid ? c->cfg.newton_iters_start : std::max(c->cfg.newton_iters_start, kColdIters),
+              c->phi_valid ? 0 : 1, restrict_ ? 1 : 0, restrict_ ? 1 : 0);
   } else if (restrict_) {
     launch_prep_burst(c->d_reps, c->R, c->stream);
   }
@@ -712,6 +722,7 @@ efpi_status efpi_set_potential(efpi_ctx* ctx, int32_t replica, const double* d_p
   const RepDev& d = ctx->h_reps[replica];
   note(hipMemcpyAsync(d.phi, d_phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
   ctx->field_valid = false;
+  ctx->phi_valid = true;
   return hip_check("set_potential");
 }
 
@@ -889,11 +900,12 @@ efpi_status efpi_macro_step_graph(efpi_ctx* ctx, const double* d_coarse_in, doub
   efpi_ctx::MacroGraph* g = nullptr;
   for (efpi_ctx::MacroGraph& m : ctx->graphs)
     if (m.in == d_coarse_in && m.out == d_coarse_out && m.cur0 == ctx->cur &&
-        m.other_zero0 == ctx->other_zero)
+        m.other_zero0 == ctx->other_zero && m.phi_valid0 == ctx->phi_valid)
       g = &m;
   if (!g) {
     const efpi_ctx::HostState before = ctx->state();
-    efpi_ctx::MacroGraph m{d_coarse_in, d_coarse_out, ctx->cur, ctx->other_zero, before, nullptr};
+    efpi_ctx::MacroGraph m{d_coarse_in, d_coarse_out, ctx->cur, ctx->other_zero,
+                           ctx->phi_valid, before, nullptr};
     hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return fail(EFPI_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
     // the same launches as efpi_macro_step, lift rotations read from the device
@@ -939,6 +951,11 @@ efpi_status check_phase(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph) {
   if ((1 << ph->jc) < ph->n_taps) return fail(EFPI_EINVAL, "2^jc must be >= n_taps");
   if (ph->levels < 0 || (d.n_cells >> ph->levels) < 1)
     return fail(EFPI_EINVAL, "levels out of range");
+  // A coarse bin sums at most 2^(levels+1) cells' charge with weights up to
+  // 2^levels: with node densities up to 16 that is below 2^40 * 16 * 2 h 4^levels,
+  // which must stay below 2^63 for the int64 histogram.
+  if (std::ldexp(d.h, 2 * ph->levels) >= 262144.0)
+    return fail(EFPI_EINVAL, "h * 4^levels must be below 2^18 (int64 phase histogram range)");
   for (int m = 0; m < ph->n_taps; ++m)
     if (!std::isfinite(ph->taps[m])) return fail(EFPI_EINVAL, "non-finite filter tap");
   return EFPI_OK;
@@ -1027,7 +1044,9 @@ efpi_status efpi_store_field(efpi_ctx* ctx) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   if (!ctx->field_valid) {
     if (!ctx->deposited) deposit_all(ctx, true);
-    run_field(ctx, ctx->cfg.newton_iters_start, 0, 1, 0);
+    run_field(ctx, ctx->phi_valid ? ctx->cfg.newton_iters_start
+                                  : std::max(ctx->cfg.newton_iters_start, kColdIters),
+              ctx->phi_valid ? 0 : 1, 1, 0);
   } else {
     launch_prep_burst(ctx->d_reps, ctx->R, ctx->stream);
   }

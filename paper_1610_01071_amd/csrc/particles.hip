@@ -165,15 +165,24 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
   const float tau_e = coev ? tau : 0.f;
 
   // Reference cell of the range: midway between its first and last cells (a
-  // cell-sorted store), or whichever of them is live.
+  // cell-sorted store), or whichever of them is live.  Ions drift after a sort,
+  // so the last ion may sit a cell or two below the first: on a periodic grid
+  // the midpoint is taken along the shorter way round.
   const int c_lo = __builtin_amdgcn_readfirstlane((int)*at(cellp, 0u));
   const int c_hi = __builtin_amdgcn_readfirstlane((int)*at(cellp, cnt - 1u));
   const bool lo_ok = (unsigned)c_lo < (unsigned)n, hi_ok = (unsigned)c_hi < (unsigned)n;
   int cref;
-  if (lo_ok && hi_ok)
-    cref = kPeriodic ? ((c_lo + (((c_hi - c_lo) & nmask) >> 1)) & nmask) : ((c_lo + c_hi) >> 1);
-  else
+  if (lo_ok && hi_ok) {
+    if (kPeriodic) {
+      int d = (c_hi - c_lo) & nmask;
+      if (d > (n >> 1)) d -= n;
+      cref = (c_lo + (d >> 1)) & nmask;
+    } else {
+      cref = (c_lo + c_hi) >> 1;
+    }
+  } else {
     cref = lo_ok ? c_lo : (hi_ok ? c_hi : 0);
+  }
   const int ebase = cref - kEBelow;
   const int qbase = cref - kQBelow;
   const int rbase = (cref >> levels) - kRBelow;

@@ -93,6 +93,14 @@ def test_phase_parameters_checked():
                 E.phase(-1, 1, 12, 6, 1, D4)):
         with pytest.raises(E.EfpiError):
             E.efpi_phase_work_size(per.ctx, 0, bad)
+    # the int64 histogram's range: h 4^levels below 2^18
+    big = E.Context(E.ConfigSpec([E.ReplicaSpec(16384, 16384.0, ppc=1)]))
+    E.efpi_phase_work_size(big.ctx, 0, E.phase(-1, 1, 6, 4, 8, D4))      # 2^16: accepted
+    with pytest.raises(E.EfpiError):
+        E.efpi_phase_work_size(big.ctx, 0, E.phase(-1, 1, 6, 4, 9, D4))  # 2^18: rejected
+    coarse = E.Context(E.ConfigSpec([E.ReplicaSpec(1024, 4096.0, ppc=1)]))   # h = 4
+    with pytest.raises(E.EfpiError):
+        E.efpi_phase_work_size(coarse.ctx, 0, E.phase(-1, 1, 6, 4, 8, D4))
 
 
 @pytest.mark.parametrize("n,levels,jf,jc,ppc,filt", LIFT_CASES)
