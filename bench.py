@@ -186,6 +186,8 @@ def main():
                     help="physical time of the kinetic-electron comparison")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the Euler / second-order / adaptive projective runs")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="ions per work item of the ensemble's particle pass (0: autotuned)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB three times (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -226,7 +228,10 @@ def headline(args, np, torch, synth, E):
     n_ions = sum(s.n_cells * s.ppc for s in specs)
     K = specs[0].burst_steps
     t0 = time.perf_counter()
-    choice = autotune.autotune(specs, tiles=(2048, TILE, 8192), grids=(0,), steps=1, warmup=1)
+    if args.tile > 0:  # a fixed launch shape (profiling runs: one shape per kernel record)
+        choice = autotune.Choice(args.tile, 0, float("nan"), [])
+    else:
+        choice = autotune.autotune(specs, tiles=(2048, TILE, 8192), grids=(0,), steps=1, warmup=1)
     t_tune = time.perf_counter() - t0
     ctx = E.Context(E.ConfigSpec(specs, newton_iters=2, newton_iters_start=4, tile=choice.tile,
                                  grid_blocks=choice.grid_blocks))
