@@ -16,7 +16,9 @@
  * Conventions that hold for every entry point:
  *  - Pointers named d_* are device pointers, h_* are host pointers.
  *  - Device memory is owned by the caller.  efpi_init binds one caller-owned
- *    workspace; the library never allocates or frees device memory.
+ *    workspace; the library never allocates or frees device memory.  Its one
+ *    device array of its own is the static scratch of
+ *    efpi_phase_restrict_static, which the loaded code object holds on each GPU.
  *  - Every call that touches the device only enqueues work on the context's
  *    HIP stream and returns; results are visible after the stream synchronises.
  *    Calls documented as synchronous say so.
@@ -361,6 +363,23 @@ efpi_status efpi_phase_work_size(efpi_ctx* ctx, int32_t replica, const efpi_phas
  * bytes, 256-byte aligned.  EFPI_EINVAL on bad parameters. */
 efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
                                 double tau, int32_t stored_field, void* d_work, double* d_out);
+
+/* Size of the static scratch of efpi_phase_restrict_static (per GPU). */
+#define EFPI_STATIC_SCRATCH_BYTES ((size_t)8 << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): efpi_phase_restrict
+ * with its int64 histogram in a static device array of EFPI_STATIC_SCRATCH_BYTES
+ * that the library's code object holds on each GPU until the process ends,
+ * instead of a caller work buffer.  Same arguments, checks, kernels and results
+ * as efpi_phase_restrict; allocates nothing.  The array's address on a device is
+ * looked up at the first efpi_init with that device current; the context's
+ * stream must belong to that device.  EFPI_EINVAL when the histogram
+ * (efpi_phase_work_size bytes) exceeds EFPI_STATIC_SCRATCH_BYTES.  Every call on
+ * one GPU uses the same array: each call clears the histogram before use, and
+ * calls that can overlap on one GPU (other streams, other threads) race. */
+efpi_status efpi_phase_restrict_static(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                       double tau, int32_t stored_field, double* d_out);
 
 /* Bytes of the caller-owned work buffer of efpi_phase_lift for replica r: the
  * refined columns [n_cells >> levels][2^jf] and the repaired CDFs

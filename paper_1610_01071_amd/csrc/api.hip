@@ -1,11 +1,13 @@
 // Host side of libefpi: configuration checks, workspace layout and the
 // extern "C" entry points declared in include/efpi.h.  Every entry point only
 // enqueues kernels on the context's stream (except those documented as
-// synchronous); the library never allocates device memory.
+// synchronous); the library never allocates device memory (its one device array,
+// the static scratch of efpi_phase_restrict_static, comes with the code object).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,12 +49,53 @@ void note(hipError_t e) {
 
 }  // namespace
 
+// ------------------------------------------------------------ static scratch --
+// The int64 histogram of efpi_phase_restrict_static: a file-scope device array
+// that every GPU the library runs on holds until the process ends.  In host code
+// its name stands for the variable, not for device memory: the device address is
+// looked up once per device (hipGetSymbolAddress at the first efpi_init with that
+// device current) and only that address goes to kernels and fills.
+static_assert(EFPI_STATIC_SCRATCH_BYTES % 256 == 0, "scratch size in 256-byte units");
+static __device__ __align__(256) long long scratch[EFPI_STATIC_SCRATCH_BYTES / sizeof(long long)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+efpi_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(EFPI_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  if (dev < 0 || dev >= kMaxDevices) return fail(EFPI_EHIP, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(EFPI_EHIP, std::string("static scratch address: ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return EFPI_OK;
+}
+
+}  // namespace
+
 struct efpi_ctx {
   efpi_config cfg{};
   std::vector<efpi_replica> reps;
   hipStream_t stream = nullptr;
   uint8_t* ws = nullptr;
   size_t ws_bytes = 0;
+  void* scratch = nullptr;  // device address of the static scratch on this device
   int R = 0;
   int tile = kDefaultTile;
   int grid_blocks = 0;
@@ -582,7 +625,11 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
     return fail(EFPI_EINVAL, "workspace must be 256-byte aligned");
   const size_t need = layout(cfg, nullptr, nullptr);
   if (bytes < need) return fail(EFPI_ENOMEM, "workspace smaller than efpi_workspace_size");
+  void* scratch_ptr = nullptr;
+  st = scratch_of_current_device(&scratch_ptr);
+  if (st != EFPI_OK) return st;
   efpi_ctx* c = new efpi_ctx();
+  c->scratch = scratch_ptr;
   c->cfg = *cfg;
   c->R = (int)cfg->n_replicas;
   c->reps.assign(cfg->replicas, cfg->replicas + c->R);
@@ -990,6 +1037,21 @@ efpi_status efpi_phase_restrict(efpi_ctx* ctx, int32_t replica, const efpi_phase
                         stored_field ? 1 : 0, d.h, static_cast<long long*>(d_work), d_out,
                         ctx->stream);
   return hip_check("phase_restrict");
+}
+
+efpi_status efpi_phase_restrict_static(efpi_ctx* ctx, int32_t replica, const efpi_phase* ph,
+                                       double tau, int32_t stored_field, double* d_out) {
+  size_t need = 0;
+  const efpi_status st = efpi_phase_work_size(ctx, replica, ph, &need);
+  if (st != EFPI_OK) return st;
+  if (need > EFPI_STATIC_SCRATCH_BYTES)
+    return fail(EFPI_EINVAL, "histogram of " + std::to_string(need) +
+                                 " bytes exceeds the static scratch (" +
+                                 std::to_string(EFPI_STATIC_SCRATCH_BYTES) + " bytes)");
+  if (!ctx->scratch) return fail(EFPI_ESTATE, "no static scratch on this context's device");
+  // the same checks and kernels as with a caller's work buffer; the histogram
+  // fill at its start clears what the previous call left in the array
+  return efpi_phase_restrict(ctx, replica, ph, tau, stored_field, ctx->scratch, d_out);
 }
 
 namespace {

@@ -128,6 +128,7 @@ def _load():
         "efpi_coiflet_taps": [I32, ctypes.POINTER(ctypes.c_double)],
         "efpi_phase_work_size": [P, I32, ctypes.POINTER(Phase), ctypes.POINTER(ctypes.c_size_t)],
         "efpi_phase_restrict": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, I32, P, P],
+        "efpi_phase_restrict_static": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, I32, P],
         "efpi_phase_lift_work_size": [P, I32, ctypes.POINTER(Phase),
                                       ctypes.POINTER(ctypes.c_size_t)],
         "efpi_phase_lift": [P, I32, ctypes.POINTER(Phase), P, U32, P],
@@ -174,7 +175,7 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
             "efpi_restrict_state", "efpi_coiflet_taps", "efpi_phase_work_size",
-            "efpi_phase_restrict",
+            "efpi_phase_restrict", "efpi_phase_restrict_static",
             "efpi_phase_lift_work_size", "efpi_phase_lift", "efpi_phase_project",
             "efpi_store_field",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_timing_read_electrons",
@@ -425,6 +426,12 @@ def efpi_phase_restrict(ctx, replica, ph: Phase, tau, work, out, stored_field=Fa
     _check(LIB.efpi_phase_restrict(ctx, replica, ctypes.byref(ph), float(tau),
                                    1 if stored_field else 0, ctypes.c_void_p(work.data_ptr()),
                                    _dev(out, torch.float64)))
+
+
+def efpi_phase_restrict_static(ctx, replica, ph: Phase, tau, out, stored_field=False):
+    _check(LIB.efpi_phase_restrict_static(ctx, replica, ctypes.byref(ph), float(tau),
+                                          1 if stored_field else 0,
+                                          _dev(out, torch.float64)))
 
 
 def efpi_phase_lift_work_size(ctx, replica, ph: Phase) -> int:
