@@ -64,8 +64,9 @@ typedef enum {
 #define EFPI_DEV_NAN 2u      /* non-finite potential or coarse value             */
 #define EFPI_DEV_OVERFLOW 4u /* lift wanted more particles than capacity         */
 #define EFPI_DEV_NEGMASS 8u  /* projected block mass below zero (clipped at lift) */
-#define EFPI_DEV_WEIGHT 16u  /* an ion weight |w| >= 32: the exact per-lane charge
-                                sums of the particle pass need |w| < 32           */
+#define EFPI_DEV_WEIGHT 16u  /* an ion weight |w| (or snapshot momentum |w V|)
+                                >= 16: the exact per-lane charge sums of the
+                                particle pass need values below 16               */
 
 /* Boundary conditions and closures. */
 #define EFPI_BC_PERIODIC 0

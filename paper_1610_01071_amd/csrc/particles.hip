@@ -20,7 +20,9 @@
 // cross-lane merge runs per ion.  Every share is first put in fixed point (unit
 // 2^-40: the charge and the snapshot mass split as rint(theta q), q - rint(theta
 // q); the momentum likewise) and held as an integer-valued binary64, so every
-// bin sum is exact and independent of order; lanes l and l + 32 share a bin.
+// bin sum is exact and independent of order; lanes l, l + 16, l + 32 and l + 48
+// share a bin.  The particle streams are read and written with nontemporal
+// accesses (each ion is touched once per pass).
 // At the end of the wave's range the bins are summed across lanes and added to
 // global memory with 64-bit integer atomics, so the grid charge and the
 // snapshots do not depend on scheduling.  Ions whose target lies outside the
@@ -67,10 +69,18 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kGroup = 4;                      // consecutive ions per vector access
-constexpr int kPer = 2 * kGroup;               // ions per lane per batch
+constexpr int kHalves = 2;                     // vector groups per lane per batch
+constexpr int kPer = kHalves * kGroup;         // ions per lane per batch
 constexpr int kBatch = kPer * kWave;           // ions per wave per batch
 constexpr int kQBins = 16;                     // node bins of a wave's charge window
-constexpr int kQSlots = 32;                    // lanes l and l + 32 share a slot
+// LDS slots per bin (lanes equal modulo kQSlots share one).  With 16 slots a
+// workgroup's windows take 26 KB of LDS, and the VGPR budget, not the LDS, sets
+// the occupancy (4 waves per SIMD against 3 with 32 slots: 607 against 666 us
+// per burst step of 148M ions).
+#ifndef EFPI_PASS_SLOTS
+#define EFPI_PASS_SLOTS 16
+#endif
+constexpr int kQSlots = EFPI_PASS_SLOTS;
 constexpr int kQBelow = 7;                     // window starts below the reference cell
 #ifndef EFPI_PASS_RBINS
 #define EFPI_PASS_RBINS 16
@@ -80,8 +90,9 @@ constexpr int kRBelow = 7;
 constexpr int kENodes = 64;                    // field window: cells (64 + 1 nodes)
 constexpr int kEBelow = 32;
 // Weights (and momenta w V) above this bound could carry a binary64 bin past 2^53
-// (at most 16384 / 4 / 32 = 128 ions share a slot at the largest tile): flagged.
-constexpr float kWeightBound = 32.f;
+// (at most 16384 / 4 / kQSlots ions share a slot at the largest tile, each below
+// kQSlots 2^40): flagged.
+constexpr float kWeightBound = (float)kQSlots;
 
 struct WaveLds {
   float2 e[kENodes + 2];          // (E^p, E_n) at the window's nodes (one spare entry)
@@ -115,16 +126,25 @@ __device__ __forceinline__ int find_replica(const int64_t* prefix, int n, int64_
 }
 
 // 8- and 16-byte accesses at a byte offset from a uniform base (native vector
-// types, so that the global address space carries through the copy)
+// types, so that the global address space carries through the copy).  Every ion
+// is read and written once per pass, so the particle streams are marked
+// nontemporal (EFPI_PASS_NT bit 0: loads, bit 1: stores).
+#ifndef EFPI_PASS_NT
+#define EFPI_PASS_NT 3
+#endif
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ T ldv(const EFPI_GLOBAL void* base, unsigned byte_off) {
-  return *(const EFPI_GLOBAL T*)((const EFPI_GLOBAL char*)base + byte_off);
+  const EFPI_GLOBAL T* a = (const EFPI_GLOBAL T*)((const EFPI_GLOBAL char*)base + byte_off);
+  if constexpr ((EFPI_PASS_NT & 1) != 0) return __builtin_nontemporal_load(a);
+  else return *a;
 }
 template <class T>
 __device__ __forceinline__ void stv(EFPI_GLOBAL void* base, unsigned byte_off, T v) {
-  *(EFPI_GLOBAL T*)((EFPI_GLOBAL char*)base + byte_off) = v;
+  EFPI_GLOBAL T* a = (EFPI_GLOBAL T*)((EFPI_GLOBAL char*)base + byte_off);
+  if constexpr ((EFPI_PASS_NT & 2) != 0) __builtin_nontemporal_store(v, a);
+  else *a = v;
 }
 
 // The ions of one wave: `cnt` slots from `t0` of replica R.  MODE as in k_particles.
@@ -209,27 +229,45 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
   double* const rbin0 = &L.r[0][0][lane & (kQSlots - 1)];
   double* const rbin1 = &L.r[1][0][lane & (kQSlots - 1)];
 
+  // one batch's raw vectors: kHalves x (4 cells, 4 offsets, 4 velocities, 4 weights)
+  struct Raw {
+    u32x2 c[kHalves];
+    f32x4 f[kHalves], v[kHalves], w[kHalves];
+  };
+  // a group that starts inside the range is read whole: slots past the range lie
+  // inside the store's allocation (rounded up to 64 slots) and are treated as
+  // absorbed and written back unchanged
+  auto load = [&](unsigned b0, Raw& x) {
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      const unsigned g = b0 + (unsigned)h * (kGroup * kWave) + (unsigned)lane * kGroup;
+      x.c[h] = u32x2{0xFFFFFFFFu, 0xFFFFFFFFu};
+      x.f[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+      x.v[h] = x.f[h];
+      x.w[h] = x.f[h];
+      if (g < cnt) {
+        x.c[h] = ldv<u32x2>(cellp, g * 2u);
+        x.f[h] = ldv<f32x4>(fracp, g * 4u);
+        x.v[h] = ldv<f32x4>(velp, g * 4u);
+        x.w[h] = ldv<f32x4>(wp, g * 4u);
+      }
+    }
+  };
+  Raw cur;
+  load(0u, cur);
   for (unsigned b0 = 0; b0 < cnt; b0 += kBatch) {
+    const bool more = b0 + kBatch < cnt;  // uniform over the wave
     int cl[kPer];
     float fr[kPer], vv[kPer], ww[kPer];
-    unsigned gi[2];
-    bool gvalid[2];
+    unsigned gi[kHalves];
+    bool gvalid[kHalves];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < kHalves; ++h) {
       const unsigned g = b0 + (unsigned)h * (kGroup * kWave) + (unsigned)lane * kGroup;
       gi[h] = g;
       gvalid[h] = g < cnt;
-      u32x2 c2 = {0xFFFFFFFFu, 0xFFFFFFFFu};
-      f32x4 f4 = {0.f, 0.f, 0.f, 0.f}, v4 = f4, w4 = f4;
-      // a group that starts inside the range is read whole: slots past the range
-      // lie inside the store's allocation (rounded up to 64 slots) and are
-      // treated as absorbed and written back unchanged
-      if (gvalid[h]) {
-        c2 = ldv<u32x2>(cellp, g * 2u);
-        f4 = ldv<f32x4>(fracp, g * 4u);
-        v4 = ldv<f32x4>(velp, g * 4u);
-        w4 = ldv<f32x4>(wp, g * 4u);
-      }
+      u32x2 c2 = cur.c[h];
+      const f32x4 f4 = cur.f[h], v4 = cur.v[h], w4 = cur.w[h];
       // slots of a group past the end of the range count as absorbed
       if (__builtin_expect(g + kGroup > cnt, 0)) {
         const unsigned left = cnt - g;  // 1 .. 3 when the group is valid
@@ -386,7 +424,7 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
       }
       if (push) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kHalves; ++h) {
           if (gvalid[h]) {
             const int b = h * kGroup;
             const u32x2 c2 = {
@@ -401,18 +439,20 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
         }
       }
     }
+    if (more) load(b0 + kBatch, cur);
   }
 
   wave_lds_sync();
   if (deposit) {
-    // bin d's total: lane l sums 8 of the 32 slots of bin l & 15 (rotated by d so
+    // bin d's total: lane l sums kQSlots / 4 of the slots of bin l & 15 (rotated by d so
     // that the reads of one pass fall in different banks), then the four partial
     // sums of every bin are added across lanes; the sums are exact
+    constexpr int per = kQSlots * kQBins / kWave;  // slots summed per lane
     const int d = lane & (kQBins - 1);
-    const int g = lane >> 4;
+    const int g = lane / kQBins;
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s += L.q[d][g * 8 + ((i + d) & 7)];
+    for (int i = 0; i < per; ++i) s += L.q[d][g * per + ((i + d) & (per - 1))];
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
     if (g == 0 && s != 0.0) {

@@ -338,6 +338,31 @@ def test_newton_status_flag():
     assert bits & E.DEV_NEWTON
 
 
+@pytest.mark.parametrize("w_big,wv_big,flag", [(15.9, 15.9, False), (16.0, 1.0, True),
+                                               (40.0, 1.0, True), (1.0, 16.0, True)])
+def test_weight_bound_flag(w_big, wv_big, flag):
+    """The particle pass keeps its per-lane bin sums exact for ion weights and
+    snapshot momenta |w V| below 16 (integer-valued binary64 below 2^53); one ion
+    at or above it sets EFPI_DEV_WEIGHT, in the deposit (w) or the restriction (w V)."""
+    E = lib()
+    spec = E.ReplicaSpec(64, 64.0, ppc=4, haar_levels=2)
+    ctx = make_ctx([spec])
+    rng = np.random.default_rng(3)
+    n = 256
+    cell = np.sort(rng.integers(0, 64, n)).astype(np.int16)
+    frac = rng.random(n).astype(np.float32)
+    v = rng.normal(0.0, 0.1, n).astype(np.float32)
+    w = np.full(n, 0.25, np.float32)
+    w[17] = w_big
+    w[200], v[200] = 1.0, wv_big   # fresh state: the snapshot velocity is v
+    set_particles(ctx, 0, cell, frac, v, w)
+    E.efpi_deposit(ctx.ctx)
+    c = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c)
+    bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    assert bool(bits & E.DEV_WEIGHT) == flag
+
+
 def test_restrict_state_matches_oracle():
     E = lib()
     spec = E.ReplicaSpec(512, 512.0, ppc=64, haar_levels=4)
