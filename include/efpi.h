@@ -299,7 +299,11 @@ efpi_status efpi_project2(efpi_ctx* ctx, const double* d_snap, const double* d_s
 
 /* One whole macro step for every replica: lift(d_coarse_in) -> restricting burst
  * of burst_steps -> restrict -> project -> d_coarse_out.  d_coarse_in and
- * d_coarse_out may alias. */
+ * d_coarse_out may alias.  The Newton solve after the lift starts from each
+ * replica's current potential (newton_iters_start iterations, see
+ * efpi_set_potential), so the result depends on that potential at the level of
+ * the remaining Newton residual: equal inputs and equal potentials give equal
+ * bits. */
 efpi_status efpi_macro_step(efpi_ctx* ctx, const double* d_coarse_in, double* d_coarse_out,
                             const uint32_t* h_shifts);
 

@@ -9,13 +9,38 @@ namespace {
 constexpr int kLiftThreads = 1024;
 constexpr int kProfThreads = 1024;
 
-// Inverse standard normal CDF of b in (0, 1), from the inverse complementary
-// error function of the smaller tail (FP32: the velocity is stored in FP32).
-// For b = (u + 1/2) 2^-32 with integer u, 2b and 2(1 - b) are exact in binary64
-// and representable in FP32, so neither tail loses precision.
+// Inverse standard normal CDF of b in (0, 1), in FP32 (the velocity is stored in
+// FP32).  With p = min(b, 1 - b), x = 1 - 2p and w = -log(4 p (1 - p)),
+// Phi^{-1}(b) = -/+ sqrt(2) x r(w) with r = erfinv(x) / x, a smooth function of
+// w (the change of variable of Giles's erfinv approximation): a degree-9
+// polynomial in w - 2.5 for w < 5 and in sqrt(w) - 3 above, with coefficients
+// fitted by least squares (fit_inverse_normal.py).  For b = (u + 1/2) 2^-32,
+// p and 4p(1 - p) are formed in binary64 from the exact b, so neither tail
+// loses precision; the result is within 1.3e-6 (3.6e-7 relative) of the exact
+// value.  Both polynomials are evaluated: the Hammersley points of a wave are
+// scattered over (0, 1), and a branch per range would diverge.
 __device__ __forceinline__ float inv_normal(double b) {
-  const float r2 = 1.41421356237f;
-  return b < 0.5 ? -r2 * erfcinvf((float)(2.0 * b)) : r2 * erfcinvf((float)(2.0 * (1.0 - b)));
+  constexpr float kC[10] = {1.501409411e+00f, 2.466402948e-01f, -4.177389666e-03f,
+                            -1.252748421e-03f, 2.183469187e-04f, -4.959743364e-06f,
+                            -3.463356052e-06f, 4.654287409e-07f, 2.328584436e-08f,
+                            -8.739831081e-09f};
+  constexpr float kT[10] = {2.832977057e+00f, 1.001676440e+00f, 9.434493259e-03f,
+                            -7.654667366e-03f, 5.764349364e-03f, -3.560388228e-03f,
+                            1.293608337e-03f, -3.136037049e-05f, -1.542049431e-04f,
+                            3.841022772e-05f};
+  const double p = fmin(b, 1.0 - b);
+  const float w = -__logf((float)(4.0 * p * (1.0 - p)));
+  const float x = (float)(1.0 - 2.0 * p);
+  const float tc = w - 2.5f;
+  const float tt = __builtin_amdgcn_sqrtf(w) - 3.0f;
+  float rc = kC[9], rt = kT[9];
+#pragma unroll
+  for (int k = 8; k >= 0; --k) {
+    rc = fmaf(rc, tc, kC[k]);
+    rt = fmaf(rt, tt, kT[k]);
+  }
+  const float z = -1.41421356237f * x * (w < 5.0f ? rc : rt);
+  return b < 0.5 ? z : -z;
 }
 
 // ---------------------------------------------------------------- profile --
@@ -129,14 +154,8 @@ __global__ __launch_bounds__(kProfThreads) void k_lift_prep(const RepDev* __rest
 }
 
 // ---------------------------------------------------------- lift particles --
-struct Gen {
-  int cell;
-  float frac;
-  double v, w;
-};
-
 // Standard normal deviate of ion m of cell c from its Hammersley point (quiet
-// start), and the ion itself from the profile values at the cell's nodes.
+// start): b = ((bitrev32(c ppc + m) + shift) mod 2^32 + 1/2) 2^-32.
 __device__ __forceinline__ float normal_of(int c, int m, int ppc, uint32_t shift) {
   const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
   const uint32_t u = __brev(idx) + shift;
@@ -144,26 +163,14 @@ __device__ __forceinline__ float normal_of(int c, int m, int ppc, uint32_t shift
   return inv_normal(b);
 }
 
-__device__ __forceinline__ Gen generate(const RepDev& R, int c, double nl, double nr, double ul,
-                                       double ur, int m, float z) {
-  Gen g;
-  const int ppc = R.ppc;
-  g.cell = c;
-  g.frac = (float)(((double)m + 0.5) / (double)ppc);
-  const double th = (double)g.frac;
-  const double nx = (1.0 - th) * nl + th * nr;
-  const double ux = (1.0 - th) * ul + th * ur;
-  g.v = ux + R.vth * (double)z;
-  g.w = nx * R.h / (double)ppc;
-  return g;
-}
-
 __device__ __forceinline__ int right_node(const RepDev& R, int c) {
   return R.bc == 0 ? ((c + 1) & (R.n_cells - 1)) : c + 1;
 }
 
-// Occupied cells of a block staged in LDS (one round of loads per block).
+// Occupied cells of a block staged in LDS (one round of loads per block), and
+// the in-cell offsets (m + 1/2) / ppc as FP32 for ppc up to kFracTable.
 constexpr int kLiftCache = 256;
+constexpr int kFracTable = 4096;
 
 __device__ double block_sum(double x, double* s_red) {
   // fixed-order tree: waves by shuffles, then the wave totals in index order
@@ -189,7 +196,11 @@ __device__ __forceinline__ int find_rep(const int64_t* prefix, int n, int64_t it
 
 // One work item per (replica, coarse block): generate the block's ions, and
 // with coarse targets rescale weights to the block mass h 2^{l/2} max(c^n_B, 0)
-// and shift velocities to the block momentum h 2^{l/2} c^j_B.
+// and shift velocities to the block momentum h 2^{l/2} c^j_B.  Ion j of the block
+// is ion m = j mod ppc of its (j / ppc)-th occupied cell; a thread walks
+// j = t, t + 1024, ... and steps (j / ppc, m) without dividing.  Offsets are
+// (float)((m + 1/2) / ppc); n and u are linear in the cell from its two nodes;
+// v = u + vth z, w = n h / ppc.
 __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict__ reps,
                                                        const int64_t* __restrict__ block_prefix,
                                                        int n_reps, int64_t total, int only_rep,
@@ -198,6 +209,7 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
   __shared__ double s_red[kLiftThreads / 64];
   __shared__ int s_c[kLiftCache];
   __shared__ double s_nl[kLiftCache], s_nr[kLiftCache], s_ul[kLiftCache], s_ur[kLiftCache];
+  __shared__ float s_frac[kFracTable];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int r = only_rep >= 0 ? only_rep : find_rep(block_prefix, n_reps, item);
     const RepDev& R = reps[r];
@@ -214,6 +226,9 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const uint32_t shift = (uint32_t)gmem(R.aux)[1];  // Cranley-Patterson rotation of this lift
     const int ncell = rb1 - rb0;
     const bool cached = ncell <= kLiftCache;
+    const bool table = ppc <= kFracTable;
+    const double vth = R.vth;
+    const double hp = R.h / (double)ppc;
     if (cached) {
       for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
         const int c = cell_of_rank[rb0 + k];
@@ -224,47 +239,75 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
         s_ul[k] = prof_u[c];
         s_ur[k] = prof_u[cr];
       }
-      __syncthreads();
     }
-    // ion j of the block; a deviate z equal to kNone is computed and returned in z
-    constexpr float kNone = -3e38f;
-    auto gen = [&](int j, float& z) {
-      const int jr = j / ppc;
-      const int m = j - jr * ppc;
-      if (cached) {
-        const int c = s_c[jr];
-        if (z == kNone) z = normal_of(c, m, ppc, shift);
-        return generate(R, c, s_nl[jr], s_nr[jr], s_ul[jr], s_ur[jr], m, z);
+    if (table)
+      for (int m = threadIdx.x; m < ppc; m += blockDim.x)
+        s_frac[m] = (float)(((double)m + 0.5) / (double)ppc);
+    __syncthreads();
+    // the thread's first ion and its stride, as (cell rank, index in the cell)
+    const int q0 = (int)threadIdx.x / ppc, m0 = (int)threadIdx.x - q0 * ppc;
+    const int qs = kLiftThreads / ppc, ms = kLiftThreads - qs * ppc;
+    auto advance = [&](int& jr, int& m) {
+      jr += qs;
+      m += ms;
+      if (m >= ppc) {
+        m -= ppc;
+        ++jr;
       }
-      const int c = cell_of_rank[rb0 + jr];
-      const int cr = right_node(R, c);
-      if (z == kNone) z = normal_of(c, m, ppc, shift);
-      return generate(R, c, prof_n[c], prof_n[cr], prof_u[c], prof_u[cr], m, z);
+    };
+    // ion (jr, m): cell, offset, and (with its deviate z) FP64 velocity and weight
+    auto ion = [&](int jr, int m, float& z, bool need_z, int& c, float& fr, double& v,
+                   double& w) {
+      double nl, nr, ul, ur;
+      if (cached) {
+        c = s_c[jr];
+        nl = s_nl[jr];
+        nr = s_nr[jr];
+        ul = s_ul[jr];
+        ur = s_ur[jr];
+      } else {
+        c = cell_of_rank[rb0 + jr];
+        const int cr = right_node(R, c);
+        nl = prof_n[c];
+        nr = prof_n[cr];
+        ul = prof_u[c];
+        ur = prof_u[cr];
+      }
+      if (need_z) z = normal_of(c, m, ppc, shift);
+      fr = table ? s_frac[m] : (float)(((double)m + 0.5) / (double)ppc);
+      const double th = (double)fr;
+      v = ((1.0 - th) * ul + th * ur) + vth * (double)z;
+      w = ((1.0 - th) * nl + th * nr) * hp;
     };
     // the first kKeep ions of every thread keep their deviate in registers
     // between the correction sums and the stores
     constexpr int kKeep = 16;
     float keep[kKeep];
-#pragma unroll
-    for (int k = 0; k < kKeep; ++k) keep[k] = kNone;
     double ratio = 1.0, dv = 0.0;
     if (coarse != nullptr) {
       double sw = 0.0, swv = 0.0;
+      int jr = q0, m = m0;
 #pragma unroll
       for (int k = 0; k < kKeep; ++k) {
-        const int j = threadIdx.x + k * kLiftThreads;
-        if (j < count) {
-          const Gen g = gen(j, keep[k]);
-          sw += g.w;
-          swv += g.w * g.v;
+        if ((int)threadIdx.x + k * kLiftThreads < count) {
+          int c;
+          float fr;
+          double v, w;
+          ion(jr, m, keep[k], true, c, fr, v, w);
+          sw += w;
+          swv += w * v;
         }
+        advance(jr, m);
       }
 #pragma unroll 1
       for (int j = threadIdx.x + kKeep * kLiftThreads; j < count; j += kLiftThreads) {
-        float z = kNone;
-        const Gen g = gen(j, z);
-        sw += g.w;
-        swv += g.w * g.v;
+        int c;
+        float fr, z;
+        double v, w;
+        ion(jr, m, z, true, c, fr, v, w);
+        sw += w;
+        swv += w * v;
+        advance(jr, m);
       }
       sw = block_sum(sw, s_red);
       swv = block_sum(swv, s_red);
@@ -279,22 +322,36 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const auto frac = gmem(R.frac);
     const auto vel = gmem(R.v);
     const auto wgt = gmem(R.w);
-    auto put = [&](int j, const Gen& g) {
+    auto put = [&](int j, int c, float fr, double v, double w) {
       const int64_t s = slot0 + j;
-      cell[s] = (int16_t)g.cell;
-      frac[s] = g.frac;
-      vel[s] = (float)(g.v + dv);
-      wgt[s] = (float)(g.w * ratio);
+      cell[s] = (int16_t)c;
+      frac[s] = fr;
+      vel[s] = (float)(v + dv);
+      wgt[s] = (float)(w * ratio);
     };
+    {
+      int jr = q0, m = m0;
 #pragma unroll
-    for (int k = 0; k < kKeep; ++k) {
-      const int j = threadIdx.x + k * kLiftThreads;
-      if (j < count) put(j, gen(j, keep[k]));
-    }
+      for (int k = 0; k < kKeep; ++k) {
+        const int j = threadIdx.x + k * kLiftThreads;
+        if (j < count) {
+          int c;
+          float fr;
+          double v, w;
+          ion(jr, m, keep[k], coarse == nullptr, c, fr, v, w);
+          put(j, c, fr, v, w);
+        }
+        advance(jr, m);
+      }
 #pragma unroll 1
-    for (int j = threadIdx.x + kKeep * kLiftThreads; j < count; j += kLiftThreads) {
-      float z = kNone;
-      put(j, gen(j, z));
+      for (int j = threadIdx.x + kKeep * kLiftThreads; j < count; j += kLiftThreads) {
+        int c;
+        float fr, z;
+        double v, w;
+        ion(jr, m, z, true, c, fr, v, w);
+        put(j, c, fr, v, w);
+        advance(jr, m);
+      }
     }
     __syncthreads();
   }

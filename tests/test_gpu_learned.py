@@ -91,8 +91,13 @@ def test_learned_run_matches_plain_efpi_and_is_faster(setup):
 
 
 def test_learned_run_is_deterministic(setup):
-    L, ctx, tr, norm, c0 = setup["L"], setup["ctx"], setup["tr"], setup["norm"], setup["c0"]
+    E, L, ctx, tr, norm, c0 = (setup[k] for k in ("E", "L", "ctx", "tr", "norm", "c0"))
+    # a macro step's first Newton solve starts from the context's potential (warm
+    # start): both runs start from the same one
+    phi0 = ctx.grid(0)[1].clone()
+    E.efpi_set_potential(ctx.ctx, 0, phi0)
     r1 = L.run_learned(ctx, tr, norm, c0, 12, seed=5)
+    E.efpi_set_potential(ctx.ctx, 0, phi0)
     r2 = L.run_learned(ctx, tr, norm, c0, 12, seed=5)
     assert torch.equal(r1.states, r2.states)
 
