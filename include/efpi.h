@@ -514,8 +514,12 @@ efpi_status efpi_nn_step(const double* d_c_n, const float* d_y, int32_t batch, i
 
 /* One learned projective step in one call: features of the three consecutive
  * states d_states[3][2][n_c] (c_{n-2}, c_{n-1}, c_n; FP64), forward pass, and
- * d_c_next[2][n_c] = c_n + delta * y.  d_ws holds at least
- * efpi_nn_workspace_size(1, n_c) bytes; d_c_next must not overlap d_states. */
+ * d_c_next[2][n_c] = c_n + delta * y, except outside the plasma's support: a
+ * block whose density in c_n is exactly zero at itself and at every block within
+ * two blocks (wrapping when periodic, only blocks inside the walls otherwise)
+ * keeps c_n (both moments), as a plain EFPI step leaves empty blocks empty.
+ * d_ws holds at least efpi_nn_workspace_size(1, n_c) bytes; d_c_next must not
+ * overlap d_states. */
 efpi_status efpi_nn_predict_step(const float* d_params, const void* d_pack,
                                  const double* d_states, int32_t n_c, int32_t periodic,
                                  const efpi_nn_norm* h_norm, double* d_c_next, void* d_ws,

@@ -15,7 +15,14 @@ Parameters, in one flat vector: for each layer W[c_out][c_in][3] then b[c_out]
 Input features of sample (c_{n-2}, c_{n-1}, c_n), for moment m in (density,
 momentum):  x[m] = (c_n - mu_m) / sigma_m,  x[2 + m] = (c_n - c_{n-1}) / delta_m,
 x[4 + m] = (c_{n-1} - c_{n-2}) / delta_m.  Output y[m] approximates
-(c_{n+1} - c_n) / delta_m, so the learned step is c_{n+1} = c_n + delta * y.
+(c_{n+1} - c_n) / delta_m, so the learned step is c_{n+1} = c_n + delta * y,
+except outside the plasma's support: a coarse block whose density in c_n is
+exactly zero at itself and at every block within SUPPORT_RADIUS (wrapping on
+periodic domains, only the existing blocks between walls) keeps c_n (both
+moments).  Plasma moves a bounded distance per macro step, and a plain EFPI
+step leaves such blocks exactly empty (no ions deposit there); the network's
+outputs are never exactly zero, so without the rule a learned step would seed
+the whole vacuum with a tiny density that the next lift fills with ions.
 
 The GPU feeds the matrix cores bfloat16 operands with FP32 accumulation.  With
 ``bf16=True`` this oracle rounds the same operands (weights, layer inputs and
@@ -27,6 +34,7 @@ from __future__ import annotations
 import numpy as np
 
 C_IN = 6
+SUPPORT_RADIUS = 2
 HIDDEN = 64
 C_OUT = 2
 WIDTHS = (C_IN, HIDDEN, HIDDEN, HIDDEN, C_OUT)
@@ -209,9 +217,29 @@ def targets(c_n, c_np1, norm):
     return (np.asarray(c_np1, dtype=np.float64) - np.asarray(c_n, dtype=np.float64)) / delta
 
 
+def outside_support(c_n, periodic: bool):
+    """[batch][n_c] mask of the blocks whose density is zero in c_n at every block
+    within SUPPORT_RADIUS of them (the learned step leaves those unchanged)."""
+    dens = np.asarray(c_n, dtype=np.float64)[:, 0, :]
+    nc = dens.shape[-1]
+    out = np.ones(dens.shape, dtype=bool)
+    for k in range(nc):
+        for d in range(-SUPPORT_RADIUS, SUPPORT_RADIUS + 1):
+            j = k + d
+            if periodic:
+                j %= nc
+            elif not 0 <= j < nc:
+                continue
+            out[:, k] &= dens[:, j] == 0.0
+    return out
+
+
 def learned_step(theta, c_nm2, c_nm1, c_n, norm, periodic: bool, bf16: bool = False):
-    """c_{n+1} = c_n + delta * y(features): the learned projective step."""
+    """c_{n+1} = c_n + delta * y(features) inside the support, c_n outside it: the
+    learned projective step."""
     x = features(c_nm2, c_nm1, c_n, norm)
     y, _ = forward(theta, x, periodic, bf16)
     delta = np.asarray(norm[2], dtype=np.float64).reshape(1, 2, 1)
-    return np.asarray(c_n, dtype=np.float64) + delta * y
+    c_n = np.asarray(c_n, dtype=np.float64)
+    keep = outside_support(c_n, periodic)[:, None, :]
+    return np.where(keep, c_n, c_n + delta * y)

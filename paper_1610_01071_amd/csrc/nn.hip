@@ -29,6 +29,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int kTile = 64;  // positions per workgroup
+constexpr int kSupportRadius = 2;  // blocks: reach of the learned step's support rule
 
 // f32 -> bf16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t to_bf16(float x) {
@@ -553,6 +554,26 @@ void launch_step(const double* cn, const float* y, int batch, int nc, const efpi
                      nc, nm, out);
 }
 
+// One learned step of a single window with the support rule: a coarse block whose
+// density is exactly zero in c_n at every block within kSupportRadius (periodic
+// wrap, or the blocks inside the walls) keeps its values (no increment); else
+// c_next = c_n + delta * y.
+__global__ void k_step_support(const double* __restrict__ cn, const float* __restrict__ y, int nc,
+                               int periodic, efpi_nn_norm nm, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * nc) return;
+  const int m = i >= nc ? 1 : 0;
+  const int k = i - m * nc;
+  bool empty = true;
+  for (int d = -kSupportRadius; d <= kSupportRadius; ++d) {
+    int j = k + d;
+    if (periodic) j = ((j % nc) + nc) % nc;
+    else if (j < 0 || j >= nc) continue;
+    empty = empty && cn[j] == 0.0;
+  }
+  out[i] = empty ? cn[i] : cn[i] + (double)nm.delta[m] * (double)y[i];
+}
+
 void launch_predict_step(const float* params, const uint16_t* pack, const double* states, int nc,
                          int periodic, const efpi_nn_norm& nm, double* out, float* ws,
                          hipStream_t stream) {
@@ -562,8 +583,8 @@ void launch_predict_step(const float* params, const uint16_t* pack, const double
                      3, nullptr, 1, nc, nm, 0.f, 0u, w.x, nullptr);
   launch_forward(params, pack, w.x, w.y, 1, nc, periodic, ws, stream);
   // states[2] is c_n of the single sample window
-  hipLaunchKernelGGL(k_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                     states + 2 * (size_t)2 * nc, w.y, n, nc, nm, out);
+  hipLaunchKernelGGL(k_step_support, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                     states + 2 * (size_t)2 * nc, w.y, nc, periodic, nm, out);
 }
 
 }  // namespace nn

@@ -11,9 +11,11 @@ orchestrates, on the GPU:
   with the library's forward, backward, loss and optimizer kernels;
 * ``run_learned``: macro steps that take the learned step, with a fine burst
   every ``judge_period`` steps that both advances the state and judges the
-  network: when the learned and burst coarse densities differ by more than
-  ``threshold`` (the error of eq. 4.2), the next ``judge_period`` steps are plain
-  EFPI.
+  network on both moments (the error of eq. 4.2 between the learned candidate
+  and the burst step, less plain EFPI's own one-step noise); these one-step
+  errors, summed over the learned steps they stand for, bound the run's
+  accumulated error, and once that sum passes its threshold for either moment
+  the rest of the run is plain EFPI.
 
 Python only chooses indices, loops and branches; all arithmetic runs in the
 library's kernels.  The one host computation is the normalisation of the
@@ -143,60 +145,90 @@ class Trainer:
 class LearnedRun:
     states: torch.Tensor      # [steps + 1][2 N_c]
     judged: int               # burst steps taken to judge the network
-    fallback: int             # plain steps taken after a failed judgement
+    fallback: int             # plain steps taken after the error bound was passed
     learned: int              # learned steps
-    eps: list                 # judge errors of the coarse density (eq. 4.2)
-    eps_momentum: list        # the same for the momentum coefficients (reported)
+    eps: list                 # one-step judge errors of the coarse density (eq. 4.2)
+    eps_momentum: list        # the same for the momentum coefficients
     wall_ms: float
+    acc: list = field(default_factory=list)           # accumulated density bound after each judgement
+    acc_momentum: list = field(default_factory=list)  # the same for the momentum
+    fell_back_at: int = -1    # macro step from which the run is plain (-1: never)
+    noise: tuple = (0.0, 0.0)  # one-step spread of two plain bursts (density, momentum)
 
 
 def run_learned(ctx: E.Context, trainer: Trainer, norm: E.NnNorm, c0: torch.Tensor, steps: int,
                 seed: int, judge_period: int = 4, threshold: float = 2e-3,
-                bootstrap: int = 2) -> LearnedRun:
+                threshold_momentum: float = None, bootstrap: int = 2) -> LearnedRun:
     """Learned-projection EFPI for `steps` macro steps from c0.
 
-    Steps 0..bootstrap-1 are plain EFPI (the network needs three states).
-    Afterwards every judge_period-th step is a fine burst (plain EFPI step with
-    the same lift rotation the plain run uses at that step); the others are
-    learned steps.  A judged step always continues from the burst result.
+    Steps 0..bootstrap-1 are plain EFPI (the network needs three states); step 0
+    is also taken a second time with another lift rotation, and the error of
+    eq. 4.2 between the two results, nu (per moment), is the one-step noise of
+    plain EFPI itself.  From step `bootstrap` on, every judge_period-th step
+    (the first one included) is a judgement: a fine burst (the plain EFPI step
+    with the lift rotation the plain run uses at that step), which the run
+    continues from, compared with the learned candidate from the same state.  The
+    one-step error e holds the burst's own noise as well as the network's error,
+    so the network's part is taken as b = sqrt(max(e^2 - nu^2 / 2, 0)) (the
+    candidate against one noisy burst, where two bursts differ by nu).  Each
+    judgement vouches for the judge_period - 1 learned steps after it: b times
+    their number is added to the accumulated-error bound of each moment before
+    they are taken (errors of successive steps add at most linearly).  When the
+    bound passes threshold (density) or threshold_momentum (momentum; default:
+    threshold), every later step is plain EFPI, so no learned step is taken on a
+    judgement that failed.  This is the paper's remark on reverting to the fine
+    solver when an error estimate fails (Sec. 3.1), applied to the learned steps.
     """
+    thr_m = threshold if threshold_momentum is None else threshold_momentum
     nc = trainer.n_c
     nc2 = c0.numel()
     dev = c0.device
     traj = torch.empty(steps + 1, nc2, dtype=torch.float64, device=dev)
     traj[0].copy_(c0)
     cand = torch.empty(nc2, dtype=torch.float64, device=dev)
-    eps_dev = torch.zeros(2, dtype=torch.float64, device=dev)
+    eps_dev = torch.zeros(4, dtype=torch.float64, device=dev)
     ws = trainer.workspace(1)
     judged = fallback = learned = 0
-    eps_log, eps_mom = [], []
-    plain_left = 0
+    eps_log, eps_mom, acc_log, accm_log = [], [], [], []
+    acc = acc_m = 0.0
+    plain_from = -1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # one-step noise of plain EFPI: step 0 with a second rotation
+    E.efpi_macro_step(ctx.ctx, traj[0], cand, [lift_shift(seed ^ 0x5BD1E995, 0)])
     for n in range(steps):
-        if n < bootstrap or plain_left > 0:
+        if n < bootstrap or plain_from >= 0:
             E.efpi_macro_step(ctx.ctx, traj[n], traj[n + 1], [lift_shift(seed, n)])
+            if n == 0:
+                E.efpi_rel_l2(cand[:nc], traj[1][:nc], eps_dev[2:3])
+                E.efpi_rel_l2(cand[nc:], traj[1][nc:], eps_dev[3:4])
             if n >= bootstrap:
-                plain_left -= 1
                 fallback += 1
             continue
         # learned step from states n-2, n-1, n
-        if (n - bootstrap) % judge_period == judge_period - 1:
+        if (n - bootstrap) % judge_period == 0:
             E.efpi_nn_predict_step(trainer.params, trainer.pack, traj[n - 2:n + 1], nc,
                                    trainer.periodic, norm, cand, ws)
             E.efpi_macro_step(ctx.ctx, traj[n], traj[n + 1], [lift_shift(seed, n)])
             E.efpi_rel_l2(cand[:nc], traj[n + 1][:nc], eps_dev[0:1])
             E.efpi_rel_l2(cand[nc:], traj[n + 1][nc:], eps_dev[1:2])
-            e, e_mom = (float(a) for a in eps_dev.cpu())
+            e, e_mom, nu, nu_m = (float(a) for a in eps_dev.cpu())
+            judged += 1
+            span = max(judge_period - 1, 1)
+            acc += span * float(np.sqrt(max(e * e - 0.5 * nu * nu, 0.0)))
+            acc_m += span * float(np.sqrt(max(e_mom * e_mom - 0.5 * nu_m * nu_m, 0.0)))
             eps_log.append(e)
             eps_mom.append(e_mom)
-            judged += 1
-            if e > threshold:
-                plain_left = judge_period
+            acc_log.append(acc)
+            accm_log.append(acc_m)
+            if acc > threshold or acc_m > thr_m:
+                plain_from = n + 1
         else:
             E.efpi_nn_predict_step(trainer.params, trainer.pack, traj[n - 2:n + 1], nc,
                                    trainer.periodic, norm, traj[n + 1], ws)
             learned += 1
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
-    return LearnedRun(traj, judged, fallback, learned, eps_log, eps_mom, wall)
+    noise = tuple(float(a) for a in eps_dev[2:4].cpu())
+    return LearnedRun(traj, judged, fallback, learned, eps_log, eps_mom, wall, acc_log, accm_log,
+                      plain_from, noise)

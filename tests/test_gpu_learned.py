@@ -70,6 +70,23 @@ def test_training_generalises_to_held_out_run(setup):
     assert setup["trained"] < 0.05 * setup["untrained"]
 
 
+def check_fallback(run, thr, thr_m, jp=4, boot=2):
+    """The run is plain from the step after the first judgement whose accumulated
+    bound passes its threshold (judgement j is taken at step boot + jp j), and
+    never before."""
+    passed = [j for j, (d, m) in enumerate(zip(run.acc, run.acc_momentum))
+              if d > thr or m > thr_m]
+    if passed:
+        assert passed[0] == len(run.acc) - 1
+        assert run.fell_back_at == boot + jp * passed[0] + 1
+        assert run.fallback == STEPS - run.fell_back_at
+    else:
+        assert run.fell_back_at == -1 and run.fallback == 0
+    # the bounds only grow
+    assert all(b >= a for a, b in zip(run.acc, run.acc[1:]))
+    assert all(b >= a for a, b in zip(run.acc_momentum, run.acc_momentum[1:]))
+
+
 def test_learned_run_matches_plain_efpi_and_is_faster(setup):
     L, ctx, tr, norm, c0 = setup["L"], setup["ctx"], setup["tr"], setup["norm"], setup["c0"]
     L.plain_run(ctx, c0, 4, seed=1)  # warm-up
@@ -79,15 +96,21 @@ def test_learned_run_matches_plain_efpi_and_is_faster(setup):
     ref = L.plain_run(ctx, c0, STEPS, seed=77)
     torch.cuda.synchronize()
     wall_plain = (time.perf_counter() - t0) * 1e3
-    run = L.run_learned(ctx, tr, norm, c0, STEPS, seed=77, judge_period=4, threshold=2e-3)
     other = L.plain_run(ctx, c0, STEPS, seed=78)
-    a = run.states[-1].cpu().numpy().reshape(2, -1)
     b = ref[-1].cpu().numpy().reshape(2, -1)
     o = other[-1].cpu().numpy().reshape(2, -1)
-    assert eps(a[0], b[0]) <= 2e-3
-    assert eps(a[1], b[1]) <= 3.0 * max(eps(o[1], b[1]), 1e-3)
-    assert run.learned >= STEPS // 2
-    assert run.wall_ms < wall_plain
+    # judged on both moments (bound 2e-3 each), then on the density alone
+    for thr_m in (2e-3, float("inf")):
+        run = L.run_learned(ctx, tr, norm, c0, STEPS, seed=77, judge_period=4, threshold=2e-3,
+                            threshold_momentum=thr_m)
+        check_fallback(run, 2e-3, thr_m)
+        a = run.states[-1].cpu().numpy().reshape(2, -1)
+        assert eps(a[0], b[0]) <= 2e-3
+        assert eps(a[1], b[1]) <= 3.0 * max(eps(o[1], b[1]), 1e-3)
+        if thr_m == float("inf"):
+            # the density bound alone lets the network take steps: faster than plain
+            assert run.learned >= 3
+            assert run.wall_ms < wall_plain
 
 
 def test_learned_run_is_deterministic(setup):
@@ -104,7 +127,33 @@ def test_learned_run_is_deterministic(setup):
 
 def test_judge_falls_back_when_threshold_is_tight(setup):
     L, ctx, tr, norm, c0 = setup["L"], setup["ctx"], setup["tr"], setup["norm"], setup["c0"]
-    run = L.run_learned(ctx, tr, norm, c0, 20, seed=9, judge_period=4, threshold=0.0)
-    assert run.judged >= 1 and run.fallback >= 4
-    # every judged step disagrees with the burst by more than zero
-    assert all(e > 0.0 for e in run.eps)
+    run = L.run_learned(ctx, tr, norm, c0, 20, seed=9, judge_period=4, threshold=-1.0)
+    # the first judgement (step 2) passes a negative bound: plain from step 3 on,
+    # and no learned step is taken
+    assert run.judged == 1 and run.fell_back_at == 3 and run.fallback == 17
+    assert run.learned == 0 and run.eps[0] > 0.0 and run.acc[0] >= 0.0
+    # the noise of plain EFPI itself: two rotations of step 0 differ
+    assert run.noise[0] > 0.0 and run.noise[1] > 0.0
+
+
+def test_momentum_only_disagreement_forces_fallback(setup):
+    """A network whose momentum output is biased by two increment scales: its
+    density steps stay within the bound while its momentum steps do not, and the
+    judge falls back on the momentum alone."""
+    import copy
+    E, L, ctx, tr, norm, c0 = (setup[k] for k in ("E", "L", "ctx", "tr", "norm", "c0"))
+    bad = copy.copy(tr)
+    bad.params = tr.params.clone()
+    bad.params[-1] += 2.0          # the momentum channel's output bias (last parameter)
+    bad.pack = torch.zeros_like(tr.pack)
+    E.efpi_nn_pack(bad.params, bad.pack)
+    phi0 = ctx.grid(0)[1].clone()
+    E.efpi_set_potential(ctx.ctx, 0, phi0)
+    run = L.run_learned(ctx, bad, norm, c0, 6, seed=5, judge_period=2, threshold=2e-3)
+    assert run.judged == 1 and run.fell_back_at == 3 and run.fallback == 3 and run.learned == 0
+    assert run.acc[0] <= 2e-3 < run.acc_momentum[0]
+    # judged on the density alone, the same run keeps its learned steps
+    E.efpi_set_potential(ctx.ctx, 0, phi0)
+    dens_only = L.run_learned(ctx, bad, norm, c0, 6, seed=5, judge_period=2, threshold=2e-3,
+                              threshold_momentum=float("inf"))
+    assert dens_only.fell_back_at == -1 and dens_only.judged == 2 and dens_only.learned == 2

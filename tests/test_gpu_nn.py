@@ -203,6 +203,34 @@ def test_predict_step_matches_oracle(periodic):
     assert rel(got - states[2], ref - states[2]) < 3e-4
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_predict_step_support_rule(periodic):
+    """A plasma on blocks 30..59 of 96 with exact vacuum elsewhere: blocks more than
+    two blocks from any density keep c_n bit for bit (both moments), the others
+    match the oracle's increments."""
+    E = lib()
+    g = np.random.default_rng(22)
+    n_c = 96
+    theta = theta_f32(22)
+    states = np.zeros((3, 2, n_c))
+    states[:, 0, 30:60] = 1.0 + 0.1 * g.standard_normal((3, 30))
+    states[:, 1, 30:60] = 0.05 * g.standard_normal((3, 30))
+    norm_t = ([0.3, 0.0], [0.45, 0.03], [2e-3, 3e-3])
+    norm32 = tuple(np.array(a, np.float32).astype(np.float64) for a in norm_t)
+    net = Net(theta, 1, n_c)
+    out = torch.empty(2 * n_c, dtype=torch.float64, device="cuda")
+    E.efpi_nn_predict_step(net.params, net.pack, to_dev(states, torch.float64), n_c, periodic,
+                           E.nn_norm(*norm_t), out, net.ws)
+    got = out.cpu().numpy().reshape(2, n_c)
+    outside = onn.outside_support(states[2:3], periodic)[0]
+    assert outside.sum() == n_c - 34
+    assert np.array_equal(got[:, outside], states[2][:, outside])
+    ref = onn.learned_step(theta, states[0:1], states[1:2], states[2:3], norm32, periodic,
+                           bf16=True)[0]
+    assert np.array_equal(ref[:, outside], states[2][:, outside])
+    assert rel(got - states[2], ref - states[2]) < 3e-4
+
+
 def test_training_noise_statistics():
     """Input-state noise of the training features: zero mean, the requested
     scale (noise * delta), independent of the exact features, deterministic."""

@@ -115,6 +115,32 @@ def test_zero_last_layer_gives_zero_increment():
     assert np.array_equal(out, c[2])
 
 
+def test_support_rule_hand_worked():
+    """Blocks whose density is zero within two blocks keep c_n; the mask by hand
+    for a plasma on blocks 5..6 of 12, with walls and periodic."""
+    c = np.zeros((1, 2, 12))
+    c[0, 0, 5:7] = 1.0
+    c[0, 1, :] = 0.25           # momentum does not enter the mask
+    walls = nn.outside_support(c, periodic=False)[0]
+    assert walls.tolist() == [True, True, True, False, False, False, False, False, False,
+                              True, True, True]
+    c2 = np.zeros((1, 2, 12))
+    c2[0, 0, 0] = 1.0            # plasma at block 0: the wrap reaches 10 and 11
+    per = nn.outside_support(c2, periodic=True)[0]
+    assert per.tolist() == [False, False, False, True, True, True, True, True, True, True,
+                            False, False]
+    wal2 = nn.outside_support(c2, periodic=False)[0]
+    assert wal2.tolist() == [False, False, False] + [True] * 9
+    # the step: unchanged outside, c_n + delta y inside (nonzero last layer)
+    theta = nn.init_params(3)
+    g = np.random.default_rng(4)
+    prev = [c + 1e-3 * g.standard_normal(c.shape) * (c != 0) for _ in range(2)]
+    norm = ([0.5, 0.1], [0.4, 0.2], [1e-2, 2e-2])
+    out = nn.learned_step(theta, prev[0], prev[1], c, norm, False)
+    assert np.array_equal(out[0][:, walls], c[0][:, walls])
+    assert np.all(out[0][:, ~walls] != c[0][:, ~walls])
+
+
 def test_adam_first_step_closed_form():
     g = np.random.default_rng(14)
     theta = g.standard_normal(50)
