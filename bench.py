@@ -201,6 +201,8 @@ def main():
     import synth
 
     cpu = None if (args.no_cpu or args.headline_only) else cpu_baseline(synth)
+    if cpu is not None:
+        print(f"[bench] cpu_baseline done", file=sys.stderr, flush=True)
 
     import paper_1610_01071_amd.efpi as E
 
@@ -417,8 +419,15 @@ def cfg1_leg(args, np, torch, synth, E):
             "note": "launch-latency bound: 25,600 ions fill 7 workgroups"}
 
 
+def _progress(name, t0):
+    """One line on stderr per finished leg (the JSON line stays alone on stdout)."""
+    print(f"[bench] {name} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+
 def run_bench(args, np, torch, synth, E):
+    t0 = time.perf_counter()
     out = headline(args, np, torch, synth, E)
+    _progress("headline", t0)
     if args.headline_only:
         return out
     from paper_1610_01071_amd import autotune
@@ -437,7 +446,9 @@ def run_bench(args, np, torch, synth, E):
     if "efpi_speedup_vs_pic" in iaw:
         out["efpi_speedup_vs_pic"] = iaw.pop("efpi_speedup_vs_pic")
     out["iaw4096"] = iaw
+    _progress("iaw4096", t0)
     out["plain_pic_128"] = cfg1_leg(args, np, torch, synth, E)
+    _progress("plain_pic_128", t0)
     if not args.no_phase:
         out["phase_space"] = phase_leg(E, torch, np, synth, c0, args)
         out["phase_space_nv2048"] = phase_leg(E, torch, np, synth, c0, args, jf=11, jc=6)
@@ -445,16 +456,20 @@ def run_bench(args, np, torch, synth, E):
             out["phase_space_kinetic"] = phase_leg(E, torch, np, synth, c0, args, kinetic=True)
             out["phase_space_kinetic_nv2048"] = phase_leg(E, torch, np, synth, c0, args,
                                                           kinetic=True, jf=11, jc=6)
+        _progress("phase_space", t0)
     if not args.no_kinetic:
         out["kinetic"] = kinetic_leg(E, torch, np, synth, c0, args)
+        _progress("kinetic", t0)
     if not args.no_slab:
         out["slab"] = slab_leg(E, torch, np, synth, args)
+        _progress("slab", t0)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_leg(E, torch, np, synth, args)
         if not args.no_kinetic:
             out["learned_kinetic"] = learned_leg(E, torch, np, synth, args, kinetic=True)
         if not args.no_slab:
             out["learned_slab"] = learned_slab_leg(E, torch, np, synth, args)
+        _progress("learned", t0)
     return out
 
 
