@@ -6,20 +6,31 @@
 namespace efpi {
 namespace {
 
-constexpr int kLiftThreads = 1024;
+// Lift workgroups: 256 threads, each keeping the velocity and weight of its first
+// EFPI_LIFT_KEEP ions in registers between the correction sums and the stores.  A
+// work item is one coarse block (a few thousand ions), so several workgroups per CU
+// hide each other's dependent loads and barriers: on the 64-replica ensemble the
+// lift takes 0.65 ms against 1.0 ms with 1024-thread workgroups.
+#ifndef EFPI_LIFT_KEEP
+#define EFPI_LIFT_KEEP 8
+#endif
+#ifndef EFPI_LIFT_THREADS
+#define EFPI_LIFT_THREADS 256
+#endif
+constexpr int kLiftThreads = EFPI_LIFT_THREADS;
 constexpr int kProfThreads = 1024;
 
-// Inverse standard normal CDF of b in (0, 1), in FP32 (the velocity is stored in
-// FP32).  With p = min(b, 1 - b), x = 1 - 2p and w = -log(4 p (1 - p)),
-// Phi^{-1}(b) = -/+ sqrt(2) x r(w) with r = erfinv(x) / x, a smooth function of
-// w (the change of variable of Giles's erfinv approximation): a degree-9
-// polynomial in w - 2.5 for w < 5 and in sqrt(w) - 3 above, with coefficients
-// fitted by least squares (fit_inverse_normal.py).  For b = (u + 1/2) 2^-32,
-// p and 4p(1 - p) are formed in binary64 from the exact b, so neither tail
-// loses precision; the result is within 1.3e-6 (3.6e-7 relative) of the exact
-// value.  Both polynomials are evaluated: the Hammersley points of a wave are
-// scattered over (0, 1), and a branch per range would diverge.
-__device__ __forceinline__ float inv_normal(double b) {
+// Inverse standard normal CDF at the Hammersley coordinate b = (u + 1/2) 2^-32, in
+// FP32 (the velocity is stored in FP32).  With p = min(b, 1 - b), x = 1 - 2p and
+// w = -log(4 p (1 - p)), Phi^{-1}(b) = -/+ sqrt(2) x r(w) with r = erfinv(x) / x, a
+// smooth function of w (the change of variable of Giles's erfinv approximation): a
+// degree-9 polynomial in w - 2.5 for w < 5 and in sqrt(w) - 3 above, with
+// coefficients fitted by least squares (fit_inverse_normal.py).  p and x come from
+// the integers: p = (min(u, ~u) + 1/2) 2^-32 and x = |u - ~u| 2^-32, so neither tail
+// loses precision in FP32; the result is within 1.3e-6 (3.6e-7 relative) of the
+// exact value for every u.  Both polynomials are evaluated: the Hammersley points of
+// a wave are scattered over (0, 1), and a branch per range would diverge.
+__device__ __forceinline__ float inv_normal(uint32_t u) {
   constexpr float kC[10] = {1.501409411e+00f, 2.466402948e-01f, -4.177389666e-03f,
                             -1.252748421e-03f, 2.183469187e-04f, -4.959743364e-06f,
                             -3.463356052e-06f, 4.654287409e-07f, 2.328584436e-08f,
@@ -28,9 +39,14 @@ __device__ __forceinline__ float inv_normal(double b) {
                             -7.654667366e-03f, 5.764349364e-03f, -3.560388228e-03f,
                             1.293608337e-03f, -3.136037049e-05f, -1.542049431e-04f,
                             3.841022772e-05f};
-  const double p = fmin(b, 1.0 - b);
-  const float w = -__logf((float)(4.0 * p * (1.0 - p)));
-  const float x = (float)(1.0 - 2.0 * p);
+  constexpr float k2m32 = 2.3283064365386963e-10f;  // 2^-32
+  const uint32_t nu = ~u;
+  const bool lower = u < nu;                       // b < 1/2
+  const uint32_t lo = lower ? u : nu;
+  const float p = ((float)lo + 0.5f) * k2m32;
+  const float x = (float)(lower ? nu - u : u - nu) * k2m32;
+  // 4 p (1 - p) >= 2^-31: log2 of the hardware is exact enough there
+  const float w = -0.693147180560f * __builtin_amdgcn_logf(4.0f * p * (1.0f - p));
   const float tc = w - 2.5f;
   const float tt = __builtin_amdgcn_sqrtf(w) - 3.0f;
   float rc = kC[9], rt = kT[9];
@@ -40,7 +56,7 @@ __device__ __forceinline__ float inv_normal(double b) {
     rt = fmaf(rt, tt, kT[k]);
   }
   const float z = -1.41421356237f * x * (w < 5.0f ? rc : rt);
-  return b < 0.5 ? z : -z;
+  return lower ? z : -z;
 }
 
 // ---------------------------------------------------------------- profile --
@@ -158,9 +174,7 @@ __global__ __launch_bounds__(kProfThreads) void k_lift_prep(const RepDev* __rest
 // start): b = ((bitrev32(c ppc + m) + shift) mod 2^32 + 1/2) 2^-32.
 __device__ __forceinline__ float normal_of(int c, int m, int ppc, uint32_t shift) {
   const uint32_t idx = (uint32_t)c * (uint32_t)ppc + (uint32_t)m;
-  const uint32_t u = __brev(idx) + shift;
-  const double b = ((double)u + 0.5) * 2.3283064365386963e-10;  // 2^-32
-  return inv_normal(b);
+  return inv_normal(__brev(idx) + shift);
 }
 
 __device__ __forceinline__ int right_node(const RepDev& R, int c) {
@@ -197,10 +211,11 @@ __device__ __forceinline__ int find_rep(const int64_t* prefix, int n, int64_t it
 // One work item per (replica, coarse block): generate the block's ions, and
 // with coarse targets rescale weights to the block mass h 2^{l/2} max(c^n_B, 0)
 // and shift velocities to the block momentum h 2^{l/2} c^j_B.  Ion j of the block
-// is ion m = j mod ppc of its (j / ppc)-th occupied cell; a thread walks
-// j = t, t + 1024, ... and steps (j / ppc, m) without dividing.  Offsets are
+// is ion m = j mod ppc of its (j / ppc)-th occupied cell; thread t walks
+// j = t, t + kLiftThreads, ... and steps (j / ppc, m) without dividing.  Offsets are
 // (float)((m + 1/2) / ppc); n and u are linear in the cell from its two nodes;
-// v = u + vth z, w = n h / ppc.
+// v = u + vth z, w = n h / ppc, formed in FP32 (the stored precision), summed
+// over the block in binary64 in a fixed order.
 __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict__ reps,
                                                        const int64_t* __restrict__ block_prefix,
                                                        int n_reps, int64_t total, int only_rep,
@@ -208,7 +223,7 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
                                                        const int64_t* __restrict__ coff) {
   __shared__ double s_red[kLiftThreads / 64];
   __shared__ int s_c[kLiftCache];
-  __shared__ double s_nl[kLiftCache], s_nr[kLiftCache], s_ul[kLiftCache], s_ur[kLiftCache];
+  __shared__ float s_nl[kLiftCache], s_dn[kLiftCache], s_ul[kLiftCache], s_du[kLiftCache];
   __shared__ float s_frac[kFracTable];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int r = only_rep >= 0 ? only_rep : find_rep(block_prefix, n_reps, item);
@@ -227,17 +242,18 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const int ncell = rb1 - rb0;
     const bool cached = ncell <= kLiftCache;
     const bool table = ppc <= kFracTable;
-    const double vth = R.vth;
-    const double hp = R.h / (double)ppc;
+    const float vth = (float)R.vth;
+    const float hp = (float)(R.h / (double)ppc);
     if (cached) {
       for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
         const int c = cell_of_rank[rb0 + k];
         const int cr = right_node(R, c);
+        const float nl = (float)prof_n[c], ul = (float)prof_u[c];
         s_c[k] = c;
-        s_nl[k] = prof_n[c];
-        s_nr[k] = prof_n[cr];
-        s_ul[k] = prof_u[c];
-        s_ur[k] = prof_u[cr];
+        s_nl[k] = nl;
+        s_dn[k] = (float)prof_n[cr] - nl;
+        s_ul[k] = ul;
+        s_du[k] = (float)prof_u[cr] - ul;
       }
     }
     if (table)
@@ -255,58 +271,50 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
         ++jr;
       }
     };
-    // ion (jr, m): cell, offset, and (with its deviate z) FP64 velocity and weight
-    auto ion = [&](int jr, int m, float& z, bool need_z, int& c, float& fr, double& v,
-                   double& w) {
-      double nl, nr, ul, ur;
-      if (cached) {
-        c = s_c[jr];
-        nl = s_nl[jr];
-        nr = s_nr[jr];
-        ul = s_ul[jr];
-        ur = s_ur[jr];
-      } else {
-        c = cell_of_rank[rb0 + jr];
-        const int cr = right_node(R, c);
-        nl = prof_n[c];
-        nr = prof_n[cr];
-        ul = prof_u[c];
-        ur = prof_u[cr];
-      }
-      if (need_z) z = normal_of(c, m, ppc, shift);
-      fr = table ? s_frac[m] : (float)(((double)m + 0.5) / (double)ppc);
-      const double th = (double)fr;
-      v = ((1.0 - th) * ul + th * ur) + vth * (double)z;
-      w = ((1.0 - th) * nl + th * nr) * hp;
+    auto cell_at = [&](int jr) { return cached ? s_c[jr] : cell_of_rank[rb0 + jr]; };
+    auto offset_at = [&](int m) {
+      return table ? s_frac[m] : (float)(((double)m + 0.5) / (double)ppc);
     };
-    // the first kKeep ions of every thread keep their deviate in registers
-    // between the correction sums and the stores
-    constexpr int kKeep = 16;
-    float keep[kKeep];
-    double ratio = 1.0, dv = 0.0;
+    // ion (jr, m) of cell c at offset fr: velocity and weight before the correction
+    auto ion = [&](int jr, int c, int m, float fr, float& v, float& w) {
+      float nl, dn, ul, du;
+      if (cached) {
+        nl = s_nl[jr];
+        dn = s_dn[jr];
+        ul = s_ul[jr];
+        du = s_du[jr];
+      } else {
+        const int cr = right_node(R, c);
+        nl = (float)prof_n[c];
+        dn = (float)prof_n[cr] - nl;
+        ul = (float)prof_u[c];
+        du = (float)prof_u[cr] - ul;
+      }
+      v = fmaf(vth, normal_of(c, m, ppc, shift), fmaf(fr, du, ul));
+      w = fmaf(fr, dn, nl) * hp;
+    };
+    // the first kKeep ions of every thread keep (v, w) in registers
+    constexpr int kKeep = EFPI_LIFT_KEEP;
+    float keep_v[kKeep], keep_w[kKeep];
+    float ratio = 1.0f, dv = 0.0f;
     if (coarse != nullptr) {
       double sw = 0.0, swv = 0.0;
       int jr = q0, m = m0;
 #pragma unroll
       for (int k = 0; k < kKeep; ++k) {
         if ((int)threadIdx.x + k * kLiftThreads < count) {
-          int c;
-          float fr;
-          double v, w;
-          ion(jr, m, keep[k], true, c, fr, v, w);
-          sw += w;
-          swv += w * v;
+          ion(jr, cell_at(jr), m, offset_at(m), keep_v[k], keep_w[k]);
+          sw += (double)keep_w[k];
+          swv += (double)keep_w[k] * (double)keep_v[k];
         }
         advance(jr, m);
       }
 #pragma unroll 1
       for (int j = threadIdx.x + kKeep * kLiftThreads; j < count; j += kLiftThreads) {
-        int c;
-        float fr, z;
-        double v, w;
-        ion(jr, m, z, true, c, fr, v, w);
-        sw += w;
-        swv += w * v;
+        float v, w;
+        ion(jr, cell_at(jr), m, offset_at(m), v, w);
+        sw += (double)w;
+        swv += (double)w * (double)v;
         advance(jr, m);
       }
       sw = block_sum(sw, s_red);
@@ -315,19 +323,20 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
       const auto cc = gmem(coarse + coff[r]);
       const double mt = fmax(cc[B], 0.0) * scale;
       const double jt = cc[R.n_coarse + B] * scale;
-      if (sw > 0.0) ratio = mt / sw;
-      if (mt > 0.0) dv = (jt - ratio * swv) / mt;
+      const double rd = sw > 0.0 ? mt / sw : 1.0;
+      ratio = (float)rd;
+      if (mt > 0.0) dv = (float)((jt - rd * swv) / mt);
     }
     const auto cell = gmem(R.cell);
     const auto frac = gmem(R.frac);
     const auto vel = gmem(R.v);
     const auto wgt = gmem(R.w);
-    auto put = [&](int j, int c, float fr, double v, double w) {
+    auto put = [&](int j, int c, float fr, float v, float w) {
       const int64_t s = slot0 + j;
       cell[s] = (int16_t)c;
       frac[s] = fr;
-      vel[s] = (float)(v + dv);
-      wgt[s] = (float)(w * ratio);
+      vel[s] = v + dv;
+      wgt[s] = w * ratio;
     };
     {
       int jr = q0, m = m0;
@@ -335,20 +344,19 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
       for (int k = 0; k < kKeep; ++k) {
         const int j = threadIdx.x + k * kLiftThreads;
         if (j < count) {
-          int c;
-          float fr;
-          double v, w;
-          ion(jr, m, keep[k], coarse == nullptr, c, fr, v, w);
-          put(j, c, fr, v, w);
+          const int c = cell_at(jr);
+          const float fr = offset_at(m);
+          if (coarse == nullptr) ion(jr, c, m, fr, keep_v[k], keep_w[k]);
+          put(j, c, fr, keep_v[k], keep_w[k]);
         }
         advance(jr, m);
       }
 #pragma unroll 1
       for (int j = threadIdx.x + kKeep * kLiftThreads; j < count; j += kLiftThreads) {
-        int c;
-        float fr, z;
-        double v, w;
-        ion(jr, m, z, true, c, fr, v, w);
+        const int c = cell_at(jr);
+        const float fr = offset_at(m);
+        float v, w;
+        ion(jr, c, m, fr, v, w);
         put(j, c, fr, v, w);
         advance(jr, m);
       }
