@@ -281,6 +281,17 @@ efpi_status efpi_project(efpi_ctx* ctx, const double* d_snap, double* d_coarse_n
  * descriptors to the device on the context's stream and waits for the copy. */
 efpi_status efpi_set_macro_dt(efpi_ctx* ctx, double macro_dt);
 
+/* Step-size rule of the adaptive projective integrator (the paper's remark on
+ * estimating the projection error, Sec. 3.1): err, the error of eq. 4.2 between the
+ * second-order and the forward-Euler projections of the coarse density, estimates
+ * the local error of a forward-Euler step, which grows as Delta t^2; so
+ * *h_next = macro_dt * f with f = min(2, max(1/2, safety (tol / err)^{1/2})) (f = 2
+ * when err = 0), then clamped to [dt_min, dt_max].  Host only and synchronous.
+ * EFPI_EINVAL unless 0 < dt_min <= dt_max, macro_dt > 0, tol > 0, safety > 0,
+ * err >= 0 (all finite) and h_next != NULL. */
+efpi_status efpi_next_macro_dt(double macro_dt, double err, double tol, double dt_min,
+                               double dt_max, double safety, double* h_next);
+
 /* Second-order projective step (the higher-order projection the paper mentions
  * after eq. 3.17, read as Adams-Bashforth 2 on the burst slopes).  From the
  * snapshots d_snap[r][0..N_e][2][N_c] (as efpi_project):

@@ -1129,6 +1129,22 @@ efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {
   return hip_check("restrict_state");
 }
 
+efpi_status efpi_next_macro_dt(double macro_dt, double err, double tol, double dt_min,
+                               double dt_max, double safety, double* h_next) {
+  if (!h_next) return fail(EFPI_EINVAL, "h_next is NULL");
+  const double v[] = {macro_dt, err, tol, dt_min, dt_max, safety};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(EFPI_EINVAL, "non-finite argument");
+  if (!(macro_dt > 0.0) || !(tol > 0.0) || !(safety > 0.0) || err < 0.0 || !(dt_min > 0.0) ||
+      dt_min > dt_max)
+    return fail(EFPI_EINVAL, "need macro_dt, tol, safety > 0, err >= 0, 0 < dt_min <= dt_max");
+  // the Euler step's local error grows as Delta t^2: the step that meets tol is
+  // Delta t (tol / err)^{1/2}; a safety factor, at most a doubling or a halving
+  const double grow = err == 0.0 ? 2.0 : std::min(2.0, std::max(0.5, safety * std::sqrt(tol / err)));
+  *h_next = std::min(dt_max, std::max(dt_min, macro_dt * grow));
+  return EFPI_OK;
+}
+
 efpi_status efpi_set_macro_dt(efpi_ctx* ctx, double macro_dt) {
   if (check_ctx(ctx) != EFPI_OK) return EFPI_EINVAL;
   if (!std::isfinite(macro_dt)) return fail(EFPI_EINVAL, "macro_dt must be finite");

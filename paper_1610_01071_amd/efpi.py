@@ -129,6 +129,7 @@ def _load():
         "efpi_phase_work_size": [P, I32, ctypes.POINTER(Phase), ctypes.POINTER(ctypes.c_size_t)],
         "efpi_phase_restrict": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, I32, P, P],
         "efpi_phase_restrict_static": [P, I32, ctypes.POINTER(Phase), ctypes.c_double, I32, P],
+        "efpi_next_macro_dt": [ctypes.c_double] * 6 + [ctypes.POINTER(ctypes.c_double)],
         "efpi_phase_lift_work_size": [P, I32, ctypes.POINTER(Phase),
                                       ctypes.POINTER(ctypes.c_size_t)],
         "efpi_phase_lift": [P, I32, ctypes.POINTER(Phase), P, U32, P],
@@ -175,7 +176,7 @@ EXPORTED = ["efpi_workspace_size", "efpi_init", "efpi_destroy", "efpi_set_stream
             "efpi_macro_step", "efpi_macro_step_graph",
             "efpi_ensemble_mean", "efpi_sort",
             "efpi_restrict_state", "efpi_coiflet_taps", "efpi_phase_work_size",
-            "efpi_phase_restrict", "efpi_phase_restrict_static",
+            "efpi_phase_restrict", "efpi_phase_restrict_static", "efpi_next_macro_dt",
             "efpi_phase_lift_work_size", "efpi_phase_lift", "efpi_phase_project",
             "efpi_store_field",
             "efpi_sync", "efpi_timing", "efpi_timing_read", "efpi_timing_read_electrons",
@@ -432,6 +433,13 @@ def efpi_phase_restrict_static(ctx, replica, ph: Phase, tau, out, stored_field=F
     _check(LIB.efpi_phase_restrict_static(ctx, replica, ctypes.byref(ph), float(tau),
                                           1 if stored_field else 0,
                                           _dev(out, torch.float64)))
+
+
+def efpi_next_macro_dt(macro_dt, err, tol, dt_min, dt_max, safety=0.9) -> float:
+    out = ctypes.c_double(0.0)
+    _check(LIB.efpi_next_macro_dt(float(macro_dt), float(err), float(tol), float(dt_min),
+                                  float(dt_max), float(safety), ctypes.byref(out)))
+    return out.value
 
 
 def efpi_phase_lift_work_size(ctx, replica, ph: Phase) -> int:

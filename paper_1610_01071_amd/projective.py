@@ -7,14 +7,13 @@ extrapolates the slopes of the last two bursts to the middle of the projection
 leap (order 2; include/efpi.h).  The adaptive integrator takes the difference of
 the two projections of the coarse density (the error of eq. 4.2) as the local
 error of a first-order step, which grows as Delta t^2, and sets the next Delta t
-from it (``next_macro_dt``), with ``efpi_set_macro_dt`` between steps.
+from it (the library's ``efpi_next_macro_dt``), with ``efpi_set_macro_dt`` between steps.
 
 Python only chooses step sizes and calls the library; all arithmetic on the
 coarse and fine states runs in the library's kernels.
 """
 from __future__ import annotations
 
-import math
 import time
 from dataclasses import dataclass
 
@@ -22,17 +21,6 @@ import torch
 
 from . import efpi as E
 from .learned import lift_shift
-
-
-def next_macro_dt(macro_dt: float, err: float, tol: float, dt_min: float, dt_max: float,
-                  safety: float = 0.9) -> float:
-    """Next projective step: Delta t (tol / err)^{1/2} * safety, changed by at
-    most a factor 2 and kept in [dt_min, dt_max] (err = 0 doubles it)."""
-    if err <= 0.0:
-        factor = 2.0
-    else:
-        factor = min(2.0, max(0.5, safety * math.sqrt(tol / err)))
-    return min(dt_max, max(dt_min, macro_dt * factor))
 
 
 @dataclass
@@ -113,7 +101,7 @@ def run_projective(ctx: E.Context, c0: torch.Tensor, t_end: float, macro_dt: flo
         gap = dt
         # the first step has no error estimate and keeps its size
         if adaptive and n > 0:
-            dt = next_macro_dt(dt, e, tol, lo, hi)
+            dt = E.efpi_next_macro_dt(dt, e, tol, lo, hi)
         n += 1
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3

@@ -116,3 +116,19 @@ def test_autotune_cache_roundtrip(tmp_path):
     autotune.save_cache(path, {k: {"tile": 2048, "grid_blocks": 4096, "ms_per_step": 1.0}})
     assert autotune.load_cache(path)[k]["tile"] == 2048
     assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
+
+
+def test_next_macro_dt_against_the_oracles_rule():
+    """The library's step-size rule (host code) against the oracle's, written apart:
+    the same steps over errors from 0 to far above tol, at and inside the clamps."""
+    from oracle import efpi as oefpi
+    import paper_1610_01071_amd.efpi as E
+    for dt in (2.0, 5.0, 7.5):
+        for err in (0.0, 1e-9, 1e-5, 2.5e-4, 1e-3, 4e-3, 1e-2, 1.0):
+            for tol, lo, hi, safety in ((1e-3, 2.0, 40.0, 0.9), (3e-4, 5.0, 7.5, 1.0)):
+                got = E.efpi_next_macro_dt(dt, err, tol, lo, hi, safety)
+                assert got == oefpi.next_macro_dt(dt, err, tol, lo, hi, safety)
+    for bad in ((0.0, 0.0, 1e-3, 1.0, 2.0), (1.0, -1.0, 1e-3, 1.0, 2.0), (1.0, 0.0, 0.0, 1.0, 2.0),
+                (1.0, 0.0, 1e-3, 3.0, 2.0), (1.0, float("nan"), 1e-3, 1.0, 2.0)):
+        with pytest.raises(E.EfpiError):
+            E.efpi_next_macro_dt(*bad)
