@@ -6,7 +6,8 @@ prefix sums against a sparse direct solve) and the FP32 field within 1e-6;
 one two-species step within 1e-5 relative (FP32 particles against FP64); loaded
 electrons: cells and offsets bit-exact, velocities and weights within 1e-6;
 total momentum conserved to FP32 rounding; the kinetic macro step within
-eps = 2e-3 (eq. 4.2) of the oracle's; graph replays bit-equal to eager steps.
+eps = 1e-4 (eq. 4.2) of the oracle's, the density's perturbation about its mean
+included; graph replays bit-equal to eager steps.
 """
 import numpy as np
 import pytest
@@ -250,7 +251,10 @@ def test_kinetic_macro_step_matches_oracle():
                                      shift)
     got = cout.view(2, -1).cpu().numpy()
     for m in range(2):
-        assert metrics.rel_l2(got[m], ref[m]) < 2e-3
+        assert metrics.rel_l2(got[m], ref[m]) < 1e-4
+    # the wave itself: the density perturbation about its mean
+    pert = metrics.rel_l2(got[0] - got[0].mean(), ref[0] - ref[0].mean())
+    assert pert < 1e-4
 
 
 def test_kinetic_graph_replays_equal_eager():

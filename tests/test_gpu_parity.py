@@ -5,7 +5,10 @@ field within 1e-6 relative after converged Newton (FP64 on both sides, the
 field rounded to FP32 on the GPU); one fine step of FP32 particles and field
 within 1e-5 relative of the FP64 oracle; lifted particles: cells and offsets
 bit-exact, velocities and weights within 1e-6 relative; burst-averaged coarse
-coefficients and the projected state within eps = 2e-3 (eq. 4.2).
+coefficients and the projected state within eps = 1e-4 (eq. 4.2), and so is the
+density's perturbation about its mean (the wave itself: a whole-array eps of the
+density 1 + 0.2 cos would hide a larger error of its amplitude).  Measured:
+1e-9 to 3e-6 (FP32 against FP64 over a 20-step burst).
 """
 import numpy as np
 import pytest
@@ -19,6 +22,12 @@ from helpers import (lib, oracle_grid, oracle_scheme, to_dev, set_particles, par
                      grid_np, x_of, periodic_dx, relmax)
 
 pytestmark = pytest.mark.gpu
+
+
+def pert_eps(a, b):
+    """eps of eq. 4.2 between the perturbations of two arrays about their means
+    (for the density of the wave, 1 + 0.2 cos: the wave's own error)."""
+    return metrics.rel_l2(a - a.mean(), b - b.mean())
 
 
 def make_ctx(specs, **kw):
@@ -228,8 +237,10 @@ def _burst_compare(spec, parts, seed_tag, newton_iters=2):
                               g, sch)
     on = oefpi.project(os_, g.dt, sch.macro_dt)
     for m in range(2):
-        assert metrics.rel_l2(gs[:, m].mean(axis=0), os_[:, m].mean(axis=0)) < 2e-3
-        assert metrics.rel_l2(gn[m], on[m]) < 2e-3
+        assert metrics.rel_l2(gs[:, m].mean(axis=0), os_[:, m].mean(axis=0)) < 1e-4
+        assert metrics.rel_l2(gn[m], on[m]) < 1e-4
+    # the wave itself, not its mean: the density perturbation about its mean
+    assert pert_eps(gn[0], on[0]) < 1e-4
     return gs, gn, os_, on
 
 
@@ -281,7 +292,8 @@ def test_macro_step_matches_oracle():
     ref, _, _ = oefpi.macro_step(c0, g, sch, shift)
     got = cout.view(2, -1).cpu().numpy()
     for m in range(2):
-        assert metrics.rel_l2(got[m], ref[m]) < 2e-3
+        assert metrics.rel_l2(got[m], ref[m]) < 1e-4
+    assert pert_eps(got[0], ref[0]) < 1e-4
     # second call from the same input: identical bits (deterministic)
     cout2 = ctx.new_coarse()
     E.efpi_macro_step(ctx.ctx, cin, cout2, [shift])
