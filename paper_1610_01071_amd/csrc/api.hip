@@ -108,6 +108,7 @@ struct efpi_ctx {
   int64_t* d_coarse_off = nullptr;
   int32_t* d_group = nullptr;
   bool kinetic = false;             // kinetic electrons (every replica)
+  bool lift_deposit = false;        // the lift deposits the ions' charge itself
   int max_nodes = 0;                // largest node count of the replicas
   std::vector<RepDev> h_ereps;      // electron descriptors (kinetic contexts)
   RepDev* d_ereps = nullptr;
@@ -288,6 +289,12 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     ctx->coarse_total = coarse_total;
     ctx->h_reps.assign(R, RepDev{});
     ctx->kinetic = kinetic;
+    // the lift's fused deposit holds a block's nodes in LDS: blocks of at most
+    // 2^kLiftMaxDepositLevels cells (kinetic contexts deposit both species after
+    // the electron load anyway)
+    ctx->lift_deposit = !kinetic;
+    for (int r = 0; r < R; ++r)
+      if (cfg->replicas[r].haar_levels > kLiftMaxDepositLevels) ctx->lift_deposit = false;
     ctx->d_ereps = reinterpret_cast<RepDev*>(p_ereps);
     ctx->d_eitem_prefix = reinterpret_cast<int64_t*>(p_eitems);
     if (kinetic) ctx->h_ereps.assign(R, RepDev{});
@@ -526,13 +533,21 @@ efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shift
   const ShiftArg sh = shifts_of(c, h_shifts);
   launch_lift_prep(c->d_reps, c->R, d_coarse, c->d_coarse_off, c->d_status,
                    h_shifts ? &sh : nullptr, c->stream);
+  // the lift deposits the new ions' charge into the next buffer as it writes them
+  if (c->lift_deposit) deposit_into_next(c);
   launch_lift_particles(c->d_reps, c->d_block_prefix, c->R, c->total_blocks, -1, d_coarse,
-                        c->d_coarse_off, nullptr, c->grid_blocks, c->stream);
+                        c->d_coarse_off, nullptr, c->grid_blocks, c->stream,
+                        c->lift_deposit ? c->cur ^ 1 : -1, c->d_status);
   if (c->kinetic) {
     load_boltzmann_electrons(c);
     mark_new_electrons(c);
   }
   mark_new_particles(c);
+  if (c->lift_deposit) {
+    c->cur ^= 1;
+    c->other_zero = false;
+    c->deposited = true;
+  }
   return hip_check("lift");
 }
 

@@ -185,6 +185,11 @@ __device__ __forceinline__ int right_node(const RepDev& R, int c) {
 // the in-cell offsets (m + 1/2) / ppc as FP32 for ppc up to kFracTable.
 constexpr int kLiftCache = 256;
 constexpr int kFracTable = 4096;
+// The lift's charge deposit: a block of 2^l cells touches 2^l + 1 nodes, held in
+// LDS with 16 slots per node (threads t and t + 16k share one) as integer-valued
+// binary64, as in the particle pass.
+constexpr int kLiftNodes = 65;
+constexpr int kLiftSlots = 16;
 
 __device__ double block_sum(double x, double* s_red) {
   // fixed-order tree: waves by shuffles, then the wave totals in index order
@@ -215,13 +220,18 @@ __device__ __forceinline__ int find_rep(const int64_t* prefix, int n, int64_t it
 // j = t, t + kLiftThreads, ... and steps (j / ppc, m) without dividing.  Offsets are
 // (float)((m + 1/2) / ppc); n and u are linear in the cell from its two nodes;
 // v = u + vth z, w = n h / ppc, formed in FP32 (the stored precision), summed
-// over the block in binary64 in a fixed order.
+// over the block in binary64 in a fixed order.  With qsel >= 0 (every replica's
+// blocks of at most 64 cells) the ions' charge is deposited into R.q[qsel] as the
+// particle pass deposits it (the same fixed-point shares of the stored w and
+// offset), so the burst needs no separate deposit pass.
 __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict__ reps,
                                                        const int64_t* __restrict__ block_prefix,
                                                        int n_reps, int64_t total, int only_rep,
                                                        const double* __restrict__ coarse,
-                                                       const int64_t* __restrict__ coff) {
+                                                       const int64_t* __restrict__ coff,
+                                                       int qsel, uint32_t* __restrict__ status) {
   __shared__ double s_red[kLiftThreads / 64];
+  __shared__ double s_q[kLiftNodes][kLiftSlots];
   __shared__ int s_c[kLiftCache];
   __shared__ float s_nl[kLiftCache], s_dn[kLiftCache], s_ul[kLiftCache], s_du[kLiftCache];
   __shared__ float s_frac[kFracTable];
@@ -259,6 +269,9 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     if (table)
       for (int m = threadIdx.x; m < ppc; m += blockDim.x)
         s_frac[m] = (float)(((double)m + 0.5) / (double)ppc);
+    const bool dep = qsel >= 0;
+    if (dep)
+      for (int k = threadIdx.x; k < kLiftNodes * kLiftSlots; k += blockDim.x) (&s_q[0][0])[k] = 0.0;
     __syncthreads();
     // the thread's first ion and its stride, as (cell rank, index in the cell)
     const int q0 = (int)threadIdx.x / ppc, m0 = (int)threadIdx.x - q0 * ppc;
@@ -331,12 +344,26 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const auto frac = gmem(R.frac);
     const auto vel = gmem(R.v);
     const auto wgt = gmem(R.w);
+    const int c0 = B << R.levels;  // first cell of the block: node c0 + d is bin d
+    const int slot = threadIdx.x & (kLiftSlots - 1);
+    bool big = false;
     auto put = [&](int j, int c, float fr, float v, float w) {
       const int64_t s = slot0 + j;
+      const float ws = w * ratio;
       cell[s] = (int16_t)c;
       frac[s] = fr;
       vel[s] = v + dv;
-      wgt[s] = w * ratio;
+      wgt[s] = ws;
+      if (dep) {
+        const double q = fx_charge(ws);
+        const double qr = fx_share(fr, q);
+        const int d = c - c0;
+        __hip_atomic_fetch_add(&s_q[d][slot], q - qr, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&s_q[d + 1][slot], qr, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        big |= !(fabsf(ws) < 16.0f);
+      }
     };
     {
       int jr = q0, m = m0;
@@ -359,6 +386,23 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
         ion(jr, c, m, fr, v, w);
         put(j, c, fr, v, w);
         advance(jr, m);
+      }
+    }
+    if (dep) {
+      // node totals (the slots in a fixed order; exact integer sums) to the grid
+      if (__any(big) && (threadIdx.x & 63) == 0) atomicOr(status, (uint32_t)EFPI_DEV_WEIGHT);
+      __syncthreads();
+      const int nodes = (1 << R.levels) + 1;
+      const int nmask = R.n_cells - 1;
+      const auto qg = reinterpret_cast<unsigned long long*>(R.q[qsel]);
+      for (int d = threadIdx.x; d < nodes; d += blockDim.x) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < kLiftSlots; ++k) t += s_q[d][k];
+        if (t != 0.0) {
+          const int node = R.bc == 0 ? ((c0 + d) & nmask) : c0 + d;
+          atomicAdd(qg + node, (unsigned long long)rint_i64(t));
+        }
       }
     }
     __syncthreads();
@@ -548,12 +592,13 @@ void launch_set_shifts(const RepDev* d_reps, int n_reps, int only_rep, const Shi
 void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
                            int64_t total_blocks, int only_rep, const double* d_coarse,
                            const int64_t* d_coff, const ShiftArg* shifts, int grid_blocks,
-                           hipStream_t stream) {
+                           hipStream_t stream, int qsel, uint32_t* d_status) {
   if (total_blocks <= 0) return;
   if (shifts) launch_set_shifts(d_reps, n_reps, only_rep, *shifts, stream);
   const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_blocks) : total_blocks;
   hipLaunchKernelGGL(k_lift, dim3((unsigned)g), dim3(kLiftThreads), 0, stream, d_reps,
-                     d_block_prefix, n_reps, total_blocks, only_rep, d_coarse, d_coff);
+                     d_block_prefix, n_reps, total_blocks, only_rep, d_coarse, d_coff, qsel,
+                     d_status);
 }
 
 void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap,

@@ -10,6 +10,23 @@ namespace efpi {
 
 constexpr double kFxScale = 1099511627776.0;     // 2^40: fixed-point charge unit 2^-40
 constexpr double kFxInv = 1.0 / 1099511627776.0;
+
+// The fixed-point charge of an ion and its CIC split, shared by every kernel that
+// deposits (the particle pass and the lift), so that all deposits are the same
+// integers: q = rint(w 2^40) as an exact binary64 integer, the right-node share
+// rint(theta q) (one rounded product, ties to even) and the left share q - rint(theta q).
+__device__ __forceinline__ double fx_charge(float w) {
+  return __builtin_rint((double)w * kFxScale);
+}
+__device__ __forceinline__ double fx_share(float theta, double q) {
+  return __builtin_rint((double)theta * q);
+}
+// rint(x) as int64 for |x| < 2^51: adding 1.5 * 2^52 leaves the integer part
+// rounded to nearest (ties to even, the IEEE default) in the low mantissa bits.
+__device__ __forceinline__ long long rint_i64(double x) {
+  const double magic = 6755399441055744.0;
+  return (long long)(__double_as_longlong(x + magic) - __double_as_longlong(magic));
+}
 constexpr int kWave = 64;
 
 #define EFPI_GLOBAL __attribute__((address_space(1)))
@@ -137,10 +154,14 @@ void launch_occupancy(const RepDev* d_reps, int n_reps, int only_rep, uint32_t* 
 void launch_set_shifts(const RepDev* d_reps, int n_reps, int only_rep, const ShiftArg& shifts,
                        hipStream_t stream);
 // Lift; with shifts == nullptr the rotations stored by launch_set_shifts are used.
+// qsel >= 0: also deposit the lifted ions' charge into R.q[qsel] (zeroed before),
+// which needs every replica's coarse blocks to be at most 64 cells wide
+// (lift_can_deposit); d_status receives EFPI_DEV_WEIGHT then.
+constexpr int kLiftMaxDepositLevels = 6;
 void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
                            int64_t total_blocks, int only_rep, const double* d_coarse,
                            const int64_t* d_coff, const ShiftArg* shifts, int grid_blocks,
-                           hipStream_t stream);
+                           hipStream_t stream, int qsel = -1, uint32_t* d_status = nullptr);
 void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap,
                      const int64_t* d_soff, hipStream_t stream);
 void launch_project(const RepDev* d_reps, int n_reps, const double* d_snap,

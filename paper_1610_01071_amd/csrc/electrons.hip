@@ -20,12 +20,6 @@ constexpr int kEPer = 16;                          // electrons per thread per c
 constexpr int kEChunk = kEThreads * kEPer;
 constexpr int kEMaxNodes = 8192;                   // 64 KB of int64 LDS
 
-// The fixed-point split of the ion deposit: q = rint(w 2^40) and the right share
-// rint(theta q), both as binary64 with ties to even; the left share is q - q_R.
-__device__ __forceinline__ double fx_q(float w) { return __builtin_rint((double)w * kFxScale); }
-__device__ __forceinline__ double fx_right(float theta, double q) {
-  return __builtin_rint((double)theta * q);
-}
 
 template <bool PUSH>
 __global__ __launch_bounds__(kEThreads) void k_electrons(const RepDev* __restrict__ ereps,
@@ -72,8 +66,8 @@ __global__ __launch_bounds__(kEThreads) void k_electrons(const RepDev* __restric
         fracp[i] = f;
         velp[i] = vn;
       }
-      const double q = fx_q(w);
-      const double qr = fx_right(f, q);
+      const double q = fx_charge(w);
+      const double qr = fx_share(f, q);
       atomicAdd(reinterpret_cast<unsigned long long*>(&s_q[cn]),
                 (unsigned long long)(-(long long)(q - qr)));
       atomicAdd(reinterpret_cast<unsigned long long*>(&s_q[(cn + 1) & nmask]),
@@ -118,7 +112,7 @@ __global__ __launch_bounds__(kEThreads) void k_ion_momentum(const RepDev* __rest
       const float ep = (1.f - f) * e[c] + f * e[(c + 1) & nmask];
       const float vc = velp[i] + kick * ep;
       const double p = __builtin_rint((double)wp[i] * (double)vc * kFxScale);
-      const double pr = fx_right(f, p);
+      const double pr = fx_share(f, p);
       atomicAdd(reinterpret_cast<unsigned long long*>(&s_q[c]),
                 (unsigned long long)(long long)(p - pr));
       atomicAdd(reinterpret_cast<unsigned long long*>(&s_q[(c + 1) & nmask]),

@@ -100,21 +100,6 @@ struct WaveLds {
   double r[2][kRBins][kQSlots];   // fixed-point (density, momentum) shares per coarse block
 };
 
-// rint(x) as int64 for |x| < 2^51: adding 1.5 * 2^52 leaves the integer part
-// rounded to nearest (ties to even, the IEEE default) in the low mantissa bits.
-__device__ __forceinline__ long long rint_i64(double x) {
-  const double magic = 6755399441055744.0;
-  return (long long)(__double_as_longlong(x + magic) - __double_as_longlong(magic));
-}
-
-// q = rint(w 2^40): the ion's charge in fixed point, as an exact binary64 integer.
-__device__ __forceinline__ double fx_charge(float w) {
-  return __builtin_rint((double)w * kFxScale);
-}
-// Right-node share rint(theta q) in binary64 (one rounded product, then ties-to-even).
-__device__ __forceinline__ double fx_share(float theta, double q) {
-  return __builtin_rint((double)theta * q);
-}
 
 __device__ __forceinline__ int find_replica(const int64_t* prefix, int n, int64_t item) {
   int lo = 0, hi = n - 1;

@@ -202,6 +202,29 @@ def test_lift_matches_oracle(n_cells, bc, levels, linear, ppc):
     assert relmax(gw, ow) < 1e-6
 
 
+@pytest.mark.parametrize("bc,levels,ppc", [(0, 2, 37), (1, 3, 50), (0, 6, 11), (1, 6, 64)])
+def test_lift_deposit_equals_the_deposit_pass(bc, levels, ppc):
+    """The lift deposits the charge of the ions it writes (blocks of up to 64
+    cells): the same int64 grid as the deposit pass over the stored ions."""
+    E = lib()
+    n = 1024
+    spec = E.ReplicaSpec(n, float(n), bc=bc, ppc=ppc, haar_levels=levels, vth=0.316)
+    ctx = make_ctx([spec])
+    n0, u0 = synth.slab_profile(n) if bc else synth.iaw_profile(n, float(n))
+    E.efpi_load_profile(ctx.ctx, 0, to_dev(n0, torch.float64), to_dev(u0, torch.float64), 5)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 40, cold=True)
+    c0 = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c0)
+    E.efpi_lift(ctx.ctx, c0, [99])
+    q_lift = ctx.grid(0)[0].clone()
+    E.efpi_deposit(ctx.ctx)
+    q_pass = ctx.grid(0)[0].clone()
+    assert int(q_lift.abs().sum().item()) > 0
+    assert torch.equal(q_lift, q_pass)
+    assert E.efpi_sync(ctx.ctx, raise_on_error=False) == 0
+
+
 def test_load_profile_matches_oracle():
     E = lib()
     spec = E.ReplicaSpec(128, 128.0, ppc=50, haar_levels=2)
