@@ -31,6 +31,8 @@ class Scheme:
     vth: float = 0.316227766016838  # sqrt(T_i / T_e) of the lifted Maxwellian
     lift_linear: bool = True  # linear interpolation of block means (else piecewise constant)
     n_floor: float = 1e-6    # density below which a cell is empty
+    moments: int = 2         # 2: density and momentum; 3: and the second velocity
+                             # moment (the EFREE variables n, V, P of Sec. 3.2)
 
 
 # ----------------------------------------------------------------------------
@@ -76,16 +78,20 @@ def fold_nodes(node_values, grid: Grid):
 # Restriction with the co-evolving frame (Sec. 3.3, App. B eqs. B.4-B.5)
 # ----------------------------------------------------------------------------
 
-def restrict_snapshot(x, v_p, e_n_at_x, w, tau, grid: Grid, levels: int, coevolving=True):
-    """Coarse (density, momentum) coefficients of one snapshot, shape (2, N_c).
+def restrict_snapshot(x, v_p, e_n_at_x, w, tau, grid: Grid, levels: int, coevolving=True,
+                      moments: int = 2):
+    """Coarse (density, momentum[, second moment]) coefficients of one snapshot,
+    shape (moments, N_c).
 
     Each particle is moved along the approximate characteristic of eq. B.4 over
     the remaining time tau = Delta t - p dt: X~ = X + tau V, V~ = V + tau E_n(X),
     with E_n the field stored when the burst started.  Its weight w and its
     momentum w V~ are deposited with CIC weights at X~ (eq. B.5; the velocity
-    histogram of the paper is replaced by the first two velocity moments), and
-    the node masses are coarsened by the fast Haar transform.  On walls, a
-    particle whose X~ lies outside [0, L) is left out of the snapshot.
+    histogram of the paper is replaced by its first velocity moments), and the
+    node masses are coarsened by the fast Haar transform.  With moments = 3 the
+    second moment w V~^2 is deposited the same way: n, nV and nV^2 + P carry the
+    EFREE variables n, V and P (Sec. 3.2) in a form linear in the particles.  On
+    walls, a particle whose X~ lies outside [0, L) is left out of the snapshot.
     With coevolving=False, tau = 0 (the plain deposition of Table 2).
     """
     x = np.asarray(x, dtype=np.float64)
@@ -99,8 +105,8 @@ def restrict_snapshot(x, v_p, e_n_at_x, w, tau, grid: Grid, levels: int, coevolv
         keep = np.ones(xt.shape, bool)
     else:
         keep = (xt >= 0.0) & (xt < grid.length)
-    out = np.empty((2, grid.n_cells >> levels))
-    for m, weight in enumerate((w, w * vt)):
+    out = np.empty((moments, grid.n_cells >> levels))
+    for m, weight in enumerate((w, w * vt, w * vt * vt)[:moments]):
         mass = pic.deposit_mass(xt[keep], np.asarray(weight)[keep], grid)
         out[m], _ = haar_analysis(fold_nodes(mass, grid) / grid.h, levels)
     return out
@@ -174,7 +180,8 @@ def next_macro_dt(macro_dt: float, err: float, tol: float, dt_min: float, dt_max
 # ----------------------------------------------------------------------------
 
 def lift_profile(coarse, grid: Grid, sch: Scheme):
-    """Fine node density n_k and momentum density j_k from the coarse coefficients.
+    """Fine node density n_k and momentum density j_k (and, with three moments, the
+    second-moment density s_k) from the coarse coefficients.
 
     The inverse Haar transform with zero details gives the block means
     2^{-l/2} c_B.  With lift_linear, the block means sit at the block centres
@@ -186,7 +193,7 @@ def lift_profile(coarse, grid: Grid, sch: Scheme):
     nb = grid.n_cells >> sch.levels
     bs = 1 << sch.levels
     out = []
-    for m in range(2):
+    for m in range(coarse.shape[0]):
         zeros = [np.zeros(grid.n_cells >> (i + 1)) for i in range(sch.levels)]
         const = haar_synthesis(coarse[m], zeros)  # block means on nodes 0..N-1
         means = const[::bs]
@@ -205,7 +212,7 @@ def lift_profile(coarse, grid: Grid, sch: Scheme):
             out.append(np.interp(k, xp, fp))
         else:
             out.append(np.interp(k, centre, means))
-    return out[0], out[1]
+    return tuple(out)
 
 
 def bit_reverse32(i):
@@ -227,7 +234,7 @@ def hammersley_b(index, shift: int):
     return (u.astype(np.float64) + 0.5) / 2.0 ** 32
 
 
-def load_particles(n_nodes, u_nodes, grid: Grid, sch: Scheme, shift: int):
+def load_particles(n_nodes, u_nodes, grid: Grid, sch: Scheme, shift: int, t_nodes=None):
     """Quiet start from fine node profiles (App. C, particle loading).
 
     Every occupied cell c (some node density above n_floor) receives ppc ions
@@ -236,8 +243,10 @@ def load_particles(n_nodes, u_nodes, grid: Grid, sch: Scheme, shift: int):
     Velocities take the inverse CDF of a shifted Maxwellian of thermal speed
     vth at the second coordinate b_i (global index i = c ppc + m), and weights
     are the density at the particle, w = n(X) h / ppc, with n and u linearly
-    interpolated between the two nodes of the cell.  Returns FP64 arrays
-    (cell, frac, v, w) in cell order; frac is the FP32 value promoted.
+    interpolated between the two nodes of the cell.  With a node temperature
+    profile t_nodes (three moments), the thermal speed of each ion is
+    sqrt(T(X)), T linear in the cell like n and u, instead of vth.  Returns FP64
+    arrays (cell, frac, v, w) in cell order; frac is the FP32 value promoted.
     """
     n_nodes = np.maximum(np.asarray(n_nodes, dtype=np.float64), 0.0)
     u_nodes = np.asarray(u_nodes, dtype=np.float64)
@@ -255,7 +264,12 @@ def load_particles(n_nodes, u_nodes, grid: Grid, sch: Scheme, shift: int):
     u_l, u_r = u_nodes[cell], u_nodes[right[cell]]
     nx = (1.0 - frac) * n_l + frac * n_r
     ux = (1.0 - frac) * u_l + frac * u_r
-    v = ux + sch.vth * ndtri(b)
+    if t_nodes is None:
+        sigma = sch.vth
+    else:
+        t_nodes = np.asarray(t_nodes, dtype=np.float64)
+        sigma = np.sqrt(np.maximum((1.0 - frac) * t_nodes[cell] + frac * t_nodes[right[cell]], 0.0))
+    v = ux + sigma * ndtri(b)
     w = nx * grid.h / sch.ppc
     return cell, frac, v, w
 
@@ -270,15 +284,32 @@ def velocity_profile(n_nodes, j_nodes, sch: Scheme):
     return u
 
 
+def temperature_profile(n_nodes, j_nodes, s_nodes, sch: Scheme):
+    """Ion temperature T = s / n - u^2 (the pressure over the density, P = s - n u^2)
+    where the density exceeds n_floor, clipped at 0; else 0."""
+    n = np.maximum(np.asarray(n_nodes, dtype=np.float64), 0.0)
+    j = np.asarray(j_nodes, dtype=np.float64)
+    s = np.asarray(s_nodes, dtype=np.float64)
+    t = np.zeros_like(n)
+    ok = n > sch.n_floor
+    u = j[ok] / n[ok]
+    t[ok] = np.maximum(s[ok] / n[ok] - u * u, 0.0)
+    return t
+
+
 def block_correct(cell, v, w, coarse, grid: Grid, sch: Scheme):
-    """Per-block mass and momentum correction of lifted particles.
+    """Per-block mass and momentum (and second-moment) correction of lifted particles.
 
     Block B holds the particles of cells c with c >> l = B.  Its weights are
-    rescaled so that their sum is the block mass h 2^{l/2} max(c^n_B, 0), then
+    rescaled so that their sum is the block mass M = h 2^{l/2} max(c^n_B, 0), then
     its velocities are shifted so that sum w v is the block momentum
-    h 2^{l/2} c^j_B (the "Maxwellian-corrected" resampling; the negative values
-    of the remark in Sec. 3.3 are clipped).  Blocks without particles or mass
-    are left unchanged.
+    J = h 2^{l/2} c^j_B (the "Maxwellian-corrected" resampling; the negative values
+    of the remark in Sec. 3.3 are clipped).  With three coarse moments the
+    velocities are also stretched about the block's mean velocity so that
+    sum w v^2 is the block's second moment S = h 2^{l/2} c^s_B: with the rescaled
+    weights, mean velocity u_g and spread G = sum w (v - u_g)^2 of the loaded
+    ions, v <- J / M + a (v - u_g), a = sqrt(max(S - J^2 / M, 0) / G).  Blocks
+    without particles or mass are left unchanged.
     """
     coarse = np.asarray(coarse, dtype=np.float64)
     nb = grid.n_cells >> sch.levels
@@ -294,18 +325,34 @@ def block_correct(cell, v, w, coarse, grid: Grid, sch: Scheme):
     ratio[ok] = mass_t[ok] / s[ok]
     w = w * ratio[blk]
     p = np.bincount(blk, weights=w * v, minlength=nb)
-    dv = np.zeros(nb)
     okm = mass_t > 0.0
-    dv[okm] = (mom_t[okm] - p[okm]) / mass_t[okm]
-    v = v + dv[blk]
+    if coarse.shape[0] < 3:
+        dv = np.zeros(nb)
+        dv[okm] = (mom_t[okm] - p[okm]) / mass_t[okm]
+        return v + dv[blk], w
+    second_t = coarse[2] * scale
+    u_g = np.zeros(nb)
+    u_t = np.zeros(nb)
+    u_g[okm] = p[okm] / mass_t[okm]
+    u_t[okm] = mom_t[okm] / mass_t[okm]
+    spread = np.bincount(blk, weights=w * (v - u_g[blk]) ** 2, minlength=nb)
+    a = np.ones(nb)
+    oks = okm & (spread > 0.0)
+    a[oks] = np.sqrt(np.maximum(second_t[oks] - mom_t[oks] ** 2 / mass_t[oks], 0.0) / spread[oks])
+    moved = okm[blk]
+    v = np.where(moved, u_t[blk] + a[blk] * (v - u_g[blk]), v)
     return v, w
 
 
 def lift(coarse, grid: Grid, sch: Scheme, shift: int, correct=True):
-    """Lifting operator: coarse coefficients -> quiet-start particles (Sec. 3.3, App. C)."""
-    n_f, j_f = lift_profile(coarse, grid, sch)
-    u_f = velocity_profile(n_f, j_f, sch)
-    cell, frac, v, w = load_particles(n_f, u_f, grid, sch, shift)
+    """Lifting operator: coarse coefficients -> quiet-start particles (Sec. 3.3, App. C).
+
+    With three coarse moments the loaded Maxwellian takes the local temperature
+    of the profiles (EFREE, Sec. 3.2) instead of the fixed vth."""
+    prof = lift_profile(coarse, grid, sch)
+    u_f = velocity_profile(prof[0], prof[1], sch)
+    t_f = temperature_profile(*prof, sch) if len(prof) > 2 else None
+    cell, frac, v, w = load_particles(prof[0], u_f, grid, sch, shift, t_f)
     if correct:
         v, w = block_correct(cell, v, w, coarse, grid, sch)
     return cell, frac, v, w
@@ -339,7 +386,7 @@ def pic_burst(x, v, w, grid: Grid, sch: Scheme, steps=None, alive=None, phi0=Non
         tau = sch.macro_dt - p * grid.dt
         en_x = pic.gather(e_n, x[alive], grid)
         snaps.append(restrict_snapshot(x[alive], vp, en_x, w[alive], tau, grid,
-                                       sch.levels, sch.coevolving))
+                                       sch.levels, sch.coevolving, sch.moments))
         if p < ne:
             x, vh, alive = pic.leapfrog_step(x, vh, w, alive, e, grid)
             _, phi, e = pic.field_from_particles(x, w, alive, grid, phi)
@@ -361,7 +408,8 @@ def macro_step(coarse, grid: Grid, sch: Scheme, shift: int, phi0=None):
 def restrict_state(x, v, w, alive, grid: Grid, sch: Scheme):
     """Plain restriction (tau = 0) of a particle state: the coarse variables at that time."""
     z = np.zeros(int(np.sum(alive)))
-    return restrict_snapshot(x[alive], v[alive], z, w[alive], 0.0, grid, sch.levels, False)
+    return restrict_snapshot(x[alive], v[alive], z, w[alive], 0.0, grid, sch.levels, False,
+                             sch.moments)
 
 
 def ensemble_mean(coarse_list):

@@ -366,3 +366,94 @@ def test_lift_profile_linear_between_block_centres():
     # and the piecewise-constant inverse Haar without the flag
     n, _ = efpi.lift_profile(coarse, Grid(8, 8.0), efpi.Scheme(levels=2, lift_linear=False))
     assert np.allclose(n, [1.0] * 4 + [3.0] * 4, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------- EFREE second moment ---
+
+def _efree_coarse(nc, levels, seed, t_range=(0.05, 0.2)):
+    """Three coarse moments of positive density and temperature: c^s = (c^j)^2 / c^n
+    + c^n T for block means n, j and a block temperature T."""
+    c = synth.random_coarse(nc, seed=seed, levels=levels)
+    t = np.random.default_rng(seed + 1).uniform(*t_range, nc)
+    return np.stack([c[0], c[1], c[1] ** 2 / c[0] + c[0] * t]), t
+
+
+def test_second_moment_restriction_by_hand():
+    # tau = 0, l = 0: node charge / h with CIC; two ions in an 8-cell periodic grid
+    g = Grid(8, 8.0)
+    x = np.array([1.25, 6.5])
+    v = np.array([2.0, -1.0])
+    w = np.array([0.5, 2.0])
+    out = efpi.restrict_snapshot(x, v, np.zeros(2), w, 0.0, g, 0, False, moments=3)
+    assert out.shape == (3, 8)
+    want_s = np.zeros(8)
+    want_s[1], want_s[2] = 0.75 * 0.5 * 4.0, 0.25 * 0.5 * 4.0     # w v^2 = 2 split 3/4, 1/4
+    want_s[6], want_s[7] = 0.5 * 2.0, 0.5 * 2.0                   # w v^2 = 2 split in half
+    assert np.allclose(out[2], want_s, rtol=0, atol=1e-15)
+    # the first two rows are the two-moment restriction
+    assert np.array_equal(out[:2], efpi.restrict_snapshot(x, v, np.zeros(2), w, 0.0, g, 0, False))
+
+
+def test_temperature_profile_by_hand():
+    sch = efpi.Scheme(n_floor=1e-3)
+    n = np.array([2.0, 1.0, 1e-4, 4.0])
+    j = np.array([1.0, 0.5, 0.0, -2.0])
+    s = np.array([2.5, 0.2, 1.0, 1.0])
+    # T = s/n - (j/n)^2: 1.25 - 0.25; 0.2 - 0.25 < 0 -> 0; below the floor -> 0; 0.25 - 0.25
+    assert np.allclose(efpi.temperature_profile(n, j, s, sch), [1.0, 0.0, 0.0, 0.0], atol=1e-15)
+
+
+def test_load_particles_with_a_temperature_profile_by_hand():
+    from scipy.special import ndtri
+    g = Grid(4, 8.0)
+    sch = efpi.Scheme(ppc=2, vth=123.0)        # vth is not used with a temperature profile
+    t = np.array([0.04, 0.36, 1.0, 0.16])
+    shift = 12345
+    cell, frac, v, w = efpi.load_particles(HAND_N, HAND_U, g, sch, shift, t)
+    b = efpi.hammersley_b(np.arange(8, dtype=np.uint64), shift)
+    # T linear in the cell (cell 3 takes node 0 on the right), sigma = sqrt(T)
+    t_at = [0.12, 0.28, 0.52, 0.84, 0.79, 0.37, 0.13, 0.07]
+    u_at = [0.025, -0.125, -0.05, 0.25, 0.3, 0.1, 0.025, 0.075]
+    assert np.allclose(v, np.array(u_at) + np.sqrt(t_at) * ndtri(b), rtol=0, atol=1e-14)
+
+
+def test_efree_block_correction_exact():
+    n, lv = 128, 3
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(levels=lv, ppc=50, moments=3)
+    coarse, _ = _efree_coarse(n >> lv, lv, 19)
+    cell, frac, v, w = efpi.lift(coarse, g, sch, synth.lift_shift(19))
+    blk = cell >> lv
+    scale = g.h * 2 ** (lv / 2)
+    assert np.allclose(np.bincount(blk, weights=w), coarse[0] * scale, rtol=1e-12)
+    assert np.allclose(np.bincount(blk, weights=w * v), coarse[1] * scale, rtol=1e-10, atol=1e-12)
+    assert np.allclose(np.bincount(blk, weights=w * v * v), coarse[2] * scale, rtol=1e-10)
+
+
+def test_efree_lift_carries_the_block_temperature():
+    # a uniform plasma at rest with a temperature that differs from vth^2: the loaded
+    # spread follows the coarse second moment, not vth
+    n, lv, ppc = 256, 4, 400
+    g = Grid(n, float(n))
+    sch = efpi.Scheme(levels=lv, ppc=ppc, moments=3, vth=0.3)
+    nc = n >> lv
+    scale = 2.0 ** (lv / 2)
+    coarse = np.stack([np.full(nc, scale), np.full(nc, 0.2 * scale),
+                       np.full(nc, (0.04 + 0.5) * scale)])       # u = 0.2, T = 0.5
+    cell, frac, v, w = efpi.lift(coarse, g, sch, synth.lift_shift(3), correct=False)
+    assert np.mean(v) == pytest.approx(0.2, abs=2e-3)
+    assert np.sqrt(np.mean((v - 0.2) ** 2)) == pytest.approx(np.sqrt(0.5), rel=5e-3)
+    x = efpi.particles_to_x(cell, frac, g)
+    back = efpi.restrict_state(x, v, w, np.ones(x.size, bool), g, sch)
+    assert metrics.rel_l2(back[2], coarse[2]) < 2e-3
+
+
+def test_efree_snapshots_equal_in_free_streaming():
+    # App. B with E = 0 for the second moment too: V~ = V, so w V~^2 moves with X~
+    g = Grid(64, 64.0, closure=NOFIELD)
+    sch = efpi.Scheme(levels=2, burst_steps=6, macro_dt=3.0, ppc=32, moments=3)
+    nn, uu = synth.iaw_profile(64, 64.0)
+    cell, frac, v, w = efpi.load_particles(nn, uu, g, sch, synth.lift_shift(5))
+    snaps, *_ = efpi.pic_burst(efpi.particles_to_x(cell, frac, g), v, w, g, sch)
+    assert snaps.shape[1] == 3
+    assert np.max(np.abs(snaps - snaps[0])) < 1e-10
