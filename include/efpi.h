@@ -64,9 +64,10 @@ typedef enum {
 #define EFPI_DEV_NAN 2u      /* non-finite potential or coarse value             */
 #define EFPI_DEV_OVERFLOW 4u /* lift wanted more particles than capacity         */
 #define EFPI_DEV_NEGMASS 8u  /* projected block mass below zero (clipped at lift) */
-#define EFPI_DEV_WEIGHT 16u  /* an ion weight |w| (or snapshot momentum |w V|)
-                                >= 16: the exact per-lane charge sums of the
-                                particle pass need values below 16               */
+#define EFPI_DEV_WEIGHT 16u  /* an ion weight |w| (or snapshot moment |w V|, or
+                                |w V^2| with EFPI_FLAG_PRESSURE) >= 16: the exact
+                                per-lane sums of the particle pass need values
+                                below 16                                         */
 
 /* Boundary conditions and closures. */
 #define EFPI_BC_PERIODIC 0
@@ -124,6 +125,17 @@ typedef struct {
 
 /* Reserve a second particle store so that efpi_sort can reorder out of place. */
 #define EFPI_FLAG_SORT_BUFFER 1u
+/* EFREE coarse variables (Sec. 3.2): three moments per replica instead of two.
+ * Besides the density n and the momentum density j = nV, the coarse state carries
+ * the second velocity moment s = nV^2 + P (P = nT, the ion pressure), restricted
+ * along the co-evolving frame like the others (sum w V~^2 by CIC at X~).  The lift
+ * loads each ion with the local thermal speed sqrt(T(X)), T = s/n - u^2 at the
+ * fine nodes (clipped at 0, 0 below n_floor) linear in the cell, instead of vth,
+ * and the block correction also stretches velocities about the block's mean so
+ * that sum w v^2 meets the block's second moment.  Every coarse array below is
+ * then [R][3][N_c] (moments n, j, s) where it reads [R][2][N_c].  Not with
+ * EFPI_CLOSURE_KINETIC. */
+#define EFPI_FLAG_PRESSURE 2u
 
 typedef struct efpi_ctx efpi_ctx; /* opaque host object owned by the library */
 
@@ -182,7 +194,8 @@ efpi_status efpi_set_potential(efpi_ctx* ctx, int32_t replica, const double* d_p
  * velocity d_u (FP64, N or N+1 nodes): App. C particle loading with uniform
  * in-cell offsets (m+1/2)/ppc, Maxwellian velocities by the inverse normal CDF at
  * the Hammersley coordinate b_i = ((bitrev32(c ppc + m) + shift) mod 2^32 + 1/2)/2^32,
- * and weights n(X) h / ppc.  Cells whose nodes are all below n_floor stay empty. */
+ * and weights n(X) h / ppc.  Cells whose nodes are all below n_floor stay empty.
+ * The thermal speed is the configured vth, also with EFPI_FLAG_PRESSURE. */
 efpi_status efpi_load_profile(efpi_ctx* ctx, int32_t replica, const double* d_n,
                               const double* d_u, uint32_t shift);
 
@@ -191,7 +204,10 @@ efpi_status efpi_load_profile(efpi_ctx* ctx, int32_t replica, const double* d_n,
  * inverse Haar (and linear interpolation of block means when lift_linear) ->
  * quiet-start ions as in efpi_load_profile with rotation h_shifts[r] -> per
  * coarse block, weights rescaled to the block mass and velocities shifted to
- * the block momentum.  d_coarse must stay valid until the work has run. */
+ * the block momentum.  With EFPI_FLAG_PRESSURE (d_coarse[r][3][N_c]) the thermal
+ * speed is sqrt(T) of the fine temperature profile and velocities are also
+ * stretched about the block mean to the block's second moment.  d_coarse must
+ * stay valid until the work has run. */
 efpi_status efpi_lift(efpi_ctx* ctx, const double* d_coarse, const uint32_t* h_shifts);
 
 /* Deposit the fixed-point CIC charge of the current particles (Sec. 2.2): ion

@@ -109,6 +109,7 @@ struct efpi_ctx {
   int32_t* d_group = nullptr;
   bool kinetic = false;             // kinetic electrons (every replica)
   bool lift_deposit = false;        // the lift deposits the ions' charge itself
+  int moments = 2;                  // coarse moments per replica (3: EFPI_FLAG_PRESSURE)
   int max_nodes = 0;                // largest node count of the replicas
   std::vector<RepDev> h_ereps;      // electron descriptors (kinetic contexts)
   RepDev* d_ereps = nullptr;
@@ -188,6 +189,11 @@ efpi_status check_config(const efpi_config* cfg) {
   if (cfg->tile != 0 && (cfg->tile % 1024 != 0 || cfg->tile < 1024 || cfg->tile > 16384))
     return fail(EFPI_EINVAL, "tile must be 0 or a multiple of 1024 in [1024, 16384]");
   if (cfg->grid_blocks < 0) return fail(EFPI_EINVAL, "grid_blocks must be >= 0");
+  if ((cfg->flags & ~(EFPI_FLAG_SORT_BUFFER | EFPI_FLAG_PRESSURE)) != 0)
+    return fail(EFPI_EINVAL, "unknown flags");
+  if ((cfg->flags & EFPI_FLAG_PRESSURE) && cfg->replicas &&
+      cfg->replicas[0].closure == EFPI_CLOSURE_KINETIC)
+    return fail(EFPI_EINVAL, "EFPI_FLAG_PRESSURE is not supported with kinetic electrons");
   for (uint32_t r = 0; r < cfg->n_replicas; ++r) {
     const efpi_replica& p = cfg->replicas[r];
     char buf[160];
@@ -250,12 +256,13 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
   const bool kinetic = cfg->replicas[0].closure == EFPI_CLOSURE_KINETIC;
   uint8_t* p_ereps = kinetic ? take(sizeof(RepDev) * R) : nullptr;
   uint8_t* p_eitems = kinetic ? take(sizeof(int64_t) * (R + 1)) : nullptr;
+  const int nm = (cfg->flags & EFPI_FLAG_PRESSURE) ? 3 : 2;  // coarse moments per replica
   int64_t snap_total = 0, coarse_total = 0;
   for (int r = 0; r < R; ++r) {
     const efpi_replica& p = cfg->replicas[r];
     const int nc = p.n_cells >> p.haar_levels;
-    snap_total += (int64_t)(p.burst_steps + 1) * 2 * nc;
-    coarse_total += 2 * nc;
+    snap_total += (int64_t)(p.burst_steps + 1) * nm * nc;
+    coarse_total += nm * nc;
   }
   uint8_t* p_snap = take(sizeof(double) * snap_total);
   uint8_t* p_coarse = take(sizeof(double) * coarse_total);
@@ -289,6 +296,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     ctx->coarse_total = coarse_total;
     ctx->h_reps.assign(R, RepDev{});
     ctx->kinetic = kinetic;
+    ctx->moments = nm;
     // the lift's fused deposit holds a block's nodes in LDS: blocks of at most
     // 2^kLiftMaxDepositLevels cells (kinetic contexts deposit both species after
     // the electron load anyway)
@@ -324,9 +332,10 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
     uint8_t* phi = take(sizeof(double) * (nn + 1));
     uint8_t* e = take(sizeof(float) * (nn + 1));
     uint8_t* en = take(sizeof(float) * (nn + 1));
-    uint8_t* rb = take(sizeof(int64_t) * (int64_t)(p.burst_steps + 1) * 2 * nc);
+    uint8_t* rb = take(sizeof(int64_t) * (int64_t)(p.burst_steps + 1) * nm * nc);
     uint8_t* pn = take(sizeof(double) * (nn + 1));
     uint8_t* pu = take(sizeof(double) * (nn + 1));
+    uint8_t* pt = nm == 3 ? take(sizeof(double) * (nn + 1)) : nullptr;
     uint8_t* cor = take(sizeof(int32_t) * n);
     uint8_t* br = take(sizeof(int32_t) * (nc + 1));
     uint8_t* aux = take(sizeof(int64_t) * 4);
@@ -364,6 +373,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
       d.ppc = p.ppc;
       d.levels = p.haar_levels;
       d.n_coarse = nc;
+      d.moments = nm;
       d.burst_steps = p.burst_steps;
       d.coevolving = p.coevolving;
       d.lift_linear = p.lift_linear;
@@ -400,6 +410,7 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
       d.coarse_tmp = ctx->d_coarse + coff;
       d.prof_n = reinterpret_cast<double*>(pn);
       d.prof_u = reinterpret_cast<double*>(pu);
+      d.prof_t = reinterpret_cast<double*>(pt);
       d.cell_of_rank = reinterpret_cast<int32_t*>(cor);
       d.block_rank = reinterpret_cast<int32_t*>(br);
       d.aux = reinterpret_cast<int64_t*>(aux);
@@ -428,8 +439,8 @@ size_t layout(const efpi_config* cfg, efpi_ctx* ctx, uint8_t* base) {
         el.aux = reinterpret_cast<int64_t*>(eaux);
       }
     }
-    soff += (int64_t)(p.burst_steps + 1) * 2 * nc;
-    coff += 2 * nc;
+    soff += (int64_t)(p.burst_steps + 1) * nm * nc;
+    coff += nm * nc;
   }
   return off;
 }
@@ -579,7 +590,7 @@ efpi_status do_burst(efpi_ctx* c, int steps, bool restrict_) {
     const bool push = p < steps;
     int flags = 0;
     if (p == 0 && c->fresh) flags |= kFresh;
-    if (restrict_) flags |= kRestrict;
+    if (restrict_) flags |= kRestrict | (c->moments == 3 ? kMoment3 : 0);
     if (push) {
       flags |= kPush;
       deposit_into_next(c);
@@ -668,8 +679,8 @@ efpi_status efpi_init(const efpi_config* cfg, void* d_workspace, size_t bytes, v
     c->h_block_prefix[r + 1] = c->h_block_prefix[r] + d.n_coarse;
     c->h_snap_off[r] = so;
     c->h_coarse_off[r] = co;
-    so += (int64_t)(d.burst_steps + 1) * 2 * d.n_coarse;
-    co += 2 * d.n_coarse;
+    so += (int64_t)(d.burst_steps + 1) * d.moments * d.n_coarse;
+    co += d.moments * d.n_coarse;
   }
   c->total_items = c->h_item_prefix[c->R];
   if (c->kinetic) {
@@ -1137,7 +1148,9 @@ efpi_status efpi_restrict_state(efpi_ctx* ctx, double* d_coarse) {
     return fail(EFPI_ESTATE, "restrict_state needs integer-time velocities or a current field");
   launch_prep_burst(ctx->d_reps, ctx->R, ctx->stream);
   launch_particles(ctx->d_reps, ctx->d_item_prefix, ctx->R, ctx->total_items, ctx->tile,
-                   ctx->grid_blocks, -1, kRestrict | (ctx->fresh ? kFresh : 0), ctx->cur ^ 1,
+                   ctx->grid_blocks, -1,
+                   kRestrict | (ctx->fresh ? kFresh : 0) | (ctx->moments == 3 ? kMoment3 : 0),
+                   ctx->cur ^ 1,
                    ctx->d_status, ctx->stream);
   launch_restrict(ctx->d_reps, ctx->R, 0, d_coarse, ctx->d_coarse_off, ctx->stream);
   ctx->last_burst_steps = -1;

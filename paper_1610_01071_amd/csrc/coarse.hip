@@ -60,29 +60,34 @@ __device__ __forceinline__ float inv_normal(uint32_t u) {
 }
 
 // ---------------------------------------------------------------- profile --
-// Fine node density and mean velocity from the coarse coefficients: inverse
-// Haar with zero details (block means 2^{-l/2} c_B), optionally linearly
-// interpolated between block centres (periodic wrap; constant past the end
-// centres on walls).
+// Fine node density and mean velocity (and, with three moments, temperature)
+// from the coarse coefficients: inverse Haar with zero details (block means
+// 2^{-l/2} c_B), optionally linearly interpolated between block centres
+// (periodic wrap; constant past the end centres on walls).  The temperature is
+// T = s / n - u^2, clipped at 0, and 0 where the density is at most n_floor.
 __device__ void profile_of(const RepDev& R, const double* __restrict__ cn) {
-  const double* cj = cn + R.n_coarse;
   const int nc = R.n_coarse;
+  const double* cj = cn + nc;
+  const double* cs = cn + 2 * nc;
+  const bool third = R.moments == 3;
   const int bs = 1 << R.levels;
   const double inv_s = 1.0 / sqrt((double)bs);
   const bool periodic = R.bc == 0;
   for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) {
-    double dn, dj;
+    int b0, b1;
+    double w0, w1;
     if (!R.lift_linear) {
-      const int B = min(k >> R.levels, nc - 1);
-      dn = cn[B] * inv_s;
-      dj = cj[B] * inv_s;
+      b0 = b1 = min(k >> R.levels, nc - 1);
+      w0 = 1.0;
+      w1 = 0.0;
     } else {
       const double u = ((double)k - 0.5 * (bs - 1)) / (double)bs;
       const double fb = floor(u);
-      int b0 = (int)fb;
+      b0 = (int)fb;
       const double th = u - fb;
-      int b1 = b0 + 1;
-      double w0 = 1.0 - th, w1 = th;
+      b1 = b0 + 1;
+      w0 = 1.0 - th;
+      w1 = th;
       if (periodic) {
         b0 = (b0 % nc + nc) % nc;
         b1 = (b1 % nc + nc) % nc;
@@ -90,12 +95,18 @@ __device__ void profile_of(const RepDev& R, const double* __restrict__ cn) {
         if (b0 < 0) { b0 = 0; b1 = 0; w0 = 1.0; w1 = 0.0; }
         if (b1 > nc - 1) { b0 = nc - 1; b1 = nc - 1; w0 = 1.0; w1 = 0.0; }
       }
-      dn = (w0 * cn[b0] + w1 * cn[b1]) * inv_s;
-      dj = (w0 * cj[b0] + w1 * cj[b1]) * inv_s;
     }
+    const double dn = R.lift_linear ? (w0 * cn[b0] + w1 * cn[b1]) * inv_s : cn[b0] * inv_s;
+    const double dj = R.lift_linear ? (w0 * cj[b0] + w1 * cj[b1]) * inv_s : cj[b0] * inv_s;
     const double nn = fmax(dn, 0.0);
+    const bool ok = nn > R.n_floor;
+    const double u = ok ? dj / nn : 0.0;
     gmem(R.prof_n)[k] = nn;
-    gmem(R.prof_u)[k] = nn > R.n_floor ? dj / nn : 0.0;
+    gmem(R.prof_u)[k] = u;
+    if (third) {
+      const double ds = R.lift_linear ? (w0 * cs[b0] + w1 * cs[b1]) * inv_s : cs[b0] * inv_s;
+      gmem(R.prof_t)[k] = ok ? fmax(ds / nn - u * u, 0.0) : 0.0;
+    }
   }
 }
 
@@ -189,7 +200,10 @@ constexpr int kFracTable = 4096;
 // LDS with 16 slots per node (threads t and t + 16k share one) as integer-valued
 // binary64, as in the particle pass.
 constexpr int kLiftNodes = 65;
-constexpr int kLiftSlots = 16;
+#ifndef EFPI_LIFT_SLOTS
+#define EFPI_LIFT_SLOTS 16
+#endif
+constexpr int kLiftSlots = EFPI_LIFT_SLOTS;
 
 __device__ double block_sum(double x, double* s_red) {
   // fixed-order tree: waves by shuffles, then the wave totals in index order
@@ -220,7 +234,12 @@ __device__ __forceinline__ int find_rep(const int64_t* prefix, int n, int64_t it
 // j = t, t + kLiftThreads, ... and steps (j / ppc, m) without dividing.  Offsets are
 // (float)((m + 1/2) / ppc); n and u are linear in the cell from its two nodes;
 // v = u + vth z, w = n h / ppc, formed in FP32 (the stored precision), summed
-// over the block in binary64 in a fixed order.  With qsel >= 0 (every replica's
+// over the block in binary64 in a fixed order.  With three coarse moments and
+// coarse targets, the thermal speed is sqrt(T) with T linear in the cell, and the
+// velocities are also stretched about the block's mean velocity u_g: v <- a v +
+// (J / M - a u_g), a = sqrt(max(S - J^2 / M, 0) / G), G = sum w (v - u_g)^2 of the
+// rescaled weights, so that sum w v^2 meets the block's second moment S = h 2^{l/2}
+// c^s_B (a = 1 without spread).  With qsel >= 0 (every replica's
 // blocks of at most 64 cells) the ions' charge is deposited into R.q[qsel] as the
 // particle pass deposits it (the same fixed-point shares of the stored w and
 // offset), so the burst needs no separate deposit pass.
@@ -234,6 +253,7 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
   __shared__ double s_q[kLiftNodes][kLiftSlots];
   __shared__ int s_c[kLiftCache];
   __shared__ float s_nl[kLiftCache], s_dn[kLiftCache], s_ul[kLiftCache], s_du[kLiftCache];
+  __shared__ float s_tl[kLiftCache], s_dt[kLiftCache];
   __shared__ float s_frac[kFracTable];
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int r = only_rep >= 0 ? only_rep : find_rep(block_prefix, n_reps, item);
@@ -243,6 +263,8 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const auto cell_of_rank = gmem(R.cell_of_rank);
     const auto prof_n = gmem(R.prof_n);
     const auto prof_u = gmem(R.prof_u);
+    const auto prof_t = gmem(R.prof_t);
+    const bool third = coarse != nullptr && R.moments == 3;  // thermal speed from T
     const int rb0 = block_rank[B];
     const int rb1 = block_rank[B + 1];
     const int ppc = R.ppc;
@@ -264,6 +286,11 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
         s_dn[k] = (float)prof_n[cr] - nl;
         s_ul[k] = ul;
         s_du[k] = (float)prof_u[cr] - ul;
+        if (third) {
+          const float tl = (float)prof_t[c];
+          s_tl[k] = tl;
+          s_dt[k] = (float)prof_t[cr] - tl;
+        }
       }
     }
     if (table)
@@ -290,28 +317,33 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     };
     // ion (jr, m) of cell c at offset fr: velocity and weight before the correction
     auto ion = [&](int jr, int c, int m, float fr, float& v, float& w) {
-      float nl, dn, ul, du;
+      float nl, dn, ul, du, sig = vth;
       if (cached) {
         nl = s_nl[jr];
         dn = s_dn[jr];
         ul = s_ul[jr];
         du = s_du[jr];
+        if (third) sig = sqrtf(fmaxf(fmaf(fr, s_dt[jr], s_tl[jr]), 0.0f));
       } else {
         const int cr = right_node(R, c);
         nl = (float)prof_n[c];
         dn = (float)prof_n[cr] - nl;
         ul = (float)prof_u[c];
         du = (float)prof_u[cr] - ul;
+        if (third) {
+          const float tl = (float)prof_t[c];
+          sig = sqrtf(fmaxf(fmaf(fr, (float)prof_t[cr] - tl, tl), 0.0f));
+        }
       }
-      v = fmaf(vth, normal_of(c, m, ppc, shift), fmaf(fr, du, ul));
+      v = fmaf(sig, normal_of(c, m, ppc, shift), fmaf(fr, du, ul));
       w = fmaf(fr, dn, nl) * hp;
     };
     // the first kKeep ions of every thread keep (v, w) in registers
     constexpr int kKeep = EFPI_LIFT_KEEP;
     float keep_v[kKeep], keep_w[kKeep];
-    float ratio = 1.0f, dv = 0.0f;
+    float ratio = 1.0f, stretch = 1.0f, dv = 0.0f;
     if (coarse != nullptr) {
-      double sw = 0.0, swv = 0.0;
+      double sw = 0.0, swv = 0.0, swvv = 0.0;
       int jr = q0, m = m0;
 #pragma unroll
       for (int k = 0; k < kKeep; ++k) {
@@ -319,6 +351,7 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
           ion(jr, cell_at(jr), m, offset_at(m), keep_v[k], keep_w[k]);
           sw += (double)keep_w[k];
           swv += (double)keep_w[k] * (double)keep_v[k];
+          if (third) swvv += (double)keep_w[k] * (double)keep_v[k] * (double)keep_v[k];
         }
         advance(jr, m);
       }
@@ -328,17 +361,27 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
         ion(jr, cell_at(jr), m, offset_at(m), v, w);
         sw += (double)w;
         swv += (double)w * (double)v;
+        if (third) swvv += (double)w * (double)v * (double)v;
         advance(jr, m);
       }
       sw = block_sum(sw, s_red);
       swv = block_sum(swv, s_red);
+      if (third) swvv = block_sum(swvv, s_red);
       const double scale = R.h * sqrt((double)(1 << R.levels));
       const auto cc = gmem(coarse + coff[r]);
       const double mt = fmax(cc[B], 0.0) * scale;
       const double jt = cc[R.n_coarse + B] * scale;
       const double rd = sw > 0.0 ? mt / sw : 1.0;
       ratio = (float)rd;
-      if (mt > 0.0) dv = (float)((jt - rd * swv) / mt);
+      if (mt > 0.0 && !third) dv = (float)((jt - rd * swv) / mt);
+      if (mt > 0.0 && third) {
+        const double st = cc[2 * R.n_coarse + B] * scale;
+        const double ug = rd * swv / mt, ut = jt / mt;
+        const double spread = rd * (swvv - 2.0 * ug * swv + ug * ug * sw);
+        const double a = spread > 0.0 ? sqrt(fmax(st - jt * jt / mt, 0.0) / spread) : 1.0;
+        stretch = (float)a;
+        dv = (float)(ut - a * ug);
+      }
     }
     const auto cell = gmem(R.cell);
     const auto frac = gmem(R.frac);
@@ -352,7 +395,7 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
       const float ws = w * ratio;
       cell[s] = (int16_t)c;
       frac[s] = fr;
-      vel[s] = v + dv;
+      vel[s] = fmaf(stretch, v, dv);  // v + dv exactly when stretch = 1
       wgt[s] = ws;
       if (dep) {
         const double q = fx_charge(ws);
@@ -414,7 +457,7 @@ __global__ void k_restrict(const RepDev* __restrict__ reps, int steps, double* _
                            const int64_t* __restrict__ soff) {
   const RepDev& R = reps[blockIdx.y];
   const int nc = R.n_coarse;
-  const int64_t count = (int64_t)(steps + 1) * 2 * nc;
+  const int64_t count = (int64_t)(steps + 1) * R.moments * nc;
   const double scale = kFxInv / R.h / sqrt((double)(1 << R.levels));
   double* out = snap + soff[blockIdx.y];
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
@@ -449,12 +492,13 @@ __global__ void k_project(const RepDev* __restrict__ reps, const double* __restr
                           const int64_t* __restrict__ soff, double* __restrict__ out,
                           const int64_t* __restrict__ coff, uint32_t* __restrict__ status) {
   const RepDev& R = reps[blockIdx.y];
+  const int nk = R.moments * R.n_coarse;  // coefficients of one snapshot
   const int nc = R.n_coarse;
   const int ne = R.burst_steps;
   const double* s = snap + soff[blockIdx.y];
   double* o = out + coff[blockIdx.y];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
-    auto snapshot = [&](int p) { return s[(int64_t)p * 2 * nc + k]; };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nk; k += gridDim.x * blockDim.x) {
+    auto snapshot = [&](int p) { return s[(int64_t)p * nk + k]; };
     const double val = project_value(snapshot, ne, R.dt, R.macro_dt);
     o[k] = val;
     if (!(fabs(val) < 1e300)) atomicOr(status, 2u);
@@ -472,16 +516,17 @@ __global__ void k_restrict_project(const RepDev* __restrict__ reps, double* __re
                                    const int64_t* __restrict__ coff,
                                    uint32_t* __restrict__ status) {
   const RepDev& R = reps[blockIdx.y];
+  const int nk = R.moments * R.n_coarse;  // coefficients of one snapshot
   const int nc = R.n_coarse;
   const int ne = R.burst_steps;
   const double scale = kFxInv / R.h / sqrt((double)(1 << R.levels));
   const auto rb = gmem(R.rbins);
   double* s = snap + soff[blockIdx.y];
   double* o = out + coff[blockIdx.y];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nk; k += gridDim.x * blockDim.x) {
     // the snapshot value as k_restrict stores it (one rounded product)
-    auto snapshot = [&](int p) { return (double)rb[(int64_t)p * 2 * nc + k] * scale; };
-    for (int p = 0; p <= ne; ++p) s[(int64_t)p * 2 * nc + k] = snapshot(p);
+    auto snapshot = [&](int p) { return (double)rb[(int64_t)p * nk + k] * scale; };
+    for (int p = 0; p <= ne; ++p) s[(int64_t)p * nk + k] = snapshot(p);
     const double v = project_value(snapshot, ne, R.dt, R.macro_dt);
     o[k] = v;
     if (!(fabs(v) < 1e300)) atomicOr(status, 2u);
@@ -504,14 +549,15 @@ __global__ void k_project2(const RepDev* __restrict__ reps, const double* __rest
                            const int64_t* __restrict__ coff, uint32_t* __restrict__ status) {
 #pragma clang fp contract(off)
   const RepDev& R = reps[blockIdx.y];
+  const int nk = R.moments * R.n_coarse;  // coefficients of one snapshot
   const int nc = R.n_coarse;
   const int ne = R.burst_steps;
   const double* s = snap + soff[blockIdx.y];
   const int64_t co = coff[blockIdx.y];
   const double leap = R.macro_dt - ne * R.dt;
   const double w = slope_prev ? R.macro_dt / (2.0 * gap) : 0.0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * nc; k += gridDim.x * blockDim.x) {
-    auto snapshot = [&](int p) { return s[(int64_t)p * 2 * nc + k]; };
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nk; k += gridDim.x * blockDim.x) {
+    auto snapshot = [&](int p) { return s[(int64_t)p * nk + k]; };
     const double f = ls_slope_value(snapshot, ne, R.dt);
     const double last = snapshot(ne);
     const double euler = last + leap * f;
@@ -528,10 +574,10 @@ __global__ void k_project2(const RepDev* __restrict__ reps, const double* __rest
 __global__ void k_ensemble_mean(const RepDev* __restrict__ reps, int n_reps,
                                 const int32_t* __restrict__ group, double* __restrict__ coarse,
                                 const int64_t* __restrict__ coff) {
-  // one block row per group leader; members share n_cells, hence 2 N_c entries
+  // one block row per group leader; members share n_cells, hence moments N_c entries
   const int r = blockIdx.y;
   if (group[r] != r) return;
-  const int count = 2 * reps[r].n_coarse;
+  const int count = reps[r].moments * reps[r].n_coarse;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
     double acc = 0.0;
     int m = 0;

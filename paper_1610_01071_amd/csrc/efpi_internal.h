@@ -56,6 +56,7 @@ struct RepDev {
   int32_t ppc, levels, n_coarse, burst_steps;
   int32_t coevolving, lift_linear, log2n;
   int32_t field_m;       // rows per thread of the field solve (N / field_m <= 512 threads)
+  int32_t moments;       // coarse moments: 2 (n, j) or 3 (n, j, s: EFREE)
   double h, inv_h, length, vth, dt, macro_dt, n_floor;
   int64_t capacity;
   int64_t item_begin;    // first particle work item of this replica
@@ -76,12 +77,13 @@ struct RepDev {
   float* e;              // node field E^p
   float* en;             // field stored at the start of the burst (App. B step 1)
   // coarse
-  int64_t* rbins;        // [K+1][2][N_c] fixed-point block sums of the snapshots
-  double* snap;          // [K+1][2][N_c] snapshots (internal macro step)
-  double* coarse_tmp;    // [2][N_c]
+  int64_t* rbins;        // [K+1][moments][N_c] fixed-point block sums of the snapshots
+  double* snap;          // [K+1][moments][N_c] snapshots (internal macro step)
+  double* coarse_tmp;    // [moments][N_c]
   // lift
   double* prof_n;        // [N+1] fine density
   double* prof_u;        // [N+1] fine mean velocity
+  double* prof_t;        // [N+1] fine temperature (three moments only)
   int32_t* cell_of_rank; // [N] occupied cells in order
   int32_t* block_rank;   // [N_c + 1] first occupied-cell rank of every block
   int64_t* aux;          // [4] per-replica scratch: [0] absorbed ions of a sort, [1] lift rotation
@@ -100,7 +102,8 @@ enum : int {
   kFresh = 1,      // velocities are at an integer time level (first pass after load)
   kRestrict = 2,   // deposit snapshot p along the approximate characteristics
   kPush = 4,       // leapfrog step and deposit of the new charge
-  kDepositOnly = 8 // deposit the charge of the current positions
+  kDepositOnly = 8, // deposit the charge of the current positions
+  kMoment3 = 16      // the snapshot also restricts the second velocity moment
 };
 
 // Launchers (defined in the kernel sources), all asynchronous on `stream`.

@@ -172,7 +172,7 @@ __device__ __forceinline__ void newton_body(const RepDev& R, NewtonLds& S, int i
   // load issued at the end would cost one more memory round trip there)
   const int n_nodes = R.n_nodes;
   const auto other = gmem(reinterpret_cast<long long*>(R.q[qsel ^ 1]));
-  const int n_bins = zero_bins ? (R.burst_steps + 1) * 2 * R.n_coarse : 0;
+  const int n_bins = zero_bins ? (R.burst_steps + 1) * R.moments * R.n_coarse : 0;
   const auto bins = gmem(reinterpret_cast<long long*>(R.rbins));
   const auto eg = gmem(R.e);
   const auto eng = gmem(R.en);
@@ -517,7 +517,7 @@ __global__ void k_prep_burst(const RepDev* __restrict__ reps) {
   const auto e = gmem(R.e);
   const auto en = gmem(R.en);
   for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) en[k] = e[k];
-  const int nb = (R.burst_steps + 1) * 2 * R.n_coarse;
+  const int nb = (R.burst_steps + 1) * R.moments * R.n_coarse;
   const auto rb = gmem(reinterpret_cast<long long*>(R.rbins));
   for (int k = threadIdx.x; k < nb; k += blockDim.x) rb[k] = 0;
 }
@@ -679,7 +679,7 @@ __device__ __forceinline__ void poisson_body(const RepDev& R, PoissonLds& S, int
   const auto other = gmem(reinterpret_cast<long long*>(R.q[qsel ^ 1]));
   for (int k = t; k < R.n_nodes; k += THREADS) other[k] = 0;
   if (zero_bins) {
-    const int nb = (R.burst_steps + 1) * 2 * R.n_coarse;
+    const int nb = (R.burst_steps + 1) * R.moments * R.n_coarse;
     const auto bins = gmem(reinterpret_cast<long long*>(R.rbins));
     for (int k = t; k < nb; k += THREADS) bins[k] = 0;
   }

@@ -1,6 +1,7 @@
 // Particle pass of the fine burst: field gather, leapfrog push, boundaries,
 // fixed-point CIC charge deposit (Sec. 2.2) and the co-evolving restriction
-// snapshot of the density and momentum moments (App. B, eqs. B.4-B.5), fused in
+// snapshot of the density and momentum moments (and, for the EFREE variables of
+// Sec. 3.2, the second velocity moment) (App. B, eqs. B.4-B.5), fused in
 // one streaming pass over the structure-of-arrays ion store.
 //
 // Work decomposition: every replica's particle slots are cut into tiles of
@@ -94,11 +95,15 @@ constexpr int kEBelow = 32;
 // kQSlots 2^40): flagged.
 constexpr float kWeightBound = (float)kQSlots;
 
+// NM: restricted moments (2: density and momentum; 3: and the second moment).
+template <int NM>
 struct WaveLds {
   float2 e[kENodes + 2];          // (E^p, E_n) at the window's nodes (one spare entry)
   double q[kQBins][kQSlots];      // fixed-point charge shares (integer-valued binary64)
-  double r[2][kRBins][kQSlots];   // fixed-point (density, momentum) shares per coarse block
+  double r[NM][kRBins][kQSlots];  // fixed-point moment shares per coarse block
 };
+template <int MODE>
+constexpr int kMoments = (MODE & kMoment3) != 0 ? 3 : 2;
 
 
 __device__ __forceinline__ int find_replica(const int64_t* prefix, int n, int64_t item) {
@@ -134,13 +139,14 @@ __device__ __forceinline__ void stv(EFPI_GLOBAL void* base, unsigned byte_off, T
 
 // The ions of one wave: `cnt` slots from `t0` of replica R.  MODE as in k_particles.
 template <int MODE, bool kPeriodic>
-__device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t t0,
-                                           unsigned cnt, int p, double pd, bool fresh, int qsel,
+__device__ __forceinline__ void wave_range(const RepDev& R, WaveLds<kMoments<MODE>>& L,
+                                           int64_t t0, unsigned cnt, int p, double pd, bool fresh, int qsel,
                                            bool& big) {
   constexpr bool restrict_ = (MODE & kRestrict) != 0;
   constexpr bool push = (MODE & kPush) != 0;
   constexpr bool deposit = push || (MODE & kDepositOnly) != 0;
   constexpr bool field = restrict_ || push;
+  constexpr int NM = kMoments<MODE>;
   const int lane = __lane_id();
   const int n = R.n_cells;
   const int nmask = n - 1;
@@ -160,7 +166,7 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
   EFPI_GLOBAL float* __restrict__ velp = gmem(R.v + t0);
   const EFPI_GLOBAL float* __restrict__ wp = gmem(R.w + t0);
   long long* qg = reinterpret_cast<long long*>(R.q[qsel]);
-  long long* rb = reinterpret_cast<long long*>(R.rbins) + (int64_t)(p < 0 ? 0 : p) * 2 * nc;
+  long long* rb = reinterpret_cast<long long*>(R.rbins) + (int64_t)(p < 0 ? 0 : p) * NM * nc;
   const float half_dt = 0.5f * dt;
   const float half_dt_r = fresh ? 0.f : half_dt;  // snapshot velocity v + half_dt_r E
   const float dt_push = fresh ? half_dt : dt;     // push: v + dt_push E
@@ -213,6 +219,7 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
   double* const qbin = &L.q[0][lane & (kQSlots - 1)];
   double* const rbin0 = &L.r[0][0][lane & (kQSlots - 1)];
   double* const rbin1 = &L.r[1][0][lane & (kQSlots - 1)];
+  double* const rbin2 = &L.r[NM - 1][0][lane & (kQSlots - 1)];  // NM = 3 only
 
   // one batch's raw vectors: kHalves x (4 cells, 4 offsets, 4 velocities, 4 weights)
   struct Raw {
@@ -341,28 +348,35 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
         // fixed-point mass and momentum with their CIC split, as the charge
         // deposit splits the charge: right share rint(theta q), left q - right
         const float wv = w * vt;
-        big |= in && !(fabsf(wv) < kWeightBound);
+        const float wvv = NM == 3 ? wv * vt : 0.f;
+        big |= in && !(fabsf(wv) < kWeightBound && fabsf(wvv) < kWeightBound);
         const double qm = fx_charge(w);
         const double qv = fx_charge(wv);
+        const double qs = NM == 3 ? fx_charge(wvv) : 0.0;
         const double thd = (double)th;
         const double qm_r = __builtin_rint(thd * qm), qv_r = __builtin_rint(thd * qv);
         const double qm_l = qm - qm_r, qv_l = qv - qv_r;
+        const double qs_r = NM == 3 ? __builtin_rint(thd * qs) : 0.0, qs_l = qs - qs_r;
         const int d = kPeriodic ? ((bl - rbase) & ncmask) : (bl - rbase);
         const bool inr = (unsigned)d < (unsigned)(kRBins - 1);
         if (in && inr) {
           lds_add(rbin0 + d * kQSlots, qm_l);
           lds_add(rbin1 + d * kQSlots, qv_l);
+          if (NM == 3) lds_add(rbin2 + d * kQSlots, qs_l);
           if (th != 0.f) {
             lds_add(rbin0 + (d + 1) * kQSlots, qm_r);
             lds_add(rbin1 + (d + 1) * kQSlots, qv_r);
+            if (NM == 3) lds_add(rbin2 + (d + 1) * kQSlots, qs_r);
           }
         } else if (in) {
           gatomic_add(rb + bl, rint_i64(qm_l));
           gatomic_add(rb + nc + bl, rint_i64(qv_l));
+          if (NM == 3) gatomic_add(rb + 2 * nc + bl, rint_i64(qs_l));
           if (th != 0.f) {
             const int br = kPeriodic ? ((bl + 1) & ncmask) : bl + 1;
             gatomic_add(rb + br, rint_i64(qm_r));
             gatomic_add(rb + nc + br, rint_i64(qv_r));
+            if (NM == 3) gatomic_add(rb + 2 * nc + br, rint_i64(qs_r));
           }
         }
       }
@@ -464,6 +478,21 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds& L, int64_t 
       const int blk = kPeriodic ? ((rbase + d) & ncmask) : (rbase + d);
       gatomic_add(rb + (int64_t)m * nc + blk, rint_i64(t));
     }
+    if (NM == 3) {
+      // the second-moment plane alone: bin b = lane % kRBins, the same way
+      constexpr int ns3 = kQSlots * kRBins / kWave;
+      const int b3 = lane & (kRBins - 1);
+      const int g3 = lane / kRBins;
+      double t3 = 0.0;
+#pragma unroll
+      for (int i = 0; i < ns3; ++i) t3 += L.r[NM - 1][b3][g3 * ns3 + ((i + b3) & (ns3 - 1))];
+#pragma unroll
+      for (int o = kRBins; o < kWave; o <<= 1) t3 += __shfl_xor(t3, o);
+      if (g3 == 0 && t3 != 0.0) {
+        const int blk = kPeriodic ? ((rbase + b3) & ncmask) : (rbase + b3);
+        gatomic_add(rb + 2 * (int64_t)nc + blk, rint_i64(t3));
+      }
+    }
   }
   wave_lds_sync();
 }
@@ -475,9 +504,9 @@ __global__ __launch_bounds__(kThreads)
 void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ item_prefix,
                  int n_reps, int64_t total_items, int tile, int p, double pd, int fresh_flag,
                  int qsel, uint32_t* __restrict__ status) {
-  __shared__ WaveLds lds[kWaves];
+  __shared__ WaveLds<kMoments<MODE>> lds[kWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  WaveLds& L = lds[wave];
+  WaveLds<kMoments<MODE>>& L = lds[wave];
   const bool fresh = fresh_flag != 0;
   const int64_t quarter = tile / kWaves;
   bool big = false;
@@ -559,9 +588,19 @@ void launch_particles(const RepDev* d_reps, const int64_t* d_item_prefix, int n_
   if (total_items <= 0) return;
   const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_items) : total_items;
   const int fresh = (flags & kFresh) ? 1 : 0;
-  const int mode = flags & (kRestrict | kPush | kDepositOnly);
+  int mode = flags & (kRestrict | kPush | kDepositOnly | kMoment3);
+  if ((mode & kRestrict) == 0) mode &= ~kMoment3;  // the second moment rides on a restriction
   const dim3 grid((unsigned)g);
   switch (mode) {
+    case kRestrict | kPush | kMoment3:
+      launch_mode<kRestrict | kPush | kMoment3>(grid, stream, ev0, ev1, d_reps, d_item_prefix,
+                                                n_reps, total_items, tile, p, fresh, qsel,
+                                                d_status);
+      break;
+    case kRestrict | kMoment3:
+      launch_mode<kRestrict | kMoment3>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps,
+                                        total_items, tile, p, fresh, qsel, d_status);
+      break;
     case kRestrict | kPush:
       launch_mode<kRestrict | kPush>(grid, stream, ev0, ev1, d_reps, d_item_prefix, n_reps,
                                      total_items, tile, p, fresh, qsel, d_status);

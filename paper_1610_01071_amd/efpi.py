@@ -21,6 +21,7 @@ ABI_VERSION = 2
 BC_PERIODIC, BC_WALLS = 0, 1
 CLOSURE_BOLTZMANN, CLOSURE_KINETIC, CLOSURE_NOFIELD = 0, 1, 2
 FLAG_SORT_BUFFER = 1
+FLAG_PRESSURE = 2  # three coarse moments (n, j, s): the EFREE variables of Sec. 3.2
 DEV_NEWTON, DEV_NAN, DEV_OVERFLOW, DEV_NEGMASS, DEV_WEIGHT = 1, 2, 4, 8, 16
 
 STATUS_NAMES = {0: "EFPI_OK", -1: "EFPI_EINVAL", -2: "EFPI_ENOMEM", -3: "EFPI_EHIP",
@@ -596,6 +597,7 @@ class Context:
         self.ctx = efpi_init(self.cfg, self.workspace, self.stream)
         self.device = self.workspace.device
         self.coarse_sizes = [r.n_coarse for r in spec.replicas]
+        self.moments = 3 if spec.flags & FLAG_PRESSURE else 2  # coarse moments per replica
 
     def close(self):
         if self.ctx is not None:
@@ -610,10 +612,10 @@ class Context:
 
     # layouts of the concatenated per-replica arrays
     def coarse_numel(self) -> int:
-        return sum(2 * nc for nc in self.coarse_sizes)
+        return sum(self.moments * nc for nc in self.coarse_sizes)
 
     def snap_numel(self) -> int:
-        return sum((r.burst_steps + 1) * 2 * r.n_coarse for r in self.spec.replicas)
+        return sum((r.burst_steps + 1) * self.moments * r.n_coarse for r in self.spec.replicas)
 
     def new_coarse(self):
         return torch.zeros(self.coarse_numel(), dtype=torch.float64, device=self.device)
@@ -624,15 +626,15 @@ class Context:
     def split_coarse(self, flat):
         out, o = [], 0
         for nc in self.coarse_sizes:
-            out.append(flat[o: o + 2 * nc].view(2, nc))
-            o += 2 * nc
+            out.append(flat[o: o + self.moments * nc].view(self.moments, nc))
+            o += self.moments * nc
         return out
 
     def split_snap(self, flat):
         out, o = [], 0
         for r in self.spec.replicas:
-            k = (r.burst_steps + 1) * 2 * r.n_coarse
-            out.append(flat[o: o + k].view(r.burst_steps + 1, 2, r.n_coarse))
+            k = (r.burst_steps + 1) * self.moments * r.n_coarse
+            out.append(flat[o: o + k].view(r.burst_steps + 1, self.moments, r.n_coarse))
             o += k
         return out
 

@@ -84,6 +84,16 @@ def random_coarse(n_coarse: int, seed: int, levels: int, mean_density: float = 1
     return np.stack([dens * scale, mom * dens * scale])
 
 
+def random_coarse_efree(n_coarse: int, seed: int, levels: int, t_range=(0.05, 0.2)):
+    """Three coarse moments (density n, momentum j, second moment s) of positive
+    density and temperature, shape (3, n_coarse): the two of random_coarse and
+    c^s = (c^j)^2 / c^n + c^n T for a block temperature T drawn uniformly in
+    t_range.  Also returns T."""
+    c = random_coarse(n_coarse, seed=seed, levels=levels)
+    t = rng(seed + 1).uniform(t_range[0], t_range[1], n_coarse)
+    return np.stack([c[0], c[1], c[1] ** 2 / c[0] + c[0] * t]), t
+
+
 def splitmix64(x: int) -> int:
     """SplitMix64 output for state x (Steele, Lea and Flood, 2014)."""
     z = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF

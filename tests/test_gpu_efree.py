@@ -1,0 +1,234 @@
+"""EFREE coarse variables (three moments n, j = nV, s = nV^2 + P; Sec. 3.2) on the
+GPU, through the C ABI, against the oracle on the same seeded inputs.
+
+Bars as for two moments: the restriction of a state within eps 1e-7 (fixed-point
+sums of FP32 ions against FP64); lifted cells and offsets bit-exact, velocities
+and weights within 1e-6 relative (FP32 against FP64, with the stretch of the
+block correction formed in binary64); the burst snapshots, the projected state
+and a macro step within eps = 1e-4 (eq. 4.2) on each moment and on the density's
+perturbation about its mean.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import efpi as oefpi
+from oracle import metrics
+from helpers import (lib, oracle_grid, oracle_scheme, to_dev, set_particles, particles_np,
+                     x_of, relmax)
+
+pytestmark = pytest.mark.gpu
+
+
+def make_ctx(specs, **kw):
+    E = lib()
+    return E.Context(E.ConfigSpec(list(specs), flags=E.FLAG_PRESSURE, **kw))
+
+
+def scheme3(spec):
+    sch = oracle_scheme(spec)
+    sch.moments = 3
+    return sch
+
+
+def pert_eps(a, b):
+    return metrics.rel_l2(a - a.mean(), b - b.mean())
+
+
+def iaw_particles(spec, seed, delta=0.2):
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    n, u = synth.iaw_profile(spec.n_cells, spec.length, delta, n_nodes=g.n_nodes)
+    c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(seed))
+    return (c.astype(np.int16), f.astype(np.float32), v.astype(np.float32), w.astype(np.float32))
+
+
+def test_context_layout():
+    E = lib()
+    spec = E.ReplicaSpec(256, 256.0, ppc=8, haar_levels=3, burst_steps=5)
+    ctx = make_ctx([spec])
+    assert ctx.moments == 3
+    assert ctx.coarse_numel() == 3 * 32
+    assert ctx.snap_numel() == 6 * 3 * 32
+    with pytest.raises(E.EfpiError):     # the second moment of kinetic runs is not built
+        make_ctx([E.ReplicaSpec(256, 256.0, closure=E.CLOSURE_KINETIC)])
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_restrict_state_matches_oracle(bc):
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, bc=bc, ppc=64, haar_levels=4, vth=0.3)
+    ctx = make_ctx([spec])
+    parts = iaw_particles(spec, 31)
+    set_particles(ctx, 0, *parts)
+    c = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c)
+    got = c.view(3, -1).cpu().numpy()
+    g, sch = oracle_grid(spec), scheme3(spec)
+    x = x_of(parts[0], parts[1], g.h)
+    ref = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                               np.ones(x.size, bool), g, sch)
+    assert ref.shape == (3, 32)
+    for m in range(3):
+        assert metrics.rel_l2(got[m], ref[m]) < 1e-7
+    assert E.efpi_sync(ctx.ctx, raise_on_error=False) == 0
+
+
+@pytest.mark.parametrize("n_cells,bc,levels,linear,ppc", [(256, 0, 3, 1, 64), (256, 0, 2, 0, 17),
+                                                          (512, 1, 4, 1, 40), (1024, 0, 6, 1, 9)])
+def test_lift_matches_oracle(n_cells, bc, levels, linear, ppc):
+    E = lib()
+    spec = E.ReplicaSpec(n_cells, float(n_cells), bc=bc, ppc=ppc, haar_levels=levels,
+                         lift_linear=linear, vth=0.25)
+    ctx = make_ctx([spec])
+    nc = n_cells >> levels
+    coarse, _ = synth.random_coarse_efree(nc, seed=41, levels=levels)
+    if bc == 1:
+        coarse[:, : nc // 4] = 0.0
+        coarse[:, -nc // 4:] = 0.0
+    shift = synth.lift_shift(41)
+    E.efpi_lift(ctx.ctx, to_dev(coarse.ravel(), torch.float64), [shift])
+    gc, gf, gv, gw = particles_np(ctx)
+    g, sch = oracle_grid(spec), scheme3(spec)
+    oc, of, ov, ow = oefpi.lift(coarse, g, sch, shift)
+    assert gc.size == oc.size
+    assert np.array_equal(gc.astype(np.int64), oc)
+    assert np.array_equal(gf, of.astype(np.float32))
+    assert relmax(gv, ov) < 1e-6
+    assert relmax(gw, ow) < 1e-6
+    # the stored ions meet every block's three moments
+    blk = gc.astype(np.int64) >> levels
+    scale = g.h * 2.0 ** (levels / 2.0)
+    w64, v64 = gw.astype(np.float64), gv.astype(np.float64)
+    for m, q in enumerate((w64, w64 * v64, w64 * v64 * v64)):
+        got = np.bincount(blk, weights=q, minlength=nc)
+        assert relmax(got, coarse[m] * scale) < 1e-5
+    assert E.efpi_sync(ctx.ctx, raise_on_error=False) == 0
+
+
+def test_lift_deposit_equals_the_deposit_pass():
+    E = lib()
+    spec = E.ReplicaSpec(1024, 1024.0, ppc=37, haar_levels=4, vth=0.3)
+    ctx = make_ctx([spec])
+    coarse, _ = synth.random_coarse_efree(64, seed=43, levels=4)
+    E.efpi_lift(ctx.ctx, to_dev(coarse.ravel(), torch.float64), [7])
+    q_lift = ctx.grid(0)[0].clone()
+    E.efpi_deposit(ctx.ctx)
+    q_pass = ctx.grid(0)[0].clone()
+    assert int(q_lift.abs().sum().item()) > 0
+    assert torch.equal(q_lift, q_pass)
+
+
+def _burst_compare(spec, parts, newton_iters=2):
+    E = lib()
+    ctx = make_ctx([spec], newton_iters=newton_iters)
+    set_particles(ctx, 0, *parts)
+    E.efpi_deposit(ctx.ctx)
+    E.efpi_solve_field(ctx.ctx, 100, cold=True)
+    E.efpi_pic_burst(ctx.ctx, spec.burst_steps, True)
+    snap = ctx.new_snap()
+    E.efpi_restrict(ctx.ctx, snap)
+    nxt = ctx.new_coarse()
+    E.efpi_project(ctx.ctx, snap, nxt)
+    E.efpi_sync(ctx.ctx)
+    gs = snap.view(spec.burst_steps + 1, 3, -1).cpu().numpy()
+    gn = nxt.view(3, -1).cpu().numpy()
+    g, sch = oracle_grid(spec), scheme3(spec)
+    cell, frac, v, w = parts
+    os_, *_ = oefpi.pic_burst(x_of(cell, frac, g.h), v.astype(np.float64), w.astype(np.float64),
+                              g, sch)
+    assert os_.shape[1] == 3
+    on = oefpi.project(os_, g.dt, sch.macro_dt)
+    for m in range(3):
+        assert metrics.rel_l2(gs[:, m].mean(axis=0), os_[:, m].mean(axis=0)) < 1e-4
+        assert metrics.rel_l2(gn[m], on[m]) < 1e-4
+    assert pert_eps(gn[0], on[0]) < 1e-4
+    assert pert_eps(gn[2], on[2]) < 1e-4
+
+
+@pytest.mark.parametrize("coev", [1, 0])
+def test_burst_restriction_periodic(coev):
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, ppc=100, haar_levels=4, burst_steps=20, macro_dt=20.0,
+                         coevolving=coev)
+    _burst_compare(spec, iaw_particles(spec, 32))
+
+
+def test_burst_restriction_walls():
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, bc=1, ppc=60, haar_levels=3, burst_steps=10, macro_dt=8.0,
+                         vth=0.1)
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    n, u = synth.slab_profile(spec.n_cells)
+    c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(33))
+    parts = (c.astype(np.int16), f.astype(np.float32), v.astype(np.float32), w.astype(np.float32))
+    _burst_compare(spec, parts, newton_iters=3)
+
+
+def test_macro_step_matches_oracle():
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, ppc=100, haar_levels=4, burst_steps=20, macro_dt=20.0)
+    ctx = make_ctx([spec])
+    g, sch = oracle_grid(spec), scheme3(spec)
+    parts = iaw_particles(spec, 34)
+    x = x_of(parts[0], parts[1], g.h)
+    c0 = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                              np.ones(x.size, bool), g, sch)
+    shift = synth.lift_shift(35)
+    cin = to_dev(c0.ravel(), torch.float64)
+    cout = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, cin, cout, [shift])
+    E.efpi_sync(ctx.ctx)
+    ref, _, _ = oefpi.macro_step(c0, g, sch, shift)
+    got = cout.view(3, -1).cpu().numpy()
+    for m in range(3):
+        assert metrics.rel_l2(got[m], ref[m]) < 1e-4
+    assert pert_eps(got[0], ref[0]) < 1e-4
+    cout2 = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, cin, cout2, [shift])
+    torch.cuda.synchronize()
+    assert torch.equal(cout, cout2)
+
+
+def test_macro_step_equals_composed_calls():
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, ppc=64, haar_levels=3, burst_steps=10, macro_dt=6.0,
+                         vth=0.316)
+    coarse, _ = synth.random_coarse_efree(64, seed=36, levels=3)
+    cin = to_dev(coarse.ravel(), torch.float64)
+    shift = synth.lift_shift(37)
+    a = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    out_a = a.new_coarse()
+    E.efpi_macro_step(a.ctx, cin, out_a, [shift])
+    b = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    E.efpi_lift(b.ctx, cin, [shift])
+    E.efpi_pic_burst(b.ctx, spec.burst_steps, True)
+    snap = b.new_snap()
+    E.efpi_restrict(b.ctx, snap)
+    out_b = b.new_coarse()
+    E.efpi_project(b.ctx, snap, out_b)
+    E.efpi_sync(a.ctx, raise_on_error=False)
+    E.efpi_sync(b.ctx, raise_on_error=False)
+    assert torch.equal(out_a, out_b)
+
+
+@pytest.mark.parametrize("wvv_big,flag", [(15.9, False), (16.0, True)])
+def test_second_moment_bound_flag(wvv_big, flag):
+    """|w V^2| at or above 16 sets EFPI_DEV_WEIGHT in the three-moment restriction."""
+    E = lib()
+    spec = E.ReplicaSpec(64, 64.0, ppc=4, haar_levels=2)
+    ctx = make_ctx([spec])
+    rng = np.random.default_rng(5)
+    n = 256
+    cell = np.sort(rng.integers(0, 64, n)).astype(np.int16)
+    frac = rng.random(n).astype(np.float32)
+    v = rng.normal(0.0, 0.1, n).astype(np.float32)
+    w = np.full(n, 0.25, np.float32)
+    w[100], v[100] = 1.0, np.float32(np.sqrt(np.float32(wvv_big)))
+    if wvv_big < 16.0:
+        assert w[100] * v[100] * v[100] < 16.0
+    set_particles(ctx, 0, cell, frac, v, w)
+    c = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c)
+    bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    assert bool(bits & E.DEV_WEIGHT) == flag

@@ -370,12 +370,9 @@ def test_lift_profile_linear_between_block_centres():
 
 # ---------------------------------------------------- EFREE second moment ---
 
-def _efree_coarse(nc, levels, seed, t_range=(0.05, 0.2)):
-    """Three coarse moments of positive density and temperature: c^s = (c^j)^2 / c^n
-    + c^n T for block means n, j and a block temperature T."""
-    c = synth.random_coarse(nc, seed=seed, levels=levels)
-    t = np.random.default_rng(seed + 1).uniform(*t_range, nc)
-    return np.stack([c[0], c[1], c[1] ** 2 / c[0] + c[0] * t]), t
+def _efree_coarse(nc, levels, seed):
+    """Three coarse moments of positive density and temperature."""
+    return synth.random_coarse_efree(nc, seed=seed, levels=levels)
 
 
 def test_second_moment_restriction_by_hand():
