@@ -177,6 +177,8 @@ def main():
                     help="the ensemble headline only (profiling runs)")
     ap.add_argument("--no-speedup", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-efree", action="store_true",
+                    help="skip the three-moment (EFREE) wave")
     ap.add_argument("--no-slab", action="store_true")
     ap.add_argument("--no-phase", action="store_true",
                     help="skip the phase-space (wavelet) coarse-variable runs")
@@ -388,6 +390,97 @@ def iaw_leg(args, np, torch, synth, E):
     return out, c0
 
 
+def efree_leg(E, torch, np, synth, args):
+    """EFREE coarse variables (Sec. 3.2: n, j = nV and s = nV^2 + P per block) on the
+    benchmark wave: the three-moment macro-step rate, and EFPI with three moments
+    against full PIC over the same horizon from the same lifted start, with eps
+    (eq. 4.2) at the horizon on the density, the second moment and the block
+    pressure P = s - j^2 / n."""
+    spec = workload_spec(E)
+    flags = E.FLAG_PRESSURE | E.FLAG_SORT_BUFFER
+    ctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4, tile=TILE,
+                                 flags=flags))
+    n_ions = spec.n_cells * spec.ppc
+    c0 = initial_coarse(E, ctx, spec, synth, torch)
+    c1 = ctx.new_coarse()
+    macro = lambda i: E.efpi_macro_step(ctx.ctx, c0, c1, [synth.lift_shift(50_000 + i)])
+    for i in range(3):
+        macro(i)
+    steps = 20
+    ms = timed(torch, lambda: [macro(3 + i) for i in range(steps)]) / steps
+    status = E.efpi_sync(ctx.ctx, raise_on_error=False)
+    ctx.close()
+    out = {"n_ions": n_ions, "ms_per_macro_step": ms,
+           "particle_updates_per_s": n_ions * spec.burst_steps / (ms * 1e-3),
+           "device_status": status}
+    if args.no_speedup:
+        return out
+
+    fine = int(round(args.horizon / spec.dt))
+    shift0 = synth.lift_shift(60_000)
+    pctx = E.Context(E.ConfigSpec([spec], newton_iters=2, newton_iters_start=4, tile=TILE,
+                                  flags=flags))
+
+    def pic_run():
+        E.efpi_lift(pctx.ctx, c0, [shift0])
+        done = 0
+        while done < fine:
+            k = min(args.sort_period, fine - done)
+            E.efpi_pic_burst(pctx.ctx, k, False)
+            done += k
+            if done < fine:
+                E.efpi_sort(pctx.ctx)
+
+    t_pic = timed(torch, pic_run)
+    c_pic = pctx.new_coarse()
+    E.efpi_restrict_state(pctx.ctx, c_pic)
+    pic_bits = E.efpi_sync(pctx.ctx, raise_on_error=False)
+    pctx.close()
+    ref = c_pic.view(3, -1).cpu().numpy()
+
+    def eps(a, b):
+        return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(a * a + b * b)))
+
+    def pressure(c):
+        return c[2] - c[1] ** 2 / c[0]
+
+    rows = []
+    for mult in (50, 75, 100, 200):
+        sp = workload_spec(E)
+        sp.macro_dt = mult * spec.dt
+        cx = E.Context(E.ConfigSpec([sp], newton_iters=2, newton_iters_start=4, tile=TILE,
+                                    flags=E.FLAG_PRESSURE))
+        m = int(round(args.horizon / sp.macro_dt))
+        a, b = cx.new_coarse(), cx.new_coarse()
+        a.copy_(c0)
+        state = {"a": a, "b": b}
+
+        def efpi_run():
+            for i in range(m):
+                sh = shift0 if i == 0 else synth.lift_shift(60_000 + i)
+                E.efpi_macro_step(cx.ctx, state["a"], state["b"], [sh])
+                state["a"], state["b"] = state["b"], state["a"]
+
+        t_efpi = timed(torch, efpi_run)
+        bits = E.efpi_sync(cx.ctx, raise_on_error=False)
+        got = state["a"].view(3, -1).cpu().numpy()
+        rows.append({"macro_dt_over_dt": mult, "macro_steps": m, "efpi_ms": t_efpi,
+                     "speedup": t_pic / t_efpi, "eps_density": eps(got[0], ref[0]),
+                     "eps_second_moment": eps(got[2], ref[2]),
+                     "eps_pressure": eps(pressure(got), pressure(ref)), "device_status": bits})
+        cx.close()
+    ok = [r for r in rows if r["eps_density"] <= args.eps_max and r["device_status"] == 0]
+    best = max(ok, key=lambda r: r["macro_dt_over_dt"]) if ok and pic_bits == 0 else None
+    out.update({
+        "efree_speedup_vs_pic": best["speedup"] if best else None,
+        "horizon": args.horizon, "eps_max": args.eps_max, "pic_fine_steps": fine,
+        "pic_ms": t_pic, "device_status_pic": pic_bits,
+        "fixed_error_macro_dt_over_dt": best["macro_dt_over_dt"] if best else None,
+        "sweep": rows,
+    })
+    return out
+
+
 def cfg1_leg(args, np, torch, synth, E):
     """Plain PIC of the small wave: L = 128, 128 cells, 200 ions per cell (25,600
     ions), 1000 steps, the cell sort every sort_period steps (autotuned)."""
@@ -449,6 +542,9 @@ def run_bench(args, np, torch, synth, E):
     _progress("iaw4096", t0)
     out["plain_pic_128"] = cfg1_leg(args, np, torch, synth, E)
     _progress("plain_pic_128", t0)
+    if not args.no_efree:
+        out["efree_iaw4096"] = efree_leg(E, torch, np, synth, args)
+        _progress("efree_iaw4096", t0)
     if not args.no_phase:
         out["phase_space"] = phase_leg(E, torch, np, synth, c0, args)
         out["phase_space_nv2048"] = phase_leg(E, torch, np, synth, c0, args, jf=11, jc=6)

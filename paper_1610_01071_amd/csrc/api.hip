@@ -548,7 +548,7 @@ efpi_status do_lift(efpi_ctx* c, const double* d_coarse, const uint32_t* h_shift
   if (c->lift_deposit) deposit_into_next(c);
   launch_lift_particles(c->d_reps, c->d_block_prefix, c->R, c->total_blocks, -1, d_coarse,
                         c->d_coarse_off, nullptr, c->grid_blocks, c->stream,
-                        c->lift_deposit ? c->cur ^ 1 : -1, c->d_status);
+                        c->lift_deposit ? c->cur ^ 1 : -1, c->d_status, c->moments == 3);
   if (c->kinetic) {
     load_boltzmann_electrons(c);
     mark_new_electrons(c);

@@ -243,6 +243,7 @@ __device__ __forceinline__ int find_rep(const int64_t* prefix, int n, int64_t it
 // blocks of at most 64 cells) the ions' charge is deposited into R.q[qsel] as the
 // particle pass deposits it (the same fixed-point shares of the stored w and
 // offset), so the burst needs no separate deposit pass.
+template <bool kThird>
 __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict__ reps,
                                                        const int64_t* __restrict__ block_prefix,
                                                        int n_reps, int64_t total, int only_rep,
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict_
     const auto prof_n = gmem(R.prof_n);
     const auto prof_u = gmem(R.prof_u);
     const auto prof_t = gmem(R.prof_t);
-    const bool third = coarse != nullptr && R.moments == 3;  // thermal speed from T
+    constexpr bool third = kThird;  // thermal speed from T (three moments, coarse targets)
     const int rb0 = block_rank[B];
     const int rb1 = block_rank[B + 1];
     const int ppc = R.ppc;
@@ -638,13 +639,18 @@ void launch_set_shifts(const RepDev* d_reps, int n_reps, int only_rep, const Shi
 void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
                            int64_t total_blocks, int only_rep, const double* d_coarse,
                            const int64_t* d_coff, const ShiftArg* shifts, int grid_blocks,
-                           hipStream_t stream, int qsel, uint32_t* d_status) {
+                           hipStream_t stream, int qsel, uint32_t* d_status, bool third) {
   if (total_blocks <= 0) return;
   if (shifts) launch_set_shifts(d_reps, n_reps, only_rep, *shifts, stream);
   const int64_t g = grid_blocks > 0 ? min((int64_t)grid_blocks, total_blocks) : total_blocks;
-  hipLaunchKernelGGL(k_lift, dim3((unsigned)g), dim3(kLiftThreads), 0, stream, d_reps,
-                     d_block_prefix, n_reps, total_blocks, only_rep, d_coarse, d_coff, qsel,
-                     d_status);
+  if (third && d_coarse != nullptr)
+    hipLaunchKernelGGL(k_lift<true>, dim3((unsigned)g), dim3(kLiftThreads), 0, stream, d_reps,
+                       d_block_prefix, n_reps, total_blocks, only_rep, d_coarse, d_coff, qsel,
+                       d_status);
+  else
+    hipLaunchKernelGGL(k_lift<false>, dim3((unsigned)g), dim3(kLiftThreads), 0, stream, d_reps,
+                       d_block_prefix, n_reps, total_blocks, only_rep, d_coarse, d_coff, qsel,
+                       d_status);
 }
 
 void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap,

@@ -159,12 +159,15 @@ void launch_set_shifts(const RepDev* d_reps, int n_reps, int only_rep, const Shi
 // Lift; with shifts == nullptr the rotations stored by launch_set_shifts are used.
 // qsel >= 0: also deposit the lifted ions' charge into R.q[qsel] (zeroed before),
 // which needs every replica's coarse blocks to be at most 64 cells wide
-// (lift_can_deposit); d_status receives EFPI_DEV_WEIGHT then.
+// (lift_can_deposit); d_status receives EFPI_DEV_WEIGHT then.  third (with
+// d_coarse): three coarse moments, thermal speeds from the temperature profile
+// and the second-moment stretch of the block correction.
 constexpr int kLiftMaxDepositLevels = 6;
 void launch_lift_particles(const RepDev* d_reps, const int64_t* d_block_prefix, int n_reps,
                            int64_t total_blocks, int only_rep, const double* d_coarse,
                            const int64_t* d_coff, const ShiftArg* shifts, int grid_blocks,
-                           hipStream_t stream, int qsel = -1, uint32_t* d_status = nullptr);
+                           hipStream_t stream, int qsel = -1, uint32_t* d_status = nullptr,
+                           bool third = false);
 void launch_restrict(const RepDev* d_reps, int n_reps, int steps, double* d_snap,
                      const int64_t* d_soff, hipStream_t stream);
 void launch_project(const RepDev* d_reps, int n_reps, const double* d_snap,
