@@ -179,6 +179,8 @@ def run_learned(ctx: E.Context, trainer: Trainer, norm: E.NnNorm, c0: torch.Tens
     judgement that failed.  This is the paper's remark on reverting to the fine
     solver when an error estimate fails (Sec. 3.1), applied to the learned steps.
     """
+    if ctx.moments != 2:
+        raise ValueError("the learned projection takes the two-moment coarse state (n, j)")
     thr_m = threshold if threshold_momentum is None else threshold_momentum
     nc = trainer.n_c
     nc2 = c0.numel()

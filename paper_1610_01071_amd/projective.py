@@ -89,7 +89,8 @@ def run_projective(ctx: E.Context, c0: torch.Tensor, t_end: float, macro_dt: flo
         E.efpi_project2(ctx.ctx, snap, prev, gap, slope[n % 2], euler, second)
         e = 0.0
         if prev is not None:
-            E.efpi_rel_l2(second[:nc2 // 2], euler[:nc2 // 2], eps, ctx.stream)
+            nd = nc2 // ctx.moments  # the density coefficients lead the state
+            E.efpi_rel_l2(second[:nd], euler[:nd], eps, ctx.stream)
             with torch.cuda.stream(ctx.stream):      # read it back on the context's stream
                 e = float(eps.item())
         cur = second if order == 2 else euler

@@ -232,3 +232,66 @@ def test_second_moment_bound_flag(wvv_big, flag):
     E.efpi_restrict_state(ctx.ctx, c)
     bits = E.efpi_sync(ctx.ctx, raise_on_error=False)
     assert bool(bits & E.DEV_WEIGHT) == flag
+
+
+def test_adaptive_projective_run_matches_oracle():
+    """Second-order adaptive projection of the three moments: every step against an
+    oracle run taking the same steps, and the step controller's error taken on the
+    density (the first N_c coefficients) as with two moments."""
+    import dataclasses
+    from paper_1610_01071_amd import projective
+    E = lib()
+    spec = E.ReplicaSpec(256, 256.0, ppc=64, haar_levels=3, burst_steps=10, macro_dt=6.0)
+    first = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    set_particles(first, 0, *iaw_particles(spec, 38))
+    c0 = first.new_coarse()
+    E.efpi_restrict_state(first.ctx, c0)
+    E.efpi_sync(first.ctx)
+    shift_of = lambda n: synth.lift_shift(1100 + n)
+    ctx = make_ctx([spec], newton_iters=3, newton_iters_start=6)
+    t_end, tol, lo, hi = 24.0, 1e-4, 1.0, 9.0
+    run = projective.run_projective(ctx, c0, t_end, 3.0, 0, order=2, tol=tol, dt_min=lo,
+                                    dt_max=hi, shift_of=shift_of)
+    E.efpi_sync(ctx.ctx)
+    assert abs(run.times[-1] - t_end) < 1e-9
+    g, sch = oracle_grid(spec), scheme3(spec)
+    c = c0.view(3, -1).cpu().numpy()
+    f_prev, gap = None, None
+    for n, dt in enumerate(run.steps):
+        sn = dataclasses.replace(sch, macro_dt=dt)
+        _, snaps, _ = oefpi.macro_step(c, g, sn, shift_of(n))
+        f, eu, sec = oefpi.project2(snaps, g.dt, dt, f_prev, gap)
+        if n > 0:
+            want = metrics.rel_l2(sec[0], eu[0])
+            assert run.err[n] == pytest.approx(want, rel=0.2), f"step {n} error estimate"
+        c, f_prev, gap = sec, f, dt
+        got = run.states[n + 1].view(3, -1).cpu().numpy()
+        for m in range(3):
+            assert metrics.rel_l2(got[m], c[m]) < 1e-4, f"step {n} moment {m}"
+        assert pert_eps(got[0], c[0]) < 1e-4, f"step {n} density perturbation"
+
+
+def test_graph_replays_equal_eager():
+    """Three-moment macro steps replayed from a captured graph equal the eager
+    ones, with eager work and synchronisation between the replays."""
+    E = lib()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        spec = E.ReplicaSpec(1024, 1024.0, ppc=40, haar_levels=4, burst_steps=8, macro_dt=4.0)
+        ce, cg = make_ctx([spec]), make_ctx([spec])
+        coarse, _ = synth.random_coarse_efree(64, seed=39, levels=4)
+        ae = to_dev(coarse.ravel(), torch.float64)
+        ag = ae.clone()
+        be, bg = ce.new_coarse(), cg.new_coarse()
+        junk = torch.zeros(1 << 20, device="cuda")
+        for i in range(4):
+            sh = [synth.lift_shift(1200 + i)]
+            E.efpi_macro_step(ce.ctx, ae, be, sh)
+            E.efpi_macro_step_graph(cg.ctx, ag, bg, sh)
+            junk.add_(1.0)
+            side.synchronize()
+            assert torch.equal(be, bg), f"step {i}"
+            ae, be = be, ae
+            ag, bg = bg, ag
+        assert E.efpi_sync(cg.ctx, raise_on_error=False) == E.efpi_sync(ce.ctx,
+                                                                        raise_on_error=False)
