@@ -500,11 +500,12 @@ __device__ __forceinline__ void wave_range(const RepDev& R, WaveLds<kMoments<MOD
 // MODE (compile time): kRestrict | kPush for a burst step, kPush for plain PIC,
 // kRestrict for the last snapshot of a burst, kDepositOnly for a charge deposit.
 template <int MODE>
-__global__ __launch_bounds__(kThreads)
-void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ item_prefix,
-                 int n_reps, int64_t total_items, int tile, int p, double pd, int fresh_flag,
-                 int qsel, uint32_t* __restrict__ status) {
-  __shared__ WaveLds<kMoments<MODE>> lds[kWaves];
+__device__ __forceinline__ void particles_body(WaveLds<kMoments<MODE>>* lds,
+                                               const RepDev* __restrict__ reps,
+                                               const int64_t* __restrict__ item_prefix,
+                                               int n_reps, int64_t total_items, int tile, int p,
+                                               double pd, int fresh_flag, int qsel,
+                                               uint32_t* __restrict__ status) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds<kMoments<MODE>>& L = lds[wave];
   const bool fresh = fresh_flag != 0;
@@ -525,6 +526,28 @@ void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ it
   if (__ballot(big) != 0ull && __lane_id() == 0)
     __hip_atomic_fetch_or(status, (uint32_t)EFPI_DEV_WEIGHT, __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads)
+void k_particles(const RepDev* __restrict__ reps, const int64_t* __restrict__ item_prefix,
+                 int n_reps, int64_t total_items, int tile, int p, double pd, int fresh_flag,
+                 int qsel, uint32_t* __restrict__ status) {
+  __shared__ WaveLds<2> lds[kWaves];
+  particles_body<MODE>(lds, reps, item_prefix, n_reps, total_items, tile, p, pd, fresh_flag,
+                       qsel, status);
+}
+
+// The three-moment restriction (kMoment3 in MODE) held to 4 waves per SIMD: its
+// extra share per ion would otherwise take the kernel past 128 VGPRs (3 waves).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_particles3(const RepDev* __restrict__ reps, const int64_t* __restrict__ item_prefix,
+                  int n_reps, int64_t total_items, int tile, int p, double pd, int fresh_flag,
+                  int qsel, uint32_t* __restrict__ status) {
+  __shared__ WaveLds<3> lds[kWaves];
+  particles_body<MODE>(lds, reps, item_prefix, n_reps, total_items, tile, p, pd, fresh_flag,
+                       qsel, status);
 }
 
 __global__ void k_fill_u8(uint8_t* p, size_t bytes) {
@@ -571,13 +594,17 @@ template <int MODE>
 void launch_mode(dim3 grid, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1,
                  const RepDev* d_reps, const int64_t* d_item_prefix, int n_reps,
                  int64_t total_items, int tile, int p, int fresh, int qsel, uint32_t* d_status) {
-  if (ev0 && ev1)
-    hipExtLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, ev0, ev1, 0, d_reps,
-                          d_item_prefix, n_reps, total_items, tile, p, (double)p, fresh, qsel,
-                          d_status);
-  else
-    hipLaunchKernelGGL(k_particles<MODE>, grid, dim3(kThreads), 0, stream, d_reps, d_item_prefix,
-                       n_reps, total_items, tile, p, (double)p, fresh, qsel, d_status);
+  auto go = [&](auto kernel) {
+    if (ev0 && ev1)
+      hipExtLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, stream, ev0, ev1, 0, d_reps,
+                            d_item_prefix, n_reps, total_items, tile, p, (double)p, fresh, qsel,
+                            d_status);
+    else
+      hipLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, stream, d_reps, d_item_prefix, n_reps,
+                         total_items, tile, p, (double)p, fresh, qsel, d_status);
+  };
+  if constexpr (kMoments<MODE> == 3) go(k_particles3<MODE>);
+  else go(k_particles<MODE>);
 }
 }  // namespace
 
