@@ -10,7 +10,9 @@ namespace {
 // EFPI_LIFT_KEEP ions in registers between the correction sums and the stores.  A
 // work item is one coarse block (a few thousand ions), so several workgroups per CU
 // hide each other's dependent loads and barriers: on the 64-replica ensemble the
-// lift takes 0.65 ms against 1.0 ms with 1024-thread workgroups.
+// lift takes 0.65 ms against 1.0 ms with 1024-thread workgroups.  The two-moment
+// kernel is held to 96 VGPRs, so five waves share a SIMD (568 against 615 us on
+// the ensemble, fused deposit included).
 #ifndef EFPI_LIFT_KEEP
 #define EFPI_LIFT_KEEP 8
 #endif
@@ -244,7 +246,8 @@ __device__ __forceinline__ int find_rep(const int64_t* prefix, int n, int64_t it
 // particle pass deposits it (the same fixed-point shares of the stored w and
 // offset), so the burst needs no separate deposit pass.
 template <bool kThird>
-__global__ __launch_bounds__(kLiftThreads) void k_lift(const RepDev* __restrict__ reps,
+__global__ __launch_bounds__(kLiftThreads) __attribute__((amdgpu_waves_per_eu(kThird ? 4 : 5)))
+void k_lift(const RepDev* __restrict__ reps,
                                                        const int64_t* __restrict__ block_prefix,
                                                        int n_reps, int64_t total, int only_rep,
                                                        const double* __restrict__ coarse,
