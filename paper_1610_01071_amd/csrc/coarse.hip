@@ -62,12 +62,18 @@ __device__ __forceinline__ float inv_normal(uint32_t u) {
 }
 
 // ---------------------------------------------------------------- profile --
+// Nodes of a replica (n_cells <= 16384, checked at init): the profile kernels keep
+// one byte per node in LDS, "density above n_floor".
+constexpr int kMaxNodes = 16385;
+
 // Fine node density and mean velocity (and, with three moments, temperature)
 // from the coarse coefficients: inverse Haar with zero details (block means
 // 2^{-l/2} c_B), optionally linearly interpolated between block centres
 // (periodic wrap; constant past the end centres on walls).  The temperature is
 // T = s / n - u^2, clipped at 0, and 0 where the density is at most n_floor.
-__device__ void profile_of(const RepDev& R, const double* __restrict__ cn) {
+// s_above[k] records n_k > n_floor for the occupancy count.
+__device__ void profile_of(const RepDev& R, const double* __restrict__ cn,
+                           uint8_t* __restrict__ s_above) {
   const int nc = R.n_coarse;
   const double* cj = cn + nc;
   const double* cs = cn + 2 * nc;
@@ -75,6 +81,7 @@ __device__ void profile_of(const RepDev& R, const double* __restrict__ cn) {
   const int bs = 1 << R.levels;
   const double inv_s = 1.0 / sqrt((double)bs);
   const bool periodic = R.bc == 0;
+#pragma unroll 4
   for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) {
     int b0, b1;
     double w0, w1;
@@ -105,6 +112,7 @@ __device__ void profile_of(const RepDev& R, const double* __restrict__ cn) {
     const double u = ok ? dj / nn : 0.0;
     gmem(R.prof_n)[k] = nn;
     gmem(R.prof_u)[k] = u;
+    s_above[k] = ok ? 1 : 0;
     if (third) {
       const double ds = R.lift_linear ? (w0 * cs[b0] + w1 * cs[b1]) * inv_s : cs[b0] * inv_s;
       gmem(R.prof_t)[k] = ok ? fmax(ds / nn - u * u, 0.0) : 0.0;
@@ -113,46 +121,54 @@ __device__ void profile_of(const RepDev& R, const double* __restrict__ cn) {
 }
 
 // -------------------------------------------------------------- occupancy --
-// A cell is occupied when one of its nodes exceeds n_floor.  Exclusive scan of
-// occupied cells gives each cell's rank; the lift puts ppc ions per rank.
-__device__ void occupancy_of(const RepDev& R, uint32_t* __restrict__ status, int* s_part) {
+// A cell is occupied when one of its nodes exceeds n_floor (s_above, filled and
+// synchronised by the caller).  Thread t takes a run of consecutive cells; an
+// exclusive scan of the runs' counts (waves by shuffles, then the wave totals)
+// gives each occupied cell its rank, and the lift puts ppc ions per rank.
+__device__ void occupancy_of(const RepDev& R, uint32_t* __restrict__ status,
+                             const uint8_t* __restrict__ s_above, int* __restrict__ s_wave) {
   const int n = R.n_cells;
   const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wid = t / kWave;
   const int per = (n + kProfThreads - 1) / kProfThreads;
   const int c0 = t * per;
+  const int c1 = min(c0 + per, n);
   const bool periodic = R.bc == 0;
-  const auto prof_n = gmem(R.prof_n);
+  auto occupied = [&](int c) {
+    const int cr = periodic ? ((c + 1) & (n - 1)) : c + 1;
+    return (s_above[c] | s_above[cr]) != 0;
+  };
   const auto block_rank = gmem(R.block_rank);
   const auto cell_of_rank = gmem(R.cell_of_rank);
   int cnt = 0;
-  for (int c = c0; c < min(c0 + per, n); ++c) {
-    const int cr = periodic ? ((c + 1) & (n - 1)) : c + 1;
-    cnt += fmax(prof_n[c], prof_n[cr]) > R.n_floor ? 1 : 0;
+  for (int c = c0; c < c1; ++c) cnt += occupied(c) ? 1 : 0;
+  int inc = cnt;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
   }
-  s_part[t] = cnt;
+  if (lane == kWave - 1) s_wave[wid] = inc;
   __syncthreads();
-  // inclusive Hillis-Steele scan of the per-thread counts
-  for (int off = 1; off < kProfThreads; off <<= 1) {
-    const int add = t >= off ? s_part[t - off] : 0;
-    __syncthreads();
-    s_part[t] += add;
-    __syncthreads();
+  int before = 0, total = 0;
+  for (int k = 0; k < kProfThreads / kWave; ++k) {
+    const int v = s_wave[k];
+    before += k < wid ? v : 0;
+    total += v;
   }
   const int64_t max_cells = R.capacity / R.ppc;
-  int rank = t > 0 ? s_part[t - 1] : 0;
+  int rank = before + inc - cnt;
   const int lmask = (1 << R.levels) - 1;
-  for (int c = c0; c < min(c0 + per, n); ++c) {
-    const int cr = periodic ? ((c + 1) & (n - 1)) : c + 1;
-    const bool occ = fmax(prof_n[c], prof_n[cr]) > R.n_floor;
+  for (int c = c0; c < c1; ++c) {
     if ((c & lmask) == 0) block_rank[c >> R.levels] = (int32_t)min((int64_t)rank, max_cells);
-    if (occ) {
+    if (occupied(c)) {
       if (rank < max_cells) cell_of_rank[rank] = c;
       ++rank;
     }
   }
-  if (t == kProfThreads - 1) {
-    const int64_t total = s_part[kProfThreads - 1];
-    const int64_t kept = min(total, max_cells);
+  if (t == 0) {
+    const int64_t kept = min((int64_t)total, max_cells);
     block_rank[R.n_coarse] = (int32_t)kept;
     *gmem(R.np) = kept * R.ppc;
     if (total > max_cells) atomicOr(status, 4u);
@@ -162,23 +178,26 @@ __device__ void occupancy_of(const RepDev& R, uint32_t* __restrict__ status, int
 __global__ __launch_bounds__(kProfThreads) void k_occupancy(const RepDev* __restrict__ reps,
                                                             int only_rep,
                                                             uint32_t* __restrict__ status) {
-  __shared__ int s_part[kProfThreads];
-  occupancy_of(reps[only_rep >= 0 ? only_rep : (int)blockIdx.x], status, s_part);
+  __shared__ uint8_t s_above[kMaxNodes];
+  __shared__ int s_wave[kProfThreads / kWave];
+  const RepDev& R = reps[only_rep >= 0 ? only_rep : (int)blockIdx.x];
+  const auto prof_n = gmem(R.prof_n);
+  for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) s_above[k] = prof_n[k] > R.n_floor;
+  __syncthreads();
+  occupancy_of(R, status, s_above, s_wave);
 }
 
-// Lift preparation of every replica in one launch: the fine profile from the
-// coarse state, then the occupied cells and their ranks, and (with set_shift)
-// the replica's rotation of the quiet start.
 __global__ __launch_bounds__(kProfThreads) void k_lift_prep(const RepDev* __restrict__ reps,
                                                             const double* __restrict__ coarse,
                                                             const int64_t* __restrict__ coff,
                                                             uint32_t* __restrict__ status,
                                                             int set_shift, const ShiftArg shifts) {
-  __shared__ int s_part[kProfThreads];
+  __shared__ uint8_t s_above[kMaxNodes];
+  __shared__ int s_wave[kProfThreads / kWave];
   const RepDev& R = reps[blockIdx.x];
-  profile_of(R, coarse + coff[blockIdx.x]);
-  __syncthreads();  // the profile written above is read by other threads below
-  occupancy_of(R, status, s_part);
+  profile_of(R, coarse + coff[blockIdx.x], s_above);
+  __syncthreads();  // s_above is read by other threads below
+  occupancy_of(R, status, s_above, s_wave);
   if (set_shift && threadIdx.x == 0) gmem(R.aux)[1] = (int64_t)shifts.s[blockIdx.x];
 }
 
