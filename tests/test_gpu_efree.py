@@ -295,3 +295,57 @@ def test_graph_replays_equal_eager():
             ag, bg = bg, ag
         assert E.efpi_sync(cg.ctx, raise_on_error=False) == E.efpi_sync(ce.ctx,
                                                                         raise_on_error=False)
+
+
+@pytest.fixture(scope="module")
+def full3():
+    """The benchmark wave (4096 cells, 1000 ions per cell, tile 4096) with three moments."""
+    import math
+    E = lib()
+    spec = E.ReplicaSpec(4096, 4096.0, ppc=1000, haar_levels=4, burst_steps=20, macro_dt=20.0,
+                         dt=0.1, vth=math.sqrt(0.1))
+    ctx = make_ctx([spec], newton_iters=2, newton_iters_start=4, tile=4096)
+    g, sch = oracle_grid(spec), scheme3(spec)
+    n, u = synth.iaw_profile(4096, 4096.0)
+    c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(2016))
+    parts = (c.astype(np.int16), f.astype(np.float32), v.astype(np.float32), w.astype(np.float32))
+    x = x_of(parts[0], parts[1], g.h)
+    c0 = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                              np.ones(x.size, bool), g, sch)
+    return dict(E=E, spec=spec, ctx=ctx, g=g, sch=sch, parts=parts, c0=c0)
+
+
+def test_fullsize_restriction(full3):
+    E, ctx, parts, c0 = full3["E"], full3["ctx"], full3["parts"], full3["c0"]
+    set_particles(ctx, 0, *parts)
+    c = ctx.new_coarse()
+    E.efpi_restrict_state(ctx.ctx, c)
+    got = c.view(3, -1).cpu().numpy()
+    for m in range(3):
+        assert metrics.rel_l2(got[m], c0[m]) < 1e-7
+
+
+def test_fullsize_lift(full3):
+    E, ctx, g, sch, c0 = full3["E"], full3["ctx"], full3["g"], full3["sch"], full3["c0"]
+    shift = synth.lift_shift(8)
+    E.efpi_lift(ctx.ctx, to_dev(c0.ravel(), torch.float64), [shift])
+    gc, gf, gv, gw = particles_np(ctx)
+    oc, of, ov, ow = oefpi.lift(c0, g, sch, shift)
+    assert np.array_equal(gc.astype(np.int64), oc)
+    assert np.array_equal(gf, of.astype(np.float32))
+    assert relmax(gv, ov) < 1e-6
+    assert relmax(gw, ow) < 1e-6
+
+
+def test_fullsize_macro_step(full3):
+    E, ctx, g, sch, c0 = full3["E"], full3["ctx"], full3["g"], full3["sch"], full3["c0"]
+    shift = synth.lift_shift(7)
+    cout = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, to_dev(c0.ravel(), torch.float64), cout, [shift])
+    assert E.efpi_sync(ctx.ctx, raise_on_error=False) == 0
+    ref, _, _ = oefpi.macro_step(c0, g, sch, shift)
+    got = cout.view(3, -1).cpu().numpy()
+    for m in range(3):
+        assert metrics.rel_l2(got[m], ref[m]) < 1e-4
+    assert pert_eps(got[0], ref[0]) < 1e-4
+    assert pert_eps(got[2], ref[2]) < 1e-4
