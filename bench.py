@@ -536,8 +536,9 @@ def run_bench(args, np, torch, synth, E):
         out["pic_sort_period_table"] = table
     out["pic_sort_period"] = args.sort_period
     iaw, c0 = iaw_leg(args, np, torch, synth, E)
-    if "efpi_speedup_vs_pic" in iaw:
-        out["efpi_speedup_vs_pic"] = iaw.pop("efpi_speedup_vs_pic")
+    for key in ("efpi_speedup_vs_pic", "efpi_speedup_vs_pic_tuned_burst"):
+        if key in iaw:
+            out[key] = iaw.pop(key)
     out["iaw4096"] = iaw
     _progress("iaw4096", t0)
     out["plain_pic_128"] = cfg1_leg(args, np, torch, synth, E)
@@ -640,6 +641,36 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
     # a speedup is reported only against a clean reference and for clean EFPI runs
     ok = [r for r in rows if r["eps_density"] <= args.eps_max and r["device_status"] == 0]
     best = max(ok, key=lambda r: r["macro_dt_over_dt"]) if ok and pic_bits == 0 else None
+    # the burst length N_e, which the paper tunes by the error it gives (Sec. 4.1): the
+    # same runs with fewer fine steps per macro step, against the same reference
+    ne_rows = []
+    for ne in (2, 4, 6, 10, 14):
+        for mult in (50, 75):
+            sp = workload_spec(E)
+            sp.burst_steps = ne
+            sp.macro_dt = mult * spec.dt
+            cx = E.Context(E.ConfigSpec([sp], newton_iters=2, newton_iters_start=4, tile=TILE))
+            m = int(round(args.horizon / sp.macro_dt))
+            a, b = cx.new_coarse(), cx.new_coarse()
+            a.copy_(c0)
+            state = {"a": a, "b": b}
+
+            def efpi_run():
+                for i in range(m):
+                    sh = shift0 if i == 0 else synth.lift_shift(20_000 + i)
+                    E.efpi_macro_step(cx.ctx, state["a"], state["b"], [sh])
+                    state["a"], state["b"] = state["b"], state["a"]
+
+            t_efpi = timed(torch, efpi_run)
+            bits = E.efpi_sync(cx.ctx, raise_on_error=False)
+            got = state["a"].view(2, -1)[0].cpu().numpy()
+            eps = float(np.sqrt(np.sum((got - ref) ** 2) / np.sum(got * got + ref * ref)))
+            ne_rows.append({"burst_steps": ne, "macro_dt_over_dt": mult, "macro_steps": m,
+                            "efpi_ms": t_efpi, "speedup": t_pic / t_efpi, "eps_density": eps,
+                            "device_status": bits})
+            cx.close()
+    ok_ne = [r for r in ne_rows if r["eps_density"] <= args.eps_max and r["device_status"] == 0]
+    best_ne = max(ok_ne, key=lambda r: r["speedup"]) if ok_ne and pic_bits == 0 else None
     extra = {}
     if not args.no_adaptive:
         pv = projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args)
@@ -648,6 +679,7 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
     return {
         **extra,
         "efpi_speedup_vs_pic": best["speedup"] if best else None,
+        "efpi_speedup_vs_pic_tuned_burst": best_ne["speedup"] if best_ne else None,
         "efpi_vs_pic": {
             "horizon": args.horizon,
             "eps_max": args.eps_max,
@@ -658,6 +690,11 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
             "device_status_pic": pic_bits,
             "fixed_error_macro_dt_over_dt": best["macro_dt_over_dt"] if best else None,
             "sweep": rows,
+            "burst_length_sweep": ne_rows,
+            "best_speedup_over_burst_lengths": best_ne["speedup"] if best_ne else None,
+            "best_burst_length": ({k: best_ne[k] for k in ("burst_steps", "macro_dt_over_dt",
+                                                           "eps_density")}
+                                  if best_ne else None),
         },
     }
 
@@ -679,9 +716,13 @@ def projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args):
     runs += [dict(order=2, macro_dt_over_dt=m) for m in (25, 50, 75, 100)]
     runs += [dict(order=o, tol=tol, dt_min_over_dt=50, dt_max_over_dt=400, macro_dt_over_dt=75)
              for o in (1, 2) for tol in (3e-4, 1e-3, 3e-3)]
+    # adaptive Euler with the short burst the fixed-step sweep finds as accurate (N_e = 6)
+    runs += [dict(order=1, tol=tol, dt_min_over_dt=50, dt_max_over_dt=400, macro_dt_over_dt=75,
+                  burst_steps=6) for tol in (3e-4, 1e-3)]
     rows = []
     for r in runs:
         sp = workload_spec(E)
+        sp.burst_steps = r.get("burst_steps", sp.burst_steps)
         sp.macro_dt = r["macro_dt_over_dt"] * spec.dt
         kw = {}
         if "tol" in r:
@@ -714,12 +755,14 @@ def projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args):
         rows.append(row)
 
     def best(sel):
-        ok = [x for x in rows if sel(x) and x["eps_density"] <= args.eps_max]
+        ok = [x for x in rows
+              if sel(x) and x["eps_density"] <= args.eps_max and x["device_status"] == 0]
         return max(ok, key=lambda x: x["speedup"]) if ok else None
 
     b1 = best(lambda x: x["order"] == 1 and "tol" not in x)
     b2 = best(lambda x: x["order"] == 2 and "tol" not in x)
-    ba = best(lambda x: "tol" in x)
+    ba = best(lambda x: "tol" in x and "burst_steps" not in x)
+    bs = best(lambda x: "tol" in x and "burst_steps" in x)
     return {
         "eps_max": args.eps_max,
         "euler_best_speedup": b1["speedup"] if b1 else None,
@@ -728,6 +771,9 @@ def projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args):
         "adaptive_best_speedup": ba["speedup"] if ba else None,
         "adaptive_best": ({k: ba[k] for k in ("order", "tol", "macro_steps", "eps_density")}
                           if ba else None),
+        "adaptive_short_burst_best_speedup": bs["speedup"] if bs else None,
+        "adaptive_short_burst_best": ({k: bs[k] for k in ("burst_steps", "tol", "macro_steps",
+                                                          "eps_density")} if bs else None),
         "runs": rows,
     }
 

@@ -324,6 +324,29 @@ def test_macro_step_matches_oracle():
     assert torch.equal(cout, cout2)
 
 
+@pytest.mark.parametrize("ne", [1, 2, 4])
+def test_short_burst_macro_step_matches_oracle(ne):
+    """Macro steps with the short bursts the benchmark's burst-length sweep runs
+    (N_e = 1, 2, 4: the LS slope of eq. 3.18 through two to five snapshots)."""
+    E = lib()
+    spec = E.ReplicaSpec(512, 512.0, ppc=100, haar_levels=4, burst_steps=ne, macro_dt=7.5)
+    ctx = make_ctx([spec])
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    parts = iaw_particles(spec, 14)
+    x = x_of(parts[0], parts[1], g.h)
+    c0 = oefpi.restrict_state(x, parts[2].astype(np.float64), parts[3].astype(np.float64),
+                              np.ones(x.size, bool), g, sch)
+    shift = synth.lift_shift(15)
+    cout = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, to_dev(c0.ravel(), torch.float64), cout, [shift])
+    assert E.efpi_sync(ctx.ctx, raise_on_error=False) == 0
+    ref, _, _ = oefpi.macro_step(c0, g, sch, shift)
+    got = cout.view(2, -1).cpu().numpy()
+    for m in range(2):
+        assert metrics.rel_l2(got[m], ref[m]) < 1e-4
+    assert pert_eps(got[0], ref[0]) < 1e-4
+
+
 @pytest.mark.parametrize("bc", [0, 1])
 def test_macro_step_equals_composed_calls(bc):
     """efpi_macro_step (fused lift preparation, fused restriction and projection)
