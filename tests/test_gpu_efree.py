@@ -349,3 +349,44 @@ def test_fullsize_macro_step(full3):
         assert metrics.rel_l2(got[m], ref[m]) < 1e-4
     assert pert_eps(got[0], ref[0]) < 1e-4
     assert pert_eps(got[2], ref[2]) < 1e-4
+
+
+def test_uneven_replicas_equal_single_contexts():
+    """Three-moment replicas of uneven sizes and boundaries in one context: every
+    replica's macro step equals that of a context holding it alone, bit for bit (the
+    per-replica offsets of the [3][N_c] coarse and [K+1][3][N_c] snapshot arrays), and
+    the ensemble mean over two equal replicas is their mean."""
+    E = lib()
+    specs = [E.ReplicaSpec(256, 256.0, ppc=48, haar_levels=2, burst_steps=6, macro_dt=3.0),
+             E.ReplicaSpec(512, 512.0, bc=1, ppc=32, haar_levels=3, burst_steps=6, macro_dt=3.0,
+                           vth=0.2),
+             E.ReplicaSpec(1024, 1024.0, ppc=24, haar_levels=4, burst_steps=6, macro_dt=3.0),
+             E.ReplicaSpec(1024, 1024.0, ppc=24, haar_levels=4, burst_steps=6, macro_dt=3.0)]
+    coarse = []
+    for r, s in enumerate(specs):
+        c, _ = synth.random_coarse_efree(s.n_cells >> s.haar_levels, seed=60 + r,
+                                         levels=s.haar_levels)
+        if s.bc == 1:
+            nc = c.shape[1]
+            c[:, : nc // 4] = 0.0
+            c[:, -nc // 4:] = 0.0
+        coarse.append(c)
+    shifts = [synth.lift_shift(70 + r) for r in range(len(specs))]
+    ctx = make_ctx(specs)
+    cin = to_dev(np.concatenate([c.ravel() for c in coarse]), torch.float64)
+    cout = ctx.new_coarse()
+    E.efpi_macro_step(ctx.ctx, cin, cout, shifts)
+    E.efpi_sync(ctx.ctx, raise_on_error=False)
+    parts = ctx.split_coarse(cout)
+    for r, s in enumerate(specs):
+        one = make_ctx([s])
+        out = one.new_coarse()
+        E.efpi_macro_step(one.ctx, to_dev(coarse[r].ravel(), torch.float64), out, [shifts[r]])
+        E.efpi_sync(one.ctx, raise_on_error=False)
+        assert torch.equal(parts[r].reshape(-1), out), f"replica {r}"
+    mean = (parts[2] + parts[3]) / 2
+    E.efpi_ensemble_mean(ctx.ctx, cout)
+    torch.cuda.synchronize()
+    parts = ctx.split_coarse(cout)
+    assert torch.allclose(parts[2], mean, rtol=1e-15, atol=0.0)
+    assert torch.equal(parts[2], parts[3])
