@@ -345,24 +345,39 @@ __device__ void interior_forward(double* A, int nf, int lane) {
   }
 }
 
-// One wave per fine node, the node's arrays in LDS: the lanes build the column
+// One wave per fine node, the node's array in LDS: the lanes build the column
 // from its two coarse columns by l levels of midpoint interpolation (eq. 3.7);
 // lane 0 takes the density and CDF sums in index order; the repair of App. C
 // follows (edges, forward and backward interior passes, averaged) on the whole
-// wave.  The lanes write the repaired CDF
-// rf[i][0..n_vf] and lane 0 the density to R.prof_n.
+// wave.  One LDS array of n_vf + 1 doubles serves every stage (the reflections
+// are done in place), so nine workgroups share a CU: the edge-repaired CDF is
+// kept in registers (entry k in lane k mod 64) for the backward pass, and the
+// forward pass's result goes to rf and is read back for the average.  The
+// lanes write the repaired CDF rf[i][0..n_vf] and lane 0 the density to
+// R.prof_n.
+constexpr int kMaxVfPerLane = ((1 << 11) + 1 + kWave - 1) / kWave;  // n_vf <= 2^11
+
+__device__ __forceinline__ void reflect_in_place(double* A, int nf, int lane) {
+  // A[k] <- 1 - A[nf - k] for every k, as one reads and one writes per pair
+  for (int k = lane; 2 * k <= nf; k += kWave) {
+    const double a = A[k], b = A[nf - k];
+    A[k] = 1.0 - b;
+    A[nf - k] = 1.0 - a;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ reps, int rep,
                                                     const double* __restrict__ cols, int levels,
                                                     int n_vf, double dv,
                                                     double* __restrict__ rf) {
-  extern __shared__ double s_cdf[];  // E, M: 2 x (n_vf + 1)
+  extern __shared__ double s_cdf[];  // [n_vf + 1]: the column at 1..n_vf, then the CDF
   const RepDev& R = reps[rep];
   const int n = R.n_cells;
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   const int nf = n_vf;
-  double* sE = s_cdf;            // the CDF, later the forward pass
-  double* sM = s_cdf + (nf + 1);  // the column, later the reflected arrays
+  double* sA = s_cdf;
   const int nxc = n >> levels;
   const int K = i >> levels;
   const int K1 = K + 1 == nxc ? 0 : K + 1;
@@ -374,7 +389,7 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
       if ((i >> j) & 1) A = mid;
       else B = mid;
     }
-    sM[k] = A;
+    sA[k + 1] = A;
   }
   __syncthreads();
   __shared__ double s_dens;
@@ -383,11 +398,11 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
     for (int k = 0; k < nf; k += 8) {  // nf is a power of two >= 16
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = sM[k + u];
+      for (int u = 0; u < 8; ++u) v[u] = sA[k + u + 1];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         run = run + v[u];
-        sE[k + u + 1] = run;
+        sA[k + u + 1] = run;
       }
     }
     const double dens = run * dv;
@@ -398,26 +413,38 @@ __global__ __launch_bounds__(kWave) void k_phase_cdf(const RepDev* __restrict__ 
   const double dens = s_dens;
   if (!(dens > R.n_floor)) return;  // the same for every lane of the workgroup
   // normalisation on all lanes; the repair below runs on the whole wave
-  for (int k = 1 + lane; k < nf; k += kWave) sE[k] = (sE[k] * dv) / dens;
+  for (int k = 1 + lane; k < nf; k += kWave) sA[k] = (sA[k] * dv) / dens;
   if (lane == 0) {
-    sE[0] = 0.0;
-    sE[nf] = 1.0;
+    sA[0] = 0.0;
+    sA[nf] = 1.0;
   }
   __syncthreads();
-  edge_low(sE, nf, lane);  // entries below 0
+  edge_low(sA, nf, lane);  // entries below 0
   // entries above 1: the same rule on the reflected array
-  for (int k = lane; k <= nf; k += kWave) sM[k] = 1.0 - sE[nf - k];
+  reflect_in_place(sA, nf, lane);
+  edge_low(sA, nf, lane);
+  reflect_in_place(sA, nf, lane);
+  // the edge-repaired CDF, kept for the backward pass
+  double e0[kMaxVfPerLane];
+#pragma unroll
+  for (int j = 0; j < kMaxVfPerLane; ++j) {
+    const int k = lane + j * kWave;
+    e0[j] = k <= nf ? sA[k] : 0.0;
+  }
+  // forward pass in place; its result goes to rf
+  interior_forward(sA, nf, lane);
+  double* out = rf + (int64_t)i * (nf + 1);
+  for (int k = lane; k <= nf; k += kWave) out[k] = sA[k];
+  __syncthreads();  // every lane has read the forward pass before the array is refilled
+  // backward pass on the reflection of the edge-repaired CDF
+#pragma unroll
+  for (int j = 0; j < kMaxVfPerLane; ++j) {
+    const int k = lane + j * kWave;
+    if (k <= nf) sA[nf - k] = 1.0 - e0[j];
+  }
   __syncthreads();
-  edge_low(sM, nf, lane);
-  for (int k = lane; k <= nf; k += kWave) sE[k] = 1.0 - sM[nf - k];
-  __syncthreads();
-  // forward pass in place, backward pass on the reflection
-  for (int k = lane; k <= nf; k += kWave) sM[k] = 1.0 - sE[nf - k];
-  __syncthreads();
-  interior_forward(sE, nf, lane);
-  interior_forward(sM, nf, lane);
-  for (int k = lane; k <= nf; k += kWave)
-    rf[(int64_t)i * (nf + 1) + k] = 0.5 * (sE[k] + (1.0 - sM[nf - k]));
+  interior_forward(sA, nf, lane);
+  for (int k = lane; k <= nf; k += kWave) out[k] = 0.5 * (out[k] + (1.0 - sA[nf - k]));
 }
 
 // v with RF(v) = b in node i's repaired CDF rf[i][0..nf]: the last bin k with
@@ -521,7 +548,7 @@ void launch_phase_lift(const RepDev* d_reps, int rep, int n_cells, int levels_x,
   const double up_scale = std::pow(2.0, 0.5 * jf) / (v_max - v_min);
   hipLaunchKernelGGL(k_phase_refine, dim3(nxc), dim3(kPhThreads), sizeof(double) * 2 * n_vf,
                      stream, d_coarse, da, up_scale, d_cols);
-  hipLaunchKernelGGL(k_phase_cdf, dim3(n_cells), dim3(kWave), sizeof(double) * 2 * (n_vf + 1),
+  hipLaunchKernelGGL(k_phase_cdf, dim3(n_cells), dim3(kWave), sizeof(double) * (n_vf + 1),
                      stream, d_reps, rep, d_cols, levels_x, n_vf, dv, d_cdf);
   launch_occupancy(d_reps, 0, rep, d_status, stream);
   hipLaunchKernelGGL(k_phase_load, dim3(4096), dim3(kPhThreads), sizeof(double) * 2 * (n_vf + 1),
