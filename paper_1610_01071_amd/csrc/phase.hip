@@ -25,6 +25,13 @@ constexpr int kPhThreads = 256;
 constexpr int kPhTile = 2048;  // ions per work item (at least)
 constexpr int kPhWin = 4;      // coarse x nodes of a work item's LDS window (at most)
 constexpr int kPhGrid = 8192;  // workgroups, striding over the work items
+// Histogram workgroups of 512 threads: at 2^11 bins (a 48 KB window, three
+// workgroups per CU) 47 us per restriction of 4,096,000 ions against 59 us with
+// 256 threads; at 2^8 bins the same (33 us); 1024 threads: 47 and 41 us.
+#ifndef EFPI_HIST_THREADS
+#define EFPI_HIST_THREADS 512
+#endif
+constexpr int kHistThreads = EFPI_HIST_THREADS;
 static_assert(kPhWin * 2048 * sizeof(long long) <= 65536, "window of 2^11 bins over 64 KB");
 
 struct PhaseHistArg {
@@ -33,7 +40,7 @@ struct PhaseHistArg {
   int levels, n_vf, win, tile, fresh, stored_field;
 };
 
-__global__ __launch_bounds__(kPhThreads) void k_phase_hist(const RepDev* __restrict__ reps,
+__global__ __launch_bounds__(kHistThreads) void k_phase_hist(const RepDev* __restrict__ reps,
                                                            int rep, PhaseHistArg a,
                                                            long long* __restrict__ hist) {
   extern __shared__ long long s_h[];  // [win][n_vf]
@@ -58,7 +65,7 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_hist(const RepDev* __restr
     const int64_t i1 = min(i0 + (int64_t)a.tile, np);
     const int c_first = min(max((int)cellp[i0], 0), nmask);
     const int base = ((c_first >> a.levels) - a.win / 2 + 1 + nxc) % nxc;
-    for (int k = threadIdx.x; k < cells; k += kPhThreads) s_h[k] = 0;
+    for (int k = threadIdx.x; k < cells; k += kHistThreads) s_h[k] = 0;
     __syncthreads();
     auto add = [&](int K, int kv, long long val) {
       const int slot = (K - base + nxc) % nxc;
@@ -75,7 +82,7 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_hist(const RepDev* __restr
       add(K, kv, s * (long long)(span - d));
       if (d) add(K + 1 == nxc ? 0 : K + 1, kv, s * (long long)d);
     };
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kPhThreads) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kHistThreads) {
       const int c = cellp[i];
       if (c < 0 || c >= n) continue;
       const float f = fracp[i];
@@ -102,7 +109,7 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_hist(const RepDev* __restr
       node_share((cn + 1) & nmask, kv, (long long)qr);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < cells; k += kPhThreads) {
+    for (int k = threadIdx.x; k < cells; k += kHistThreads) {
       const long long val = s_h[k];
       if (val != 0) {
         const int K = (base + k / a.n_vf) % nxc;
@@ -585,7 +592,7 @@ void launch_phase_restrict(const RepDev* d_reps, int rep, int n_cells, int level
   ha.stored_field = stored_field;
   launch_fill_u8(d_hist, sizeof(long long) * (size_t)nxc * n_vf, stream);
   const size_t lds = sizeof(long long) * (size_t)ha.win * n_vf;
-  hipLaunchKernelGGL(k_phase_hist, dim3(kPhGrid), dim3(kPhThreads), lds, stream, d_reps, rep, ha,
+  hipLaunchKernelGGL(k_phase_hist, dim3(kPhGrid), dim3(kHistThreads), lds, stream, d_reps, rep, ha,
                      d_hist);
   PhaseDwtArg da;
   const double dv = (v_max - v_min) / n_vf;
