@@ -330,19 +330,39 @@ __device__ void interior_forward(double* A, int nf, int lane) {
         break;
       }
     }
-    // sum of A[km .. kp - 1] in index order, extended by one term as kp moves right
+    // sum of A[km .. kp - 1] in index order, extended by one term as kp moves right.
+    // The lanes test the next 64 right ends at once: lane l takes kp + l with the sum
+    // extended term by term up to it (the sequential sums, bit for bit), and the first
+    // lane whose ramp is monotone, or that reaches nf, decides.
     double dF, sum = seq_sum(A, km, kp, 0.0);
+    const double akm = A[km];
     while (true) {
-      const int span = kp - km;
-      dF = 2.0 / (span - 1) * (sum / span - A[km]);
-      if (0.0 <= (span - 1) * dF && A[km] + (span - 1) * dF <= A[kp]) break;
-      if (kp >= nf) {
-        dF = (A[nf] - A[km]) / (nf - km);
-        kp = nf;
+      const int kq = kp + lane;
+      const bool valid = kq <= nf;  // the method never moves kp past nf
+      double s = sum;
+      for (int t = kp; t < kq && valid; ++t) s = s + A[t];
+      bool ok = false;
+      double d = 0.0;
+      if (valid) {
+        const int span = kq - km;
+        d = 2.0 / (span - 1) * (s / span - akm);
+        ok = 0.0 <= (span - 1) * d && akm + (span - 1) * d <= A[kq];
+      }
+      const unsigned long long m = __ballot(valid && (ok || kq >= nf));
+      if (m) {
+        const int l = first_lane(m);
+        const bool ok_l = __shfl(ok ? 1 : 0, l) != 0;
+        dF = __shfl(d, l);
+        kp += l;
+        if (!ok_l) {  // kp = nf without a monotone ramp: the straight line to A[nf]
+          dF = (A[nf] - akm) / (nf - km);
+          kp = nf;
+        }
         break;
       }
-      sum = sum + A[kp];
-      ++kp;
+      // no lane stopped: all 64 right ends lie below nf
+      sum = __shfl(s, kWave - 1) + A[kp + kWave - 1];
+      kp += kWave;
     }
     const double base = A[km];
     __syncthreads();
