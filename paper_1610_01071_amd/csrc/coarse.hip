@@ -81,8 +81,8 @@ __device__ void profile_of(const RepDev& R, const double* __restrict__ cn,
                            uint8_t* __restrict__ s_above) {
   const int nc = R.n_coarse;
   const double* cj = cn + nc;
-  const double* cs = cn + 2 * nc;
   const bool third = R.moments == 3;
+  const double* cs = third ? cn + 2 * nc : cn;  // second moments (read only with three)
   const int bs = 1 << R.levels;
   const double inv_s = 1.0 / sqrt((double)bs);
   const bool periodic = R.bc == 0;
