@@ -144,6 +144,7 @@ def _burst_compare(spec, parts, newton_iters=2):
         assert metrics.rel_l2(gn[m], on[m]) < 1e-4
     assert pert_eps(gn[0], on[0]) < 1e-4
     assert pert_eps(gn[2], on[2]) < 1e-4
+    return gs, gn, os_, on
 
 
 @pytest.mark.parametrize("coev", [1, 0])
@@ -163,6 +164,27 @@ def test_burst_restriction_walls():
     c, f, v, w = oefpi.load_particles(n, u, g, sch, synth.lift_shift(33))
     parts = (c.astype(np.int16), f.astype(np.float32), v.astype(np.float32), w.astype(np.float32))
     _burst_compare(spec, parts, newton_iters=3)
+
+
+def test_burst_with_positions_moved_past_the_walls():
+    """A plasma filling the walled box: over tau up to 20 the co-evolving positions of
+    the outer ions leave [0, L) and drop out of all three moments of the snapshots."""
+    E = lib()
+    n = 512
+    spec = E.ReplicaSpec(n, float(n), bc=1, ppc=40, haar_levels=3, burst_steps=20,
+                         macro_dt=20.0, vth=0.8)
+    g, sch = oracle_grid(spec), oracle_scheme(spec)
+    dens, u = synth.slab_profile(n, width=1.0)
+    cell, frac, v, w = oefpi.load_particles(dens, u, g, sch, synth.lift_shift(45))
+    parts = (cell.astype(np.int16), frac.astype(np.float32), v.astype(np.float32),
+             w.astype(np.float32))
+    gs, gn, os_, on = _burst_compare(spec, parts, newton_iters=3)
+    w64, v64 = w.astype(np.float64), v.astype(np.float64)
+    scale = 2.0 ** (-sch.levels / 2.0) / g.h
+    assert np.sum(os_[0, 0]) < 0.98 * np.sum(w64) * scale
+    assert np.sum(os_[0, 2]) < 0.98 * np.sum(w64 * v64 * v64) * scale
+    for m in (0, 2):
+        assert abs(np.sum(gs[0, m]) / np.sum(os_[0, m]) - 1.0) < 2e-3
 
 
 def test_macro_step_matches_oracle():
