@@ -721,9 +721,9 @@ def projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args):
     runs += [dict(order=2, macro_dt_over_dt=m) for m in (25, 50, 75, 100)]
     runs += [dict(order=o, tol=tol, dt_min_over_dt=50, dt_max_over_dt=400, macro_dt_over_dt=75)
              for o in (1, 2) for tol in (3e-4, 1e-3, 3e-3)]
-    # adaptive Euler with the short burst the fixed-step sweep finds as accurate (N_e = 6)
+    # adaptive Euler with the short bursts the fixed-step sweep finds as accurate
     runs += [dict(order=1, tol=tol, dt_min_over_dt=50, dt_max_over_dt=400, macro_dt_over_dt=75,
-                  burst_steps=6) for tol in (3e-4, 1e-3)]
+                  burst_steps=ne) for ne in (2, 6) for tol in (3e-4, 1e-3)]
     rows = []
     for r in runs:
         sp = workload_spec(E)
