@@ -536,7 +536,8 @@ def run_bench(args, np, torch, synth, E):
         out["pic_sort_period_table"] = table
     out["pic_sort_period"] = args.sort_period
     iaw, c0 = iaw_leg(args, np, torch, synth, E)
-    for key in ("efpi_speedup_vs_pic", "efpi_speedup_vs_pic_tuned_burst"):
+    for key in ("efpi_speedup_vs_pic", "efpi_speedup_vs_pic_tuned_burst",
+                "efpi_adaptive_speedup_vs_pic", "efpi_adaptive_speedup_vs_pic_short_burst"):
         if key in iaw:
             out[key] = iaw.pop(key)
     out["iaw4096"] = iaw
@@ -680,6 +681,7 @@ def speedup_sweep(E, torch, np, synth, ctx, spec, c0, args):
     if not args.no_adaptive:
         pv = projective_leg(E, torch, np, synth, spec, c0, ref, t_pic, shift0, args)
         extra["efpi_adaptive_speedup_vs_pic"] = pv["adaptive_best_speedup"]
+        extra["efpi_adaptive_speedup_vs_pic_short_burst"] = pv["adaptive_short_burst_best_speedup"]
         extra["projective_vs_pic"] = pv
     return {
         **extra,
