@@ -132,9 +132,12 @@ typedef struct {
  * loads each ion with the local thermal speed sqrt(T(X)), T = s/n - u^2 at the
  * fine nodes (clipped at 0, 0 below n_floor) linear in the cell, instead of vth,
  * and the block correction also stretches velocities about the block's mean so
- * that sum w v^2 meets the block's second moment.  Every coarse array below is
- * then [R][3][N_c] (moments n, j, s) where it reads [R][2][N_c].  Not with
- * EFPI_CLOSURE_KINETIC. */
+ * that sum w v^2 meets the block's second moment.  Every coarse and snapshot
+ * array of a context (efpi_lift, efpi_restrict, efpi_project, efpi_project2,
+ * efpi_macro_step, efpi_macro_step_graph, efpi_restrict_state,
+ * efpi_ensemble_mean) then holds three moments n, j, s where it reads [2]
+ * below: [R][3][N_c] and [R][K+1][3][N_c].  The learned-projection calls keep
+ * two.  Not with EFPI_CLOSURE_KINETIC. */
 #define EFPI_FLAG_PRESSURE 2u
 
 typedef struct efpi_ctx efpi_ctx; /* opaque host object owned by the library */
