@@ -391,6 +391,23 @@ def test_second_moment_restriction_by_hand():
     assert np.array_equal(out[:2], efpi.restrict_snapshot(x, v, np.zeros(2), w, 0.0, g, 0, False))
 
 
+def test_coevolving_moments_by_hand():
+    # App. B with tau = 2 and a stored field: X~ = X + tau V, V~ = V + tau E_n(X); the
+    # mass, w V~ and w V~^2 go by CIC to the nodes around X~ (l = 0, h = 1)
+    g = Grid(8, 8.0)
+    x = np.array([1.25, 6.5])
+    v = np.array([0.5, -0.25])
+    e = np.array([0.1, -0.2])
+    w = np.array([0.5, 2.0])
+    out = efpi.restrict_snapshot(x, v, e, w, 2.0, g, 0, True, moments=3)
+    # X~ = 2.25 (3/4 to node 2, 1/4 to node 3) and 6.0 (all to node 6); V~ = 0.7, -0.65
+    want = np.zeros((3, 8))
+    for m, (a, b) in enumerate(((0.5, 2.0), (0.5 * 0.7, 2.0 * -0.65),
+                                (0.5 * 0.49, 2.0 * 0.4225))):
+        want[m, 2], want[m, 3], want[m, 6] = 0.75 * a, 0.25 * a, b
+    assert np.allclose(out, want, rtol=0, atol=1e-14)
+
+
 def test_temperature_profile_by_hand():
     sch = efpi.Scheme(n_floor=1e-3)
     n = np.array([2.0, 1.0, 1e-4, 4.0])
