@@ -784,7 +784,7 @@ efpi_status efpi_get_grid(efpi_ctx* ctx, int32_t replica, int64_t* d_q, double* 
   if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
   const RepDev& d = ctx->h_reps[replica];
   if (d_q) note(hipMemcpyAsync(d_q, d.q[ctx->cur], sizeof(int64_t) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
-  if (d_phi) note(hipMemcpyAsync(d_phi, d.phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (d_phi) launch_phi_copy(ctx->d_reps, replica, d.phi, d_phi, 1, ctx->stream);
   if (d_e) note(hipMemcpyAsync(d_e, d.e, sizeof(float) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
   return hip_check("get_grid");
 }
@@ -793,7 +793,7 @@ efpi_status efpi_set_potential(efpi_ctx* ctx, int32_t replica, const double* d_p
   if (check_rep(ctx, replica) != EFPI_OK) return EFPI_EINVAL;
   if (!d_phi) return fail(EFPI_EINVAL, "d_phi is NULL");
   const RepDev& d = ctx->h_reps[replica];
-  note(hipMemcpyAsync(d.phi, d_phi, sizeof(double) * d.n_nodes, hipMemcpyDeviceToDevice, ctx->stream));
+  launch_phi_copy(ctx->d_reps, replica, d_phi, d.phi, 0, ctx->stream);
   ctx->field_valid = false;
   ctx->phi_valid = true;
   return hip_check("set_potential");

@@ -132,6 +132,20 @@ void launch_electrons(const RepDev* d_ereps, int n_reps, int push, int fresh, in
 // Linear periodic Poisson solve from R.q[qsel] of every replica in one launch
 // (Newton's shape: R.field_m rows per thread): phi, E (and E_n with save_en), the
 // other charge buffer cleared, the snapshot bins with zero_bins.
+// Storage slot of node k's potential.  A field-solve thread keeps its M consecutive
+// nodes in registers; the pair (2j, 2j + 1) of thread t is stored at pair slot
+// j T + t (T = N / M threads), so that the solve's loads and stores of phi are
+// coalesced across the threads.  Node N (walls) and M = 1 keep the natural order
+// (with M = 2 the two orders coincide).
+__host__ __device__ __forceinline__ int64_t phi_slot(int k, int n_cells, int m) {
+  if (m < 2 || k >= n_cells) return k;
+  const int t = k / m, r = k - t * m;
+  return 2 * ((int64_t)(r >> 1) * (n_cells / m) + t) + (r & 1);
+}
+// Copy a replica's potential between the natural node order (the caller's) and the
+// solve's storage order: to_natural != 0 reads the store into dst[0..n_nodes).
+void launch_phi_copy(const RepDev* d_reps, int rep, const double* d_src, double* d_dst,
+                     int to_natural, hipStream_t stream);
 void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
                     uint32_t* d_status, hipStream_t stream);
 // Electron loading profile of every replica: density exp(phi), mean velocity the

@@ -141,7 +141,7 @@ __global__ void k_electron_profile(const RepDev* __restrict__ reps,
   // node density q 2^-40 / h against n_floor, i.e. q against n_floor h 2^40
   const double qfloor = R.n_floor * R.h * kFxScale;
   for (int k = threadIdx.x; k < R.n_nodes; k += blockDim.x) {
-    pn[k] = exp(phi[k]);
+    pn[k] = exp(phi[phi_slot(k, R.n_cells, R.field_m)]);
     if (from_moments) {
       const double q = (double)qi[k];
       pu[k] = q > qfloor ? (double)ji[k] / q : 0.0;

@@ -215,10 +215,11 @@ __device__ __forceinline__ void newton_body(const RepDev& R, NewtonLds& S, int i
           phi[j] = log(fmax(charge(j) / s, 1e-8));
         }
       } else if constexpr (M >= 2) {
-        const auto p2 = gmem(reinterpret_cast<const f64x2*>(R.phi)) + t * (M / 2);
+        // storage order of phi_slot: pair j of thread t at pair slot j T + t
+        const auto p2 = gmem(reinterpret_cast<const f64x2*>(R.phi)) + t;
 #pragma unroll
         for (int j = 0; j < M / 2; ++j) {
-          const f64x2 v = p2[j];
+          const f64x2 v = p2[j * T];
           phi[2 * j] = v.x;
           phi[2 * j + 1] = v.y;
         }
@@ -435,9 +436,9 @@ __device__ __forceinline__ void newton_body(const RepDev& R, NewtonLds& S, int i
   __syncthreads();
   if (act) {
     if constexpr (M >= 2) {
-      const auto p2 = reinterpret_cast<EFPI_GLOBAL f64x2*>(phig) + t * (M / 2);
+      const auto p2 = reinterpret_cast<EFPI_GLOBAL f64x2*>(phig) + t;  // phi_slot order
 #pragma unroll
-      for (int j = 0; j < M / 2; ++j) p2[j] = f64x2{phi[2 * j], phi[2 * j + 1]};
+      for (int j = 0; j < M / 2; ++j) p2[j * T] = f64x2{phi[2 * j], phi[2 * j + 1]};
     } else {
       phig[t] = phi[0];
     }
@@ -654,9 +655,9 @@ __device__ __forceinline__ void poisson_body(const RepDev& R, PoissonLds& S, int
     const auto eg = gmem(R.e);
     const auto eng = gmem(R.en);
     if constexpr (M >= 4) {
-      const auto p2 = reinterpret_cast<EFPI_GLOBAL f64x2*>(phig) + t * (M / 2);
+      const auto p2 = reinterpret_cast<EFPI_GLOBAL f64x2*>(phig) + t;  // phi_slot order
 #pragma unroll
-      for (int j = 0; j < M / 2; ++j) p2[j] = f64x2{r[2 * j], r[2 * j + 1]};
+      for (int j = 0; j < M / 2; ++j) p2[j * T] = f64x2{r[2 * j], r[2 * j + 1]};
       const auto e4 = reinterpret_cast<EFPI_GLOBAL f32x4*>(eg) + t * (M / 4);
       const auto n4 = reinterpret_cast<EFPI_GLOBAL f32x4*>(eng) + t * (M / 4);
 #pragma unroll
@@ -702,6 +703,25 @@ __global__ __launch_bounds__(kFieldThreads) void k_poisson(const RepDev* __restr
 }
 
 }  // namespace
+
+namespace {
+__global__ void k_phi_copy(const RepDev* __restrict__ reps, int rep, const double* __restrict__ src,
+                           double* __restrict__ dst, int to_natural) {
+  const RepDev& R = reps[rep];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < R.n_nodes;
+       k += gridDim.x * blockDim.x) {
+    const int64_t s = phi_slot(k, R.n_cells, R.field_m);
+    if (to_natural) dst[k] = src[s];
+    else dst[s] = src[k];
+  }
+}
+}  // namespace
+
+void launch_phi_copy(const RepDev* d_reps, int rep, const double* d_src, double* d_dst,
+                     int to_natural, hipStream_t stream) {
+  hipLaunchKernelGGL(k_phi_copy, dim3(64), dim3(256), 0, stream, d_reps, rep, d_src, d_dst,
+                     to_natural);
+}
 
 void launch_poisson(const RepDev* d_reps, int n_reps, int qsel, int save_en, int zero_bins,
                     uint32_t* d_status, hipStream_t stream) {
