@@ -466,11 +466,7 @@ efpi_status check_rep(efpi_ctx* ctx, int32_t r) {
 }
 
 void deposit_into_next(efpi_ctx* c) {
-  const int nxt = c->cur ^ 1;
-  if (!c->other_zero) {
-    for (int r = 0; r < c->R; ++r)
-      launch_fill_u8(c->h_reps[r].q[nxt], sizeof(int64_t) * c->h_reps[r].n_nodes, c->stream);
-  }
+  if (!c->other_zero) launch_zero_charge(c->d_reps, c->R, c->cur ^ 1, c->stream);
 }
 
 void run_newton(efpi_ctx* c, int iters, int cold, int save_en, int zero_bins) {

@@ -142,6 +142,8 @@ __host__ __device__ __forceinline__ int64_t phi_slot(int k, int n_cells, int m) 
   const int t = k / m, r = k - t * m;
   return 2 * ((int64_t)(r >> 1) * (n_cells / m) + t) + (r & 1);
 }
+// Clear q[which] of every replica (one launch).
+void launch_zero_charge(const RepDev* d_reps, int n_reps, int which, hipStream_t stream);
 // Copy a replica's potential between the natural node order (the caller's) and the
 // solve's storage order: to_natural != 0 reads the store into dst[0..n_nodes).
 void launch_phi_copy(const RepDev* d_reps, int rep, const double* d_src, double* d_dst,

@@ -717,6 +717,20 @@ __global__ void k_phi_copy(const RepDev* __restrict__ reps, int rep, const doubl
 }
 }  // namespace
 
+namespace {
+// Every replica's charge buffer q[which] cleared in one launch (block row r: replica r).
+__global__ void k_zero_charge(const RepDev* __restrict__ reps, int which) {
+  const RepDev& R = reps[blockIdx.y];
+  const auto q = gmem(reinterpret_cast<long long*>(R.q[which]));
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < R.n_nodes; k += gridDim.x * blockDim.x)
+    q[k] = 0;
+}
+}  // namespace
+
+void launch_zero_charge(const RepDev* d_reps, int n_reps, int which, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_charge, dim3(8, n_reps), dim3(256), 0, stream, d_reps, which);
+}
+
 void launch_phi_copy(const RepDev* d_reps, int rep, const double* d_src, double* d_dst,
                      int to_natural, hipStream_t stream) {
   hipLaunchKernelGGL(k_phi_copy, dim3(64), dim3(256), 0, stream, d_reps, rep, d_src, d_dst,
