@@ -385,6 +385,20 @@ def test_invalid_config_rejected():
         make_ctx([E.ReplicaSpec(100, 100.0)])  # not a power of two
 
 
+@pytest.mark.parametrize("n_cells,bc", [(128, 0), (2048, 1), (4096, 0), (16384, 1)])
+def test_potential_round_trip(n_cells, bc):
+    """The field solve stores the potential in its own order (pairs of each thread's
+    nodes side by side); efpi_set_potential and efpi_get_grid translate, so a
+    potential comes back bit for bit, node N of a walled grid included."""
+    E = lib()
+    ctx = make_ctx([E.ReplicaSpec(n_cells, float(n_cells), bc=bc, ppc=1)])
+    nn = n_cells + (1 if bc == 1 else 0)
+    phi = np.random.default_rng(n_cells).standard_normal(nn)
+    E.efpi_set_potential(ctx.ctx, 0, to_dev(phi, torch.float64))
+    _, got, _ = grid_np(ctx)
+    assert np.array_equal(got[:nn], phi)
+
+
 def test_newton_status_flag():
     E = lib()
     spec = E.ReplicaSpec(256, 256.0, bc=1, ppc=16, haar_levels=2, vth=0.1)
