@@ -705,6 +705,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_poisson(const RepDev* __restr
 }  // namespace
 
 namespace {
+// A replica's potential between the natural node order and the solve's (phi_slot).
 __global__ void k_phi_copy(const RepDev* __restrict__ reps, int rep, const double* __restrict__ src,
                            double* __restrict__ dst, int to_natural) {
   const RepDev& R = reps[rep];
@@ -715,9 +716,7 @@ __global__ void k_phi_copy(const RepDev* __restrict__ reps, int rep, const doubl
     else dst[s] = src[k];
   }
 }
-}  // namespace
 
-namespace {
 // Every replica's charge buffer q[which] cleared in one launch (block row r: replica r).
 __global__ void k_zero_charge(const RepDev* __restrict__ reps, int which) {
   const RepDev& R = reps[blockIdx.y];
