@@ -127,6 +127,14 @@ def test_phase_lift_matches_oracle(n, levels, jf, jc, ppc, filt):
     assert np.max(np.abs(gw - rw)) <= 1e-6 * np.max(np.abs(rw))
 
 
+def test_phase_lift_matches_oracle_at_the_papers_resolution():
+    """The lift at the paper's velocity resolution (2^11 bins, 2^6 Coiflet-12
+    coefficients per node) on 1024 cells and l = 4: cells and offsets bit-exact,
+    velocities and weights within 1e-6 (the CDF repair's decisions are the oracle's).
+    The oracle's repair runs node by node in Python, about 20 s here."""
+    test_phase_lift_matches_oracle(1024, 4, 11, 6, 8, "coif12")
+
+
 @pytest.mark.parametrize("n,levels,jf,jc,ppc,filt", [(128, 2, 6, 4, 48, "d4"),
                                                      (4096, 4, 8, 5, 8, "coif12")])
 def test_phase_macro_step_matches_oracle(n, levels, jf, jc, ppc, filt):
