@@ -27,7 +27,9 @@ constexpr int kPhWin = 4;      // coarse x nodes of a work item's LDS window (at
 constexpr int kPhGrid = 8192;  // workgroups, striding over the work items
 // Histogram workgroups of 512 threads: at 2^11 bins (a 48 KB window, three
 // workgroups per CU) 47 us per restriction of 4,096,000 ions against 59 us with
-// 256 threads; at 2^8 bins the same (33 us); 1024 threads: 47 and 41 us.
+// 256 threads; at 2^8 bins the same (33 us); 1024 threads: 47 and 41 us.  (Since
+// the ion loop lost its integer divisions and issues its field gathers first:
+// 41 us at 2^11 bins, 28 us at 2^8.)
 #ifndef EFPI_HIST_THREADS
 #define EFPI_HIST_THREADS 512
 #endif
@@ -60,6 +62,7 @@ __global__ __launch_bounds__(kHistThreads) void k_phase_hist(const RepDev* __res
   const float half_dt = 0.5f * (float)R.dt;
   const float tau_inv_h = a.tau * (float)R.inv_h;
   const int cells = a.win * a.n_vf;
+  const int lvf = __builtin_ctz(a.n_vf);
   for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
     const int64_t i0 = item * a.tile;
     const int64_t i1 = min(i0 + (int64_t)a.tile, np);
@@ -67,8 +70,10 @@ __global__ __launch_bounds__(kHistThreads) void k_phase_hist(const RepDev* __res
     const int base = ((c_first >> a.levels) - a.win / 2 + 1 + nxc) % nxc;
     for (int k = threadIdx.x; k < cells; k += kHistThreads) s_h[k] = 0;
     __syncthreads();
+    // no integer division in the ion loop: K and base lie in [0, nxc)
     auto add = [&](int K, int kv, long long val) {
-      const int slot = (K - base + nxc) % nxc;
+      int slot = K - base;
+      if (slot < 0) slot += nxc;
       if (slot < a.win)
         atomicAdd(reinterpret_cast<unsigned long long*>(&s_h[slot * a.n_vf + kv]),
                   (unsigned long long)val);
@@ -82,18 +87,26 @@ __global__ __launch_bounds__(kHistThreads) void k_phase_hist(const RepDev* __res
       add(K, kv, s * (long long)(span - d));
       if (d) add(K + 1 == nxc ? 0 : K + 1, kv, s * (long long)d);
     };
+    const bool need_e = !a.fresh || a.tau != 0.f;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kHistThreads) {
+      // every load of the ion, its field gathers included, is issued before the
+      // ion is tested (an ion outside the grid gathers at node 0 and is skipped)
       const int c = cellp[i];
-      if (c < 0 || c >= n) continue;
       const float f = fracp[i];
       const float w = wp[i];
       float v = velp[i];
+      const int cc = (c >= 0 && c < n) ? c : 0;
+      const float e0 = need_e ? e[cc] : 0.f;
+      const float e1 = need_e ? e[(cc + 1) & nmask] : 0.f;
+      const float n0 = a.stored_field ? en_[cc] : 0.f;
+      const float n1 = a.stored_field ? en_[(cc + 1) & nmask] : 0.f;
+      if (c < 0 || c >= n) continue;
       float ep = 0.f;
-      if (!a.fresh || a.tau != 0.f) ep = (1.f - f) * e[c] + f * e[(c + 1) & nmask];
+      if (need_e) ep = (1.f - f) * e0 + f * e1;
       if (!a.fresh) v += half_dt * ep;  // time-centred velocity after a burst
       // co-evolving frame: X + tau v, V = v + tau E_n(X) (App. B), E_n the field
       // stored at the burst start or the current one
-      const float en = a.stored_field ? (1.f - f) * en_[c] + f * en_[(c + 1) & nmask] : ep;
+      const float en = a.stored_field ? (1.f - f) * n0 + f * n1 : ep;
       const float xs = f + tau_inv_h * v;
       const float fl = floorf(xs);
       const bool wrap_up = (xs - fl) >= 1.f;
@@ -112,8 +125,10 @@ __global__ __launch_bounds__(kHistThreads) void k_phase_hist(const RepDev* __res
     for (int k = threadIdx.x; k < cells; k += kHistThreads) {
       const long long val = s_h[k];
       if (val != 0) {
-        const int K = (base + k / a.n_vf) % nxc;
-        atomicAdd(reinterpret_cast<unsigned long long*>(&hist[(int64_t)K * a.n_vf + k % a.n_vf]),
+        int K = base + (k >> lvf);  // n_vf = 2^lvf; a window slot is below win <= nxc
+        if (K >= nxc) K -= nxc;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&hist[(int64_t)K * a.n_vf +
+                                                             (k & (a.n_vf - 1))]),
                   (unsigned long long)val);
       }
     }
