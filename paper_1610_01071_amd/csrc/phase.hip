@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kPhThreads) void k_phase_refine(const double* __res
       for (int m = 0; m < a.n_taps; ++m) {
         const int r = t - m;
         if (r & 1) continue;
-        const int k = ((r % n2 + n2) % n2) >> 1;
+        const int k = (r & (n2 - 1)) >> 1;  // r mod n2 (n2 a power of two, r >= -15)
         acc = acc + a.taps[m] * cur[k];
       }
       nxt[t] = acc;
