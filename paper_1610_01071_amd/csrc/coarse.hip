@@ -103,8 +103,8 @@ __device__ void profile_of(const RepDev& R, const double* __restrict__ cn,
       w0 = 1.0 - th;
       w1 = th;
       if (periodic) {
-        b0 = (b0 % nc + nc) % nc;
-        b1 = (b1 % nc + nc) % nc;
+        b0 &= nc - 1;  // nc is a power of two: the periodic index without dividing
+        b1 &= nc - 1;
       } else {
         if (b0 < 0) { b0 = 0; b1 = 0; w0 = 1.0; w1 = 0.0; }
         if (b1 > nc - 1) { b0 = nc - 1; b1 = nc - 1; w0 = 1.0; w1 = 0.0; }
